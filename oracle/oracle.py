@@ -1,0 +1,200 @@
+"""ctypes shim over the FP64 CPU oracle (pinn_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg are the only users.  The product path never imports this module,
+and this module never imports the product package.
+
+Network and PDE descriptions are plain dicts (the same dicts the seeded input
+generator produces), so that nothing but data is shared with the HIP path:
+
+  net = {"d_in", "d_out", "widths": [..], "act": "tanh"|"sin", "w0", "n_freq",
+         "rwf", "has_bias"}
+  pde = {"pde": "burgers"|"euler1d"|"ns2d"|"maxwell", "lap_mask", "coef": [..4],
+         "lambda_res": [..3], "norm_N"}
+Arrays may be float32; they are promoted to float64 before the call.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "pinn_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+PDE_IDS = {"burgers": 1, "euler1d": 2, "ns2d": 3, "maxwell": 4}
+ACTS = {"tanh": 0, "sin": 1}
+
+
+class _Net(ctypes.Structure):
+    _fields_ = [("d_in", ctypes.c_int32), ("d_out", ctypes.c_int32),
+                ("n_hidden", ctypes.c_int32), ("width", ctypes.c_int32 * 8),
+                ("act", ctypes.c_int32), ("w0", ctypes.c_double),
+                ("n_freq", ctypes.c_int32), ("rwf", ctypes.c_int32),
+                ("has_bias", ctypes.c_int32)]
+
+
+class _Pde(ctypes.Structure):
+    _fields_ = [("pde_id", ctypes.c_int32), ("lap_mask", ctypes.c_int32),
+                ("coef", ctypes.c_double * 4), ("lambda_res", ctypes.c_double * 3),
+                ("norm_N", ctypes.c_double)]
+
+
+class _Anchor(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("targets", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("out_mask", ctypes.c_int32),
+                ("lambda_", ctypes.c_double)]
+
+
+def build(force=False):
+    """Compile the oracle with gcc (plain -O2, IEEE semantics, OpenMP)."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                           "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        L.or_param_count.restype = ctypes.c_int64
+        L.or_param_count.argtypes = [ctypes.POINTER(_Net)]
+        L.or_forward_jets.restype = ctypes.c_int
+        L.or_forward_jets.argtypes = [ctypes.POINTER(_Net), ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p]
+        L.or_pde_residual.restype = ctypes.c_int
+        L.or_pde_residual.argtypes = [ctypes.POINTER(_Pde), ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        L.or_n_residuals.restype = ctypes.c_int
+        L.or_n_residuals.argtypes = [ctypes.c_int]
+        L.or_loss_grad.restype = ctypes.c_int
+        L.or_loss_grad.argtypes = [ctypes.POINTER(_Net), ctypes.POINTER(_Pde),
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int64, ctypes.POINTER(_Anchor), ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _net(spec):
+    n = _Net()
+    n.d_in = int(spec["d_in"])
+    n.d_out = int(spec["d_out"])
+    widths = list(spec["widths"])
+    n.n_hidden = len(widths)
+    for i, w in enumerate(widths):
+        n.width[i] = int(w)
+    n.act = ACTS[spec.get("act", "tanh")]
+    n.w0 = float(spec.get("w0", 1.0))
+    n.n_freq = int(spec.get("n_freq", 0))
+    n.rwf = int(bool(spec.get("rwf", False)))
+    n.has_bias = int(bool(spec.get("has_bias", True)))
+    return n
+
+
+def _pde(spec):
+    p = _Pde()
+    p.pde_id = PDE_IDS[spec["pde"]]
+    p.lap_mask = int(spec.get("lap_mask", 0))
+    coef = list(spec.get("coef", [])) + [0.0] * 4
+    for i in range(4):
+        p.coef[i] = float(coef[i])
+    lam = list(spec.get("lambda_res", [1.0, 1.0, 1.0])) + [1.0] * 3
+    for i in range(3):
+        p.lambda_res[i] = float(lam[i])
+    p.norm_N = float(spec.get("norm_N", 0.0))
+    return p
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def n_channels(net_spec, lap_mask):
+    return 1 + int(net_spec["d_in"]) + (1 if lap_mask else 0)
+
+
+def n_residuals(pde_name):
+    return 1 if pde_name == "burgers" else 3
+
+
+def param_count(net_spec):
+    n = _net(net_spec)
+    return int(lib().or_param_count(ctypes.byref(n)))
+
+
+def forward_jets(net_spec, lap_mask, params, B, pts):
+    """Output jets, shape (n, d_out, C): channel 0 value, 1+k d/dx_k, 1+d_in Laplacian."""
+    n = _net(net_spec)
+    params = _f64(params)
+    pts = _f64(pts).reshape(-1, n.d_in)
+    Bv = None if B is None else _f64(B)
+    C = n_channels(net_spec, lap_mask)
+    out = np.zeros((pts.shape[0], n.d_out, C))
+    rc = lib().or_forward_jets(ctypes.byref(n), int(lap_mask), _ptr(params), _ptr(Bv), _ptr(pts),
+                               pts.shape[0], _ptr(out))
+    if rc != 0:
+        raise ValueError("or_forward_jets failed: %d" % rc)
+    return out
+
+
+def pde_residual(pde_spec, d_in, d_out, jets):
+    """Residuals (n, n_res) of the PDE stage alone, from given output jets (n, d_out, C)."""
+    p = _pde(pde_spec)
+    jets = _f64(jets)
+    nres = n_residuals(pde_spec["pde"])
+    out = np.zeros((jets.shape[0], nres))
+    rc = lib().or_pde_residual(ctypes.byref(p), int(d_in), int(d_out), _ptr(jets), jets.shape[0],
+                               _ptr(out))
+    if rc != 0:
+        raise ValueError("or_pde_residual failed: %d" % rc)
+    return out
+
+
+def loss_grad(net_spec, pde_spec, params, B, pts, anchors=(), want_grad=True,
+              want_residual=True, n_threads=0):
+    """Loss terms, residuals and the parameter gradient in FP64.
+
+    anchors: sequence of dicts {"points" (n x d_in), "targets" (n x d_out), "out_mask",
+    "lambda"}.  Returns dict(loss=[total, res_0.., anchor_0..], residual, grad)."""
+    n = _net(net_spec)
+    p = _pde(pde_spec)
+    params = _f64(params)
+    pts = _f64(pts).reshape(-1, n.d_in)
+    Bv = None if B is None else _f64(B)
+    nres = n_residuals(pde_spec["pde"])
+    keep = []
+    arr = (_Anchor * max(1, len(anchors)))()
+    for i, a in enumerate(anchors):
+        ap = _f64(a["points"]).reshape(-1, n.d_in)
+        at = _f64(a["targets"]).reshape(-1, n.d_out)
+        keep += [ap, at]
+        arr[i].points = ap.ctypes.data
+        arr[i].targets = at.ctypes.data
+        arr[i].n = ap.shape[0]
+        arr[i].out_mask = int(a.get("out_mask", 1))
+        arr[i].lambda_ = float(a.get("lambda", 1.0))
+    loss = np.zeros(1 + nres + len(anchors))
+    res = np.zeros((pts.shape[0], nres)) if want_residual else None
+    grad = np.zeros(param_count(net_spec)) if want_grad else None
+    rc = lib().or_loss_grad(ctypes.byref(n), ctypes.byref(p), _ptr(params), _ptr(Bv), _ptr(pts),
+                            pts.shape[0], arr, len(anchors), _ptr(res), _ptr(loss), _ptr(grad),
+                            int(n_threads))
+    if rc != 0:
+        raise ValueError("or_loss_grad failed: %d" % rc)
+    return {"loss": loss, "residual": res, "grad": grad}

@@ -1,0 +1,494 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test checks the oracle against what the paper and the mathematics fix:
+closed forms (single-neuron networks, manufactured analytic fields whose residual is
+known, networks that represent an exact solution), symbolic differentiation (sympy),
+finite differences, the paper's own autograd formulation (torch FP64, Sec. 2.3) and
+invariants of the mean-squared loss.  The paper prints no residual, loss or gradient
+value for a concrete network, so there is no printed worked example to pin against.
+"""
+import math
+
+import numpy as np
+import pytest
+import sympy as sp
+import torch
+
+from paper_2604_15645_amd import synth
+
+torch.set_default_dtype(torch.float64)
+
+PDES = {
+    "burgers": dict(pde="burgers", lap_mask=1, coef=[0.01 / math.pi, 0, 0, 0]),
+    "euler1d": dict(pde="euler1d", lap_mask=0, coef=[1.4, 0, 0, 0]),
+    "ns2d": dict(pde="ns2d", lap_mask=3, coef=[100.0, 0, 0, 0]),
+    "maxwell": dict(pde="maxwell", lap_mask=0, coef=[1.0, 1.0, 0, 0]),
+}
+D_IN = {"burgers": 2, "euler1d": 2, "ns2d": 2, "maxwell": 3}
+D_OUT = {"burgers": 1, "euler1d": 3, "ns2d": 3, "maxwell": 3}
+
+
+def small_net(pde, widths=(6, 5), act="tanh", n_freq=0, rwf=False, has_bias=True, w0=1.0):
+    return dict(d_in=D_IN[pde], d_out=D_OUT[pde], widths=list(widths), act=act, w0=w0,
+                n_freq=n_freq, rwf=rwf, has_bias=has_bias)
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+# --------------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("act", ["tanh", "sin"])
+def test_single_neuron_jets_closed_form(oracle, act):
+    """u = c*sigma(w.x + b) + d: first derivatives and the Laplacian from sympy."""
+    x, t = sp.symbols("x t")
+    w = [0.7, -1.3]
+    b, c, d, w0 = 0.2, 1.5, -0.4, 1.7
+    z = w[0] * x + w[1] * t + b
+    u = c * (sp.tanh(z) if act == "tanh" else sp.sin(w0 * z)) + d
+    net = dict(d_in=2, d_out=1, widths=[1], act=act, w0=w0, n_freq=0, rwf=False, has_bias=True)
+    params = np.array(w + [b] + [c] + [d])
+    pts = rng(1).uniform(-1, 1, size=(7, 2))
+    for lap_mask in (1, 2, 3):
+        jets = oracle.forward_jets(net, lap_mask, params, None, pts)
+        for i, (xv, tv) in enumerate(pts):
+            sub = {x: xv, t: tv}
+            lap = 0
+            if lap_mask & 1:
+                lap += sp.diff(u, x, 2)
+            if lap_mask & 2:
+                lap += sp.diff(u, t, 2)
+            exp = [float(u.subs(sub)), float(sp.diff(u, x).subs(sub)),
+                   float(sp.diff(u, t).subs(sub)), float(lap.subs(sub))]
+            assert np.allclose(jets[i, 0], exp, rtol=1e-14, atol=1e-14)
+
+
+def test_fourier_embedding_readout_closed_form(oracle):
+    """Zero hidden layers: the output is a linear read-out of [cos(xB), sin(xB)]."""
+    x, y, t = sp.symbols("x y t")
+    r = rng(2)
+    m = 3
+    B = r.normal(0, 2.0, size=(3, m))
+    Wout = r.normal(0, 1.0, size=(1, 2 * m))
+    bout = np.array([0.3])
+    v = [B[0, j] * x + B[1, j] * y + B[2, j] * t for j in range(m)]
+    feats = [sp.cos(vj) for vj in v] + [sp.sin(vj) for vj in v]
+    u = sum(Wout[0, j] * feats[j] for j in range(2 * m)) + bout[0]
+    net = dict(d_in=3, d_out=1, widths=[], act="tanh", w0=1.0, n_freq=m, rwf=False,
+               has_bias=True)
+    params = np.concatenate([Wout.ravel(), bout])
+    pts = r.uniform(0, 1, size=(5, 3))
+    jets = oracle.forward_jets(net, 3, params, B, pts)
+    for i, p in enumerate(pts):
+        sub = dict(zip((x, y, t), p))
+        exp = [u, sp.diff(u, x), sp.diff(u, y), sp.diff(u, t), sp.diff(u, x, 2) + sp.diff(u, y, 2)]
+        exp = [float(e.subs(sub)) for e in exp]
+        assert np.allclose(jets[i, 0], exp, rtol=1e-13, atol=1e-13)
+
+
+# ------------------------------------------------------------- finite differences
+
+@pytest.mark.parametrize("variant", ["tanh", "sin", "rff", "rwf", "rff_rwf_sin"])
+def test_jets_match_finite_differences(oracle, variant):
+    act = "sin" if "sin" in variant else "tanh"
+    n_freq = 4 if "rff" in variant else 0
+    rwf = "rwf" in variant
+    net = dict(d_in=3, d_out=2, widths=[7, 6, 5], act=act, w0=1.3, n_freq=n_freq, rwf=rwf,
+               has_bias=True)
+    r = rng(3)
+    params = synth.init_params(net, r, perturb=True).astype(np.float64)
+    B = r.normal(0, 1.0, size=(3, n_freq)) if n_freq else None
+    pts = r.uniform(-1, 1, size=(6, 3))
+    lap_mask = 5  # inputs 0 and 2
+    jets = oracle.forward_jets(net, lap_mask, params, B, pts)
+    h = 2.5e-4
+
+    def d1(k, ch):
+        """Fourth-order central difference of channel ch along input k."""
+        e = np.zeros(3)
+        e[k] = h
+        f = [oracle.forward_jets(net, lap_mask, params, B, pts + s * e)[:, :, ch]
+             for s in (2, 1, -1, -2)]
+        return (-f[0] + 8 * f[1] - 8 * f[2] + f[3]) / (12 * h)
+
+    scale = np.abs(jets).max()
+    lap_fd = 0
+    for k in range(3):
+        assert np.abs(jets[:, :, 1 + k] - d1(k, 0)).max() <= 1e-8 * scale
+        if lap_mask & (1 << k):
+            lap_fd = lap_fd + d1(k, 1 + k)
+    assert np.abs(jets[:, :, 4] - lap_fd).max() <= 1e-7 * scale
+
+
+@pytest.mark.parametrize("pde,variant", [("burgers", "rwf"), ("burgers", "rff_sin"),
+                                         ("euler1d", "rff"), ("ns2d", "rwf"),
+                                         ("maxwell", "rff_sin"), ("ns2d", "nobias")])
+def test_gradient_matches_central_differences(oracle, pde, variant):
+    """Every parameter of a tiny network: central differences of the FP64 loss."""
+    net = small_net(pde, widths=(5, 4), act="sin" if "sin" in variant else "tanh",
+                    n_freq=3 if "rff" in variant else 0, rwf="rwf" in variant,
+                    has_bias=variant != "nobias")
+    r = rng(4)
+    params = synth.init_params(net, r, perturb=True).astype(np.float64)
+    B = r.normal(0, 1.0, size=(net["d_in"], net["n_freq"])) if net["n_freq"] else None
+    pts = r.uniform(0.05, 0.95, size=(9, net["d_in"]))
+    anchors = []
+    if pde == "burgers":
+        ap = r.uniform(-1, 1, size=(4, 2))
+        anchors = [dict(points=ap, targets=np.sin(ap[:, :1]), out_mask=1, **{"lambda": 0.7})]
+    spec = dict(PDES[pde], lambda_res=[1.0, 0.5, 2.0])
+    res = oracle.loss_grad(net, spec, params, B, pts, anchors)
+    g = res["grad"]
+    fd = np.zeros_like(g)
+    for i in range(params.size):
+        h = 1e-6 * max(1.0, abs(params[i]))
+        pp = params.copy()
+        pp[i] += h
+        lp = oracle.loss_grad(net, spec, pp, B, pts, anchors, want_grad=False)["loss"][0]
+        pp[i] -= 2 * h
+        lm = oracle.loss_grad(net, spec, pp, B, pts, anchors, want_grad=False)["loss"][0]
+        fd[i] = (lp - lm) / (2 * h)
+    scale = max(1e-3, np.abs(g).max())
+    assert np.abs(fd - g).max() <= 1e-6 * scale
+
+
+def test_output_bias_gradient_closed_form(oracle):
+    """Burgers: shifting the output bias by delta shifts u only, so
+    dL/db_out = (2/N) sum r_i u_x,i + sum over anchor sets (2/N_s) sum (u - target)."""
+    case = synth.make_case("burgers", n_points=200, seed=11, perturb=True)
+    case["anchors"] = [dict(a, points=a["points"][:40], targets=a["targets"][:40])
+                       for a in case["anchors"]]
+    net, pde = case["net"], case["pde"]
+    res = oracle.loss_grad(net, pde, case["params"], None, case["points"], case["anchors"])
+    jets = oracle.forward_jets(net, 1, case["params"], None, case["points"])
+    r = res["residual"][:, 0]
+    expect = 2.0 / len(r) * np.sum(r * jets[:, 0, 1])
+    for a in case["anchors"]:
+        ja = oracle.forward_jets(net, 1, case["params"], None, a["points"])
+        expect += 2.0 / len(a["points"]) * np.sum(ja[:, 0, 0] - a["targets"][:, 0])
+    assert abs(res["grad"][-1] - expect) <= 1e-12 * max(1.0, abs(expect))
+
+
+# ------------------------------------------------- the paper's autograd formulation
+
+def torch_network(net, params, B):
+    """The network of Sec. 2.2 / App. A built from torch ops, FP64."""
+    dims = synth.layer_dims(net)
+    off = 0
+    layers = []
+    for no, ni in dims:
+        W = params[off:off + no * ni].view(no, ni)
+        off += no * ni
+        s = b = None
+        if net.get("rwf"):
+            s = params[off:off + no]
+            off += no
+        if net.get("has_bias", True):
+            b = params[off:off + no]
+            off += no
+        layers.append((W, s, b))
+    Bt = None if B is None else torch.as_tensor(B, dtype=torch.float64)
+
+    def f(x):
+        h = x
+        if Bt is not None:
+            xm = x @ Bt
+            h = torch.cat([torch.cos(xm), torch.sin(xm)], -1)
+        for li, (W, s, b) in enumerate(layers):
+            if s is not None:
+                W = torch.diag_embed(torch.exp(s)) @ W
+            h = h @ W.T
+            if b is not None:
+                h = h + b
+            if li < len(layers) - 1:
+                h = torch.tanh(h) if net["act"] == "tanh" else torch.sin(net["w0"] * h)
+        return h
+    return f
+
+
+def torch_loss(net, pde, params_np, B, pts_np, anchors):
+    params = torch.tensor(np.asarray(params_np, dtype=np.float64), requires_grad=True)
+    f = torch_network(net, params, B)
+    x = torch.tensor(np.asarray(pts_np, dtype=np.float64), requires_grad=True)
+    y = f(x)
+
+    def d(q, k):
+        return torch.autograd.grad(q.sum(), x, create_graph=True)[0][:, k]
+
+    name = pde["pde"]
+    if name == "burgers":
+        nu = pde["coef"][0]
+        u = y[:, 0]
+        ux = d(u, 0)
+        res = [d(u, 1) + u * ux - nu * d(ux, 0)]
+    elif name == "euler1d":
+        gam = pde["coef"][0]
+        rho, u, p = y[:, 0], y[:, 1], y[:, 2]
+        E = p / ((gam - 1.0) * rho) + 0.5 * u * u
+        q = [rho, rho * u, rho * E]
+        fl = [rho * u, rho * u * u + p, u * (rho * E + p)]
+        res = [d(q[i], 1) + d(fl[i], 0) for i in range(3)]
+    elif name == "ns2d":
+        Re = pde["coef"][0]
+        u, v, p = y[:, 0], y[:, 1], y[:, 2]
+        ux, uy, vx, vy = d(u, 0), d(u, 1), d(v, 0), d(v, 1)
+        lu = d(ux, 0) + d(uy, 1)
+        lv = d(vx, 0) + d(vy, 1)
+        res = [ux + vy, u * ux + v * uy + d(p, 0) - lu / Re, u * vx + v * vy + d(p, 1) - lv / Re]
+    else:
+        eps, mu = pde["coef"][0], pde["coef"][1]
+        ez, hx, hy = y[:, 0], y[:, 1], y[:, 2]
+        res = [d(ez, 2) - (d(hy, 0) - d(hx, 1)) / eps, d(hx, 2) + d(ez, 1) / mu,
+               d(hy, 2) - d(ez, 0) / mu]
+    lam = pde.get("lambda_res", [1, 1, 1])
+    terms = [lam[i] * (r * r).mean() for i, r in enumerate(res)]
+    for a in anchors:
+        ya = f(torch.tensor(np.asarray(a["points"], dtype=np.float64)))
+        tg = torch.tensor(np.asarray(a["targets"], dtype=np.float64))
+        acc = 0
+        for o in range(net["d_out"]):
+            if a["out_mask"] & (1 << o):
+                acc = acc + ((ya[:, o] - tg[:, o]) ** 2).mean()
+        terms.append(a["lambda"] * acc)
+    total = sum(terms)
+    grad = torch.autograd.grad(total, params)[0]
+    return (np.array([total.item()] + [t.item() for t in terms]),
+            np.stack([r.detach().numpy() for r in res], 1), grad.numpy())
+
+
+@pytest.mark.parametrize("pde,variant", [("burgers", "plain"), ("burgers", "rff_rwf"),
+                                         ("euler1d", "rff"), ("ns2d", "rwf"),
+                                         ("ns2d", "sin"), ("maxwell", "rff_sin"),
+                                         ("maxwell", "plain")])
+def test_oracle_matches_torch_autograd(oracle, pde, variant):
+    """The paper computes residuals and gradients with autograd (Sec. 2.3); the oracle's
+    forward-mode jets and reverse sweep must give the same numbers.  The Euler residual
+    here is the autograd of the conservative fluxes, not the product-rule expansion."""
+    net = small_net(pde, widths=(8, 7, 6), act="sin" if "sin" in variant else "tanh",
+                    n_freq=4 if "rff" in variant else 0, rwf="rwf" in variant, w0=1.1)
+    r = rng(5)
+    params = synth.init_params(net, r, perturb=True).astype(np.float64)
+    B = r.normal(0, 1.5, size=(net["d_in"], net["n_freq"])) if net["n_freq"] else None
+    pts = r.uniform(0.05, 0.95, size=(33, net["d_in"]))
+    if pde == "euler1d":
+        # keep density and pressure away from zero: shift the output biases
+        L = synth.layer_dims(net)[-1][0]
+        params[-L:] += np.array([2.0, 0.3, 1.5])
+    anchors = []
+    if pde == "burgers":
+        anchors = [dict(points=r.uniform(-1, 1, size=(5, 2)),
+                        targets=r.normal(size=(5, 1)), out_mask=1, **{"lambda": 0.9})]
+    spec = dict(PDES[pde], lambda_res=[1.0, 0.7, 1.3])
+    got = oracle.loss_grad(net, spec, params, B, pts, anchors)
+    loss, res, grad = torch_loss(net, spec, params, B, pts, anchors)
+    assert relerr(got["loss"], loss) < 1e-12
+    assert relerr(got["residual"], res) < 1e-12
+    assert relerr(got["grad"], grad) < 1e-11
+
+
+# ------------------------------------------------------------ residual stage alone
+
+def analytic_jets(fields, syms, lap_syms, pts):
+    """Output jets (n, n_fields, C) of analytic fields by symbolic differentiation."""
+    out = []
+    for p in pts:
+        sub = dict(zip(syms, p))
+        row = []
+        for f in fields:
+            ch = [f] + [sp.diff(f, s) for s in syms]
+            if lap_syms:
+                ch.append(sum(sp.diff(f, s, 2) for s in lap_syms))
+            row.append([float(sp.N(c.subs(sub))) for c in ch])
+        out.append(row)
+    return np.array(out)
+
+
+def test_burgers_manufactured(oracle):
+    x, t = sp.symbols("x t")
+    pts = rng(6).uniform([-1, 0], [1, 1], size=(6, 2))
+    nu = 0.01 / math.pi
+    pde = dict(pde="burgers", lap_mask=1, coef=[nu, 0, 0, 0])
+    # u = x / (1 + t) solves u_t + u u_x = 0 and has u_xx = 0
+    j = analytic_jets([x / (1 + t)], (x, t), (x,), pts)
+    assert np.abs(oracle.pde_residual(pde, 2, 1, j)).max() < 1e-14
+    # u = sin(pi x) exp(-t): r = e^{-t} sin(pi x)(nu pi^2 - 1) + pi e^{-2t} sin(pi x) cos(pi x)
+    j = analytic_jets([sp.sin(sp.pi * x) * sp.exp(-t)], (x, t), (x,), pts)
+    xv, tv = pts[:, 0], pts[:, 1]
+    exp = (np.exp(-tv) * np.sin(np.pi * xv) * (nu * np.pi ** 2 - 1)
+           + np.pi * np.exp(-2 * tv) * np.sin(np.pi * xv) * np.cos(np.pi * xv))
+    assert np.allclose(oracle.pde_residual(pde, 2, 1, j)[:, 0], exp, rtol=1e-13, atol=1e-14)
+
+
+def test_euler_manufactured(oracle):
+    x, t = sp.symbols("x t")
+    pts = rng(7).uniform([0, 0], [1, 0.2], size=(6, 2))
+    pde = dict(pde="euler1d", lap_mask=0, coef=[1.4, 0, 0, 0])
+    u0, p0 = 0.7, 1.3
+    # entropy wave: density advected with constant velocity and pressure
+    rho = 1 + sp.Rational(1, 5) * sp.sin(sp.pi * (x - u0 * t))
+    j = analytic_jets([rho, sp.Float(u0) + 0 * x, sp.Float(p0) + 0 * x], (x, t), (), pts)
+    assert np.abs(oracle.pde_residual(pde, 2, 3, j)).max() < 1e-13
+    # a general smooth state: the conservative form differentiated symbolically
+    rho = 1.2 + 0.3 * sp.sin(2 * x + t)
+    u = 0.4 * sp.cos(x - 3 * t)
+    p = 1.0 + 0.2 * x * x + 0.1 * t
+    g = 1.4
+    rE = p / (g - 1) + rho * u * u / 2
+    q = [rho, rho * u, rE]
+    fl = [rho * u, rho * u * u + p, u * (rE + p)]
+    j = analytic_jets([rho, u, p], (x, t), (), pts)
+    got = oracle.pde_residual(pde, 2, 3, j)
+    for i, pt in enumerate(pts):
+        sub = {x: pt[0], t: pt[1]}
+        exp = [float((sp.diff(q[k], t) + sp.diff(fl[k], x)).subs(sub)) for k in range(3)]
+        assert np.allclose(got[i], exp, rtol=1e-12, atol=1e-13)
+
+
+def test_navier_stokes_kovasznay(oracle):
+    """Kovasznay flow solves the steady incompressible equations exactly."""
+    x, y = sp.symbols("x y")
+    Re = 40.0
+    lam = Re / 2 - math.sqrt(Re * Re / 4 + 4 * math.pi ** 2)
+    u = 1 - sp.exp(lam * x) * sp.cos(2 * sp.pi * y)
+    v = lam / (2 * sp.pi) * sp.exp(lam * x) * sp.sin(2 * sp.pi * y)
+    p = (1 - sp.exp(2 * lam * x)) / 2
+    pts = rng(8).uniform(-0.5, 1.0, size=(6, 2))
+    j = analytic_jets([u, v, p], (x, y), (x, y), pts)
+    pde = dict(pde="ns2d", lap_mask=3, coef=[Re, 0, 0, 0])
+    assert np.abs(oracle.pde_residual(pde, 2, 3, j)).max() < 1e-12
+
+
+def test_maxwell_plane_wave(oracle):
+    x, y, t = sp.symbols("x y t")
+    kx, ky = 1.3, -0.6
+    w = math.hypot(kx, ky)
+    phi = kx * x + ky * y - w * t
+    ez = sp.cos(phi)
+    pts = rng(9).uniform(0, 1, size=(6, 3))
+    j = analytic_jets([ez, ky / w * ez, -kx / w * ez], (x, y, t), (), pts)
+    pde = dict(pde="maxwell", lap_mask=0, coef=[1.0, 1.0, 0, 0])
+    assert np.abs(oracle.pde_residual(pde, 3, 3, j)).max() < 1e-14
+    # a wave with the wrong speed leaves a residual proportional to (w' - |k|^2 / w')
+    w2 = 2.0
+    phi2 = kx * x + ky * y - w2 * t
+    ez2 = sp.cos(phi2)
+    j = analytic_jets([ez2, ky / w2 * ez2, -kx / w2 * ez2], (x, y, t), (), pts)
+    r = oracle.pde_residual(pde, 3, 3, j)
+    ph = kx * pts[:, 0] + ky * pts[:, 1] - w2 * pts[:, 2]
+    assert np.allclose(r[:, 0], (w2 - (kx * kx + ky * ky) / w2) * np.sin(ph), atol=1e-14)
+    assert np.abs(r[:, 1:]).max() < 1e-14
+
+
+# ----------------------------------------------------- exactly representable networks
+
+def exact_case(kind):
+    r = rng(10)
+    if kind == "maxwell_wave":
+        kx, ky = 2.0, -1.5
+        w = math.hypot(kx, ky)
+        m = 2
+        B = np.array([[kx, 0.4], [ky, 1.1], [-w, -0.3]])
+        Wout = np.zeros((3, 2 * m))
+        Wout[0, 0], Wout[1, 0], Wout[2, 0] = 1.0, ky / w, -kx / w
+        net = dict(d_in=3, d_out=3, widths=[], act="tanh", w0=1.0, n_freq=m, rwf=False,
+                   has_bias=True)
+        params = np.concatenate([Wout.ravel(), r.normal(size=3)])
+        return net, PDES["maxwell"], params, B, r.uniform(0, 1, size=(40, 3))
+    if kind == "euler_entropy":
+        u0 = 0.6
+        B = np.array([[math.pi], [-math.pi * u0]])
+        Wout = np.zeros((3, 2))
+        Wout[0, 1] = 0.2
+        net = dict(d_in=2, d_out=3, widths=[], act="tanh", w0=1.0, n_freq=1, rwf=False,
+                   has_bias=True)
+        params = np.concatenate([Wout.ravel(), [1.0, u0, 1.1]])
+        return net, PDES["euler1d"], params, B, r.uniform(0, 1, size=(40, 2))
+    if kind == "ns_couette":
+        Wout = np.array([[0.0, 1.0], [0.0, 0.0], [0.0, 0.0]])
+        net = dict(d_in=2, d_out=3, widths=[], act="tanh", w0=1.0, n_freq=0, rwf=False,
+                   has_bias=True)
+        params = np.concatenate([Wout.ravel(), [0.0, 0.0, 0.3]])
+        return net, PDES["ns2d"], params, None, r.uniform(0, 1, size=(40, 2))
+    raise KeyError(kind)
+
+
+@pytest.mark.parametrize("kind", ["maxwell_wave", "euler_entropy", "ns_couette"])
+def test_exact_representable_networks(oracle, kind):
+    net, pde, params, B, pts = exact_case(kind)
+    res = oracle.loss_grad(net, pde, params, B, pts)
+    assert np.abs(res["residual"]).max() < 1e-14
+    assert res["loss"][0] < 1e-28
+    assert np.abs(res["grad"]).max() < 1e-14
+
+
+@pytest.mark.parametrize("pde", ["burgers", "euler1d", "ns2d", "maxwell"])
+def test_constant_output_network_has_zero_residual(oracle, pde):
+    """With W_out = 0 the outputs are the output biases: every derivative vanishes."""
+    net = small_net(pde, widths=(6, 6), n_freq=3, act="sin")
+    r = rng(12)
+    params = synth.init_params(net, r, perturb=True).astype(np.float64)
+    no, ni = synth.layer_dims(net)[-1]
+    start = params.size - (no * ni + no)
+    params[start:start + no * ni] = 0.0
+    B = r.normal(size=(net["d_in"], 3))
+    res = oracle.loss_grad(net, PDES[pde], params, B, r.uniform(0, 1, size=(20, net["d_in"])))
+    assert np.abs(res["residual"]).max() == 0.0
+    assert res["loss"][0] == 0.0
+    assert np.abs(res["grad"]).max() == 0.0
+
+
+# --------------------------------------------------------------------- invariants
+
+def test_loss_invariances(oracle):
+    case = synth.make_case("euler", n_points=300, seed=13, perturb=True)
+    net, pde, p, B, x = case["net"], case["pde"], case["params"], case["B"], case["points"]
+    base = oracle.loss_grad(net, pde, p, B, x)
+    perm = rng(14).permutation(len(x))
+    pr = oracle.loss_grad(net, pde, p, B, x[perm])
+    assert relerr(pr["loss"], base["loss"]) < 1e-14
+    assert relerr(pr["grad"], base["grad"]) < 1e-13
+    assert np.array_equal(pr["residual"], base["residual"][perm])
+    dup = oracle.loss_grad(net, pde, p, B, np.concatenate([x, x]))
+    assert relerr(dup["loss"], base["loss"]) < 1e-14
+    assert relerr(dup["grad"], base["grad"]) < 1e-13
+    # shards with the global N: N-weighted shard sums reproduce the whole
+    tot_l = 0
+    tot_g = 0
+    for sl in (slice(0, 77), slice(77, 201), slice(201, 300)):
+        s = oracle.loss_grad(net, dict(pde, norm_N=300.0), p, B, x[sl])
+        tot_l = tot_l + s["loss"]
+        tot_g = tot_g + s["grad"]
+    assert relerr(tot_l, base["loss"]) < 1e-14
+    assert relerr(tot_g, base["grad"]) < 1e-13
+
+
+def test_thread_count_does_not_change_bits(oracle):
+    case = synth.make_case("ns", n_points=500, seed=15, perturb=True)
+    a = oracle.loss_grad(case["net"], case["pde"], case["params"], None, case["points"], n_threads=1)
+    b = oracle.loss_grad(case["net"], case["pde"], case["params"], None, case["points"], n_threads=5)
+    assert np.array_equal(a["loss"], b["loss"])
+    assert np.array_equal(a["grad"], b["grad"])
+
+
+def test_planted_mistake_is_caught(oracle):
+    """A dropped term in the oracle (here: Laplacian coefficient zeroed through nu) must
+    show up against the closed form: the viscous Burgers pin fails with nu removed."""
+    x, t = sp.symbols("x t")
+    pts = rng(16).uniform([-1, 0], [1, 1], size=(4, 2))
+    j = analytic_jets([sp.sin(sp.pi * x) * sp.exp(-t)], (x, t), (x,), pts)
+    nu = 0.05
+    xv, tv = pts[:, 0], pts[:, 1]
+    exp = (np.exp(-tv) * np.sin(np.pi * xv) * (nu * np.pi ** 2 - 1)
+           + np.pi * np.exp(-2 * tv) * np.sin(np.pi * xv) * np.cos(np.pi * xv))
+    wrong = oracle.pde_residual(dict(pde="burgers", lap_mask=1, coef=[0, 0, 0, 0]), 2, 1, j)
+    assert not np.allclose(wrong[:, 0], exp, rtol=1e-6)
+    right = oracle.pde_residual(dict(pde="burgers", lap_mask=1, coef=[nu, 0, 0, 0]), 2, 1, j)
+    assert np.allclose(right[:, 0], exp, rtol=1e-13)
