@@ -1,0 +1,178 @@
+/*
+ * pinn.h -- C ABI of the fused PINN residual + parameter-gradient library (libpinn.so,
+ * gfx950 / MI355X).
+ *
+ * The operation (paper: QPINNACLE, arXiv 2604.15645):
+ *   network   Sec. 2.2: z = W a + b per layer, a = sigma(z), linear output layer;
+ *             sigma = tanh (Sec. 2.2) or sin(w0 z) (App. A.5).  Optional input embedding
+ *             by random Fourier features [cos(xB), sin(xB)] (Sec. 2.6.1, App. A.2) and
+ *             optional weight factorisation W = diag(exp s) V on every linear layer
+ *             (Sec. 2.6.2).
+ *   residual  per PDE, "left side minus right side" of the printed equation:
+ *             Burgers (Sec. 4.3, with viscosity nu u_xx), 1D Euler in conservative form
+ *             (Sec. 4.6), steady incompressible Navier-Stokes (Sec. 4.4), 2D Maxwell
+ *             (Sec. 4.8).
+ *   loss      Sec. 2.3: L = sum_c lambda_c (1/N) sum_i r_c(x_i)^2
+ *                         + sum_s lambda_s (1/N_s) sum_i sum_{o in mask_s} (y_o(x_i) - t_{o,i})^2
+ *   gradient  dL/dtheta for every parameter theta (the quantity the optimiser of Sec. 2.3
+ *             consumes).  The Fourier matrix B is fixed (no gradient); inputs are not
+ *             differentiated.
+ *
+ * Conventions shared by every entry point.
+ *   Pointers are DEVICE pointers unless marked (host).  The caller owns every buffer,
+ *   including the workspace; the library holds no state between calls and allocates
+ *   nothing.  Calls are asynchronous on `stream` (a hipStream_t; NULL = the null stream);
+ *   the return code reports argument errors (checked on the host, before any HIP call)
+ *   and launch errors.  Calls sharing a workspace must not overlap.
+ *   Points: n x d_in, row-major, FP32, inputs ordered (x,t) Burgers/Euler, (x,y) NS,
+ *   (x,y,t) Maxwell.  Parameters: FP32, flat, per linear layer l = 0..n_hidden (input
+ *   side first): [W_l or V_l (n_out x n_in, row-major)] [s_l (n_out) if rwf]
+ *   [b_l (n_out) if has_bias].  Gradient: FP64 in the same layout.
+ *   Device limits: d_in <= 3, d_out <= 3, 1 + d_in + (Laplacian needed) <= 4 derivative
+ *   channels, hidden widths multiples of 32 and <= 256, n_freq a multiple of 16 with
+ *   2*n_freq <= 256, n_hidden in 1..8.
+ */
+#ifndef PINN_H
+#define PINN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* pinn_stream_t; /* == hipStream_t */
+
+typedef enum {
+  PINN_OK = 0,
+  PINN_E_INVALID = -1,     /* malformed descriptor, null pointer, bad size          */
+  PINN_E_UNSUPPORTED = -2, /* valid request outside what the kernels implement      */
+  PINN_E_WORKSPACE = -3,   /* ws_bytes smaller than pinn_workspace_bytes() reports  */
+  PINN_E_NONFINITE = -4,   /* PINN_FLAG_CHECK_FINITE found NaN/Inf in the parameters */
+  PINN_E_HIP = -5          /* a HIP runtime call or kernel launch failed            */
+} pinn_status;
+
+typedef enum {
+  PINN_PDE_BURGERS = 1,       /* in (x,t), out u:          u_t + u u_x - nu u_xx       */
+  PINN_PDE_EULER1D = 2,       /* in (x,t), out (rho,u,p):  conservative 1D Euler       */
+  PINN_PDE_NS2D_STEADY = 3,   /* in (x,y), out (u,v,p):    continuity + 2 momentum     */
+  PINN_PDE_MAXWELL_TE2D = 4   /* in (x,y,t), out (E_z,H_x,H_y)                          */
+} pinn_pde_id;
+
+typedef enum { PINN_ACT_TANH = 0, PINN_ACT_SIN = 1 } pinn_act;
+
+typedef enum {
+  PINN_PREC_FP32 = 0,   /* FP32 matrix cores (v_mfma_f32_16x16x4_f32), FP32 accumulate   */
+  PINN_PREC_BF16X3 = 1  /* each product a*b as hi*hi + hi*lo + lo*hi with a = hi + lo,
+                           hi = bf16(a), lo = bf16(a - hi), BF16 matrix cores, FP32
+                           accumulate                                                    */
+} pinn_prec;
+
+/* Opt-in flags (bitwise or). */
+#define PINN_FLAG_CHECK_FINITE 1 /* scan the parameters for NaN/Inf first; this call then
+                                    synchronises `stream` (the check mirrors the NaN test
+                                    on the network input in App. B)                   */
+
+/* (host) Network descriptor. */
+typedef struct {
+  int32_t d_in, d_out;   /* 1..3 each                                                    */
+  int32_t n_hidden;      /* hidden layers L                                              */
+  int32_t width[8];      /* hidden widths                                                */
+  int32_t act;           /* pinn_act                                                     */
+  float w0;              /* sine frequency, sigma(z) = sin(w0 z)                          */
+  int32_t n_freq;        /* 0: identity embedding; m > 0: Fourier features, B is d_in x m */
+  int32_t rwf;           /* 1: every linear layer stored as (V, s), W = diag(exp s) V    */
+  int32_t has_bias;      /* 1: every linear layer has a bias                             */
+} pinn_net;
+
+/* (host) PDE descriptor. */
+typedef struct {
+  int32_t pde_id;        /* pinn_pde_id                                                  */
+  int32_t lap_mask;      /* bit k: input k belongs to the Laplacian set S (Burgers: x,
+                            NS: x and y; Euler and Maxwell need none)                     */
+  double coef[4];        /* Burgers: nu | Euler: gamma | NS: Re | Maxwell: eps, mu       */
+  double lambda_res[3];  /* weight of each residual component's mean square             */
+  double norm_N;         /* divisor of the residual means; 0 = n_points of this call.
+                            A caller that shards the points passes the global count.     */
+} pinn_pde;
+
+/* (host) Value-only supervision set (initial / boundary data).  Device arrays. */
+typedef struct {
+  const float* points;   /* n x d_in                                                     */
+  const float* targets;  /* n x d_out (only outputs in out_mask are read)               */
+  int64_t n;
+  int32_t out_mask;      /* bit o: output o is supervised                               */
+  double lambda;
+} pinn_anchor;
+
+/* (host) Optional launch shape; NULL selects the built-in plan.  Fields <= 0 = default. */
+typedef struct {
+  int32_t tile_points;   /* points per work-group tile: 16, 32, 64 or 128                */
+  int32_t grid;          /* work-groups of the persistent launch                          */
+  int32_t n_slots;       /* FP64 gradient accumulator copies (atomics spread over them)   */
+  int32_t reserved;
+} pinn_tune;
+
+/* Number of FP32 parameters of the network (layout above).  < 0 on a bad descriptor. */
+int64_t pinn_param_count(const pinn_net* net);
+
+/* Number of residual components of a PDE (1 or 3); < 0 if unknown. */
+int pinn_n_residuals(int pde_id);
+
+/* Workspace bytes needed by pinn_residual_fwd / _bwd for this problem and plan.
+ * `with_grad` = 1 for _bwd.  Writes *bytes (host).  Errors as for the compute calls. */
+int pinn_workspace_bytes(const pinn_net* net, const pinn_pde* pde, int64_t n_points,
+                         const pinn_anchor* anchors, int n_anchor, int prec, int with_grad,
+                         const pinn_tune* tune, size_t* bytes);
+
+/* Residual and loss (no gradient).
+ *   params     FP32 [pinn_param_count]
+ *   fourier_B  FP32 d_in x n_freq row-major, or NULL when n_freq == 0
+ *   points     FP32 n_points x d_in
+ *   anchors    (host) array of n_anchor value-supervision sets (device arrays inside)
+ *   residual   FP32 n_points x n_res, or NULL
+ *   loss       FP64 [1 + n_res + n_anchor]: total, each residual component's weighted
+ *              mean square, each anchor set's weighted mean square
+ *   workspace  device buffer of ws_bytes >= pinn_workspace_bytes(..., with_grad = 0) */
+int pinn_residual_fwd(const pinn_net* net, const pinn_pde* pde, const float* params,
+                      const float* fourier_B, const float* points, int64_t n_points,
+                      const pinn_anchor* anchors, int n_anchor, int prec, uint32_t flags,
+                      const pinn_tune* tune, float* residual, double* loss, void* workspace,
+                      size_t ws_bytes, pinn_stream_t stream);
+
+/* The fused step: residual, loss and dL/dtheta in one call.
+ *   grad       FP64 [pinn_param_count], overwritten (parameter layout)
+ *   other arguments as pinn_residual_fwd; workspace sized with with_grad = 1.
+ * The parameter-gradient sum over points is accumulated in FP64; the result does not
+ * depend on the order of the points beyond FP64 rounding. */
+int pinn_residual_bwd(const pinn_net* net, const pinn_pde* pde, const float* params,
+                      const float* fourier_B, const float* points, int64_t n_points,
+                      const pinn_anchor* anchors, int n_anchor, int prec, uint32_t flags,
+                      const pinn_tune* tune, float* residual, double* loss, double* grad,
+                      void* workspace, size_t ws_bytes, pinn_stream_t stream);
+
+/* Many independent networks in one persistent launch (the paper's benchmark sweeps ran
+ * each network separately).  Instance i has its own descriptor nets[i] (host array), the
+ * shared PDE `pde`, its own params[i], points[i] (n_points[i] x d_in) and grads[i]
+ * (FP64, parameter layout); losses (device, FP64) receives n_inst x (1 + n_res) values
+ * (total, then per residual component; no anchor sets).  All instances must share
+ * d_in, d_out, act, n_freq == 0 and rwf; widths and depths may differ.
+ *   tune_table (host, nullable): n_inst pinn_tune entries, the tile shape per instance.
+ * Workspace from pinn_batched_workspace_bytes. */
+int pinn_batched_workspace_bytes(const pinn_net* nets, const pinn_pde* pde,
+                                 const int64_t* n_points, int n_inst, int prec,
+                                 const pinn_tune* tune_table, size_t* bytes);
+int pinn_batched_bwd(const pinn_net* nets, const pinn_pde* pde, const float* const* params,
+                     const float* const* points, const int64_t* n_points, int n_inst,
+                     int prec, const pinn_tune* tune_table, double* const* grads,
+                     double* losses, void* workspace, size_t ws_bytes, pinn_stream_t stream);
+
+/* Static description of an error code. */
+const char* pinn_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PINN_H */

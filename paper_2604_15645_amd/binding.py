@@ -1,0 +1,245 @@
+"""ctypes binding of libpinn.so (include/pinn.h), with torch providing device memory and
+the current stream.  Argument marshalling only: every step of the computation runs in
+the library's HIP kernels.  Raises if the library is missing: there is no fallback."""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpinn.so")
+
+PDE_IDS = {"burgers": 1, "euler1d": 2, "ns2d": 3, "maxwell": 4}
+ACTS = {"tanh": 0, "sin": 1}
+PRECS = {"fp32": 0, "bf16x3": 1}
+FLAG_CHECK_FINITE = 1
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported configuration",
+          -3: "workspace too small", -4: "non-finite parameter", -5: "HIP runtime error"}
+
+
+class PinnNet(ctypes.Structure):
+    _fields_ = [("d_in", ctypes.c_int32), ("d_out", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
+                ("width", ctypes.c_int32 * 8), ("act", ctypes.c_int32), ("w0", ctypes.c_float),
+                ("n_freq", ctypes.c_int32), ("rwf", ctypes.c_int32), ("has_bias", ctypes.c_int32)]
+
+
+class PinnPde(ctypes.Structure):
+    _fields_ = [("pde_id", ctypes.c_int32), ("lap_mask", ctypes.c_int32),
+                ("coef", ctypes.c_double * 4), ("lambda_res", ctypes.c_double * 3),
+                ("norm_N", ctypes.c_double)]
+
+
+class PinnAnchor(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("targets", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("out_mask", ctypes.c_int32), ("lambda_", ctypes.c_double)]
+
+
+class PinnTune(ctypes.Structure):
+    _fields_ = [("tile_points", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("n_slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class PinnError(RuntimeError):
+    def __init__(self, where, code):
+        super().__init__("%s: %s (%d)" % (where, STATUS.get(code, "unknown"), code))
+        self.code = code
+
+
+_lib = None
+
+# Symbols the header declares (checked by the CPU tests).
+EXPORTS = ["pinn_param_count", "pinn_n_residuals", "pinn_workspace_bytes", "pinn_residual_fwd",
+           "pinn_residual_bwd", "pinn_batched_workspace_bytes", "pinn_batched_bwd",
+           "pinn_status_string"]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpinn.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        L.pinn_param_count.restype = ctypes.c_int64
+        L.pinn_param_count.argtypes = [P(PinnNet)]
+        L.pinn_n_residuals.restype = ctypes.c_int
+        L.pinn_n_residuals.argtypes = [ctypes.c_int]
+        L.pinn_workspace_bytes.restype = ctypes.c_int
+        L.pinn_workspace_bytes.argtypes = [P(PinnNet), P(PinnPde), ctypes.c_int64, P(PinnAnchor),
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_int, P(PinnTune),
+                                           P(ctypes.c_size_t)]
+        common = [P(PinnNet), P(PinnPde), vp, vp, vp, ctypes.c_int64, P(PinnAnchor), ctypes.c_int,
+                  ctypes.c_int, ctypes.c_uint32, P(PinnTune), vp, vp]
+        L.pinn_residual_fwd.restype = ctypes.c_int
+        L.pinn_residual_fwd.argtypes = common + [vp, ctypes.c_size_t, vp]
+        L.pinn_residual_bwd.restype = ctypes.c_int
+        L.pinn_residual_bwd.argtypes = common + [vp, vp, ctypes.c_size_t, vp]
+        L.pinn_status_string.restype = ctypes.c_char_p
+        L.pinn_status_string.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def net_struct(spec):
+    n = PinnNet()
+    n.d_in = int(spec["d_in"])
+    n.d_out = int(spec["d_out"])
+    widths = list(spec["widths"])
+    if len(widths) > 8:
+        raise ValueError("at most 8 hidden layers")
+    n.n_hidden = len(widths)
+    for i, w in enumerate(widths):
+        n.width[i] = int(w)
+    n.act = ACTS[spec.get("act", "tanh")]
+    n.w0 = float(spec.get("w0", 1.0))
+    n.n_freq = int(spec.get("n_freq", 0))
+    n.rwf = int(bool(spec.get("rwf", False)))
+    n.has_bias = int(bool(spec.get("has_bias", True)))
+    return n
+
+
+def pde_struct(spec):
+    p = PinnPde()
+    p.pde_id = PDE_IDS[spec["pde"]]
+    p.lap_mask = int(spec.get("lap_mask", 0))
+    coef = list(spec.get("coef", [])) + [0.0] * 4
+    for i in range(4):
+        p.coef[i] = float(coef[i])
+    lam = list(spec.get("lambda_res", [1.0, 1.0, 1.0])) + [1.0] * 3
+    for i in range(3):
+        p.lambda_res[i] = float(lam[i])
+    p.norm_N = float(spec.get("norm_N", 0.0))
+    return p
+
+
+def tune_struct(tune):
+    if tune is None:
+        return None
+    t = PinnTune()
+    t.tile_points = int(tune.get("tile_points", 0))
+    t.grid = int(tune.get("grid", 0))
+    t.n_slots = int(tune.get("n_slots", 0))
+    return t
+
+
+def n_residuals(pde_name):
+    return lib().pinn_n_residuals(PDE_IDS[pde_name])
+
+
+def param_count(net_spec):
+    n = net_struct(net_spec)
+    r = lib().pinn_param_count(ctypes.byref(n))
+    if r < 0:
+        raise PinnError("pinn_param_count", int(r))
+    return int(r)
+
+
+def _anchor_array(anchors):
+    arr = (PinnAnchor * max(1, len(anchors)))()
+    for i, a in enumerate(anchors):
+        pts, tgt = a["points"], a["targets"]
+        arr[i].points = pts.data_ptr() if isinstance(pts, torch.Tensor) else 0
+        arr[i].targets = tgt.data_ptr() if isinstance(tgt, torch.Tensor) else 0
+        arr[i].n = int(pts.shape[0])
+        arr[i].out_mask = int(a.get("out_mask", 1))
+        arr[i].lambda_ = float(a.get("lambda", 1.0))
+    return arr
+
+
+def workspace_bytes(net_spec, pde_spec, n_points, anchors=(), prec="bf16x3", with_grad=True,
+                    tune=None):
+    n, p = net_struct(net_spec), pde_struct(pde_spec)
+    arr = _anchor_array(anchors)
+    t = tune_struct(tune)
+    out = ctypes.c_size_t(0)
+    rc = lib().pinn_workspace_bytes(ctypes.byref(n), ctypes.byref(p), int(n_points), arr, len(anchors),
+                                    PRECS[prec], int(bool(with_grad)),
+                                    ctypes.byref(t) if t is not None else None, ctypes.byref(out))
+    if rc != 0:
+        raise PinnError("pinn_workspace_bytes", rc)
+    return int(out.value)
+
+
+class Workspace:
+    """A reusable device buffer (grown on demand) for the library's scratch."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes):
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_default_ws = {}
+
+
+def _ws(device):
+    key = str(device)
+    if key not in _default_ws:
+        _default_ws[key] = Workspace(device)
+    return _default_ws[key]
+
+
+def _check_dev(t, name, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s tensor" % (name, dtype))
+
+
+def residual_step(net_spec, pde_spec, params, B, points, anchors=(), prec="bf16x3", grad=True,
+                  residual=True, tune=None, flags=0, workspace=None, out=None):
+    """One call of pinn_residual_bwd (grad=True) or pinn_residual_fwd.
+
+    params, B, points and the anchors' points/targets are FP32 device tensors.  Returns
+    dict(loss = FP64 [1 + n_res + n_anchor], grad = FP64 [n_params] or None,
+    residual = FP32 [n, n_res] or None).  `out` may hold preallocated result tensors."""
+    _check_dev(params, "params")
+    _check_dev(points, "points")
+    if B is not None:
+        _check_dev(B, "fourier_B")
+    for a in anchors:
+        _check_dev(a["points"], "anchor points")
+        _check_dev(a["targets"], "anchor targets")
+    dev = points.device
+    n, p = net_struct(net_spec), pde_struct(pde_spec)
+    arr = _anchor_array(anchors)
+    t = tune_struct(tune)
+    tref = ctypes.byref(t) if t is not None else None
+    npts = int(points.shape[0])
+    nres = n_residuals(pde_spec["pde"])
+    size = ctypes.c_size_t(0)
+    rc = lib().pinn_workspace_bytes(ctypes.byref(n), ctypes.byref(p), npts, arr, len(anchors),
+                                    PRECS[prec], int(bool(grad)), tref, ctypes.byref(size))
+    if rc != 0:
+        raise PinnError("pinn_workspace_bytes", rc)
+    ws = (workspace or _ws(dev)).get(int(size.value))
+    out = out or {}
+    loss = out.get("loss")
+    if loss is None:
+        loss = torch.empty(1 + nres + len(anchors), dtype=torch.float64, device=dev)
+    res = out.get("residual")
+    if residual and res is None:
+        res = torch.empty((npts, nres), dtype=torch.float32, device=dev)
+    g = out.get("grad")
+    if grad and g is None:
+        g = torch.empty(param_count(net_spec), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    args = [ctypes.byref(n), ctypes.byref(p), params.data_ptr(),
+            B.data_ptr() if B is not None else None, points.data_ptr(), npts, arr, len(anchors),
+            PRECS[prec], int(flags), tref, res.data_ptr() if residual else None, loss.data_ptr()]
+    if grad:
+        rc = lib().pinn_residual_bwd(*args, g.data_ptr(), ws.data_ptr(), ws.numel(), stream)
+        where = "pinn_residual_bwd"
+    else:
+        rc = lib().pinn_residual_fwd(*args, ws.data_ptr(), ws.numel(), stream)
+        where = "pinn_residual_fwd"
+    if rc != 0:
+        raise PinnError(where, rc)
+    return {"loss": loss, "grad": g if grad else None, "residual": res if residual else None}

@@ -1,0 +1,532 @@
+// pinn_api.cpp -- host side of the C ABI declared in include/pinn.h: descriptor checks
+// (before any HIP call), launch planning, workspace layout and the launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <set>
+
+#include "../../include/pinn.h"
+#include "pinn_internal.h"
+
+using namespace pinn;
+
+namespace {
+
+constexpr int64_t kAlign = 256;
+constexpr int kGridCap = 256;  // MI355X: 256 compute units, one 512-thread work-group each
+
+int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+struct Dims {
+  int L, n_layers, d_in, d_out, e;
+  int n_in[kMaxLayers], n_out[kMaxLayers];
+  int64_t off_w[kMaxLayers], off_s[kMaxLayers], off_b[kMaxLayers];
+  int64_t n_params;
+  int hmax;      // widest hidden layer
+  int H;         // width bucket of the kernels: 32, 64, 128 or 256
+};
+
+int check_net(const pinn_net* net, Dims* d) {
+  if (!net) return PINN_E_INVALID;
+  if (net->d_in < 1 || net->d_in > 3 || net->d_out < 1 || net->d_out > 3) return PINN_E_INVALID;
+  if (net->n_hidden < 0 || net->n_hidden > kMaxHidden) return PINN_E_INVALID;
+  if (net->act != PINN_ACT_TANH && net->act != PINN_ACT_SIN) return PINN_E_INVALID;
+  if (net->n_freq < 0 || net->n_freq > 4096) return PINN_E_INVALID;
+  if ((net->rwf != 0 && net->rwf != 1) || (net->has_bias != 0 && net->has_bias != 1)) return PINN_E_INVALID;
+  if (!std::isfinite(net->w0)) return PINN_E_INVALID;
+  for (int l = 0; l < net->n_hidden; ++l)
+    if (net->width[l] < 1 || net->width[l] > 4096) return PINN_E_INVALID;
+  Dims& D = *d;
+  D.L = net->n_hidden;
+  D.n_layers = D.L + 1;
+  D.d_in = net->d_in;
+  D.d_out = net->d_out;
+  D.e = net->n_freq > 0 ? 2 * net->n_freq : net->d_in;
+  int64_t off = 0;
+  D.hmax = 0;
+  for (int l = 0; l < D.n_layers; ++l) {
+    D.n_in[l] = l == 0 ? D.e : net->width[l - 1];
+    D.n_out[l] = l == D.L ? D.d_out : net->width[l];
+    if (l < D.L) D.hmax = std::max(D.hmax, D.n_out[l]);
+    D.off_w[l] = off;
+    off += (int64_t)D.n_in[l] * D.n_out[l];
+    D.off_s[l] = -1;
+    D.off_b[l] = -1;
+    if (net->rwf) { D.off_s[l] = off; off += D.n_out[l]; }
+    if (net->has_bias) { D.off_b[l] = off; off += D.n_out[l]; }
+  }
+  D.n_params = off;
+  D.H = D.hmax <= 32 ? 32 : D.hmax <= 64 ? 64 : D.hmax <= 128 ? 128 : 256;
+  return PINN_OK;
+}
+
+// What the kernels implement (beyond what the descriptor format allows).
+int check_supported(const pinn_net* net, const Dims& D, int lap_mask) {
+  if (net->n_hidden < 1) return PINN_E_UNSUPPORTED;
+  for (int l = 0; l < D.L; ++l)
+    if (D.n_out[l] % 32 != 0 || D.n_out[l] > 256) return PINN_E_UNSUPPORTED;
+  if (net->n_freq > 0 && (net->n_freq % 16 != 0 || 2 * net->n_freq > 256)) return PINN_E_UNSUPPORTED;
+  const int C = 1 + net->d_in + (lap_mask ? 1 : 0);
+  if (C > 4) return PINN_E_UNSUPPORTED;
+  if (lap_mask && net->d_in != 2) return PINN_E_UNSUPPORTED;
+  return PINN_OK;
+}
+
+int check_pde(const pinn_net* net, const pinn_pde* pde) {
+  if (!pde) return PINN_E_INVALID;
+  if (pde->lap_mask < 0 || (pde->lap_mask & ~((1 << net->d_in) - 1))) return PINN_E_INVALID;
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(pde->lambda_res[k]) || pde->lambda_res[k] < 0) return PINN_E_INVALID;
+  if (!std::isfinite(pde->norm_N) || pde->norm_N < 0) return PINN_E_INVALID;
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(pde->coef[k])) return PINN_E_INVALID;
+  switch (pde->pde_id) {
+    case PINN_PDE_BURGERS:
+      if (net->d_in != 2 || !(pde->lap_mask & 1)) return PINN_E_UNSUPPORTED;
+      return PINN_OK;
+    case PINN_PDE_EULER1D:
+      if (net->d_in != 2 || net->d_out != 3 || !(pde->coef[0] > 1.0)) return PINN_E_UNSUPPORTED;
+      return PINN_OK;
+    case PINN_PDE_NS2D_STEADY:
+      if (net->d_in != 2 || net->d_out != 3 || (pde->lap_mask & 3) != 3 || pde->coef[0] == 0.0)
+        return PINN_E_UNSUPPORTED;
+      return PINN_OK;
+    case PINN_PDE_MAXWELL_TE2D:
+      if (net->d_in != 3 || net->d_out != 3 || pde->coef[0] == 0.0 || pde->coef[1] == 0.0)
+        return PINN_E_UNSUPPORTED;
+      return PINN_OK;
+    default:
+      return PINN_E_UNSUPPORTED;
+  }
+}
+
+int n_res_of(int pde_id) {
+  switch (pde_id) {
+    case PINN_PDE_BURGERS: return 1;
+    case PINN_PDE_EULER1D:
+    case PINN_PDE_NS2D_STEADY:
+    case PINN_PDE_MAXWELL_TE2D: return 3;
+    default: return -1;
+  }
+}
+
+// Forward tile size: the largest of the width bucket's default that fits the LDS budget.
+int default_fwd_p(int H) { return H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128; }
+int default_bwd_p(int H) { return H == 256 ? 16 : H == 128 ? 32 : H == 64 ? 64 : 128; }
+constexpr int kEmbedBwdP = 16;
+constexpr size_t kLdsBudget = 160 * 1024;
+
+size_t fwd_lds(int P, int kmax, int H) {
+  const int WN = std::min(8, H / 16);
+  const int WC = 8 / WN;
+  size_t b = (size_t)4 * P * (kmax * 4 + 16);  // X
+  b += (size_t)P * 16;                           // PT
+  b += (size_t)P * 12 * 4 * 2;                   // YJ, YB
+  b += kWaves * 4 * 4;                           // RED
+  b += kMaxTerms * 8;                            // LOSS
+  b += (size_t)WC * 3 * H * 8 + 3 * 8;           // WL, BL
+  return b;
+}
+size_t bwd_lds(int PB, int n_in, int n_out, bool with_r) {
+  size_t b = (size_t)n_in * (4 * PB * 4 + 16);
+  if (with_r) b += (size_t)4 * PB * (n_out * 4 + 16);
+  return b;
+}
+
+struct Plan {
+  Dims D;
+  int prec, act;
+  int n_res, n_anchor, n_seg;
+  int64_t seg_start[1 + kMaxAnchors], seg_n[1 + kMaxAnchors];
+  int64_t n_pad;
+  int pf, pb;             // forward tile points, backward sub-tile points (hidden layers)
+  int kmax;
+  int64_t n_tiles, n_sub, n_sub0;
+  int grid_f, grid_b, grid_b0, grid_g0;
+  size_t lds_f, lds_b, lds_b0;
+  bool with_grad;
+  // workspace offsets
+  int64_t o_pts, o_wf[kMaxLayers], o_wb[kMaxLayers], o_w[kMaxLayers], o_b[kMaxLayers];
+  int64_t o_zs[kMaxHidden], o_zb[2], o_loss, o_out, o_layer[kMaxLayers], o_flag;
+  int64_t bytes;
+};
+
+int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const pinn_anchor* anchors,
+              int n_anchor, int prec, int with_grad, const pinn_tune* tune, Plan* P) {
+  Plan& p = *P;
+  std::memset(&p, 0, sizeof(p));
+  int rc = check_net(net, &p.D);
+  if (rc) return rc;
+  rc = check_pde(net, pde);
+  if (rc) return rc;
+  if (prec != PINN_PREC_FP32 && prec != PINN_PREC_BF16X3) return PINN_E_INVALID;
+  if (n_points < 0 || n_anchor < 0 || n_anchor > kMaxAnchors) return PINN_E_INVALID;
+  if (n_anchor > 0 && !anchors) return PINN_E_INVALID;
+  for (int a = 0; a < n_anchor; ++a) {
+    if (anchors[a].n < 0 || !std::isfinite(anchors[a].lambda) || anchors[a].lambda < 0) return PINN_E_INVALID;
+    if (anchors[a].out_mask <= 0 || anchors[a].out_mask >= (1 << net->d_out)) return PINN_E_INVALID;
+  }
+  if (n_points + [&] { int64_t t = 0; for (int a = 0; a < n_anchor; ++a) t += anchors[a].n; return t; }() == 0)
+    return PINN_E_INVALID;
+  rc = check_supported(net, p.D, pde->lap_mask);
+  if (rc) return rc;
+  const Dims& D = p.D;
+  p.prec = prec;
+  p.act = net->act;
+  p.with_grad = with_grad != 0;
+  p.n_res = n_res_of(pde->pde_id);
+  p.n_anchor = n_anchor;
+  p.n_seg = 1 + n_anchor;
+  int64_t cur = 0;
+  for (int s = 0; s < p.n_seg; ++s) {
+    p.seg_start[s] = cur;
+    p.seg_n[s] = s == 0 ? n_points : anchors[s - 1].n;
+    cur += align_up(std::max<int64_t>(p.seg_n[s], 1), kSegAlign);
+  }
+  p.n_pad = cur;
+  p.kmax = std::max(D.e, D.hmax);
+  if (p.kmax % 32) p.kmax = (int)align_up(p.kmax, 32);
+  // tile sizes
+  p.pf = default_fwd_p(D.H);
+  if (tune && tune->tile_points > 0) {
+    int t = tune->tile_points;
+    if (t != 16 && t != p.pf) return PINN_E_UNSUPPORTED;
+    p.pf = t;
+  }
+  if (fwd_lds(p.pf, p.kmax, D.H) > kLdsBudget) p.pf = 16;
+  if (fwd_lds(p.pf, p.kmax, D.H) > kLdsBudget) return PINN_E_UNSUPPORTED;
+  p.pb = default_bwd_p(D.H);
+  p.lds_f = fwd_lds(p.pf, p.kmax, D.H);
+  p.lds_b = bwd_lds(p.pb, D.H, D.H, true);
+  p.lds_b0 = bwd_lds(kEmbedBwdP, 256, D.H, false);
+  if (p.lds_b > kLdsBudget || p.lds_b0 > kLdsBudget) return PINN_E_UNSUPPORTED;
+  p.n_tiles = p.n_pad / p.pf;
+  p.n_sub = p.n_pad / p.pb;
+  p.n_sub0 = p.n_pad / kEmbedBwdP;
+  int cap = kGridCap;
+  if (tune && tune->grid > 0) cap = tune->grid;
+  p.grid_f = (int)std::min<int64_t>(p.n_tiles, cap);
+  p.grid_b = (int)std::min<int64_t>(p.n_sub, cap);
+  p.grid_b0 = (int)std::min<int64_t>(p.n_sub0, cap);
+  p.grid_g0 = (int)std::min<int64_t>(std::max<int64_t>(1, p.n_pad / 4 / 64), 128);
+  // workspace layout
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) { int64_t r = o; o = align_up(o + bytes, kAlign); return r; };
+  p.o_pts = take(p.n_pad * 16);
+  for (int l = 0; l < D.n_layers; ++l) {
+    const int64_t nbo = (D.n_out[l] + 15) / 16, kci = (D.n_in[l] + 31) / 32;
+    const int64_t nbi = (D.n_in[l] + 15) / 16, kco = (D.n_out[l] + 31) / 32;
+    p.o_wf[l] = take(nbo * kci * 64 * 32);
+    p.o_wb[l] = take(nbi * kco * 64 * 32);
+    p.o_w[l] = take((int64_t)D.n_out[l] * D.n_in[l] * 4);
+    p.o_b[l] = take((int64_t)D.n_out[l] * 4);
+  }
+  p.o_loss = take((int64_t)p.grid_f * kMaxTerms * 8);
+  p.o_flag = take(16);
+  if (p.with_grad) {
+    for (int l = 0; l < D.L; ++l) p.o_zs[l] = take(p.n_pad * 4 * D.n_out[l] * 4);
+    p.o_zb[0] = take(p.n_pad * 4 * D.hmax * 4);
+    p.o_zb[1] = take(p.n_pad * 4 * D.hmax * 4);
+    p.o_out = take((int64_t)p.grid_f * D.d_out * (D.n_in[D.L] + 1) * 8);
+    for (int l = 0; l < D.L; ++l) {
+      int grid = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : p.grid_g0) : p.grid_b;
+      p.o_layer[l] = take((int64_t)grid * D.n_out[l] * (D.n_in[l] + 1) * 8);
+    }
+  }
+  p.bytes = o;
+  return PINN_OK;
+}
+
+int hip_rc(hipError_t e) { return e == hipSuccess ? PINN_OK : PINN_E_HIP; }
+
+NetDev make_netdev(const pinn_net* net, const pinn_pde* pde, const Plan& p, char* ws, const float* B) {
+  NetDev nd;
+  std::memset(&nd, 0, sizeof(nd));
+  const Dims& D = p.D;
+  nd.L = D.L;
+  nd.d_in = D.d_in;
+  nd.d_out = D.d_out;
+  nd.e = D.e;
+  nd.n_freq = net->n_freq;
+  nd.lap_mask = pde->lap_mask;
+  nd.lapch = pde->lap_mask ? 1 + D.d_in : -1;
+  nd.w0 = net->w0;
+  nd.B = B;
+  for (int l = 0; l < D.n_layers; ++l) {
+    LayerDev& L = nd.layer[l];
+    L.n_in = D.n_in[l];
+    L.n_out = D.n_out[l];
+    L.nbo = (D.n_out[l] + 15) / 16;
+    L.kci = (D.n_in[l] + 31) / 32;
+    L.nbi = (D.n_in[l] + 15) / 16;
+    L.kco = (D.n_out[l] + 31) / 32;
+    L.wf = ws + p.o_wf[l];
+    L.wb = ws + p.o_wb[l];
+    L.w = reinterpret_cast<const float*>(ws + p.o_w[l]);
+    L.b = reinterpret_cast<const float*>(ws + p.o_b[l]);
+  }
+  return nd;
+}
+
+int run(const pinn_net* net, const pinn_pde* pde, const float* params, const float* B, const float* points,
+        int64_t n_points, const pinn_anchor* anchors, int n_anchor, int prec, uint32_t flags,
+        const pinn_tune* tune, float* residual, double* loss, double* grad, void* workspace,
+        size_t ws_bytes, pinn_stream_t stream_, bool with_grad) {
+  Plan p;
+  int rc = make_plan(net, pde, n_points, anchors, n_anchor, prec, with_grad, tune, &p);
+  if (rc) return rc;
+  if (!params || !loss || !workspace || (n_points > 0 && !points)) return PINN_E_INVALID;
+  if (with_grad && !grad) return PINN_E_INVALID;
+  if (net->n_freq > 0 && !B) return PINN_E_INVALID;
+  for (int a = 0; a < n_anchor; ++a)
+    if (anchors[a].n > 0 && (!anchors[a].points || !anchors[a].targets)) return PINN_E_INVALID;
+  if ((int64_t)ws_bytes < p.bytes) return PINN_E_WORKSPACE;
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return PINN_E_INVALID;
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  char* ws = static_cast<char*>(workspace);
+  const Dims& D = p.D;
+
+  if (flags & PINN_FLAG_CHECK_FINITE) {
+    int* flag = reinterpret_cast<int*>(ws + p.o_flag);
+    rc = launch_check_finite(params, D.n_params, flag, stream);
+    if (rc) return rc;
+    int h = 0;
+    if (hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess) return PINN_E_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return PINN_E_HIP;
+    if (h) return PINN_E_NONFINITE;
+  }
+
+  // points
+  {
+    PointsArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.d_in = D.d_in;
+    a.n_seg = p.n_seg;
+    for (int s = 0; s < p.n_seg; ++s) {
+      a.start[s] = p.seg_start[s];
+      a.n[s] = p.seg_n[s];
+      a.src[s] = s == 0 ? points : anchors[s - 1].points;
+    }
+    a.n_pad = p.n_pad;
+    a.dst = reinterpret_cast<float4*>(ws + p.o_pts);
+    rc = launch_points(a, stream);
+    if (rc) return rc;
+  }
+  // weights
+  {
+    StageArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n_layers = D.n_layers;
+    a.rwf = net->rwf;
+    a.has_bias = net->has_bias;
+    a.params = params;
+    int64_t cum = 0;
+    for (int l = 0; l < D.n_layers; ++l) {
+      a.off_w[l] = D.off_w[l];
+      a.off_s[l] = D.off_s[l];
+      a.off_b[l] = D.off_b[l];
+      a.n_in[l] = D.n_in[l];
+      a.n_out[l] = D.n_out[l];
+      a.wf[l] = ws + p.o_wf[l];
+      a.wb[l] = ws + p.o_wb[l];
+      a.w[l] = reinterpret_cast<float*>(ws + p.o_w[l]);
+      a.b[l] = reinterpret_cast<float*>(ws + p.o_b[l]);
+      const int64_t nbo = (D.n_out[l] + 15) / 16, kci = (D.n_in[l] + 31) / 32;
+      const int64_t nbi = (D.n_in[l] + 15) / 16, kco = (D.n_out[l] + 31) / 32;
+      a.cum[l] = cum;
+      cum += nbo * kci * 64 + nbi * kco * 64 + (int64_t)D.n_out[l] * D.n_in[l] + D.n_out[l];
+    }
+    a.cum[D.n_layers] = cum;
+    rc = launch_stage(prec, a, stream);
+    if (rc) return rc;
+  }
+
+  const NetDev nd = make_netdev(net, pde, p, ws, B);
+  Work wk;
+  std::memset(&wk, 0, sizeof(wk));
+  wk.n_pad = p.n_pad;
+  wk.pts = reinterpret_cast<const float4*>(ws + p.o_pts);
+  wk.loss_slots = reinterpret_cast<double*>(ws + p.o_loss);
+  if (p.with_grad) {
+    for (int l = 0; l < D.L; ++l) wk.zs[l] = reinterpret_cast<float*>(ws + p.o_zs[l]);
+    wk.zb[0] = reinterpret_cast<float*>(ws + p.o_zb[0]);
+    wk.zb[1] = reinterpret_cast<float*>(ws + p.o_zb[1]);
+    wk.out_slots = reinterpret_cast<double*>(ws + p.o_out);
+    for (int l = 0; l < D.L; ++l) wk.layer_slots[l] = reinterpret_cast<double*>(ws + p.o_layer[l]);
+  }
+  const double N = pde->norm_N > 0 ? pde->norm_N : (double)n_points;
+  {
+    FwdArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.net = nd;
+    a.pde.pde_id = pde->pde_id;
+    a.pde.n_res = p.n_res;
+    for (int k = 0; k < 4; ++k) a.pde.coef[k] = (float)pde->coef[k];
+    for (int k = 0; k < 3; ++k) a.pde.seed_scale[k] = N > 0 ? (float)(2.0 * pde->lambda_res[k] / N) : 0.0f;
+    a.seg.n_seg = p.n_seg;
+    for (int s = 0; s < p.n_seg; ++s) {
+      a.seg.start[s] = p.seg_start[s];
+      a.seg.n[s] = p.seg_n[s];
+    }
+    for (int k = 0; k < n_anchor; ++k) {
+      a.seg.targets[k] = anchors[k].targets;
+      a.seg.out_mask[k] = anchors[k].out_mask;
+      a.seg.lam_anchor[k] = anchors[k].n > 0 ? (float)(2.0 * anchors[k].lambda / (double)anchors[k].n) : 0.0f;
+    }
+    a.work = wk;
+    a.n_tiles = p.n_tiles;
+    a.kmax = p.kmax;
+    a.with_grad = p.with_grad;
+    a.residual = residual;
+    rc = launch_forward(prec, net->act, D.H, p.pf, a, p.grid_f, p.lds_f, stream);
+    if (rc) return rc;
+  }
+  int cur = 0;
+  if (p.with_grad) {
+    for (int j = D.L - 1; j >= 1; --j) {
+      BwdArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.net = nd;
+      a.work = wk;
+      a.layer = j;
+      a.n_sub = p.n_sub;
+      a.zb_in = wk.zb[cur];
+      a.zb_out = wk.zb[cur ^ 1];
+      a.z_prev = wk.zs[j - 1];
+      a.slots = wk.layer_slots[j];
+      rc = launch_backward(prec, net->act, D.H, false, a, p.grid_b, p.lds_b, stream);
+      if (rc) return rc;
+      cur ^= 1;
+    }
+    if (net->n_freq > 0) {
+      BwdArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.net = nd;
+      a.work = wk;
+      a.layer = 0;
+      a.n_sub = p.n_sub0;
+      a.zb_in = wk.zb[cur];
+      a.zb_out = nullptr;
+      a.z_prev = nullptr;
+      a.slots = wk.layer_slots[0];
+      rc = launch_backward(prec, net->act, D.H, true, a, p.grid_b0, p.lds_b0, stream);
+      if (rc) return rc;
+    } else {
+      Grad0Args a;
+      a.zb = wk.zb[cur];
+      a.pts = wk.pts;
+      a.n_out = D.n_out[0];
+      a.d_in = D.d_in;
+      a.n_cb = p.n_pad / 4;
+      a.slots = wk.layer_slots[0];
+      rc = launch_grad0(a, p.grid_g0, stream);
+      if (rc) return rc;
+    }
+    for (int l = 0; l < D.n_layers; ++l) {
+      ReduceArgs a;
+      a.n_out = D.n_out[l];
+      a.n_in = D.n_in[l];
+      a.rwf = net->rwf;
+      a.has_bias = net->has_bias;
+      a.params = params;
+      a.off_w = D.off_w[l];
+      a.off_s = D.off_s[l];
+      a.off_b = D.off_b[l];
+      a.grad = grad;
+      if (l == D.L) {
+        a.slots = wk.out_slots;
+        a.n_slots = p.grid_f;
+      } else {
+        a.slots = wk.layer_slots[l];
+        a.n_slots = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : p.grid_g0) : p.grid_b;
+      }
+      rc = launch_reduce_layer(a, stream);
+      if (rc) return rc;
+    }
+  }
+  {
+    LossArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.slots = wk.loss_slots;
+    a.n_slots = p.grid_f;
+    a.n_res = p.n_res;
+    a.n_anchor = n_anchor;
+    for (int k = 0; k < 3; ++k) a.w_res[k] = N > 0 ? pde->lambda_res[k] / N : 0.0;
+    for (int k = 0; k < n_anchor; ++k)
+      a.w_anchor[k] = anchors[k].n > 0 ? anchors[k].lambda / (double)anchors[k].n : 0.0;
+    a.loss = loss;
+    rc = launch_reduce_loss(a, stream);
+    if (rc) return rc;
+  }
+  return hip_rc(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t pinn_param_count(const pinn_net* net) {
+  Dims D;
+  int rc = check_net(net, &D);
+  return rc ? rc : D.n_params;
+}
+
+int pinn_n_residuals(int pde_id) { return n_res_of(pde_id); }
+
+int pinn_workspace_bytes(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const pinn_anchor* anchors,
+                         int n_anchor, int prec, int with_grad, const pinn_tune* tune, size_t* bytes) {
+  if (!bytes) return PINN_E_INVALID;
+  Plan p;
+  int rc = make_plan(net, pde, n_points, anchors, n_anchor, prec, with_grad, tune, &p);
+  if (rc) return rc;
+  *bytes = (size_t)p.bytes;
+  return PINN_OK;
+}
+
+int pinn_residual_fwd(const pinn_net* net, const pinn_pde* pde, const float* params, const float* fourier_B,
+                      const float* points, int64_t n_points, const pinn_anchor* anchors, int n_anchor, int prec,
+                      uint32_t flags, const pinn_tune* tune, float* residual, double* loss, void* workspace,
+                      size_t ws_bytes, pinn_stream_t stream) {
+  return run(net, pde, params, fourier_B, points, n_points, anchors, n_anchor, prec, flags, tune, residual, loss,
+             nullptr, workspace, ws_bytes, stream, false);
+}
+
+int pinn_residual_bwd(const pinn_net* net, const pinn_pde* pde, const float* params, const float* fourier_B,
+                      const float* points, int64_t n_points, const pinn_anchor* anchors, int n_anchor, int prec,
+                      uint32_t flags, const pinn_tune* tune, float* residual, double* loss, double* grad,
+                      void* workspace, size_t ws_bytes, pinn_stream_t stream) {
+  return run(net, pde, params, fourier_B, points, n_points, anchors, n_anchor, prec, flags, tune, residual, loss,
+             grad, workspace, ws_bytes, stream, true);
+}
+
+int pinn_batched_workspace_bytes(const pinn_net* nets, const pinn_pde* pde, const int64_t* n_points, int n_inst,
+                                 int prec, const pinn_tune* tune_table, size_t* bytes) {
+  (void)nets; (void)pde; (void)n_points; (void)n_inst; (void)prec; (void)tune_table; (void)bytes;
+  return PINN_E_UNSUPPORTED;
+}
+
+int pinn_batched_bwd(const pinn_net* nets, const pinn_pde* pde, const float* const* params,
+                     const float* const* points, const int64_t* n_points, int n_inst, int prec,
+                     const pinn_tune* tune_table, double* const* grads, double* losses, void* workspace,
+                     size_t ws_bytes, pinn_stream_t stream) {
+  (void)nets; (void)pde; (void)params; (void)points; (void)n_points; (void)n_inst; (void)prec;
+  (void)tune_table; (void)grads; (void)losses; (void)workspace; (void)ws_bytes; (void)stream;
+  return PINN_E_UNSUPPORTED;
+}
+
+const char* pinn_status_string(int status) {
+  switch (status) {
+    case PINN_OK: return "ok";
+    case PINN_E_INVALID: return "invalid argument";
+    case PINN_E_UNSUPPORTED: return "unsupported configuration";
+    case PINN_E_WORKSPACE: return "workspace too small";
+    case PINN_E_NONFINITE: return "non-finite parameter";
+    case PINN_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

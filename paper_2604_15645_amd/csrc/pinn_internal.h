@@ -1,0 +1,154 @@
+// pinn_internal.h -- descriptors shared by the host planner (pinn_api.cpp) and the HIP
+// kernels (pinn_kernels.hip).  Not part of the public C ABI.
+#pragma once
+#include <stdint.h>
+#include <stddef.h>
+
+#include <hip/hip_runtime.h>
+
+namespace pinn {
+
+constexpr int kMaxHidden = 8;
+constexpr int kMaxLayers = kMaxHidden + 1;
+constexpr int kMaxAnchors = 8;
+constexpr int kMaxTerms = 3 + kMaxAnchors;
+constexpr int kSegAlign = 128;  // every point segment starts at a multiple of this
+constexpr int kWaves = 8;
+constexpr int kThreads = 64 * kWaves;
+
+enum { kFP32 = 0, kBF16X3 = 1 };
+enum { kTanh = 0, kSin = 1 };
+enum { kBurgers = 1, kEuler1D = 2, kNS2D = 3, kMaxwell = 4 };
+
+// One linear layer as the kernels see it (all pointers into the workspace).
+struct LayerDev {
+  int n_in, n_out;     // true sizes
+  int nbo, kci;        // forward fragments: n_out/16 blocks (padded) x n_in/32 chunks (padded)
+  int nbi, kco;        // backward fragments: n_in/16 blocks x n_out/32 chunks
+  const char* wf;      // forward fragments  [nbo][kci][64 lanes][32 B]
+  const char* wb;      // backward fragments [nbi][kco][64 lanes][32 B]
+  const float* w;      // effective weights, FP32, n_out x n_in row-major
+  const float* b;      // bias, FP32, n_out (zeros without bias)
+};
+
+struct NetDev {
+  int L;               // hidden layers
+  int d_in, d_out;
+  int e;               // embedding width (d_in or 2 * n_freq)
+  int n_freq;
+  int lap_mask;        // inputs in the Laplacian set
+  int lapch;           // channel of the Laplacian (-1 if none)
+  float w0;
+  const float* B;      // Fourier matrix d_in x n_freq (device, caller's)
+  LayerDev layer[kMaxLayers];
+};
+
+struct SegDev {
+  int n_seg;                       // 1 + number of anchor sets
+  int64_t start[1 + kMaxAnchors];  // first padded point of the segment
+  int64_t n[1 + kMaxAnchors];      // valid points
+  const float* targets[kMaxAnchors];
+  int out_mask[kMaxAnchors];
+  float lam_anchor[kMaxAnchors];   // seed scale: 2 lambda / N_s
+};
+
+struct PdeDev {
+  int pde_id, n_res;
+  float coef[4];
+  float seed_scale[3];             // 2 lambda_c / N
+};
+
+// Workspace pieces used by the kernels.
+struct Work {
+  int64_t n_pad;                   // padded point count (all segments)
+  const float4* pts;               // n_pad x (x, y, t, 0)
+  float* zs[kMaxHidden];           // pre-activation stash per hidden layer, fragment-major
+  float* zb[2];                    // adjoint ping-pong, fragment-major
+  double* loss_slots;              // [grid_f][kMaxTerms] sums of squares
+  double* out_slots;               // [grid_f][d_out * (n_L + 1)] output-layer W and b sums
+  double* layer_slots[kMaxHidden]; // [grid_b][n_out * (n_in + 1)] hidden/embedding layer sums
+};
+
+// Kernel argument blocks (passed by value).
+struct StageArgs {
+  int n_layers;
+  int rwf, has_bias;
+  const float* params;
+  int64_t off_w[kMaxLayers], off_s[kMaxLayers], off_b[kMaxLayers];
+  int n_in[kMaxLayers], n_out[kMaxLayers];
+  char* wf[kMaxLayers];
+  char* wb[kMaxLayers];
+  float* w[kMaxLayers];
+  float* b[kMaxLayers];
+  int64_t cum[kMaxLayers + 1];  // cumulative thread counts per layer
+};
+
+struct PointsArgs {
+  int d_in;
+  int n_seg;
+  int64_t start[1 + kMaxAnchors], n[1 + kMaxAnchors];
+  const float* src[1 + kMaxAnchors];
+  int64_t n_pad;
+  float4* dst;
+};
+
+struct FwdArgs {
+  NetDev net;
+  PdeDev pde;
+  SegDev seg;
+  Work work;
+  int64_t n_tiles;
+  int kmax;          // widest GEMM input (R-layout row width, elements)
+  int with_grad;
+  float* residual;   // caller's n x n_res or null
+};
+
+struct BwdArgs {
+  NetDev net;
+  Work work;
+  int layer;          // linear layer j (input side 0)
+  int64_t n_sub;      // sub-tiles of the padded point set
+  const float* zb_in;   // adjoint of this layer's output (fragment-major, n_out wide)
+  float* zb_out;        // adjoint of the previous hidden layer's pre-activation (or null)
+  const float* z_prev;  // stash of the previous hidden layer (null for layer 0)
+  double* slots;        // [gridDim][n_out * (n_in + 1)]
+};
+
+struct Grad0Args {
+  const float* zb;
+  const float4* pts;
+  int n_out, d_in;
+  int64_t n_cb;       // cp blocks of the padded point set
+  double* slots;      // [gridDim][n_out * (d_in + 1)]
+};
+
+struct ReduceArgs {
+  const double* slots;
+  int n_slots;
+  int n_out, n_in;
+  int rwf, has_bias;
+  const float* params;
+  int64_t off_w, off_s, off_b;
+  double* grad;
+};
+
+struct LossArgs {
+  const double* slots;
+  int n_slots;
+  int n_res, n_anchor;
+  double w_res[3];        // lambda_c / N
+  double w_anchor[kMaxAnchors];  // lambda_s / N_s
+  double* loss;
+};
+
+// Launchers (pinn_kernels.hip).  Each returns a pinn_status value.
+int launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t s);
+int launch_points(const PointsArgs& a, hipStream_t s);
+int launch_stage(int prec, const StageArgs& a, hipStream_t s);
+int launch_forward(int prec, int act, int H, int P, const FwdArgs& a, int grid, size_t lds, hipStream_t s);
+int launch_backward(int prec, int act, int H, bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s);
+int launch_grad0(const Grad0Args& a, int grid, hipStream_t s);
+int launch_reduce_layer(const ReduceArgs& a, hipStream_t s);
+int launch_reduce_loss(const LossArgs& a, hipStream_t s);
+
+}  // namespace pinn

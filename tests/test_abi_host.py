@@ -1,0 +1,126 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared symbol, and
+rejects malformed requests with the documented status before touching the GPU."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2604_15645_amd import binding, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libpinn.so not built")
+    return binding.lib()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pinn.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(pinn_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_what_the_binding_expects():
+    assert declared_functions() == sorted(binding.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_param_count_matches_layout():
+    for name in synth.CONFIGS:
+        net = synth.CONFIGS[name]["net"]
+        assert binding.param_count(net) == synth.param_count(net)
+    # the published shapes: 2 -> 3x32 -> 1 Burgers has 2,241 parameters
+    assert binding.param_count(synth.CONFIGS["burgers"]["net"]) == 2241
+    assert binding.param_count(synth.CONFIGS["maxwell"]["net"]) == 395523
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.pinn_status_string(code).decode() == binding.STATUS[code]
+
+
+def ws(net, pde, n=100, anchors=(), prec="fp32", grad=True, tune=None):
+    return binding.workspace_bytes(net, pde, n, anchors, prec, grad, tune)
+
+
+def code_of(fn):
+    with pytest.raises(binding.PinnError) as e:
+        fn()
+    return e.value.code
+
+
+def test_validation_errors(lib):
+    c = synth.CONFIGS
+    net, pde = dict(c["burgers"]["net"]), dict(c["burgers"]["pde"])
+    assert ws(net, pde) > 0
+    assert code_of(lambda: ws(dict(net, d_in=0), pde)) == -1
+    assert code_of(lambda: ws(dict(net, widths=[0, 32]), pde)) == -1
+    assert code_of(lambda: ws(net, dict(pde, pde="ns2d"))) == -2          # ns needs 3 outputs
+    assert code_of(lambda: ws(net, dict(pde, lap_mask=0))) == -2          # burgers needs u_xx
+    assert code_of(lambda: ws(net, dict(pde, lap_mask=8))) == -1          # input 3 does not exist
+    assert code_of(lambda: ws(dict(net, widths=[48, 48]), pde)) == -2     # widths: multiples of 32
+    assert code_of(lambda: ws(dict(net, widths=[512]), pde)) == -2        # at most 256 wide
+    assert code_of(lambda: ws(dict(net, widths=[]), pde)) == -2           # at least one hidden layer
+    assert code_of(lambda: ws(net, pde, n=-1)) == -1
+    assert code_of(lambda: ws(net, pde, n=0)) == -1                       # nothing to evaluate
+    assert code_of(lambda: ws(net, dict(pde, lambda_res=[-1, 1, 1]))) == -1
+    assert code_of(lambda: ws(net, dict(pde, coef=[math.nan, 0, 0, 0]))) == -1
+    mx, mp = c["maxwell"]["net"], c["maxwell"]["pde"]
+    assert code_of(lambda: ws(mx, dict(mp, lap_mask=1))) == -2            # 5 jet channels
+    assert code_of(lambda: ws(dict(mx, n_freq=20), mp)) == -2             # m multiple of 16
+    eu, ep = c["euler"]["net"], c["euler"]["pde"]
+    assert code_of(lambda: ws(eu, dict(ep, coef=[1.0, 0, 0, 0]))) == -2   # gamma > 1
+
+
+def test_compute_calls_reject_before_any_hip_call(lib):
+    """Null pointers and a short workspace fail on the host (no GPU in this container)."""
+    c = synth.CONFIGS["burgers"]
+    n, p = binding.net_struct(c["net"]), binding.pde_struct(c["pde"])
+    loss = ctypes.c_double * 4
+    buf = loss()
+    arr = (binding.PinnAnchor * 1)()
+    size = ctypes.c_size_t(0)
+    rc = lib.pinn_workspace_bytes(ctypes.byref(n), ctypes.byref(p), 100, arr, 0, 0, 1, None,
+                                  ctypes.byref(size))
+    assert rc == 0 and size.value > 0
+    fake = 1 << 20  # never dereferenced: the calls below must fail on argument checks
+    common = [ctypes.byref(n), ctypes.byref(p)]
+    # params missing
+    rc = lib.pinn_residual_bwd(*common, None, None, fake, 100, arr, 0, 0, 0, None, None,
+                               ctypes.addressof(buf), fake, fake, size.value, None)
+    assert rc == -1
+    # grad missing
+    rc = lib.pinn_residual_bwd(*common, fake, None, fake, 100, arr, 0, 0, 0, None, None,
+                               ctypes.addressof(buf), None, fake, size.value, None)
+    assert rc == -1
+    # workspace too small
+    rc = lib.pinn_residual_bwd(*common, fake, None, fake, 100, arr, 0, 0, 0, None, None,
+                               ctypes.addressof(buf), fake, fake, size.value - 1, None)
+    assert rc == -3
+    # fourier matrix missing for an RFF network
+    e = synth.CONFIGS["euler"]
+    ne, pe = binding.net_struct(e["net"]), binding.pde_struct(e["pde"])
+    rc = lib.pinn_workspace_bytes(ctypes.byref(ne), ctypes.byref(pe), 100, arr, 0, 0, 0, None,
+                                  ctypes.byref(size))
+    assert rc == 0
+    rc = lib.pinn_residual_fwd(ctypes.byref(ne), ctypes.byref(pe), fake, None, fake, 100, arr, 0, 0,
+                               0, None, None, ctypes.addressof(buf), fake, size.value, None)
+    assert rc == -1
+
+
+def test_workspace_grows_with_points_and_gradient():
+    c = synth.CONFIGS["ns"]
+    a = ws(c["net"], c["pde"], n=1000)
+    b = ws(c["net"], c["pde"], n=100000)
+    f = ws(c["net"], c["pde"], n=100000, grad=False)
+    assert b > a and f < b
+    # the stash of every hidden layer dominates: 5 layers x 4 channels x 128 x 4 B per point
+    assert b >= 100000 * 5 * 4 * 128 * 4

@@ -1,0 +1,126 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same seeded inputs.
+
+Tolerances (normwise, relative): FP32 <= 1e-5 and BF16X3 <= 1e-4 on every
+residual component, every loss term and the whole parameter gradient."""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4}
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    import torch
+    return torch.device("cuda:0")
+
+
+def to_dev(case, dev):
+    import torch
+    t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    anchors = [dict(a, points=t(a["points"]), targets=t(a["targets"])) for a in case["anchors"]]
+    return t(case["params"]), t(case["B"]), t(case["points"]), anchors
+
+
+def run_gpu(case, dev, prec, grad=True, tune=None):
+    import torch
+    from paper_2604_15645_amd import binding
+    params, B, pts, anchors = to_dev(case, dev)
+    out = binding.residual_step(case["net"], case["pde"], params, B, pts, anchors, prec=prec,
+                                grad=grad, residual=True, tune=tune)
+    torch.cuda.synchronize()
+    return {k: (None if v is None else v.cpu().numpy()) for k, v in out.items()}
+
+
+def run_oracle(oracle, case, grad=True):
+    return oracle.loss_grad(case["net"], case["pde"], case["params"], case["B"], case["points"],
+                            case["anchors"], want_grad=grad)
+
+
+def check(got, ref, prec, what=""):
+    tol = TOL[prec]
+    nres = ref["residual"].shape[1]
+    errs = {}
+    for c in range(nres):
+        errs["res%d" % c] = relerr(got["residual"][:, c], ref["residual"][:, c])
+    for k in range(len(ref["loss"])):
+        errs["loss%d" % k] = abs(got["loss"][k] - ref["loss"][k]) / max(abs(ref["loss"][k]), 1e-300)
+    if ref.get("grad") is not None and got.get("grad") is not None:
+        errs["grad"] = relerr(got["grad"], ref["grad"])
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    print(what, prec, {k: "%.2e" % v for k, v in errs.items()})
+    assert not bad, (what, prec, bad)
+
+
+CASES = [("burgers", 1000), ("euler", 900), ("ns", 700), ("maxwell", 300)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("name,n", CASES)
+def test_parity_configs(oracle, dev, name, n, prec):
+    from paper_2604_15645_amd import synth
+    case = synth.make_case(name, n_points=n, seed=1000 + n, perturb=True)
+    check(run_gpu(case, dev, prec), run_oracle(oracle, case), prec, name)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_forward_only_matches(oracle, dev, prec):
+    from paper_2604_15645_amd import synth
+    case = synth.make_case("ns", n_points=333, seed=7, perturb=True)
+    got = run_gpu(case, dev, prec, grad=False)
+    assert got["grad"] is None
+    check(got, run_oracle(oracle, case, grad=False), prec, "ns-fwd")
+
+
+@pytest.mark.parametrize("n", [1, 5, 129])
+def test_tiny_and_ragged_point_counts(oracle, dev, n):
+    from paper_2604_15645_amd import synth
+    case = synth.make_case("euler", n_points=n, seed=40 + n, perturb=True)
+    check(run_gpu(case, dev, "fp32"), run_oracle(oracle, case), "fp32", "euler-n%d" % n)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_uneven_widths_no_bias_sine(oracle, dev, prec):
+    """Widths that differ per layer, no biases, sine activation with w0 != 1."""
+    from paper_2604_15645_amd import synth
+    net = dict(d_in=2, d_out=3, widths=[64, 32, 128, 64], act="sin", w0=1.7, n_freq=0,
+               rwf=False, has_bias=False)
+    pde = dict(pde="ns2d", lap_mask=3, coef=[40.0, 0, 0, 0], lambda_res=[1.0, 0.5, 2.0])
+    case = synth.make_custom(net, pde, [(0, 1), (0, 1)], 500, seed=77)
+    check(run_gpu(case, dev, prec), run_oracle(oracle, case), prec, "uneven")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_rff_rwf_burgers_with_anchor_weights(oracle, dev, prec):
+    from paper_2604_15645_amd import synth
+    net = dict(d_in=2, d_out=1, widths=[128, 128], act="tanh", w0=1.0, n_freq=32, rwf=True,
+               has_bias=True)
+    pde = dict(pde="burgers", lap_mask=1, coef=[0.02, 0, 0, 0], lambda_res=[0.8, 1, 1],
+               norm_N=0.0)
+    rng = np.random.Generator(np.random.PCG64(5))
+    ap = rng.uniform(-1, 1, size=(70, 2)).astype(np.float32)
+    anchors = [dict(points=ap, targets=np.sin(ap[:, :1]).astype(np.float32), out_mask=1,
+                    **{"lambda": 3.0})]
+    case = synth.make_custom(net, pde, [(-1, 1), (0, 1)], 400, seed=9, sigma=1.5, anchors=anchors)
+    check(run_gpu(case, dev, prec), run_oracle(oracle, case), prec, "rff-rwf-burgers")
+
+
+def test_repeat_is_bitwise_identical(dev):
+    from paper_2604_15645_amd import synth
+    case = synth.make_case("maxwell", n_points=2000, seed=3, perturb=True)
+    a = run_gpu(case, dev, "bf16x3")
+    b = run_gpu(case, dev, "bf16x3")
+    for k in ("loss", "grad", "residual"):
+        assert np.array_equal(a[k], b[k]), k
