@@ -168,6 +168,20 @@ int pinn_batched_bwd(const pinn_net* nets, const pinn_pde* pde, const float* con
                      int prec, const pinn_tune* tune_table, double* const* grads,
                      double* losses, void* workspace, size_t ws_bytes, pinn_stream_t stream);
 
+/* Per-kernel timing (tracing aid).  While enabled, every kernel launch made by the compute
+ * calls of this process is bracketed by HIP events recorded on the call's stream; the
+ * events cost a few microseconds per launch and do not synchronise anything.
+ * pinn_timing_collect synchronises the recorded events, writes (host) up to max_entries
+ * summaries (kernel name, launches, summed milliseconds) in first-seen order, sets
+ * *n_entries, and clears the record.  Not for concurrent use from several threads. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+} pinn_kernel_time;
+int pinn_timing_enable(int on);
+int pinn_timing_collect(pinn_kernel_time* out, int max_entries, int* n_entries);
+
 /* Static description of an error code. */
 const char* pinn_status_string(int status);
 

@@ -40,6 +40,11 @@ class PinnTune(ctypes.Structure):
                 ("n_slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
 class PinnError(RuntimeError):
     def __init__(self, where, code):
         super().__init__("%s: %s (%d)" % (where, STATUS.get(code, "unknown"), code))
@@ -51,7 +56,7 @@ _lib = None
 # Symbols the header declares (checked by the CPU tests).
 EXPORTS = ["pinn_param_count", "pinn_n_residuals", "pinn_workspace_bytes", "pinn_residual_fwd",
            "pinn_residual_bwd", "pinn_batched_workspace_bytes", "pinn_batched_bwd",
-           "pinn_status_string"]
+           "pinn_timing_enable", "pinn_timing_collect", "pinn_status_string"]
 
 
 def lib():
@@ -76,6 +81,10 @@ def lib():
         L.pinn_residual_fwd.argtypes = common + [vp, ctypes.c_size_t, vp]
         L.pinn_residual_bwd.restype = ctypes.c_int
         L.pinn_residual_bwd.argtypes = common + [vp, vp, ctypes.c_size_t, vp]
+        L.pinn_timing_enable.restype = ctypes.c_int
+        L.pinn_timing_enable.argtypes = [ctypes.c_int]
+        L.pinn_timing_collect.restype = ctypes.c_int
+        L.pinn_timing_collect.argtypes = [P(KernelTime), ctypes.c_int, P(ctypes.c_int)]
         L.pinn_status_string.restype = ctypes.c_char_p
         L.pinn_status_string.argtypes = [ctypes.c_int]
         _lib = L
@@ -243,3 +252,17 @@ def residual_step(net_spec, pde_spec, params, B, points, anchors=(), prec="bf16x
     if rc != 0:
         raise PinnError(where, rc)
     return {"loss": loss, "grad": g if grad else None, "residual": res if residual else None}
+
+
+def timing_enable(on=True):
+    lib().pinn_timing_enable(int(bool(on)))
+
+
+def timing_collect():
+    """{kernel name: (launches, total ms)} recorded since the last collect."""
+    arr = (KernelTime * 64)()
+    n = ctypes.c_int(0)
+    rc = lib().pinn_timing_collect(arr, 64, ctypes.byref(n))
+    if rc != 0:
+        raise PinnError("pinn_timing_collect", rc)
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n.value)}

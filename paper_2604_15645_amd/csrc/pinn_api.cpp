@@ -7,6 +7,8 @@
 #include <cstring>
 #include <mutex>
 #include <set>
+#include <string>
+#include <vector>
 
 #include "../../include/pinn.h"
 #include "pinn_internal.h"
@@ -242,6 +244,47 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? PINN_OK : PINN_E_HIP; }
 
+// ---------------------------------------------------------------- optional event timing
+struct TimedLaunch {
+  const char* name;
+  hipEvent_t start, stop;
+};
+struct Timing {
+  std::mutex mu;
+  bool on = false;
+  std::vector<TimedLaunch> rec;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Timing& timing() {
+  static Timing t;
+  return t;
+}
+
+// Launch through f(), bracketed by events when timing is enabled.
+template <typename F>
+int timed(const char* name, hipStream_t s, F f) {
+  Timing& T = timing();
+  if (!T.on) return f();
+  std::lock_guard<std::mutex> lk(T.mu);
+  TimedLaunch tl{name, T.get(), T.get()};
+  if (!tl.start || !tl.stop) return PINN_E_HIP;
+  if (hipEventRecord(tl.start, s) != hipSuccess) return PINN_E_HIP;
+  int rc = f();
+  if (hipEventRecord(tl.stop, s) != hipSuccess) return PINN_E_HIP;
+  T.rec.push_back(tl);
+  return rc;
+}
+
 NetDev make_netdev(const pinn_net* net, const pinn_pde* pde, const Plan& p, char* ws, const float* B) {
   NetDev nd;
   std::memset(&nd, 0, sizeof(nd));
@@ -291,7 +334,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
 
   if (flags & PINN_FLAG_CHECK_FINITE) {
     int* flag = reinterpret_cast<int*>(ws + p.o_flag);
-    rc = launch_check_finite(params, D.n_params, flag, stream);
+    rc = timed("k_check_finite", stream, [&] { return launch_check_finite(params, D.n_params, flag, stream); });
     if (rc) return rc;
     int h = 0;
     if (hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess) return PINN_E_HIP;
@@ -312,7 +355,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     }
     a.n_pad = p.n_pad;
     a.dst = reinterpret_cast<float4*>(ws + p.o_pts);
-    rc = launch_points(a, stream);
+    rc = timed("k_points", stream, [&] { return launch_points(a, stream); });
     if (rc) return rc;
   }
   // weights
@@ -340,7 +383,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       cum += nbo * kci * 64 + nbi * kco * 64 + (int64_t)D.n_out[l] * D.n_in[l] + D.n_out[l];
     }
     a.cum[D.n_layers] = cum;
-    rc = launch_stage(prec, a, stream);
+    rc = timed("k_stage", stream, [&] { return launch_stage(prec, a, stream); });
     if (rc) return rc;
   }
 
@@ -381,7 +424,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     a.kmax = p.kmax;
     a.with_grad = p.with_grad;
     a.residual = residual;
-    rc = launch_forward(prec, net->act, D.H, p.pf, a, p.grid_f, p.lds_f, stream);
+    rc = timed("k_forward", stream, [&] { return launch_forward(prec, net->act, D.H, p.pf, a, p.grid_f, p.lds_f, stream); });
     if (rc) return rc;
   }
   int cur = 0;
@@ -397,7 +440,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.zb_out = wk.zb[cur ^ 1];
       a.z_prev = wk.zs[j - 1];
       a.slots = wk.layer_slots[j];
-      rc = launch_backward(prec, net->act, D.H, false, a, p.grid_b, p.lds_b, stream);
+      rc = timed("k_backward", stream, [&] { return launch_backward(prec, net->act, D.H, false, a, p.grid_b, p.lds_b, stream); });
       if (rc) return rc;
       cur ^= 1;
     }
@@ -412,7 +455,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.zb_out = nullptr;
       a.z_prev = nullptr;
       a.slots = wk.layer_slots[0];
-      rc = launch_backward(prec, net->act, D.H, true, a, p.grid_b0, p.lds_b0, stream);
+      rc = timed("k_backward_embed", stream, [&] { return launch_backward(prec, net->act, D.H, true, a, p.grid_b0, p.lds_b0, stream); });
       if (rc) return rc;
     } else {
       Grad0Args a;
@@ -422,7 +465,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.d_in = D.d_in;
       a.n_cb = p.n_pad / 4;
       a.slots = wk.layer_slots[0];
-      rc = launch_grad0(a, p.grid_g0, stream);
+      rc = timed("k_grad0", stream, [&] { return launch_grad0(a, p.grid_g0, stream); });
       if (rc) return rc;
     }
     for (int l = 0; l < D.n_layers; ++l) {
@@ -443,7 +486,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
         a.slots = wk.layer_slots[l];
         a.n_slots = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : p.grid_g0) : p.grid_b;
       }
-      rc = launch_reduce_layer(a, stream);
+      rc = timed("k_reduce_layer", stream, [&] { return launch_reduce_layer(a, stream); });
       if (rc) return rc;
     }
   }
@@ -458,7 +501,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     for (int k = 0; k < n_anchor; ++k)
       a.w_anchor[k] = anchors[k].n > 0 ? anchors[k].lambda / (double)anchors[k].n : 0.0;
     a.loss = loss;
-    rc = launch_reduce_loss(a, stream);
+    rc = timed("k_reduce_loss", stream, [&] { return launch_reduce_loss(a, stream); });
     if (rc) return rc;
   }
   return hip_rc(hipGetLastError());
@@ -515,6 +558,49 @@ int pinn_batched_bwd(const pinn_net* nets, const pinn_pde* pde, const float* con
   (void)nets; (void)pde; (void)params; (void)points; (void)n_points; (void)n_inst; (void)prec;
   (void)tune_table; (void)grads; (void)losses; (void)workspace; (void)ws_bytes; (void)stream;
   return PINN_E_UNSUPPORTED;
+}
+
+int pinn_timing_enable(int on) {
+  Timing& T = timing();
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.on = on != 0;
+  return PINN_OK;
+}
+
+int pinn_timing_collect(pinn_kernel_time* out, int max_entries, int* n_entries) {
+  if (!n_entries || max_entries < 0 || (max_entries > 0 && !out)) return PINN_E_INVALID;
+  Timing& T = timing();
+  std::lock_guard<std::mutex> lk(T.mu);
+  std::vector<std::string> names;
+  std::vector<int64_t> count;
+  std::vector<double> ms;
+  int rc = PINN_OK;
+  for (auto& tl : T.rec) {
+    float t = 0.0f;
+    if (hipEventSynchronize(tl.stop) != hipSuccess || hipEventElapsedTime(&t, tl.start, tl.stop) != hipSuccess)
+      rc = PINN_E_HIP;
+    size_t k = 0;
+    while (k < names.size() && names[k] != tl.name) ++k;
+    if (k == names.size()) {
+      names.emplace_back(tl.name);
+      count.push_back(0);
+      ms.push_back(0.0);
+    }
+    count[k] += 1;
+    ms[k] += t;
+    T.pool.push_back(tl.start);
+    T.pool.push_back(tl.stop);
+  }
+  T.rec.clear();
+  int n = 0;
+  for (size_t k = 0; k < names.size() && n < max_entries; ++k, ++n) {
+    std::memset(out[n].name, 0, sizeof(out[n].name));
+    std::strncpy(out[n].name, names[k].c_str(), sizeof(out[n].name) - 1);
+    out[n].launches = count[k];
+    out[n].total_ms = ms[k];
+  }
+  *n_entries = n;
+  return rc;
 }
 
 const char* pinn_status_string(int status) {
