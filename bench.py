@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--sample", type=int, default=16384, help="CPU-baseline / parity prefix")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -130,6 +132,15 @@ def main():
     from paper_2604_15645_amd import binding, synth
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4, "launches": 3}))
+        return
     name = args.config
     n_points = args.points or synth.CONFIGS[name]["n_points"]
     case, params, B, pts, anchors = make_inputs(name, n_points, dev)

@@ -185,34 +185,38 @@ __device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int 
 
 // ------------------------------------------------------------------ activation
 
-// sin and cos of a moderate argument: Cody-Waite reduction by pi/2 with a three-part
-// constant (each step one fused multiply-add), then Taylor polynomials on [-pi/4, pi/4]
-// (truncation below 3e-9 there, so FP32 rounding dominates).
-__device__ __forceinline__ void sincos_cw(float x, float& s, float& c) {
-  const float k = rintf(x * 0.6366197466850281f);
-  float r = fmaf(-k, 1.5707963705062866f, x);
-  r = fmaf(-k, -4.371138828673793e-08f, r);
-  r = fmaf(-k, -1.7151245100058819e-15f, r);
-  const float r2 = r * r;
-  const float sp = r + r * r2 * (-1.0f / 6 + r2 * (1.0f / 120 + r2 * (-1.0f / 5040 + r2 * (1.0f / 362880))));
-  const float cp = 1.0f + r2 * (-0.5f + r2 * (1.0f / 24 + r2 * (-1.0f / 720 + r2 * (1.0f / 40320 + r2 * (-1.0f / 3628800)))));
-  const int q = ((int)k) & 3;
-  s = q == 0 ? sp : q == 1 ? cp : q == 2 ? -sp : -cp;
-  c = q == 0 ? cp : q == 1 ? -sp : q == 2 ? -cp : sp;
+// tanh z = 1 - 2 / (exp(2|z|) + 1), sign of z; the hardware base-2 exponential and
+// reciprocal (absolute error about 1e-7, far below the FP32 tolerance of the path).
+__device__ __forceinline__ float tanh_fast(float z) {
+  const float e = __builtin_amdgcn_exp2f(fabsf(z) * 2.885390043258667f);  // exp(2|z|)
+  const float t = 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+  return copysignf(t, z);
+}
+
+// sin and cos: Cody-Waite reduction by 2 pi with a two-part constant (each step one fused
+// multiply-add, so the reduced argument is accurate to FP32 rounding), then the hardware
+// sine and cosine, which take their argument in revolutions.
+__device__ __forceinline__ void sincos_fast(float x, float& s, float& c) {
+  const float k = rintf(x * 0.15915493667125702f);
+  float r = fmaf(-k, 6.2831854820251465f, x);
+  r = fmaf(-k, -1.7484555314695172e-07f, r);
+  const float u = r * 0.15915493667125702f;
+  s = __builtin_amdgcn_sinf(u);
+  c = __builtin_amdgcn_cosf(u);
 }
 
 template <int ACT>
 __device__ __forceinline__ void act_eval(float z, float w0, float& s0, float& s1, float& s2, float& s3) {
   if (ACT == kTanh) {
-    float t = tanhf(z);
-    float d = 1.0f - t * t;
+    const float t = tanh_fast(z);
+    const float d = 1.0f - t * t;
     s0 = t;
     s1 = d;
     s2 = -2.0f * t * d;
     s3 = d * (6.0f * t * t - 2.0f);
   } else {
     float sn, cs;
-    sincos_cw(w0 * z, sn, cs);
+    sincos_fast(w0 * z, sn, cs);
     s0 = sn;
     s1 = w0 * cs;
     s2 = -w0 * w0 * sn;
@@ -379,7 +383,7 @@ __device__ __forceinline__ void rff_jets(const NetDev& net, const float4 x, int 
   if (net.lap_mask & 2) bl += b1 * b1;
   if (net.lap_mask & 4) bl += b2 * b2;
   float sn, cs;
-  sincos_cw(v, sn, cs);
+  sincos_fast(v, sn, cs);
   cj.x = cs;
   sj.x = sn;
   cj.y = -sn * b0;
@@ -504,7 +508,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_forward(const FwdArgs A) {
   constexpr int CPB = S::CPB, NBW = S::NBW, CBW = S::CBW, WN = S::WN;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const NetDev& net = A.net;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, l16 = lane & 15;
   const int wn = wave % WN, wc = wave / WN;
   const int L = net.L, dout = net.d_out;
@@ -753,7 +758,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_forward(const FwdArgs A) {
         float wo[3], wsum[3] = {0.f, 0.f, 0.f};
 #pragma unroll
         for (int o = 0; o < 3; ++o) wo[o] = o < dout ? lout.w[o * nL + n] : 0.0f;
-#pragma unroll
+#pragma unroll 1
         for (int c = 0; c < CBW; ++c) {
           const int cb = wc * CBW + c;
           const int p = 4 * cb + g;
@@ -828,7 +833,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const NetDev& net = A.net;
   const LayerDev& ly = net.layer[A.layer];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, l16 = lane & 15;
   const int n_in = ly.n_in, n_out = ly.n_out;
   const int nob = n_out / 16, nib = n_in / 16;
@@ -852,9 +858,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
 
   for (int64_t sub = blockIdx.x; sub < A.n_sub; sub += gridDim.x) {
     const int64_t cb0 = sub * CPB;
-    __syncthreads();
-    // (1) adjoint of z into R (only needed for the input adjoint)
+    __syncthreads();  // the previous sub-tile is done with R and Q
     if (has_prev) {
+      // (1) adjoint of z (this layer's output) into the R layout
       for (int f = wave; f < CPB * nob; f += kWaves) {
         const int cb = f % CPB, ob = f / CPB;
         const f4 zb = to_f4(*jet_frag(const_cast<float*>(A.zb_in), cb0 + cb, ob, nob, lane));
@@ -863,9 +869,25 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) Pr::put(base + (size_t)r * rs, o & 7, zb[r]);
       }
-    }
-    // (2) layer-input jets into Q: recomputed activations, or the embedding
-    if (has_prev) {
+      __syncthreads();
+      // (2) adjoint of the layer input: abar[cp][i] = sum_o zbar[cp][o] W[o][i]
+      f4 acca[NIBA][CBA];
+#pragma unroll
+      for (int k = 0; k < NIBA; ++k)
+#pragma unroll
+        for (int c = 0; c < CBA; ++c) acca[k][c] = f4{0.f, 0.f, 0.f, 0.f};
+      {
+        int blk[NIBA];
+        bool ok[NIBA];
+#pragma unroll
+        for (int k = 0; k < NIBA; ++k) {
+          blk[k] = wa + WA * k;
+          ok[k] = blk[k] < nib;
+        }
+        gemm_tile<PREC, NIBA, CBA>(acca, R, rs, wca * CBA, ly.wb, ly.kco, blk, ok, lane);
+      }
+      // (3) one pass over the previous layer's pre-activations: recomputed activation jets
+      // into Q (operand of the weight gradient) and the activation adjoint
 #pragma unroll
       for (int k = 0; k < NIBA; ++k) {
         const int ib = wa + WA * k;
@@ -881,11 +903,13 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
           int unit, pos0;
           q_pos(cb, g, unit, pos0);
           Pr::put4(Q + (size_t)n * qs + unit * 32, pos0, a);
+          const f4 zb = jet_act_adj(z, acca[k][c], s1, s2, s3, net.lapch, net.lap_mask);
+          *jet_frag(A.zb_out, cb0 + cb, ib, nbs_prev, lane) = to_float4(zb);
           __builtin_amdgcn_sched_barrier(0);
         }
       }
     } else {
-      // Fourier-feature embedding of the sub-tile's points
+      // Fourier-feature embedding of the sub-tile's points into Q
       const int m = net.n_freq;
       for (int idx = tid; idx < PB * m; idx += kThreads) {
         const int p = idx / m, j = idx - (idx / m) * m;
@@ -898,8 +922,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
         Pr::put4(Q + (size_t)(m + j) * qs + unit * 32, pos0, sj);
       }
     }
-    __syncthreads();
-    // (3) weight gradient: W_bar[o][i] += sum_cp zbar[cp][o] a[cp][i]
+    __syncthreads();  // Q complete
+    // (4) weight gradient: W_bar[o][i] += sum_cp zbar[cp][o] a[cp][i]
     for (int cc = 0; cc < CPB / 2; ++cc) {
       Raw ao[NOBW];
 #pragma unroll
@@ -921,40 +945,6 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
 #pragma unroll
         for (int i = 0; i < NOBW; ++i)
           if (wo + WO * i < nob) Pr::mma(accw[i][k], ao[i], bq);
-      }
-    }
-    if (!has_prev) continue;
-    // R was completed before the barrier above
-    // (4) adjoint of the layer input: abar[cp][i] = sum_o zbar[cp][o] W[o][i]
-    f4 acca[NIBA][CBA];
-#pragma unroll
-    for (int k = 0; k < NIBA; ++k)
-#pragma unroll
-      for (int c = 0; c < CBA; ++c) acca[k][c] = f4{0.f, 0.f, 0.f, 0.f};
-    {
-      int blk[NIBA];
-      bool ok[NIBA];
-#pragma unroll
-      for (int k = 0; k < NIBA; ++k) {
-        blk[k] = wa + WA * k;
-        ok[k] = blk[k] < nib;
-      }
-      gemm_tile<PREC, NIBA, CBA>(acca, R, rs, wca * CBA, ly.wb, ly.kco, blk, ok, lane);
-    }
-    // (5) activation adjoint -> adjoint of the previous layer's pre-activation
-#pragma unroll
-    for (int k = 0; k < NIBA; ++k) {
-      const int ib = wa + WA * k;
-      if (ib >= nib) continue;
-#pragma unroll
-      for (int c = 0; c < CBA; ++c) {
-        const int cb = wca * CBA + c;
-        const f4 z = to_f4(*jet_frag(const_cast<float*>(A.z_prev), cb0 + cb, ib, nbs_prev, lane));
-        float s0, s1, s2, s3;
-        act_eval<ACT>(z.x, net.w0, s0, s1, s2, s3);
-        const f4 zb = jet_act_adj(z, acca[k][c], s1, s2, s3, net.lapch, net.lap_mask);
-        *jet_frag(A.zb_out, cb0 + cb, ib, nbs_prev, lane) = to_float4(zb);
-        __builtin_amdgcn_sched_barrier(0);
       }
     }
   }
@@ -986,7 +976,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
 // identity embedding's jets are (x, unit vectors, 0).
 
 __global__ __launch_bounds__(256) void k_grad0(const Grad0Args A) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
+  const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nob = A.n_out / 16;
   __shared__ double red[4][256 * 4];
   for (int i = threadIdx.x; i < 4 * 256 * 4; i += blockDim.x) (&red[0][0])[i] = 0.0;
