@@ -37,7 +37,7 @@ class PinnAnchor(ctypes.Structure):
 
 class PinnTune(ctypes.Structure):
     _fields_ = [("tile_points", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("n_slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_slots", ctypes.c_int32), ("chunk_points", ctypes.c_int32)]
 
 
 class KernelTime(ctypes.Structure):
@@ -81,6 +81,12 @@ def lib():
         L.pinn_residual_fwd.argtypes = common + [vp, ctypes.c_size_t, vp]
         L.pinn_residual_bwd.restype = ctypes.c_int
         L.pinn_residual_bwd.argtypes = common + [vp, vp, ctypes.c_size_t, vp]
+        L.pinn_batched_workspace_bytes.restype = ctypes.c_int
+        L.pinn_batched_workspace_bytes.argtypes = [P(PinnNet), P(PinnPde), P(ctypes.c_int64), ctypes.c_int,
+                                                   ctypes.c_int, P(PinnTune), P(ctypes.c_size_t)]
+        L.pinn_batched_bwd.restype = ctypes.c_int
+        L.pinn_batched_bwd.argtypes = [P(PinnNet), P(PinnPde), P(vp), P(vp), P(ctypes.c_int64), ctypes.c_int,
+                                       ctypes.c_int, P(PinnTune), P(vp), vp, vp, ctypes.c_size_t, vp]
         L.pinn_timing_enable.restype = ctypes.c_int
         L.pinn_timing_enable.argtypes = [ctypes.c_int]
         L.pinn_timing_collect.restype = ctypes.c_int
@@ -130,6 +136,7 @@ def tune_struct(tune):
     t.tile_points = int(tune.get("tile_points", 0))
     t.grid = int(tune.get("grid", 0))
     t.n_slots = int(tune.get("n_slots", 0))
+    t.chunk_points = int(tune.get("chunk_points", 0))
     return t
 
 
@@ -266,3 +273,61 @@ def timing_collect():
     if rc != 0:
         raise PinnError("pinn_timing_collect", rc)
     return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n.value)}
+
+
+def _batch_structs(net_specs, n_points, tune_table):
+    n = len(net_specs)
+    nets = (PinnNet * n)(*[net_struct(s) for s in net_specs])
+    npts = (ctypes.c_int64 * n)(*[int(x) for x in n_points])
+    tt = None
+    if tune_table is not None:
+        tt = (PinnTune * n)(*[tune_struct(t or {}) for t in tune_table])
+    return nets, npts, tt
+
+
+def batched_workspace_bytes(net_specs, pde_spec, n_points, prec="bf16x3", tune_table=None):
+    nets, npts, tt = _batch_structs(net_specs, n_points, tune_table)
+    p = pde_struct(pde_spec)
+    out = ctypes.c_size_t(0)
+    rc = lib().pinn_batched_workspace_bytes(nets, ctypes.byref(p), npts, len(net_specs), PRECS[prec], tt,
+                                            ctypes.byref(out))
+    if rc != 0:
+        raise PinnError("pinn_batched_workspace_bytes", rc)
+    return int(out.value)
+
+
+def batched_step(net_specs, pde_spec, params, points, prec="bf16x3", tune_table=None, workspace=None,
+                 out=None):
+    """One pinn_batched_bwd call over independent networks.
+
+    params[i], points[i]: FP32 device tensors.  Returns dict(losses = FP64 [n_inst, 1 + n_res],
+    grads = list of FP64 [n_params_i])."""
+    n = len(net_specs)
+    for i in range(n):
+        _check_dev(params[i], "params[%d]" % i)
+        _check_dev(points[i], "points[%d]" % i)
+    dev = points[0].device
+    nets, npts, tt = _batch_structs(net_specs, [p.shape[0] for p in points], tune_table)
+    p = pde_struct(pde_spec)
+    size = ctypes.c_size_t(0)
+    rc = lib().pinn_batched_workspace_bytes(nets, ctypes.byref(p), npts, n, PRECS[prec], tt, ctypes.byref(size))
+    if rc != 0:
+        raise PinnError("pinn_batched_workspace_bytes", rc)
+    ws = (workspace or _ws(dev)).get(int(size.value))
+    out = out or {}
+    nres = n_residuals(pde_spec["pde"])
+    losses = out.get("losses")
+    if losses is None:
+        losses = torch.empty((n, 1 + nres), dtype=torch.float64, device=dev)
+    grads = out.get("grads")
+    if grads is None:
+        grads = [torch.empty(param_count(s), dtype=torch.float64, device=dev) for s in net_specs]
+    pp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in params])
+    xp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in points])
+    gp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in grads])
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = lib().pinn_batched_bwd(nets, ctypes.byref(p), pp, xp, npts, n, PRECS[prec], tt, gp, losses.data_ptr(),
+                                ws.data_ptr(), ws.numel(), stream)
+    if rc != 0:
+        raise PinnError("pinn_batched_bwd", rc)
+    return {"losses": losses, "grads": grads}

@@ -153,6 +153,7 @@ struct Plan {
   // workspace offsets
   int64_t o_pts, o_wf[kMaxLayers], o_wb[kMaxLayers], o_w[kMaxLayers], o_b[kMaxLayers];
   int64_t o_zs[kMaxHidden], o_zb[2], o_loss, o_out, o_layer[kMaxLayers], o_flag;
+  int64_t zs_stride;
   int64_t bytes;
 };
 
@@ -229,7 +230,8 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   p.o_loss = take((int64_t)p.grid_f * kMaxTerms * 8);
   p.o_flag = take(16);
   if (p.with_grad) {
-    for (int l = 0; l < D.L; ++l) p.o_zs[l] = take(p.n_pad * 4 * D.n_out[l] * 4);
+    p.zs_stride = p.n_pad * 4 * D.hmax;
+    p.o_zs[0] = take(p.zs_stride * D.L * 4);
     p.o_zb[0] = take(p.n_pad * 4 * D.hmax * 4);
     p.o_zb[1] = take(p.n_pad * 4 * D.hmax * 4);
     p.o_out = take((int64_t)p.grid_f * D.d_out * (D.n_in[D.L] + 1) * 8);
@@ -394,7 +396,8 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
   wk.pts = reinterpret_cast<const float4*>(ws + p.o_pts);
   wk.loss_slots = reinterpret_cast<double*>(ws + p.o_loss);
   if (p.with_grad) {
-    for (int l = 0; l < D.L; ++l) wk.zs[l] = reinterpret_cast<float*>(ws + p.o_zs[l]);
+    wk.zs0 = reinterpret_cast<float*>(ws + p.o_zs[0]);
+    wk.zs_stride = p.zs_stride;
     wk.zb[0] = reinterpret_cast<float*>(ws + p.o_zb[0]);
     wk.zb[1] = reinterpret_cast<float*>(ws + p.o_zb[1]);
     wk.out_slots = reinterpret_cast<double*>(ws + p.o_out);
@@ -438,7 +441,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.n_sub = p.n_sub;
       a.zb_in = wk.zb[cur];
       a.zb_out = wk.zb[cur ^ 1];
-      a.z_prev = wk.zs[j - 1];
+      a.z_prev = wk.zs0 + (j - 1) * wk.zs_stride;
       a.slots = wk.layer_slots[j];
       rc = timed("k_backward", stream, [&] { return launch_backward(prec, net->act, D.H, false, a, p.grid_b, p.lds_b, stream); });
       if (rc) return rc;
@@ -479,6 +482,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.off_s = D.off_s[l];
       a.off_b = D.off_b[l];
       a.grad = grad;
+      a.slot_stride = (int64_t)D.n_out[l] * (D.n_in[l] + 1);
       if (l == D.L) {
         a.slots = wk.out_slots;
         a.n_slots = p.grid_f;
@@ -504,6 +508,320 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     rc = timed("k_reduce_loss", stream, [&] { return launch_reduce_loss(a, stream); });
     if (rc) return rc;
   }
+  return hip_rc(hipGetLastError());
+}
+
+
+// ---------------------------------------------------------------- many networks, one launch
+
+struct BatchPlan {
+  int n_inst, prec, act, n_res, n_items, grid;
+  std::vector<Dims> D;
+  std::vector<int64_t> chunk, pts_off, n_pad, item0, n_items_of, n_eff, slot_base;
+  std::vector<int> kmax;
+  std::vector<BatchItem> items;
+  std::vector<int64_t> order;
+  int64_t n_pad_all, scratch_per_wg, n_slot_doubles;
+  size_t lds;
+  // workspace offsets
+  int64_t o_pts, o_tables, tables_bytes, o_counter, o_loss, o_grad, o_scratch;
+  std::vector<int64_t> o_wf[kMaxLayers], o_wb[kMaxLayers], o_w[kMaxLayers], o_b[kMaxLayers];
+  int64_t bytes;
+};
+
+int default_chunk(int H) { return H == 256 ? 1024 : H == 128 ? 2048 : 4096; }
+
+int make_batch_plan(const pinn_net* nets, const pinn_pde* pde, const int64_t* n_points, int n_inst, int prec,
+                    const pinn_tune* tune, BatchPlan* out) {
+  BatchPlan& b = *out;
+  if (!nets || !pde || !n_points || n_inst <= 0 || n_inst > 65536) return PINN_E_INVALID;
+  if (prec != PINN_PREC_FP32 && prec != PINN_PREC_BF16X3) return PINN_E_INVALID;
+  b.n_inst = n_inst;
+  b.prec = prec;
+  b.act = nets[0].act;
+  b.D.resize(n_inst);
+  b.chunk.resize(n_inst);
+  b.kmax.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    int rc = check_net(&nets[i], &b.D[i]);
+    if (rc) return rc;
+    rc = check_pde(&nets[i], pde);
+    if (rc) return rc;
+    rc = check_supported(&nets[i], b.D[i], pde->lap_mask);
+    if (rc) return rc;
+    if (nets[i].n_freq != 0 || nets[i].act != b.act || nets[i].d_in != nets[0].d_in ||
+        nets[i].d_out != nets[0].d_out)
+      return PINN_E_UNSUPPORTED;
+    if (n_points[i] <= 0) return PINN_E_INVALID;
+    int c = default_chunk(b.D[i].H);
+    if (tune && tune[i].chunk_points > 0) {
+      if (tune[i].chunk_points % kSegAlign) return PINN_E_INVALID;
+      c = tune[i].chunk_points;
+    }
+    if (tune && tune[i].tile_points > 0 && tune[i].tile_points != default_fwd_p(b.D[i].H)) return PINN_E_UNSUPPORTED;
+    b.chunk[i] = c;
+    b.kmax[i] = (int)align_up(std::max(b.D[i].e, b.D[i].hmax), 32);
+  }
+  b.n_res = n_res_of(pde->pde_id);
+  // points, items, slots
+  b.pts_off.resize(n_inst);
+  b.n_pad.resize(n_inst);
+  b.item0.resize(n_inst);
+  b.n_items_of.resize(n_inst);
+  b.n_eff.resize(n_inst);
+  b.slot_base.resize(n_inst);
+  int64_t pts = 0, slots = 0;
+  b.items.clear();
+  b.scratch_per_wg = 0;
+  b.lds = 0;
+  std::vector<double> cost;
+  for (int i = 0; i < n_inst; ++i) {
+    const Dims& D = b.D[i];
+    b.pts_off[i] = pts;
+    b.n_pad[i] = align_up(n_points[i], kSegAlign);
+    pts += b.n_pad[i];
+    int64_t ne = 0, flops = 0;
+    for (int l = 0; l < D.n_layers; ++l) {
+      ne += (int64_t)D.n_out[l] * (D.n_in[l] + 1);
+      flops += (int64_t)D.n_out[l] * D.n_in[l];
+    }
+    b.n_eff[i] = ne;
+    b.item0[i] = (int64_t)b.items.size();
+    b.slot_base[i] = slots;
+    for (int64_t p0 = 0; p0 < b.n_pad[i]; p0 += b.chunk[i]) {
+      BatchItem it;
+      it.inst = i;
+      it.p0 = p0;
+      it.p1 = std::min<int64_t>(p0 + b.chunk[i], b.n_pad[i]);
+      it.slot_off = slots;
+      slots += ne;
+      b.items.push_back(it);
+      cost.push_back((double)(it.p1 - it.p0) * (double)flops);
+    }
+    b.n_items_of[i] = (int64_t)b.items.size() - b.item0[i];
+    const int64_t stride = b.chunk[i] * 4 * D.hmax;
+    b.scratch_per_wg = std::max<int64_t>(b.scratch_per_wg, stride * (D.L + 2));
+    b.lds = std::max(b.lds, batched_lds(b.kmax[i], D.H));
+  }
+  if (b.lds > kLdsBudget) return PINN_E_UNSUPPORTED;
+  b.n_pad_all = pts;
+  b.n_slot_doubles = slots;
+  b.n_items = (int)b.items.size();
+  b.order.resize(b.n_items);
+  for (int q = 0; q < b.n_items; ++q) b.order[q] = q;
+  std::stable_sort(b.order.begin(), b.order.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
+  b.grid = std::min(b.n_items, (tune && tune[0].grid > 0) ? tune[0].grid : kGridCap);
+  // workspace
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) { int64_t r = o; o = align_up(o + bytes, kAlign); return r; };
+  b.o_pts = take(b.n_pad_all * 16);
+  for (int l = 0; l < kMaxLayers; ++l) {
+    b.o_wf[l].assign(n_inst, 0);
+    b.o_wb[l].assign(n_inst, 0);
+    b.o_w[l].assign(n_inst, 0);
+    b.o_b[l].assign(n_inst, 0);
+  }
+  for (int i = 0; i < n_inst; ++i) {
+    const Dims& D = b.D[i];
+    for (int l = 0; l < D.n_layers; ++l) {
+      const int64_t nbo = (D.n_out[l] + 15) / 16, kci = (D.n_in[l] + 31) / 32;
+      const int64_t nbi = (D.n_in[l] + 15) / 16, kco = (D.n_out[l] + 31) / 32;
+      b.o_wf[l][i] = take(nbo * kci * 64 * 32);
+      b.o_wb[l][i] = take(nbi * kco * 64 * 32);
+      b.o_w[l][i] = take((int64_t)D.n_out[l] * D.n_in[l] * 4);
+      b.o_b[l][i] = take((int64_t)D.n_out[l] * 4);
+    }
+  }
+  int64_t n_rows_entries = 0;
+  for (int i = 0; i < n_inst; ++i) n_rows_entries += b.D[i].n_layers;
+  b.tables_bytes = (int64_t)sizeof(BatchInst) * n_inst + (int64_t)sizeof(BatchItem) * b.n_items +
+                   (int64_t)sizeof(int64_t) * b.n_items + (int64_t)sizeof(BatchRow) * n_rows_entries +
+                   (int64_t)n_inst * (sizeof(int64_t) + sizeof(int) + 3 * sizeof(double)) + 64 * 8;
+  b.o_tables = take(b.tables_bytes);
+  b.o_counter = take(16);
+  b.o_loss = take((int64_t)b.n_items * kMaxTerms * 8);
+  b.o_grad = take(b.n_slot_doubles * 8);
+  b.o_scratch = take(b.scratch_per_wg * 4 * b.grid);
+  b.bytes = o;
+  return PINN_OK;
+}
+
+int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* params, const float* const* points,
+                const int64_t* n_points, int n_inst, int prec, const pinn_tune* tune, double* const* grads,
+                double* losses, void* workspace, size_t ws_bytes, pinn_stream_t stream_) {
+  BatchPlan b;
+  int rc = make_batch_plan(nets, pde, n_points, n_inst, prec, tune, &b);
+  if (rc) return rc;
+  if (!params || !points || !grads || !losses || !workspace) return PINN_E_INVALID;
+  for (int i = 0; i < n_inst; ++i)
+    if (!params[i] || !points[i] || !grads[i]) return PINN_E_INVALID;
+  if ((int64_t)ws_bytes < b.bytes) return PINN_E_WORKSPACE;
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return PINN_E_INVALID;
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  char* ws = static_cast<char*>(workspace);
+
+  // host tables, uploaded in one copy
+  std::vector<char> host((size_t)b.tables_bytes, 0);
+  char* hp = host.data();
+  BatchInst* hinst = reinterpret_cast<BatchInst*>(hp);
+  BatchItem* hitems = reinterpret_cast<BatchItem*>(hinst + n_inst);
+  int64_t* horder = reinterpret_cast<int64_t*>(hitems + b.n_items);
+  BatchRow* hrows = reinterpret_cast<BatchRow*>(horder + b.n_items);
+  int64_t n_entries = 0;
+  for (int i = 0; i < n_inst; ++i) n_entries += b.D[i].n_layers;
+  int64_t* hitem0 = reinterpret_cast<int64_t*>(hrows + n_entries);
+  int* hnitems = reinterpret_cast<int*>(hitem0 + n_inst);
+  double* hw = reinterpret_cast<double*>(
+      reinterpret_cast<char*>(hnitems) + align_up((int64_t)n_inst * sizeof(int), 8));
+  char* dbase = ws + b.o_tables;
+  auto dev = [&](const void* hptr) { return dbase + (static_cast<const char*>(hptr) - hp); };
+
+  int64_t row0 = 0;
+  int64_t entry = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const Dims& D = b.D[i];
+    BatchInst& in = hinst[i];
+    std::memset(&in, 0, sizeof(in));
+    NetDev& nd = in.net;
+    nd.L = D.L;
+    nd.d_in = D.d_in;
+    nd.d_out = D.d_out;
+    nd.e = D.e;
+    nd.n_freq = 0;
+    nd.lap_mask = pde->lap_mask;
+    nd.lapch = pde->lap_mask ? 1 + D.d_in : -1;
+    nd.w0 = nets[i].w0;
+    nd.B = nullptr;
+    for (int l = 0; l < D.n_layers; ++l) {
+      LayerDev& L = nd.layer[l];
+      L.n_in = D.n_in[l];
+      L.n_out = D.n_out[l];
+      L.nbo = (D.n_out[l] + 15) / 16;
+      L.kci = (D.n_in[l] + 31) / 32;
+      L.nbi = (D.n_in[l] + 15) / 16;
+      L.kco = (D.n_out[l] + 31) / 32;
+      L.wf = ws + b.o_wf[l][i];
+      L.wb = ws + b.o_wb[l][i];
+      L.w = reinterpret_cast<const float*>(ws + b.o_w[l][i]);
+      L.b = reinterpret_cast<const float*>(ws + b.o_b[l][i]);
+    }
+    in.H = D.H;
+    in.kmax = b.kmax[i];
+    in.pts_off = b.pts_off[i];
+    in.n = n_points[i];
+    int64_t eo = 0;
+    for (int l = 0; l < D.n_layers; ++l) {
+      in.eff_off[l] = eo;
+      eo += (int64_t)D.n_out[l] * (D.n_in[l] + 1);
+    }
+    in.zs_stride = b.chunk[i] * 4 * D.hmax;
+    in.zb_off[0] = in.zs_stride * D.L;
+    in.zb_off[1] = in.zs_stride * (D.L + 1);
+    for (int l = 0; l < D.n_layers; ++l, ++entry) {
+      BatchRow& r = hrows[entry];
+      r.row0 = row0;
+      row0 += D.n_out[l];
+      r.slot0 = b.slot_base[i] + in.eff_off[l];
+      r.slot_stride = b.n_eff[i];
+      r.n_items = (int)b.n_items_of[i];
+      r.n_out = D.n_out[l];
+      r.n_in = D.n_in[l];
+      r.rwf = nets[i].rwf;
+      r.has_bias = nets[i].has_bias;
+      r.params = params[i];
+      r.off_w = D.off_w[l];
+      r.off_s = D.off_s[l];
+      r.off_b = D.off_b[l];
+      r.grad = grads[i];
+    }
+    hitem0[i] = b.item0[i];
+    hnitems[i] = (int)b.n_items_of[i];
+    for (int k = 0; k < 3; ++k) hw[i * 3 + k] = pde->lambda_res[k] / (double)n_points[i];
+  }
+  for (int q = 0; q < b.n_items; ++q) {
+    hitems[q] = b.items[q];
+    horder[q] = b.order[q];
+  }
+  if (hipMemcpyAsync(dbase, hp, host.size(), hipMemcpyHostToDevice, stream) != hipSuccess) return PINN_E_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return PINN_E_HIP;
+
+  for (int i = 0; i < n_inst; ++i) {
+    const Dims& D = b.D[i];
+    PointsArgs pa;
+    std::memset(&pa, 0, sizeof(pa));
+    pa.d_in = D.d_in;
+    pa.n_seg = 1;
+    pa.start[0] = 0;
+    pa.n[0] = n_points[i];
+    pa.src[0] = points[i];
+    pa.n_pad = b.n_pad[i];
+    pa.dst = reinterpret_cast<float4*>(ws + b.o_pts) + b.pts_off[i];
+    rc = timed("k_points", stream, [&] { return launch_points(pa, stream); });
+    if (rc) return rc;
+    StageArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.n_layers = D.n_layers;
+    sa.rwf = nets[i].rwf;
+    sa.has_bias = nets[i].has_bias;
+    sa.params = params[i];
+    int64_t cum = 0;
+    for (int l = 0; l < D.n_layers; ++l) {
+      sa.off_w[l] = D.off_w[l];
+      sa.off_s[l] = D.off_s[l];
+      sa.off_b[l] = D.off_b[l];
+      sa.n_in[l] = D.n_in[l];
+      sa.n_out[l] = D.n_out[l];
+      sa.wf[l] = ws + b.o_wf[l][i];
+      sa.wb[l] = ws + b.o_wb[l][i];
+      sa.w[l] = reinterpret_cast<float*>(ws + b.o_w[l][i]);
+      sa.b[l] = reinterpret_cast<float*>(ws + b.o_b[l][i]);
+      const int64_t nbo = (D.n_out[l] + 15) / 16, kci = (D.n_in[l] + 31) / 32;
+      const int64_t nbi = (D.n_in[l] + 15) / 16, kco = (D.n_out[l] + 31) / 32;
+      sa.cum[l] = cum;
+      cum += nbo * kci * 64 + nbi * kco * 64 + (int64_t)D.n_out[l] * D.n_in[l] + D.n_out[l];
+    }
+    sa.cum[D.n_layers] = cum;
+    rc = timed("k_stage", stream, [&] { return launch_stage(prec, sa, stream); });
+    if (rc) return rc;
+  }
+  int* counter = reinterpret_cast<int*>(ws + b.o_counter);
+  rc = timed("k_zero_int", stream, [&] { return launch_zero_int(counter, stream); });
+  if (rc) return rc;
+  BatchArgs ba;
+  std::memset(&ba, 0, sizeof(ba));
+  ba.inst = reinterpret_cast<const BatchInst*>(dev(hinst));
+  ba.items = reinterpret_cast<const BatchItem*>(dev(hitems));
+  ba.order = reinterpret_cast<const int64_t*>(dev(horder));
+  ba.n_items = b.n_items;
+  ba.counter = counter;
+  ba.pde.pde_id = pde->pde_id;
+  ba.pde.n_res = b.n_res;
+  for (int k = 0; k < 4; ++k) ba.pde.coef[k] = (float)pde->coef[k];
+  ba.pts = reinterpret_cast<const float4*>(ws + b.o_pts);
+  ba.scratch = reinterpret_cast<float*>(ws + b.o_scratch);
+  ba.scratch_per_wg = b.scratch_per_wg;
+  ba.loss_slots = reinterpret_cast<double*>(ws + b.o_loss);
+  ba.grad_slots = reinterpret_cast<double*>(ws + b.o_grad);
+  for (int k = 0; k < 3; ++k) ba.lambda_res[k] = (float)pde->lambda_res[k];
+  rc = timed("k_batched", stream, [&] { return launch_batched(prec, b.act, ba, b.grid, b.lds, stream); });
+  if (rc) return rc;
+  BatchReduceArgs ra;
+  ra.rows = reinterpret_cast<const BatchRow*>(dev(hrows));
+  ra.n_entries = (int)n_entries;
+  ra.n_rows = row0;
+  ra.grad_slots = ba.grad_slots;
+  rc = timed("k_reduce_batched", stream, [&] { return launch_reduce_batched(ra, stream); });
+  if (rc) return rc;
+  BatchLossArgs la;
+  la.loss_slots = ba.loss_slots;
+  la.item0 = reinterpret_cast<const int64_t*>(dev(hitem0));
+  la.n_items = reinterpret_cast<const int*>(dev(hnitems));
+  la.w_res = reinterpret_cast<const double*>(dev(hw));
+  la.n_inst = n_inst;
+  la.n_res = b.n_res;
+  la.losses = losses;
+  rc = timed("k_reduce_loss_batched", stream, [&] { return launch_reduce_loss_batched(la, stream); });
+  if (rc) return rc;
   return hip_rc(hipGetLastError());
 }
 
@@ -547,17 +865,20 @@ int pinn_residual_bwd(const pinn_net* net, const pinn_pde* pde, const float* par
 
 int pinn_batched_workspace_bytes(const pinn_net* nets, const pinn_pde* pde, const int64_t* n_points, int n_inst,
                                  int prec, const pinn_tune* tune_table, size_t* bytes) {
-  (void)nets; (void)pde; (void)n_points; (void)n_inst; (void)prec; (void)tune_table; (void)bytes;
-  return PINN_E_UNSUPPORTED;
+  if (!bytes) return PINN_E_INVALID;
+  BatchPlan bp;
+  int rc = make_batch_plan(nets, pde, n_points, n_inst, prec, tune_table, &bp);
+  if (rc) return rc;
+  *bytes = (size_t)bp.bytes;
+  return PINN_OK;
 }
 
 int pinn_batched_bwd(const pinn_net* nets, const pinn_pde* pde, const float* const* params,
                      const float* const* points, const int64_t* n_points, int n_inst, int prec,
                      const pinn_tune* tune_table, double* const* grads, double* losses, void* workspace,
                      size_t ws_bytes, pinn_stream_t stream) {
-  (void)nets; (void)pde; (void)params; (void)points; (void)n_points; (void)n_inst; (void)prec;
-  (void)tune_table; (void)grads; (void)losses; (void)workspace; (void)ws_bytes; (void)stream;
-  return PINN_E_UNSUPPORTED;
+  return run_batched(nets, pde, params, points, n_points, n_inst, prec, tune_table, grads, losses, workspace,
+                     ws_bytes, stream);
 }
 
 int pinn_timing_enable(int on) {

@@ -62,7 +62,8 @@ struct PdeDev {
 struct Work {
   int64_t n_pad;                   // padded point count (all segments)
   const float4* pts;               // n_pad x (x, y, t, 0)
-  float* zs[kMaxHidden];           // pre-activation stash per hidden layer, fragment-major
+  float* zs0;                      // pre-activation stash of hidden layer 0, fragment-major;
+  int64_t zs_stride;               // layer j starts zs_stride floats after layer j - 1
   float* zb[2];                    // adjoint ping-pong, fragment-major
   double* loss_slots;              // [grid_f][kMaxTerms] sums of squares
   double* out_slots;               // [grid_f][d_out * (n_L + 1)] output-layer W and b sums
@@ -125,6 +126,7 @@ struct Grad0Args {
 struct ReduceArgs {
   const double* slots;
   int n_slots;
+  int64_t slot_stride;    // doubles between consecutive slots
   int n_out, n_in;
   int rwf, has_bias;
   const float* params;
@@ -141,6 +143,66 @@ struct LossArgs {
   double* loss;
 };
 
+// Many independent networks in one persistent launch.
+struct BatchInst {
+  NetDev net;
+  int H;                     // width bucket
+  int kmax;                  // widest product input (R-layout row width)
+  int64_t pts_off;           // first padded point of the instance in the shared buffer
+  int64_t n;                 // valid points
+  int64_t eff_off[kMaxLayers];  // offset of layer l's sums inside an item slot
+  int64_t zs_stride;         // floats between hidden layers' stash in the work-group scratch
+  int64_t zb_off[2];         // adjoint ping-pong offsets in the work-group scratch (floats)
+};
+
+struct BatchItem {
+  int inst;
+  int64_t p0, p1;            // padded point range of the instance (multiples of 128)
+  int64_t slot_off;          // offset of the item's gradient slot (doubles)
+};
+
+struct BatchArgs {
+  const BatchInst* inst;
+  const BatchItem* items;
+  const int64_t* order;      // items in the order the queue hands them out
+  int n_items;
+  int* counter;              // zeroed before the launch
+  PdeDev pde;
+  const float4* pts;
+  float* scratch;            // per work-group jet buffers
+  int64_t scratch_per_wg;    // floats
+  double* loss_slots;        // [n_items][kMaxTerms]
+  double* grad_slots;
+  float lambda_res[3];       // residual weights; the seed scale is 2 lambda / n per instance
+};
+
+struct BatchRow {            // one (instance, layer): rows [row0, row0 + n_out) of the grid
+  int64_t row0;
+  int64_t slot0;             // first item's slot for this layer (doubles)
+  int64_t slot_stride;       // between consecutive items' slots
+  int n_items;
+  int n_out, n_in, rwf, has_bias;
+  const float* params;
+  int64_t off_w, off_s, off_b;
+  double* grad;
+};
+
+struct BatchReduceArgs {
+  const BatchRow* rows;
+  int n_entries;
+  int64_t n_rows;
+  const double* grad_slots;
+};
+
+struct BatchLossArgs {
+  const double* loss_slots;
+  const int64_t* item0;      // first item of each instance
+  const int* n_items;
+  const double* w_res;       // [n_inst][3] lambda_c / N_i
+  int n_inst, n_res;
+  double* losses;            // [n_inst][1 + n_res]
+};
+
 // Launchers (pinn_kernels.hip).  Each returns a pinn_status value.
 int launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t s);
 int launch_points(const PointsArgs& a, hipStream_t s);
@@ -150,5 +212,10 @@ int launch_backward(int prec, int act, int H, bool embed, const BwdArgs& a, int 
 int launch_grad0(const Grad0Args& a, int grid, hipStream_t s);
 int launch_reduce_layer(const ReduceArgs& a, hipStream_t s);
 int launch_reduce_loss(const LossArgs& a, hipStream_t s);
+int launch_batched(int prec, int act, const BatchArgs& a, int grid, size_t lds, hipStream_t s);
+int launch_reduce_batched(const BatchReduceArgs& a, hipStream_t s);
+int launch_reduce_loss_batched(const BatchLossArgs& a, hipStream_t s);
+int launch_zero_int(int* p, hipStream_t s);
+size_t batched_lds(int kmax_max, int H_max);
 
 }  // namespace pinn

@@ -488,8 +488,7 @@ __global__ void k_fill(double* p, int64_t n) {
 
 // ================================================================== forward
 
-
-// Compile-time shape of the forward kernel: hidden width bound H, tile points P.
+// Compile-time shape of the forward tile: hidden width bound H, tile points P.
 template <int H, int P>
 struct FwdShape {
   static constexpr int CPB = P / 4;                    // 16-row cp blocks per tile
@@ -501,85 +500,193 @@ struct FwdShape {
   static_assert(CPB % WC == 0, "tile too small for the wave split");
 };
 
+// LDS of the forward tile body.
+struct FwdLds {
+  char* X;       // R-layout tile (4P rows)
+  float4* PT;    // tile points
+  float* YJ;     // [P][3][4] output jets
+  float* YB;     // [P][3][4] output-jet adjoints
+  float* RED;    // [kWaves][4] wave partial sums
+  double* LOSS;  // [kMaxTerms] sums of squares (FP64, per work item)
+  double* WL;    // [WC][3][H] output-layer weight-gradient sums
+  double* BL;    // [3] output-layer bias-gradient sums
+};
+
+template <int H, int P>
+__device__ __forceinline__ FwdLds fwd_carve(char* smem, int rs) {
+  FwdLds s;
+  s.X = smem;
+  s.PT = reinterpret_cast<float4*>(smem + (size_t)4 * P * rs);
+  s.YJ = reinterpret_cast<float*>(s.PT + P);
+  s.YB = s.YJ + P * 12;
+  s.RED = s.YB + P * 12;
+  s.LOSS = reinterpret_cast<double*>(s.RED + kWaves * 4);
+  s.WL = s.LOSS + kMaxTerms;
+  s.BL = s.WL + FwdShape<H, P>::WC * 3 * H;
+  return s;
+}
+
+template <int H, int P>
+__device__ __forceinline__ void fwd_begin(const FwdLds& s) {
+  for (int i = threadIdx.x; i < kMaxTerms; i += kThreads) s.LOSS[i] = 0.0;
+  for (int i = threadIdx.x; i < FwdShape<H, P>::WC * 3 * H + 3; i += kThreads) s.WL[i] = 0.0;
+}
+
+// Write the accumulated sums of a run of tiles: loss terms, and (with the gradient) the
+// output layer's weight and bias sums in its [d_out][n_L] then [d_out] layout.
+template <int H, int P>
+__device__ __forceinline__ void fwd_end(const FwdLds& s, double* loss_slot, double* out_slot, int dout, int nL,
+                                        bool with_grad) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < kMaxTerms; i += kThreads) loss_slot[i] = s.LOSS[i];
+  if (with_grad) {
+    for (int i = threadIdx.x; i < dout * nL; i += kThreads) {
+      const int o = i / nL, n = i - o * nL;
+      double t = 0.0;
+      for (int c = 0; c < FwdShape<H, P>::WC; ++c) t += s.WL[(c * 3 + o) * H + n];
+      out_slot[i] = t;
+    }
+    for (int o = threadIdx.x; o < dout; o += kThreads) out_slot[dout * nL + o] = s.BL[o];
+  }
+}
+
+// What a tile is: residual points (kind 0) or one value-supervision set (kind 1).
+struct TileSeg {
+  int kind;
+  int nvalid;            // valid points of the tile (the rest is padding)
+  int term;              // first loss term this tile adds to
+  const float* targets;  // kind 1: targets of the tile's first point (d_out per point)
+  int out_mask;
+  float lam;             // kind 1: 2 lambda / N_s
+  float* residual;       // kind 0: residual of the tile's first point, or null
+};
+
+// One tile of P points through the whole forward pass: embedding jets, hidden layers
+// (stash of every pre-activation), output layer, residual, loss partial sums, output-jet
+// seed and (with the gradient) the output layer's backward.  pts: the tile's points;
+// zs: stash of hidden layer 0 with zs_stride floats between layers; zb0: adjoint of the
+// last hidden layer; cb_st: first cp block of this tile in those buffers.
 template <int PREC, int ACT, int H, int P>
-__global__ __launch_bounds__(kThreads, 1) void k_forward(const FwdArgs A) {
+__device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, const float4* pts, float* zs,
+                                         int64_t zs_stride, float* zb0, int64_t cb_st, const TileSeg& sg, int rs,
+                                         bool with_grad, const FwdLds& s) {
   using S = FwdShape<H, P>;
   using Pr = Prec<PREC>;
   constexpr int CPB = S::CPB, NBW = S::NBW, CBW = S::CBW, WN = S::WN;
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  const NetDev& net = A.net;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, l16 = lane & 15;
   const int wn = wave % WN, wc = wave / WN;
   const int L = net.L, dout = net.d_out;
-  const int rs = r_stride(A.kmax);
-
-  // LDS carve-up
-  char* X = smem;                                             // R-layout tile
-  float4* PT = reinterpret_cast<float4*>(X + (size_t)4 * P * rs);  // points
-  float* YJ = reinterpret_cast<float*>(PT + P);               // [P][3][4] output jets
-  float* YB = YJ + P * 12;                                    // [P][3][4] output-jet adjoints
-  float* RED = YB + P * 12;                                   // [kWaves][4]
-  double* LOSS = reinterpret_cast<double*>(RED + kWaves * 4); // [kMaxTerms]
-  double* WL = LOSS + kMaxTerms;                              // [WC][3][H] output-layer W sums
-  double* BL = WL + S::WC * 3 * H;                            // [3] output-layer b sums
-
-  for (int i = tid; i < kMaxTerms; i += kThreads) LOSS[i] = 0.0;
-  for (int i = tid; i < S::WC * 3 * H + 3; i += kThreads) WL[i] = 0.0;
-
+  char* X = s.X;
   const LayerDev& lout = net.layer[L];
-  for (int64_t tile = blockIdx.x; tile < A.n_tiles; tile += gridDim.x) {
-    const int64_t p0 = tile * P;
-    const int s = seg_of(A.seg, p0);
-    const int64_t nvalid_i = A.seg.start[s] + A.seg.n[s] - p0;
-    const int nvalid = nvalid_i < 0 ? 0 : (nvalid_i > P ? P : (int)nvalid_i);
-    __syncthreads();  // previous tile's LDS use is over
-    for (int p = tid; p < P; p += kThreads) PT[p] = A.work.pts[p0 + p];
-    __syncthreads();
 
-    f4 acc[NBW][CBW];
-    // ---- layer 0
-    const LayerDev& l0 = net.layer[0];
-    if (net.n_freq == 0) {
-      // identity embedding: z = W x + b on the value channel, d z / d x_k = W[:, k]
+  __syncthreads();  // the previous user of the LDS is done
+  for (int p = tid; p < P; p += kThreads) s.PT[p] = pts[p];
+  __syncthreads();
+
+  f4 acc[NBW][CBW];
+  // ---- layer 0
+  const LayerDev& l0 = net.layer[0];
+  if (net.n_freq == 0) {
+    // identity embedding: z = W x + b on the value channel, d z / d x_k = W[:, k]
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+      const int nb = wn + WN * i;
+      const bool ok = nb * 16 < l0.n_out;
+      const int n = ok ? 16 * nb + l16 : 0;
+      float w[3] = {0.f, 0.f, 0.f};
+      float bn = 0.f;
+      if (ok) {
+        for (int k = 0; k < net.d_in; ++k) w[k] = l0.w[n * net.d_in + k];
+        bn = l0.b[n];
+      }
+#pragma unroll
+      for (int c = 0; c < CBW; ++c) {
+        const float4 x = s.PT[4 * (wc * CBW + c) + g];
+        f4 z;
+        z.x = bn + w[0] * x.x + w[1] * x.y + w[2] * x.z;
+        z.y = w[0];
+        z.z = w[1];
+        z.w = net.d_in > 2 ? w[2] : 0.0f;
+        acc[i][c] = z;
+      }
+    }
+  } else {
+    // Fourier-feature jets into the R layout, then z = W gamma + b
+    const int m = net.n_freq;
+    for (int idx = tid; idx < P * m; idx += kThreads) {
+      const int p = idx / m, j = idx - (idx / m) * m;
+      f4 cj, sj;
+      rff_jets(net, s.PT[p], j, cj, sj);
+      char* rowc = X + (size_t)(4 * p) * rs;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        Pr::put(rowc + (size_t)c * rs + (j >> 3) * 32, j & 7, cj[c]);
+        Pr::put(rowc + (size_t)c * rs + ((m + j) >> 3) * 32, (m + j) & 7, sj[c]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NBW; ++i)
+#pragma unroll
+      for (int c = 0; c < CBW; ++c) acc[i][c] = f4{0.f, 0.f, 0.f, 0.f};
+    {
+      int blk[NBW];
+      bool ok[NBW];
+#pragma unroll
+      for (int i = 0; i < NBW; ++i) {
+        blk[i] = wn + WN * i;
+        ok[i] = blk[i] < l0.nbo;
+      }
+      gemm_tile<PREC, NBW, CBW>(acc, X, rs, wc * CBW, l0.wf, l0.kci, blk, ok, lane);
+    }
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+      const int nb = wn + WN * i;
+      const float bn = nb < l0.nbo ? l0.b[16 * nb + l16] : 0.0f;
+#pragma unroll
+      for (int c = 0; c < CBW; ++c) acc[i][c].x += bn;
+    }
+  }
+
+  // ---- hidden layers: acc holds z of layer j
+  for (int j = 0; j < L; ++j) {
+    const LayerDev& lj = net.layer[j];
+    const int nbs = lj.n_out / 16;
+    if (with_grad) {
+      float* zsj = zs + j * zs_stride;
 #pragma unroll
       for (int i = 0; i < NBW; ++i) {
         const int nb = wn + WN * i;
-        const bool ok = nb * 16 < l0.n_out;
-        const int n = ok ? 16 * nb + l16 : 0;
-        float w[3] = {0.f, 0.f, 0.f};
-        float bn = 0.f;
-        if (ok) {
-          for (int k = 0; k < net.d_in; ++k) w[k] = l0.w[n * net.d_in + k];
-          bn = l0.b[n];
-        }
+        if (nb < nbs)
+#pragma unroll
+          for (int c = 0; c < CBW; ++c)
+            *jet_frag(zsj, cb_st + wc * CBW + c, nb, nbs, lane) = to_float4(acc[i][c]);
+      }
+    }
+    __syncthreads();  // every wave is done reading the layer input from X
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+      const int nb = wn + WN * i;
+      if (nb < nbs) {
+        const int n = 16 * nb + l16;
 #pragma unroll
         for (int c = 0; c < CBW; ++c) {
-          const float4 x = PT[4 * (wc * CBW + c) + g];
-          f4 z;
-          z.x = bn + w[0] * x.x + w[1] * x.y + w[2] * x.z;
-          z.y = w[0];
-          z.z = w[1];
-          z.w = net.d_in > 2 ? w[2] : 0.0f;
-          acc[i][c] = z;
-        }
-      }
-    } else {
-      // Fourier-feature jets into the R layout, then z = W gamma + b
-      const int m = net.n_freq;
-      for (int idx = tid; idx < P * m; idx += kThreads) {
-        const int p = idx / m, j = idx - (idx / m) * m;
-        f4 cj, sj;
-        rff_jets(net, PT[p], j, cj, sj);
-        char* rowc = X + (size_t)(4 * p) * rs;
+          const int cb = wc * CBW + c;
+          float s0, s1, s2, s3;
+          act_eval<ACT>(acc[i][c].x, net.w0, s0, s1, s2, s3);
+          const f4 a = jet_act(acc[i][c], s0, s1, s2, net.lapch, net.lap_mask);
+          char* base = X + (size_t)(16 * cb + 4 * g) * rs + (n >> 3) * 32;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          Pr::put(rowc + (size_t)c * rs + (j >> 3) * 32, j & 7, cj[c]);
-          Pr::put(rowc + (size_t)c * rs + ((m + j) >> 3) * 32, (m + j) & 7, sj[c]);
+          for (int r = 0; r < 4; ++r) Pr::put(base + (size_t)r * rs, n & 7, a[r]);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
-      __syncthreads();
+    }
+    __syncthreads();
+    if (j + 1 < L) {
+      const LayerDev& ln = net.layer[j + 1];
 #pragma unroll
       for (int i = 0; i < NBW; ++i)
 #pragma unroll
@@ -590,223 +697,169 @@ __global__ __launch_bounds__(kThreads, 1) void k_forward(const FwdArgs A) {
 #pragma unroll
         for (int i = 0; i < NBW; ++i) {
           blk[i] = wn + WN * i;
-          ok[i] = blk[i] < l0.nbo;
+          ok[i] = blk[i] < ln.nbo;
         }
-        gemm_tile<PREC, NBW, CBW>(acc, X, rs, wc * CBW, l0.wf, l0.kci, blk, ok, lane);
+        gemm_tile<PREC, NBW, CBW>(acc, X, rs, wc * CBW, ln.wf, ln.kci, blk, ok, lane);
       }
 #pragma unroll
       for (int i = 0; i < NBW; ++i) {
         const int nb = wn + WN * i;
-        const float bn = nb < l0.nbo ? l0.b[16 * nb + l16] : 0.0f;
+        const float bn = nb < ln.nbo ? ln.b[16 * nb + l16] : 0.0f;
 #pragma unroll
         for (int c = 0; c < CBW; ++c) acc[i][c].x += bn;
       }
     }
+  }
 
-    // ---- hidden layers: acc holds z of layer j
-    for (int j = 0; j < L; ++j) {
-      const LayerDev& lj = net.layer[j];
-      const int nbs = lj.n_out / 16;
-      if (A.with_grad) {
-#pragma unroll
-        for (int i = 0; i < NBW; ++i) {
-          const int nb = wn + WN * i;
-          if (nb < nbs)
-#pragma unroll
-            for (int c = 0; c < CBW; ++c)
-              *jet_frag(A.work.zs[j], tile * CPB + wc * CBW + c, nb, nbs, lane) = to_float4(acc[i][c]);
-        }
-      }
-      __syncthreads();  // every wave is done reading the layer input from X
-#pragma unroll
-      for (int i = 0; i < NBW; ++i) {
-        const int nb = wn + WN * i;
-        if (nb < nbs) {
-          const int n = 16 * nb + l16;
-#pragma unroll
-          for (int c = 0; c < CBW; ++c) {
-            const int cb = wc * CBW + c;
-            float s0, s1, s2, s3;
-            act_eval<ACT>(acc[i][c].x, net.w0, s0, s1, s2, s3);
-            const f4 a = jet_act(acc[i][c], s0, s1, s2, net.lapch, net.lap_mask);
-            char* base = X + (size_t)(16 * cb + 4 * g) * rs + (n >> 3) * 32;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) Pr::put(base + (size_t)r * rs, n & 7, a[r]);
-            __builtin_amdgcn_sched_barrier(0);
-          }
-        }
-      }
-      __syncthreads();
-      if (j + 1 < L) {
-        const LayerDev& ln = net.layer[j + 1];
-#pragma unroll
-        for (int i = 0; i < NBW; ++i)
-#pragma unroll
-          for (int c = 0; c < CBW; ++c) acc[i][c] = f4{0.f, 0.f, 0.f, 0.f};
-        {
-          int blk[NBW];
-          bool ok[NBW];
-#pragma unroll
-          for (int i = 0; i < NBW; ++i) {
-            blk[i] = wn + WN * i;
-            ok[i] = blk[i] < ln.nbo;
-          }
-          gemm_tile<PREC, NBW, CBW>(acc, X, rs, wc * CBW, ln.wf, ln.kci, blk, ok, lane);
-        }
-#pragma unroll
-        for (int i = 0; i < NBW; ++i) {
-          const int nb = wn + WN * i;
-          const float bn = nb < ln.nbo ? ln.b[16 * nb + l16] : 0.0f;
-#pragma unroll
-          for (int c = 0; c < CBW; ++c) acc[i][c].x += bn;
-        }
-      }
+  // ---- output layer (d_out <= 3 columns of one 16-wide block): waves over cp blocks
+  for (int cb = wave; cb < CPB; cb += kWaves) {
+    f4 y = f4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < lout.kci; ++kc) {
+      const Raw bw = glob_frag(lout.wf, 0, kc, lout.kci, lane);
+      const Raw a = lds_unit(X, 16 * cb + l16, 4 * kc + g, rs);
+      Pr::mma(y, a, bw);
     }
-
-    // ---- output layer (d_out <= 3 columns of one 16-wide block): waves over cp blocks
-    for (int cb = wave; cb < CPB; cb += kWaves) {
-      f4 y = f4{0.f, 0.f, 0.f, 0.f};
-      for (int kc = 0; kc < lout.kci; ++kc) {
-        const Raw bw = glob_frag(lout.wf, 0, kc, lout.kci, lane);
-        const Raw a = lds_unit(X, 16 * cb + l16, 4 * kc + g, rs);
-        Pr::mma(y, a, bw);
-      }
-      if (l16 < dout) {
-        y.x += lout.b[l16];
-        float* dst = YJ + ((4 * cb + g) * 3 + l16) * 4;
-        *reinterpret_cast<float4*>(dst) = to_float4(y);
-      }
-    }
-    __syncthreads();
-
-    // ---- residual (or supervision misfit), loss partial sums and the output-jet seed
-    float part[3] = {0.f, 0.f, 0.f};
-    if (tid < P) {
-      const int p = tid;
-      float y[3][4], yb[3][4];
-#pragma unroll
-      for (int o = 0; o < 3; ++o)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) y[o][c] = o < dout ? YJ[(p * 3 + o) * 4 + c] : 0.0f;
-      const bool valid = p < nvalid;
-      if (s == 0) {
-        float r[3];
-        residual_point(A.pde, net.lapch, y, r, yb);
-        if (valid) {
-          for (int c = 0; c < A.pde.n_res; ++c) part[c] = r[c] * r[c];
-          if (A.residual) {
-            const int64_t gi = p0 + p - A.seg.start[0];
-            for (int c = 0; c < A.pde.n_res; ++c) A.residual[gi * A.pde.n_res + c] = r[c];
-          }
-        }
-      } else {
-        const int a = s - 1;
-        const int64_t gi = p0 + p - A.seg.start[s];
-#pragma unroll
-        for (int o = 0; o < 3; ++o)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) yb[o][c] = 0.0f;
-        if (valid) {
-          for (int o = 0; o < dout; ++o) {
-            if (!(A.seg.out_mask[a] & (1 << o))) continue;
-            const float d = y[o][0] - A.seg.targets[a][gi * dout + o];
-            part[0] += d * d;
-            yb[o][0] = A.seg.lam_anchor[a] * d;
-          }
-        }
-      }
-      if (!valid) {
-#pragma unroll
-        for (int o = 0; o < 3; ++o)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) yb[o][c] = 0.0f;
-      }
-#pragma unroll
-      for (int o = 0; o < 3; ++o)
-        *reinterpret_cast<float4*>(YB + (p * 3 + o) * 4) = make_float4(yb[o][0], yb[o][1], yb[o][2], yb[o][3]);
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const float v = wave_sum(part[k]);
-      if (lane == 0) RED[wave * 4 + k] = v;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      const int nterm = s == 0 ? A.pde.n_res : 1;
-      const int base = s == 0 ? 0 : A.pde.n_res + (s - 1);
-      for (int k = 0; k < nterm; ++k) {
-        double t = 0.0;
-        for (int w = 0; w < kWaves; ++w) t += (double)RED[w * 4 + k];
-        LOSS[base + k] += t;
-      }
-    }
-
-    // ---- output layer backward: W_out / b_out sums, adjoint of the last hidden layer
-    if (A.with_grad) {
-      const int nL = lout.n_in;
-      const int nbs = nL / 16;
-      if (tid < dout) {
-        float t = 0.0f;
-        for (int p = 0; p < P; ++p) t += YB[(p * 3 + tid) * 4];
-        BL[tid] += (double)t;
-      }
-#pragma unroll
-      for (int i = 0; i < NBW; ++i) {
-        const int nb = wn + WN * i;
-        if (nb >= nbs) continue;
-        const int n = 16 * nb + l16;
-        float wo[3], wsum[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-        for (int o = 0; o < 3; ++o) wo[o] = o < dout ? lout.w[o * nL + n] : 0.0f;
-#pragma unroll 1
-        for (int c = 0; c < CBW; ++c) {
-          const int cb = wc * CBW + c;
-          const int p = 4 * cb + g;
-          const f4 z = to_f4(*jet_frag(A.work.zs[L - 1], tile * CPB + cb, nb, nbs, lane));
-          float s0, s1, s2, s3;
-          act_eval<ACT>(z.x, net.w0, s0, s1, s2, s3);
-          const f4 a = jet_act(z, s0, s1, s2, net.lapch, net.lap_mask);
-          f4 ab = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int o = 0; o < 3; ++o) {
-            const float4 yb4 = *reinterpret_cast<const float4*>(YB + (p * 3 + o) * 4);
-            const f4 yb = to_f4(yb4);
-            ab += yb * wo[o];
-            wsum[o] += yb.x * a.x + yb.y * a.y + yb.z * a.z + yb.w * a.w;
-          }
-          const f4 zb = jet_act_adj(z, ab, s1, s2, s3, net.lapch, net.lap_mask);
-          *jet_frag(A.work.zb[0], tile * CPB + cb, nb, nbs, lane) = to_float4(zb);
-          __builtin_amdgcn_sched_barrier(0);
-        }
-#pragma unroll
-        for (int o = 0; o < 3; ++o) {
-          float v = wsum[o];
-          v += __shfl_xor(v, 16, 64);
-          v += __shfl_xor(v, 32, 64);
-          if (g == 0 && o < dout) WL[(wc * 3 + o) * H + n] += (double)v;
-        }
-      }
+    if (l16 < dout) {
+      y.x += lout.b[l16];
+      float* dst = s.YJ + ((4 * cb + g) * 3 + l16) * 4;
+      *reinterpret_cast<float4*>(dst) = to_float4(y);
     }
   }
   __syncthreads();
-  // per-work-group partial sums
-  double* ls = A.work.loss_slots + (size_t)blockIdx.x * kMaxTerms;
-  for (int i = tid; i < kMaxTerms; i += kThreads) ls[i] = LOSS[i];
-  if (A.with_grad) {
-    const int nL = lout.n_in;
-    double* os = A.work.out_slots + (size_t)blockIdx.x * dout * (nL + 1);
-    for (int i = tid; i < dout * nL; i += kThreads) {
-      const int o = i / nL, n = i - o * nL;
-      double t = 0.0;
-      for (int c = 0; c < S::WC; ++c) t += WL[(c * 3 + o) * H + n];
-      os[i] = t;
+
+  // ---- residual (or supervision misfit), loss partial sums and the output-jet seed
+  float part[3] = {0.f, 0.f, 0.f};
+  if (tid < P) {
+    const int p = tid;
+    float y[3][4], yb[3][4];
+#pragma unroll
+    for (int o = 0; o < 3; ++o)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) y[o][c] = o < dout ? s.YJ[(p * 3 + o) * 4 + c] : 0.0f;
+    const bool valid = p < sg.nvalid;
+    if (sg.kind == 0) {
+      float r[3];
+      residual_point(pde, net.lapch, y, r, yb);
+      if (valid) {
+        for (int c = 0; c < pde.n_res; ++c) part[c] = r[c] * r[c];
+        if (sg.residual)
+          for (int c = 0; c < pde.n_res; ++c) sg.residual[(int64_t)p * pde.n_res + c] = r[c];
+      }
+    } else {
+#pragma unroll
+      for (int o = 0; o < 3; ++o)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) yb[o][c] = 0.0f;
+      if (valid) {
+        for (int o = 0; o < dout; ++o) {
+          if (!(sg.out_mask & (1 << o))) continue;
+          const float d = y[o][0] - sg.targets[(int64_t)p * dout + o];
+          part[0] += d * d;
+          yb[o][0] = sg.lam * d;
+        }
+      }
     }
-    for (int o = tid; o < dout; o += kThreads) os[dout * nL + o] = BL[o];
+    if (!valid) {
+#pragma unroll
+      for (int o = 0; o < 3; ++o)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) yb[o][c] = 0.0f;
+    }
+#pragma unroll
+    for (int o = 0; o < 3; ++o)
+      *reinterpret_cast<float4*>(s.YB + (p * 3 + o) * 4) = make_float4(yb[o][0], yb[o][1], yb[o][2], yb[o][3]);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float v = wave_sum(part[k]);
+    if (lane == 0) s.RED[wave * 4 + k] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int nterm = sg.kind == 0 ? pde.n_res : 1;
+    for (int k = 0; k < nterm; ++k) {
+      double t = 0.0;
+      for (int w = 0; w < kWaves; ++w) t += (double)s.RED[w * 4 + k];
+      s.LOSS[sg.term + k] += t;
+    }
+  }
+
+  // ---- output layer backward: W_out / b_out sums, adjoint of the last hidden layer
+  if (with_grad) {
+    const int nL = lout.n_in;
+    const int nbs = nL / 16;
+    float* zsl = zs + (L - 1) * zs_stride;
+    if (tid < dout) {
+      float t = 0.0f;
+      for (int p = 0; p < P; ++p) t += s.YB[(p * 3 + tid) * 4];
+      s.BL[tid] += (double)t;
+    }
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+      const int nb = wn + WN * i;
+      if (nb >= nbs) continue;
+      const int n = 16 * nb + l16;
+      float wo[3], wsum[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int o = 0; o < 3; ++o) wo[o] = o < dout ? lout.w[o * nL + n] : 0.0f;
+#pragma unroll 1
+      for (int c = 0; c < CBW; ++c) {
+        const int cb = wc * CBW + c;
+        const int p = 4 * cb + g;
+        const f4 z = to_f4(*jet_frag(zsl, cb_st + cb, nb, nbs, lane));
+        float s0, s1, s2, s3;
+        act_eval<ACT>(z.x, net.w0, s0, s1, s2, s3);
+        const f4 a = jet_act(z, s0, s1, s2, net.lapch, net.lap_mask);
+        f4 ab = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+          const f4 yb = to_f4(*reinterpret_cast<const float4*>(s.YB + (p * 3 + o) * 4));
+          ab += yb * wo[o];
+          wsum[o] += yb.x * a.x + yb.y * a.y + yb.z * a.z + yb.w * a.w;
+        }
+        const f4 zb = jet_act_adj(z, ab, s1, s2, s3, net.lapch, net.lap_mask);
+        *jet_frag(zb0, cb_st + cb, nb, nbs, lane) = to_float4(zb);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int o = 0; o < 3; ++o) {
+        float v = wsum[o];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (g == 0 && o < dout) s.WL[(wc * 3 + o) * H + n] += (double)v;
+      }
+    }
   }
 }
 
-// ================================================================== backward (one layer)
+template <int PREC, int ACT, int H, int P>
+__global__ __launch_bounds__(kThreads, 1) void k_forward(const FwdArgs A) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int rs = r_stride(A.kmax);
+  const FwdLds s = fwd_carve<H, P>(smem, rs);
+  fwd_begin<H, P>(s);
+  for (int64_t tile = blockIdx.x; tile < A.n_tiles; tile += gridDim.x) {
+    const int64_t p0 = tile * P;
+    const int sid = seg_of(A.seg, p0);
+    const int64_t nv = A.seg.start[sid] + A.seg.n[sid] - p0;
+    TileSeg sg;
+    sg.nvalid = nv < 0 ? 0 : (nv > P ? P : (int)nv);
+    sg.kind = sid == 0 ? 0 : 1;
+    sg.term = sid == 0 ? 0 : A.pde.n_res + (sid - 1);
+    sg.targets = sid == 0 ? nullptr : A.seg.targets[sid - 1] + (p0 - A.seg.start[sid]) * A.net.d_out;
+    sg.out_mask = sid == 0 ? 0 : A.seg.out_mask[sid - 1];
+    sg.lam = sid == 0 ? 0.0f : A.seg.lam_anchor[sid - 1];
+    sg.residual = (sid == 0 && A.residual) ? A.residual + (p0 - A.seg.start[0]) * A.pde.n_res : nullptr;
+    fwd_tile<PREC, ACT, H, P>(A.net, A.pde, A.work.pts + p0, A.work.zs0, A.work.zs_stride, A.work.zb[0],
+                              tile * (P / 4), sg, rs, A.with_grad != 0, s);
+  }
+  fwd_end<H, P>(s, A.work.loss_slots + (size_t)blockIdx.x * kMaxTerms,
+                A.with_grad ? A.work.out_slots + (size_t)blockIdx.x * A.net.d_out * (A.net.layer[A.net.L].n_in + 1)
+                            : nullptr,
+                A.net.d_out, A.net.layer[A.net.L].n_in, A.with_grad != 0);
+}
 
+// ================================================================== backward (one layer)
 
 template <int NOB, int NIB, int PB>
 struct BwdShape {
@@ -824,138 +877,143 @@ struct BwdShape {
   static_assert(CPB % 2 == 0 && CPB % WCA == 0, "sub-tile too small");
 };
 
+// One sub-tile of PB points of linear layer `layer`'s backward: the weight-gradient sums
+// (accw, bsum, kept by the caller across sub-tiles), and for layers with a predecessor
+// the input adjoint and activation adjoint (zb_out).  cb0: first cp block of the
+// sub-tile in the jet buffers; pts: the sub-tile's points (Fourier embedding only).
 template <int PREC, int ACT, int NOB, int NIB, int PB>
-__global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
+__device__ __forceinline__ void bwd_subtile(const NetDev& net, int layer, const float4* pts, int64_t cb0,
+                                            const float* zb_in, float* zb_out, const float* z_prev, char* smem,
+                                            f4 (&accw)[BwdShape<NOB, NIB, PB>::NOBW][BwdShape<NOB, NIB, PB>::NIBW],
+                                            float (&bsum)[BwdShape<NOB, NIB, PB>::NOBW]) {
   using S = BwdShape<NOB, NIB, PB>;
   using Pr = Prec<PREC>;
   constexpr int CPB = S::CPB, NOBW = S::NOBW, NIBW = S::NIBW, NIBA = S::NIBA, CBA = S::CBA;
   constexpr int WO = S::WO, WA = S::WA;
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  const NetDev& net = A.net;
-  const LayerDev& ly = net.layer[A.layer];
+  const LayerDev& ly = net.layer[layer];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, l16 = lane & 15;
   const int n_in = ly.n_in, n_out = ly.n_out;
   const int nob = n_out / 16, nib = n_in / 16;
   const int nbs_prev = n_in / 16;
-  const bool has_prev = A.z_prev != nullptr;
+  const bool has_prev = z_prev != nullptr;
   const int rs = r_stride(n_out);
   const int qs = q_stride(4 * PB);
-  char* Q = smem;                                   // A (layer input jets), Q layout
+  char* Q = smem;                                   // layer-input jets, Q layout
   char* R = smem + (size_t)n_in * qs;               // adjoint of z, R layout
   const int wo = wave % WO, wi = wave / WO;
   const int wa = wave % WA, wca = wave / WA;
 
-  f4 accw[NOBW][NIBW];
+  __syncthreads();  // the previous user of the LDS is done
+  if (has_prev) {
+    // (1) adjoint of z (this layer's output) into the R layout
+    for (int f = wave; f < CPB * nob; f += kWaves) {
+      const int cb = f % CPB, ob = f / CPB;
+      const f4 zb = to_f4(*jet_frag(const_cast<float*>(zb_in), cb0 + cb, ob, nob, lane));
+      const int o = 16 * ob + l16;
+      char* base = R + (size_t)(16 * cb + 4 * g) * rs + (o >> 3) * 32;
 #pragma unroll
-  for (int i = 0; i < NOBW; ++i)
+      for (int r = 0; r < 4; ++r) Pr::put(base + (size_t)r * rs, o & 7, zb[r]);
+    }
+    __syncthreads();
+    // (2) adjoint of the layer input: abar[cp][i] = sum_o zbar[cp][o] W[o][i]
+    f4 acca[NIBA][CBA];
 #pragma unroll
-    for (int k = 0; k < NIBW; ++k) accw[i][k] = f4{0.f, 0.f, 0.f, 0.f};
-  float bsum[NOBW];
+    for (int k = 0; k < NIBA; ++k)
 #pragma unroll
-  for (int i = 0; i < NOBW; ++i) bsum[i] = 0.f;
-
-  for (int64_t sub = blockIdx.x; sub < A.n_sub; sub += gridDim.x) {
-    const int64_t cb0 = sub * CPB;
-    __syncthreads();  // the previous sub-tile is done with R and Q
-    if (has_prev) {
-      // (1) adjoint of z (this layer's output) into the R layout
-      for (int f = wave; f < CPB * nob; f += kWaves) {
-        const int cb = f % CPB, ob = f / CPB;
-        const f4 zb = to_f4(*jet_frag(const_cast<float*>(A.zb_in), cb0 + cb, ob, nob, lane));
-        const int o = 16 * ob + l16;
-        char* base = R + (size_t)(16 * cb + 4 * g) * rs + (o >> 3) * 32;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Pr::put(base + (size_t)r * rs, o & 7, zb[r]);
-      }
-      __syncthreads();
-      // (2) adjoint of the layer input: abar[cp][i] = sum_o zbar[cp][o] W[o][i]
-      f4 acca[NIBA][CBA];
-#pragma unroll
-      for (int k = 0; k < NIBA; ++k)
-#pragma unroll
-        for (int c = 0; c < CBA; ++c) acca[k][c] = f4{0.f, 0.f, 0.f, 0.f};
-      {
-        int blk[NIBA];
-        bool ok[NIBA];
-#pragma unroll
-        for (int k = 0; k < NIBA; ++k) {
-          blk[k] = wa + WA * k;
-          ok[k] = blk[k] < nib;
-        }
-        gemm_tile<PREC, NIBA, CBA>(acca, R, rs, wca * CBA, ly.wb, ly.kco, blk, ok, lane);
-      }
-      // (3) one pass over the previous layer's pre-activations: recomputed activation jets
-      // into Q (operand of the weight gradient) and the activation adjoint
+      for (int c = 0; c < CBA; ++c) acca[k][c] = f4{0.f, 0.f, 0.f, 0.f};
+    {
+      int blk[NIBA];
+      bool ok[NIBA];
 #pragma unroll
       for (int k = 0; k < NIBA; ++k) {
-        const int ib = wa + WA * k;
-        if (ib >= nib) continue;
-        const int n = 16 * ib + l16;
-#pragma unroll
-        for (int c = 0; c < CBA; ++c) {
-          const int cb = wca * CBA + c;
-          const f4 z = to_f4(*jet_frag(const_cast<float*>(A.z_prev), cb0 + cb, ib, nbs_prev, lane));
-          float s0, s1, s2, s3;
-          act_eval<ACT>(z.x, net.w0, s0, s1, s2, s3);
-          const f4 a = jet_act(z, s0, s1, s2, net.lapch, net.lap_mask);
-          int unit, pos0;
-          q_pos(cb, g, unit, pos0);
-          Pr::put4(Q + (size_t)n * qs + unit * 32, pos0, a);
-          const f4 zb = jet_act_adj(z, acca[k][c], s1, s2, s3, net.lapch, net.lap_mask);
-          *jet_frag(A.zb_out, cb0 + cb, ib, nbs_prev, lane) = to_float4(zb);
-          __builtin_amdgcn_sched_barrier(0);
-        }
+        blk[k] = wa + WA * k;
+        ok[k] = blk[k] < nib;
       }
-    } else {
-      // Fourier-feature embedding of the sub-tile's points into Q
-      const int m = net.n_freq;
-      for (int idx = tid; idx < PB * m; idx += kThreads) {
-        const int p = idx / m, j = idx - (idx / m) * m;
-        f4 cj, sj;
-        rff_jets(net, A.work.pts[cb0 * 4 + p], j, cj, sj);
-        const int cb = p >> 2, gg = p & 3;
+      gemm_tile<PREC, NIBA, CBA>(acca, R, rs, wca * CBA, ly.wb, ly.kco, blk, ok, lane);
+    }
+    // (3) one pass over the previous layer's pre-activations: recomputed activation jets
+    // into Q (operand of the weight gradient) and the activation adjoint
+#pragma unroll
+    for (int k = 0; k < NIBA; ++k) {
+      const int ib = wa + WA * k;
+      if (ib >= nib) continue;
+      const int n = 16 * ib + l16;
+#pragma unroll
+      for (int c = 0; c < CBA; ++c) {
+        const int cb = wca * CBA + c;
+        const f4 z = to_f4(*jet_frag(const_cast<float*>(z_prev), cb0 + cb, ib, nbs_prev, lane));
+        float s0, s1, s2, s3;
+        act_eval<ACT>(z.x, net.w0, s0, s1, s2, s3);
+        const f4 a = jet_act(z, s0, s1, s2, net.lapch, net.lap_mask);
         int unit, pos0;
-        q_pos(cb, gg, unit, pos0);
-        Pr::put4(Q + (size_t)j * qs + unit * 32, pos0, cj);
-        Pr::put4(Q + (size_t)(m + j) * qs + unit * 32, pos0, sj);
+        q_pos(cb, g, unit, pos0);
+        Pr::put4(Q + (size_t)n * qs + unit * 32, pos0, a);
+        const f4 zb = jet_act_adj(z, acca[k][c], s1, s2, s3, net.lapch, net.lap_mask);
+        *jet_frag(zb_out, cb0 + cb, ib, nbs_prev, lane) = to_float4(zb);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
-    __syncthreads();  // Q complete
-    // (4) weight gradient: W_bar[o][i] += sum_cp zbar[cp][o] a[cp][i]
-    for (int cc = 0; cc < CPB / 2; ++cc) {
-      Raw ao[NOBW];
-#pragma unroll
-      for (int i = 0; i < NOBW; ++i) {
-        const int ob = wo + WO * i;
-        if (ob < nob) {
-          const float4 v0 = *jet_frag(const_cast<float*>(A.zb_in), cb0 + 2 * cc, ob, nob, lane);
-          const float4 v1 = *jet_frag(const_cast<float*>(A.zb_in), cb0 + 2 * cc + 1, ob, nob, lane);
-          const float f[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-          ao[i] = Pr::make(f);
-          bsum[i] += v0.x + v1.x;
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < NIBW; ++k) {
-        const int ib = wi + S::WI * k;
-        if (ib >= nib) continue;
-        const Raw bq = lds_unit(Q, 16 * ib + l16, 4 * cc + g, qs);
-#pragma unroll
-        for (int i = 0; i < NOBW; ++i)
-          if (wo + WO * i < nob) Pr::mma(accw[i][k], ao[i], bq);
-      }
+  } else {
+    // Fourier-feature embedding of the sub-tile's points into Q
+    const int m = net.n_freq;
+    for (int idx = tid; idx < PB * m; idx += kThreads) {
+      const int p = idx / m, j = idx - (idx / m) * m;
+      f4 cj, sj;
+      rff_jets(net, pts[p], j, cj, sj);
+      const int cb = p >> 2, gg = p & 3;
+      int unit, pos0;
+      q_pos(cb, gg, unit, pos0);
+      Pr::put4(Q + (size_t)j * qs + unit * 32, pos0, cj);
+      Pr::put4(Q + (size_t)(m + j) * qs + unit * 32, pos0, sj);
     }
   }
-  // flush this work-group's sums (FP32 over its range) to its FP64 slot
-  double* slot = A.slots + (size_t)blockIdx.x * n_out * (n_in + 1);
+  __syncthreads();  // Q complete
+  // (4) weight gradient: W_bar[o][i] += sum_cp zbar[cp][o] a[cp][i]
+  for (int cc = 0; cc < CPB / 2; ++cc) {
+    Raw ao[NOBW];
 #pragma unroll
-  for (int i = 0; i < NOBW; ++i) {
-    const int ob = wo + WO * i;
-    if (ob >= nob) continue;
+    for (int i = 0; i < NOBW; ++i) {
+      const int ob = wo + WO * i;
+      if (ob < nob) {
+        const float4 v0 = *jet_frag(const_cast<float*>(zb_in), cb0 + 2 * cc, ob, nob, lane);
+        const float4 v1 = *jet_frag(const_cast<float*>(zb_in), cb0 + 2 * cc + 1, ob, nob, lane);
+        const float f[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        ao[i] = Pr::make(f);
+        bsum[i] += v0.x + v1.x;
+      }
+    }
 #pragma unroll
     for (int k = 0; k < NIBW; ++k) {
+      const int ib = wi + S::WI * k;
+      if (ib >= nib) continue;
+      const Raw bq = lds_unit(Q, 16 * ib + l16, 4 * cc + g, qs);
+#pragma unroll
+      for (int i = 0; i < NOBW; ++i)
+        if (wo + WO * i < nob) Pr::mma(accw[i][k], ao[i], bq);
+    }
+  }
+}
+
+// Store the weight-gradient sums (FP32 over the run of sub-tiles) as FP64 into a slot laid
+// out [n_out][n_in] then [n_out] (bias).
+template <int NOB, int NIB, int PB>
+__device__ __forceinline__ void bwd_flush(const f4 (&accw)[BwdShape<NOB, NIB, PB>::NOBW][BwdShape<NOB, NIB, PB>::NIBW],
+                                          const float (&bsum)[BwdShape<NOB, NIB, PB>::NOBW], double* slot, int n_out,
+                                          int n_in) {
+  using S = BwdShape<NOB, NIB, PB>;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, l16 = lane & 15;
+  const int wo = wave % S::WO, wi = wave / S::WO;
+  const int nob = n_out / 16, nib = n_in / 16;
+#pragma unroll
+  for (int i = 0; i < S::NOBW; ++i) {
+    const int ob = wo + S::WO * i;
+    if (ob >= nob) continue;
+#pragma unroll
+    for (int k = 0; k < S::NIBW; ++k) {
       const int ib = wi + S::WI * k;
       if (ib >= nib) continue;
 #pragma unroll
@@ -970,23 +1028,42 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
   }
 }
 
+template <int PREC, int ACT, int NOB, int NIB, int PB>
+__global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
+  using S = BwdShape<NOB, NIB, PB>;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  f4 accw[S::NOBW][S::NIBW];
+#pragma unroll
+  for (int i = 0; i < S::NOBW; ++i)
+#pragma unroll
+    for (int k = 0; k < S::NIBW; ++k) accw[i][k] = f4{0.f, 0.f, 0.f, 0.f};
+  float bsum[S::NOBW];
+#pragma unroll
+  for (int i = 0; i < S::NOBW; ++i) bsum[i] = 0.f;
+  for (int64_t sub = blockIdx.x; sub < A.n_sub; sub += gridDim.x)
+    bwd_subtile<PREC, ACT, NOB, NIB, PB>(A.net, A.layer, A.work.pts + sub * PB, sub * S::CPB, A.zb_in, A.zb_out,
+                                         A.z_prev, smem, accw, bsum);
+  const LayerDev& ly = A.net.layer[A.layer];
+  bwd_flush<NOB, NIB, PB>(accw, bsum, A.slots + (size_t)blockIdx.x * ly.n_out * (ly.n_in + 1), ly.n_out, ly.n_in);
+}
+
 // ================================================================== first layer, identity
 
 // W_bar[o][k] = sum_points (zbar0[o] x_k + zbar_{1+k}[o]), b_bar[o] = sum zbar0[o]: the
-// identity embedding's jets are (x, unit vectors, 0).
-
-__global__ __launch_bounds__(256) void k_grad0(const Grad0Args A) {
+// identity embedding's jets are (x, unit vectors, 0).  Sums over cp blocks [cb_lo, cb_hi)
+// of the adjoint buffer (points pts[4 cb + ...]) into slot [n_out][d_in] then [n_out].
+// red: LDS scratch of kWaves * 256 * 4 floats.
+__device__ __forceinline__ void grad0_range(const float* zb, const float4* pts, int n_out, int d_in, int64_t cb_lo,
+                                            int64_t cb_hi, double* slot, float* red) {
   const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nob = A.n_out / 16;
-  __shared__ double red[4][256 * 4];
-  for (int i = threadIdx.x; i < 4 * 256 * 4; i += blockDim.x) (&red[0][0])[i] = 0.0;
+  const int nob = n_out / 16;
   __syncthreads();
   for (int ob = 0; ob < nob; ++ob) {
     float s[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int64_t cb = (int64_t)blockIdx.x * 4 + wave; cb < A.n_cb; cb += (int64_t)gridDim.x * 4) {
-      const float4 z = *jet_frag(const_cast<float*>(A.zb), cb, ob, nob, lane);
-      const float4 x = A.pts[4 * cb + g];
+    for (int64_t cb = cb_lo + wave; cb < cb_hi; cb += kWaves) {
+      const float4 z = *jet_frag(const_cast<float*>(zb), cb, ob, nob, lane);
+      const float4 x = pts[4 * cb + g];
       s[0] += z.x * x.x + z.y;
       s[1] += z.x * x.y + z.z;
       s[2] += z.x * x.z + z.w;
@@ -997,15 +1074,114 @@ __global__ __launch_bounds__(256) void k_grad0(const Grad0Args A) {
       float v = s[k];
       v += __shfl_xor(v, 16, 64);
       v += __shfl_xor(v, 32, 64);
-      if (g == 0) red[wave][(16 * ob + l16) * 4 + k] = (double)v;
+      if (g == 0) red[(wave * 256 + 16 * ob + l16) * 4 + k] = v;
     }
   }
   __syncthreads();
-  double* slot = A.slots + (size_t)blockIdx.x * A.n_out * (A.d_in + 1);
-  for (int i = threadIdx.x; i < A.n_out; i += blockDim.x) {
-    for (int k = 0; k < A.d_in; ++k)
-      slot[(size_t)i * A.d_in + k] = red[0][i * 4 + k] + red[1][i * 4 + k] + red[2][i * 4 + k] + red[3][i * 4 + k];
-    slot[(size_t)A.n_out * A.d_in + i] = red[0][i * 4 + 3] + red[1][i * 4 + 3] + red[2][i * 4 + 3] + red[3][i * 4 + 3];
+  for (int i = threadIdx.x; i < n_out; i += kThreads) {
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int w = 0; w < kWaves; ++w)
+      for (int k = 0; k < 4; ++k) t[k] += (double)red[(w * 256 + i) * 4 + k];
+    for (int k = 0; k < d_in; ++k) slot[(size_t)i * d_in + k] = t[k];
+    slot[(size_t)n_out * d_in + i] = t[3];
+  }
+}
+
+__global__ __launch_bounds__(kThreads, 1) void k_grad0(const Grad0Args A) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int64_t per = (A.n_cb + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = lo + per < A.n_cb ? lo + per : A.n_cb;
+  grad0_range(A.zb, A.pts, A.n_out, A.d_in, lo, hi, A.slots + (size_t)blockIdx.x * A.n_out * (A.d_in + 1),
+              reinterpret_cast<float*>(smem));
+}
+
+// ================================================================== many networks, one launch
+
+// Work item i: instance items[i].inst, padded points [p0, p1) of that instance (multiples
+// of 128).  A work-group takes items from the counter in the order `order` (longest first),
+// runs the forward over the item's tiles and then every layer's backward over the same
+// points, keeping each layer's weight-gradient sums in registers over the item, and writes
+// them with the loss sums to the item's own FP64 slots.  Slots are per item, so the
+// result does not depend on which work-group ran which item.
+template <int PREC, int ACT, int H>
+__device__ __forceinline__ void run_item(const BatchArgs& A, const BatchInst& in, const BatchItem& it, int64_t item,
+                                         char* smem) {
+  constexpr int PF = H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128;
+  constexpr int PB = H == 256 ? 16 : H == 128 ? 32 : H == 64 ? 64 : 128;
+  const NetDev& net = in.net;
+  float* scratch = A.scratch + (size_t)blockIdx.x * A.scratch_per_wg;
+  float* zs = scratch;
+  float* zb[2] = {scratch + in.zb_off[0], scratch + in.zb_off[1]};
+  const float4* pts = A.pts + in.pts_off + it.p0;
+  const int64_t npts = it.p1 - it.p0;
+  double* loss_slot = A.loss_slots + (size_t)item * kMaxTerms;
+  double* gslot = A.grad_slots + it.slot_off;
+  PdeDev pde = A.pde;
+  for (int c = 0; c < 3; ++c) pde.seed_scale[c] = 2.0f * A.lambda_res[c] / (float)in.n;
+  // forward over the item's tiles
+  {
+    const int rs = r_stride(in.kmax);
+    const FwdLds s = fwd_carve<H, PF>(smem, rs);
+    fwd_begin<H, PF>(s);
+    for (int64_t t = 0; t < npts / PF; ++t) {
+      const int64_t nv = in.n - (it.p0 + t * PF);
+      TileSeg sg;
+      sg.nvalid = nv < 0 ? 0 : (nv > PF ? PF : (int)nv);
+      sg.kind = 0;
+      sg.term = 0;
+      sg.targets = nullptr;
+      sg.out_mask = 0;
+      sg.lam = 0.0f;
+      sg.residual = nullptr;
+      fwd_tile<PREC, ACT, H, PF>(net, pde, pts + t * PF, zs, in.zs_stride, zb[0], t * (PF / 4), sg, rs, true, s);
+    }
+    const int nL = net.layer[net.L].n_in;
+    fwd_end<H, PF>(s, loss_slot, gslot + in.eff_off[net.L], net.d_out, nL, true);
+  }
+  // backward, hidden layers last to first
+  int cur = 0;
+  for (int j = net.L - 1; j >= 1; --j) {
+    using S = BwdShape<H / 16, H / 16, PB>;
+    f4 accw[S::NOBW][S::NIBW];
+#pragma unroll
+    for (int i = 0; i < S::NOBW; ++i)
+#pragma unroll
+      for (int k = 0; k < S::NIBW; ++k) accw[i][k] = f4{0.f, 0.f, 0.f, 0.f};
+    float bsum[S::NOBW];
+#pragma unroll
+    for (int i = 0; i < S::NOBW; ++i) bsum[i] = 0.f;
+    for (int64_t sub = 0; sub < npts / PB; ++sub)
+      bwd_subtile<PREC, ACT, H / 16, H / 16, PB>(net, j, pts + sub * PB, sub * S::CPB, zb[cur], zb[cur ^ 1],
+                                                 zs + (j - 1) * in.zs_stride, smem, accw, bsum);
+    bwd_flush<H / 16, H / 16, PB>(accw, bsum, gslot + in.eff_off[j], net.layer[j].n_out, net.layer[j].n_in);
+    cur ^= 1;
+  }
+  // first layer (identity embedding)
+  grad0_range(zb[cur], pts, net.layer[0].n_out, net.d_in, 0, npts / 4, gslot + in.eff_off[0],
+              reinterpret_cast<float*>(smem));
+  __syncthreads();
+}
+
+template <int PREC, int ACT>
+__global__ __launch_bounds__(kThreads, 1) void k_batched(const BatchArgs A) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  __shared__ int s_q;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_q = atomicAdd(A.counter, 1);
+    __syncthreads();
+    const int q = __builtin_amdgcn_readfirstlane(s_q);
+    if (q >= A.n_items) break;
+    const int64_t item = A.order[q];
+    const BatchItem it = A.items[item];
+    const BatchInst& in = A.inst[it.inst];
+    switch (in.H) {
+      case 32: run_item<PREC, ACT, 32>(A, in, it, item, smem); break;
+      case 64: run_item<PREC, ACT, 64>(A, in, it, item, smem); break;
+      case 128: run_item<PREC, ACT, 128>(A, in, it, item, smem); break;
+      default: run_item<PREC, ACT, 256>(A, in, it, item, smem); break;
+    }
   }
 }
 
@@ -1015,16 +1191,13 @@ __global__ __launch_bounds__(256) void k_grad0(const Grad0Args A) {
 // layout: with factorised weights W = diag(exp s) V, dL/dV = exp(s) dL/dW and
 // dL/ds_o = sum_i W_oi dL/dW_oi (Sec. 2.6.2).
 
-__global__ void k_reduce_layer(const ReduceArgs A) {
-  const int o = blockIdx.x;
-  if (o >= A.n_out) return;
-  const size_t stride = (size_t)A.n_out * (A.n_in + 1);
+__device__ __forceinline__ void reduce_row(const ReduceArgs& A, int o) {
   double es = 1.0;
   if (A.rwf) es = exp((double)A.params[A.off_s + o]);
   double ssum = 0.0;
   for (int i = threadIdx.x; i < A.n_in; i += blockDim.x) {
     double t = 0.0;
-    for (int sl = 0; sl < A.n_slots; ++sl) t += A.slots[sl * stride + (size_t)o * A.n_in + i];
+    for (int sl = 0; sl < A.n_slots; ++sl) t += A.slots[sl * A.slot_stride + (int64_t)o * A.n_in + i];
     const double v = (double)A.params[A.off_w + (int64_t)o * A.n_in + i];
     A.grad[A.off_w + (int64_t)o * A.n_in + i] = es * t;
     ssum += t * es * v;
@@ -1040,12 +1213,56 @@ __global__ void k_reduce_layer(const ReduceArgs A) {
     if (A.rwf) A.grad[A.off_s + o] = red[0];
     if (A.has_bias) {
       double t = 0.0;
-      for (int sl = 0; sl < A.n_slots; ++sl) t += A.slots[sl * stride + (size_t)A.n_out * A.n_in + o];
+      for (int sl = 0; sl < A.n_slots; ++sl) t += A.slots[sl * A.slot_stride + (int64_t)A.n_out * A.n_in + o];
       A.grad[A.off_b + o] = t;
     }
   }
 }
 
+__global__ void k_reduce_layer(const ReduceArgs A) {
+  if ((int)blockIdx.x < A.n_out) reduce_row(A, blockIdx.x);
+}
+
+// Per-instance reductions of the item slots: one block per (instance, layer, output row).
+__global__ void k_reduce_batched(const BatchReduceArgs A) {
+  const int64_t r = blockIdx.x;
+  int lo = 0, hi = A.n_entries - 1;
+  while (lo < hi) {  // last entry with row0 <= r
+    const int mid = (lo + hi + 1) / 2;
+    if (A.rows[mid].row0 <= r) lo = mid; else hi = mid - 1;
+  }
+  const BatchRow e = A.rows[lo];
+  ReduceArgs a;
+  a.slots = A.grad_slots + e.slot0;
+  a.n_slots = e.n_items;
+  a.slot_stride = e.slot_stride;
+  a.n_out = e.n_out;
+  a.n_in = e.n_in;
+  a.rwf = e.rwf;
+  a.has_bias = e.has_bias;
+  a.params = e.params;
+  a.off_w = e.off_w;
+  a.off_s = e.off_s;
+  a.off_b = e.off_b;
+  a.grad = e.grad;
+  reduce_row(a, (int)(r - e.row0));
+}
+
+__global__ void k_reduce_loss_batched(const BatchLossArgs A) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n_inst) return;
+  double total = 0.0;
+  for (int k = 0; k < A.n_res; ++k) {
+    double t = 0.0;
+    for (int s = 0; s < A.n_items[i]; ++s) t += A.loss_slots[(size_t)(A.item0[i] + s) * kMaxTerms + k];
+    t *= A.w_res[i * 3 + k];
+    A.losses[(size_t)i * (1 + A.n_res) + 1 + k] = t;
+    total += t;
+  }
+  A.losses[(size_t)i * (1 + A.n_res)] = total;
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
 
 __global__ void k_reduce_loss(const LossArgs A) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -1174,7 +1391,56 @@ int launch_backward(int prec, int act, int H, bool embed, const BwdArgs& a, int 
 }
 
 int launch_grad0(const Grad0Args& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_grad0, dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_grad0, dim3(grid), dim3(kThreads), kWaves * 256 * 4 * sizeof(float), s, a);
+  return status(hipGetLastError());
+}
+
+int launch_zero_int(int* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, p);
+  return status(hipGetLastError());
+}
+
+size_t batched_lds(int kmax, int H) {
+  const int PF = H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128;
+  const int PB = H == 256 ? 16 : H == 128 ? 32 : H == 64 ? 64 : 128;
+  const int WN = H / 16 < kWaves ? H / 16 : kWaves;
+  const int WC = kWaves / WN;
+  size_t f = (size_t)4 * PF * r_stride(kmax) + (size_t)PF * 16 + (size_t)PF * 12 * 4 * 2 + kWaves * 4 * 4 +
+             kMaxTerms * 8 + (size_t)WC * 3 * H * 8 + 3 * 8;
+  size_t b = (size_t)H * q_stride(4 * PB) + (size_t)4 * PB * r_stride(H);
+  size_t g = (size_t)kWaves * 256 * 4 * sizeof(float);
+  size_t m = f > b ? f : b;
+  return m > g ? m : g;
+}
+
+int launch_batched(int prec, int act, const BatchArgs& a, int grid, size_t lds, hipStream_t s) {
+  const void* k;
+  if (prec == kFP32)
+    k = act == kTanh ? reinterpret_cast<const void*>(k_batched<kFP32, kTanh>)
+                     : reinterpret_cast<const void*>(k_batched<kFP32, kSin>);
+  else
+    k = act == kTanh ? reinterpret_cast<const void*>(k_batched<kBF16X3, kTanh>)
+                     : reinterpret_cast<const void*>(k_batched<kBF16X3, kSin>);
+  if (lds > 65536 &&
+      hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return -5;
+  if (prec == kFP32) {
+    if (act == kTanh) hipLaunchKernelGGL((k_batched<kFP32, kTanh>), dim3(grid), dim3(kThreads), lds, s, a);
+    else hipLaunchKernelGGL((k_batched<kFP32, kSin>), dim3(grid), dim3(kThreads), lds, s, a);
+  } else {
+    if (act == kTanh) hipLaunchKernelGGL((k_batched<kBF16X3, kTanh>), dim3(grid), dim3(kThreads), lds, s, a);
+    else hipLaunchKernelGGL((k_batched<kBF16X3, kSin>), dim3(grid), dim3(kThreads), lds, s, a);
+  }
+  return status(hipGetLastError());
+}
+
+int launch_reduce_batched(const BatchReduceArgs& a, hipStream_t s) {
+  if (a.n_rows > 0) hipLaunchKernelGGL(k_reduce_batched, dim3((unsigned)a.n_rows), dim3(256), 0, s, a);
+  return status(hipGetLastError());
+}
+
+int launch_reduce_loss_batched(const BatchLossArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_loss_batched, dim3((a.n_inst + 63) / 64), dim3(64), 0, s, a);
   return status(hipGetLastError());
 }
 
