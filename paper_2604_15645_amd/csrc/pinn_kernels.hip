@@ -63,6 +63,22 @@ struct Prec<kFP32> {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.b.z), __uint_as_float(y.b.z), acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.b.w), __uint_as_float(y.b.w), acc, 0, 0, 0);
   }
+  // acc[i][c] += a[c] * b[i] for a whole register tile; the loops run over independent
+  // accumulators innermost so that consecutive products never wait on each other.  The
+  // order of the eight partial products into each accumulator is that of mma().
+  template <int NB, int CB>
+  static __device__ __forceinline__ void mma_tile(f4 (&acc)[NB][CB], const Raw (&a)[CB], const Raw (&b)[NB]) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const uint32_t x = j < 4 ? (&a[c].a.x)[j] : (&a[c].b.x)[j - 4];
+          const uint32_t y = j < 4 ? (&b[i].a.x)[j] : (&b[i].b.x)[j - 4];
+          acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x), __uint_as_float(y), acc[i][c], 0, 0, 0);
+        }
+  }
   static __device__ __forceinline__ Raw make(const float (&f)[8]) {
     Raw r;
     r.a = make_uint4(__float_as_uint(f[0]), __float_as_uint(f[1]), __float_as_uint(f[2]), __float_as_uint(f[3]));
@@ -89,6 +105,29 @@ struct Prec<kBF16X3> {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, yh, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yl, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yh, acc, 0, 0, 0);
+  }
+  // Register-tile form of mma(): each of the three products in turn over all
+  // accumulators, same per-accumulator order as mma().
+  template <int NB, int CB>
+  static __device__ __forceinline__ void mma_tile(f4 (&acc)[NB][CB], const Raw (&a)[CB], const Raw (&b)[NB]) {
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[c].b),
+                                                            __builtin_bit_cast(bf16x8, b[i].a), acc[i][c], 0, 0, 0);
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[c].a),
+                                                            __builtin_bit_cast(bf16x8, b[i].b), acc[i][c], 0, 0, 0);
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[c].a),
+                                                            __builtin_bit_cast(bf16x8, b[i].a), acc[i][c], 0, 0, 0);
   }
   static __device__ __forceinline__ Raw make(const float (&f)[8]) {
     bf16x8 h, l;
@@ -157,28 +196,47 @@ __device__ __forceinline__ float4* jet_frag(float* buf, int64_t cb, int nb, int 
 
 // acc[i][c] += A(cp block cb0 + c) * W(block blk[i])^T over all reduction chunks: the A
 // operand comes from an R-layout tile in LDS, the B operand from fragment-major weights.
-// Two A fragments are live at a time (the next one is read while the current one feeds
-// the matrix cores); the scheduling barriers keep the compiler from hoisting more.
+// Every block index must be valid (callers clamp them; results of clamped duplicates are
+// discarded), so the loop body has no branches and the products of one chunk issue back
+// to back over independent accumulators.
 template <int PREC, int NB, int CB>
 __device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int rs, int cb0,
-                                          const char* frags, int kchunks, const int (&blk)[NB],
-                                          const bool (&ok)[NB], int lane) {
+                                          const char* frags, int kchunks, const int (&blk)[NB], int lane) {
   const int g = lane >> 4, l16 = lane & 15;
+  const char* xa = X + (size_t)(16 * cb0 + l16) * rs + g * 32;
+  const char* fb[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) fb[i] = frags + ((size_t)blk[i] * kchunks * 64 + lane) * 32;
+  constexpr int CG = CB > 8 ? 8 : CB;  // A fragments live at a time
+  static_assert(CB % CG == 0, "cp blocks per wave");
   for (int kc = 0; kc < kchunks; ++kc) {
     Raw bw[NB];
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
-      if (ok[i]) bw[i] = glob_frag(frags, blk[i], kc, kchunks, lane);
-    Raw a = lds_unit(X, 16 * cb0 + l16, 4 * kc + g, rs);
+    for (int i = 0; i < NB; ++i) {
+      const uint4* p = reinterpret_cast<const uint4*>(fb[i] + (size_t)kc * 2048);
+      bw[i].a = p[0];
+      bw[i].b = p[1];
+    }
 #pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      Raw an = a;
-      if (c + 1 < CB) an = lds_unit(X, 16 * (cb0 + c + 1) + l16, 4 * kc + g, rs);
+    for (int c0 = 0; c0 < CB; c0 += CG) {
+      Raw a[CG];
+#pragma unroll
+      for (int c = 0; c < CG; ++c) {
+        const uint4* p = reinterpret_cast<const uint4*>(xa + (size_t)(c0 + c) * 16 * rs + kc * 128);
+        a[c].a = p[0];
+        a[c].b = p[1];
+      }
+      f4 (&part)[NB][CB] = acc;
+      f4 sub[NB][CG];
 #pragma unroll
       for (int i = 0; i < NB; ++i)
-        if (ok[i]) Prec<PREC>::mma(acc[i][c], a, bw[i]);
-      a = an;
-      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < CG; ++c) sub[i][c] = part[i][c0 + c];
+      Prec<PREC>::template mma_tile<NB, CG>(sub, a, bw);
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int c = 0; c < CG; ++c) part[i][c0 + c] = sub[i][c];
     }
   }
 }
@@ -633,13 +691,9 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       for (int c = 0; c < CBW; ++c) acc[i][c] = f4{0.f, 0.f, 0.f, 0.f};
     {
       int blk[NBW];
-      bool ok[NBW];
 #pragma unroll
-      for (int i = 0; i < NBW; ++i) {
-        blk[i] = wn + WN * i;
-        ok[i] = blk[i] < l0.nbo;
-      }
-      gemm_tile<PREC, NBW, CBW>(acc, X, rs, wc * CBW, l0.wf, l0.kci, blk, ok, lane);
+      for (int i = 0; i < NBW; ++i) blk[i] = min(wn + WN * i, l0.nbo - 1);
+      gemm_tile<PREC, NBW, CBW>(acc, X, rs, wc * CBW, l0.wf, l0.kci, blk, lane);
     }
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
@@ -693,13 +747,9 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
         for (int c = 0; c < CBW; ++c) acc[i][c] = f4{0.f, 0.f, 0.f, 0.f};
       {
         int blk[NBW];
-        bool ok[NBW];
 #pragma unroll
-        for (int i = 0; i < NBW; ++i) {
-          blk[i] = wn + WN * i;
-          ok[i] = blk[i] < ln.nbo;
-        }
-        gemm_tile<PREC, NBW, CBW>(acc, X, rs, wc * CBW, ln.wf, ln.kci, blk, ok, lane);
+        for (int i = 0; i < NBW; ++i) blk[i] = min(wn + WN * i, ln.nbo - 1);
+        gemm_tile<PREC, NBW, CBW>(acc, X, rs, wc * CBW, ln.wf, ln.kci, blk, lane);
       }
 #pragma unroll
       for (int i = 0; i < NBW; ++i) {
@@ -925,13 +975,9 @@ __device__ __forceinline__ void bwd_subtile(const NetDev& net, int layer, const 
       for (int c = 0; c < CBA; ++c) acca[k][c] = f4{0.f, 0.f, 0.f, 0.f};
     {
       int blk[NIBA];
-      bool ok[NIBA];
 #pragma unroll
-      for (int k = 0; k < NIBA; ++k) {
-        blk[k] = wa + WA * k;
-        ok[k] = blk[k] < nib;
-      }
-      gemm_tile<PREC, NIBA, CBA>(acca, R, rs, wca * CBA, ly.wb, ly.kco, blk, ok, lane);
+      for (int k = 0; k < NIBA; ++k) blk[k] = min(wa + WA * k, nib - 1);
+      gemm_tile<PREC, NIBA, CBA>(acca, R, rs, wca * CBA, ly.wb, ly.kco, blk, lane);
     }
     // (3) one pass over the previous layer's pre-activations: recomputed activation jets
     // into Q (operand of the weight gradient) and the activation adjoint
@@ -971,27 +1017,23 @@ __device__ __forceinline__ void bwd_subtile(const NetDev& net, int layer, const 
   }
   __syncthreads();  // Q complete
   // (4) weight gradient: W_bar[o][i] += sum_cp zbar[cp][o] a[cp][i]
+  // Out-of-range blocks are clamped to the last valid one; their sums are never stored.
   for (int cc = 0; cc < CPB / 2; ++cc) {
     Raw ao[NOBW];
 #pragma unroll
     for (int i = 0; i < NOBW; ++i) {
-      const int ob = wo + WO * i;
-      if (ob < nob) {
-        const float4 v0 = *jet_frag(const_cast<float*>(zb_in), cb0 + 2 * cc, ob, nob, lane);
-        const float4 v1 = *jet_frag(const_cast<float*>(zb_in), cb0 + 2 * cc + 1, ob, nob, lane);
-        const float f[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-        ao[i] = Pr::make(f);
-        bsum[i] += v0.x + v1.x;
-      }
+      const int ob = min(wo + WO * i, nob - 1);
+      const float4 v0 = *jet_frag(const_cast<float*>(zb_in), cb0 + 2 * cc, ob, nob, lane);
+      const float4 v1 = *jet_frag(const_cast<float*>(zb_in), cb0 + 2 * cc + 1, ob, nob, lane);
+      const float f[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+      ao[i] = Pr::make(f);
+      bsum[i] += v0.x + v1.x;
     }
 #pragma unroll
     for (int k = 0; k < NIBW; ++k) {
-      const int ib = wi + S::WI * k;
-      if (ib >= nib) continue;
-      const Raw bq = lds_unit(Q, 16 * ib + l16, 4 * cc + g, qs);
+      const Raw bq = lds_unit(Q, 16 * min(wi + S::WI * k, nib - 1) + l16, 4 * cc + g, qs);
 #pragma unroll
-      for (int i = 0; i < NOBW; ++i)
-        if (wo + WO * i < nob) Pr::mma(accw[i][k], ao[i], bq);
+      for (int i = 0; i < NOBW; ++i) Pr::mma(accw[i][k], ao[i], bq);
     }
   }
 }
