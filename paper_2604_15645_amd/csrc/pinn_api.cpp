@@ -117,8 +117,8 @@ int n_res_of(int pde_id) {
 
 // Forward tile size: the largest of the width bucket's default that fits the LDS budget.
 int default_fwd_p(int H) { return H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128; }
-int default_bwd_p(int H) { return H == 256 ? 16 : H == 128 ? 32 : H == 64 ? 64 : 128; }
-constexpr int kEmbedBwdP = 16;
+int default_bwd_p(int H) { return 2048 / H; }
+int embed_bwd_p(int H) { return H == 256 ? 8 : 16; }
 constexpr size_t kLdsBudget = 160 * 1024;
 
 size_t fwd_lds(int P, int kmax, int H) {
@@ -132,9 +132,11 @@ size_t fwd_lds(int P, int kmax, int H) {
   b += (size_t)WC * 3 * H * 8 + 3 * 8;           // WL, BL
   return b;
 }
-size_t bwd_lds(int PB, int n_in, int n_out, bool with_r) {
-  size_t b = (size_t)n_in * (4 * PB * 4 + 16);
-  if (with_r) b += (size_t)4 * PB * (n_out * 4 + 16);
+// Layer backward: staged output adjoint (and staged input pre-activations), Q tile, and
+// (hidden layers) R tile.
+size_t bwd_lds(int PB, int n_in, int n_out, bool with_prev) {
+  size_t b = (size_t)PB * n_out * 16 + (size_t)n_in * (4 * PB * 4 + 16);
+  if (with_prev) b += (size_t)PB * n_in * 16 + (size_t)4 * PB * (n_out * 4 + 16);
   return b;
 }
 
@@ -204,11 +206,11 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   p.pb = default_bwd_p(D.H);
   p.lds_f = fwd_lds(p.pf, p.kmax, D.H);
   p.lds_b = bwd_lds(p.pb, D.H, D.H, true);
-  p.lds_b0 = bwd_lds(kEmbedBwdP, 256, D.H, false);
+  p.lds_b0 = bwd_lds(embed_bwd_p(D.H), 256, D.H, false);
   if (p.lds_b > kLdsBudget || p.lds_b0 > kLdsBudget) return PINN_E_UNSUPPORTED;
   p.n_tiles = p.n_pad / p.pf;
   p.n_sub = p.n_pad / p.pb;
-  p.n_sub0 = p.n_pad / kEmbedBwdP;
+  p.n_sub0 = p.n_pad / embed_bwd_p(D.H);
   int cap = kGridCap;
   if (tune && tune->grid > 0) cap = tune->grid;
   p.grid_f = (int)std::min<int64_t>(p.n_tiles, cap);

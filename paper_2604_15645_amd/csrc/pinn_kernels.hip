@@ -33,6 +33,13 @@
 
 #include "pinn_internal.h"
 
+#ifndef PINN_R_PAIR
+#define PINN_R_PAIR 1
+#endif
+#ifndef PINN_PREFETCH_B
+#define PINN_PREFETCH_B 0
+#endif
+
 namespace pinn {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
@@ -93,6 +100,10 @@ struct Prec<kFP32> {
   static __device__ __forceinline__ void put4(char* unit, int pos0, f4 x) {
     *reinterpret_cast<float4*>(unit + 4 * pos0) = to_float4(x);
   }
+  // two consecutive elements at an even position
+  static __device__ __forceinline__ void put2(char* unit, int pos, float x, float y) {
+    *reinterpret_cast<float2*>(unit + 4 * pos) = make_float2(x, y);
+  }
 };
 
 __device__ __forceinline__ __bf16 bf16_rne(float x) { return (__bf16)x; }
@@ -147,6 +158,16 @@ struct Prec<kBF16X3> {
     reinterpret_cast<__bf16*>(unit)[pos] = h;
     reinterpret_cast<__bf16*>(unit + 16)[pos] = bf16_rne(x - (float)h);
   }
+  static __device__ __forceinline__ void put2(char* unit, int pos, float x, float y) {
+    typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+    bf16x2 h, l;
+    h[0] = bf16_rne(x);
+    h[1] = bf16_rne(y);
+    l[0] = bf16_rne(x - (float)h[0]);
+    l[1] = bf16_rne(y - (float)h[1]);
+    *reinterpret_cast<uint32_t*>(unit + 2 * pos) = __builtin_bit_cast(uint32_t, h);
+    *reinterpret_cast<uint32_t*>(unit + 16 + 2 * pos) = __builtin_bit_cast(uint32_t, l);
+  }
   static __device__ __forceinline__ void put4(char* unit, int pos0, f4 x) {
     bf16x4 h, l;
 #pragma unroll
@@ -159,6 +180,31 @@ struct Prec<kBF16X3> {
     *reinterpret_cast<uint2*>(unit + 16 + 2 * pos0) = __builtin_bit_cast(uint2, l);
   }
 };
+
+// Value of lane l ^ 1 (a data-parallel-primitive lane swap within each pair of lanes).
+__device__ __forceinline__ float swap_pair(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+}
+
+// Write the 4 channels of column n (rows base, base + rs, ... of an R-layout tile, unit of
+// column n already applied).  Lanes l and l ^ 1 hold neighbouring columns n (even) and
+// n + 1; after one exchange the even lane writes rows 0 and 1 and the odd lane rows 2 and
+// 3, two columns per write: half the LDS writes of one column per write.  Both lanes of
+// every pair must be active.
+template <int PREC>
+__device__ __forceinline__ void put_rows(char* base, int rs, int n, f4 a) {
+#if PINN_R_PAIR
+  const bool odd = n & 1;
+  const float r0 = swap_pair(odd ? a[0] : a[2]);
+  const float r1 = swap_pair(odd ? a[1] : a[3]);
+  const int row = odd ? 2 : 0, pos = n & 6;
+  Prec<PREC>::put2(base + (size_t)row * rs, pos, odd ? r0 : a[0], odd ? a[2] : r0);
+  Prec<PREC>::put2(base + (size_t)(row + 1) * rs, pos, odd ? r1 : a[1], odd ? a[3] : r1);
+#else
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Prec<PREC>::put(base + (size_t)r * rs, n & 7, a[r]);
+#endif
+}
 
 __device__ __forceinline__ Raw lds_unit(const char* base, int row, int unit, int stride) {
   const uint4* p = reinterpret_cast<const uint4*>(base + (size_t)row * stride + unit * 32);
@@ -209,14 +255,34 @@ __device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int 
   for (int i = 0; i < NB; ++i) fb[i] = frags + ((size_t)blk[i] * kchunks * 64 + lane) * 32;
   constexpr int CG = CB > 8 ? 8 : CB;  // A fragments live at a time
   static_assert(CB % CG == 0, "cp blocks per wave");
+  Raw bw[NB];
+#if PINN_PREFETCH_B
+  // weight fragments of chunk kc + 1 are loaded while chunk kc is multiplied
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const uint4* p = reinterpret_cast<const uint4*>(fb[i]);
+    bw[i].a = p[0];
+    bw[i].b = p[1];
+  }
+#endif
   for (int kc = 0; kc < kchunks; ++kc) {
-    Raw bw[NB];
+#if PINN_PREFETCH_B
+    Raw bn[NB];
+    const int kn = kc + 1 < kchunks ? kc + 1 : kc;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const uint4* p = reinterpret_cast<const uint4*>(fb[i] + (size_t)kn * 2048);
+      bn[i].a = p[0];
+      bn[i].b = p[1];
+    }
+#else
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const uint4* p = reinterpret_cast<const uint4*>(fb[i] + (size_t)kc * 2048);
       bw[i].a = p[0];
       bw[i].b = p[1];
     }
+#endif
 #pragma unroll
     for (int c0 = 0; c0 < CB; c0 += CG) {
       Raw a[CG];
@@ -238,6 +304,10 @@ __device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int 
 #pragma unroll
         for (int c = 0; c < CG; ++c) part[i][c0 + c] = sub[i][c];
     }
+#if PINN_PREFETCH_B
+#pragma unroll
+    for (int i = 0; i < NB; ++i) bw[i] = bn[i];
+#endif
   }
 }
 
@@ -678,11 +748,8 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       f4 cj, sj;
       rff_jets(net, s.PT[p], j, cj, sj);
       char* rowc = X + (size_t)(4 * p) * rs;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        Pr::put(rowc + (size_t)c * rs + (j >> 3) * 32, j & 7, cj[c]);
-        Pr::put(rowc + (size_t)c * rs + ((m + j) >> 3) * 32, (m + j) & 7, sj[c]);
-      }
+      put_rows<PREC>(rowc + (j >> 3) * 32, rs, j, cj);
+      put_rows<PREC>(rowc + ((m + j) >> 3) * 32, rs, m + j, sj);
     }
     __syncthreads();
 #pragma unroll
@@ -731,9 +798,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
           float s0, s1, s2, s3;
           act_eval<ACT>(acc[i][c].x, net.w0, s0, s1, s2, s3);
           const f4 a = jet_act(acc[i][c], s0, s1, s2, net.lapch, net.lap_mask);
-          char* base = X + (size_t)(16 * cb + 4 * g) * rs + (n >> 3) * 32;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) Pr::put(base + (size_t)r * rs, n & 7, a[r]);
+          put_rows<PREC>(X + (size_t)(16 * cb + 4 * g) * rs + (n >> 3) * 32, rs, n, a);
           __builtin_amdgcn_sched_barrier(0);
         }
       }
@@ -838,7 +903,6 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
   if (with_grad) {
     const int nL = lout.n_in;
     const int nbs = nL / 16;
-    float* zsl = zs + (L - 1) * zs_stride;
     if (tid < dout) {
       float t = 0.0f;
       for (int p = 0; p < P; ++p) t += s.YB[(p * 3 + tid) * 4];
@@ -852,11 +916,14 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       float wo[3], wsum[3] = {0.f, 0.f, 0.f};
 #pragma unroll
       for (int o = 0; o < 3; ++o) wo[o] = o < dout ? lout.w[o * nL + n] : 0.0f;
-#pragma unroll 1
+      // pre-activation jets of the last hidden layer: still in the accumulators when the
+      // tile is small, else read back from the stash (fewer live registers)
+      constexpr bool kLive = CBW <= 8;
+#pragma unroll(kLive ? CBW : 1)
       for (int c = 0; c < CBW; ++c) {
         const int cb = wc * CBW + c;
         const int p = 4 * cb + g;
-        const f4 z = to_f4(*jet_frag(zsl, cb_st + cb, nb, nbs, lane));
+        const f4 z = kLive ? acc[i][c] : to_f4(*jet_frag(zs + (L - 1) * zs_stride, cb_st + cb, nb, nbs, lane));
         float s0, s1, s2, s3;
         act_eval<ACT>(z.x, net.w0, s0, s1, s2, s3);
         const f4 a = jet_act(z, s0, s1, s2, net.lapch, net.lap_mask);
@@ -927,15 +994,53 @@ struct BwdShape {
   static_assert(CPB % 2 == 0 && CPB % WCA == 0, "sub-tile too small");
 };
 
-// One sub-tile of PB points of linear layer `layer`'s backward: the weight-gradient sums
-// (accw, bsum, kept by the caller across sub-tiles), and for layers with a predecessor
-// the input adjoint and activation adjoint (zb_out).  cb0: first cp block of the
-// sub-tile in the jet buffers; pts: the sub-tile's points (Fourier embedding only).
+// LDS regions of the layer backward for sub-tiles of PB points:
+//   ZB  staged adjoint fragments of the layer output (PB x n_out jets, fragment-major),
+//   ZP  staged pre-activation fragments of the layer input (PB x n_in), hidden layers only,
+//   Q   layer-input jets in the Q layout (B operand of the weight gradient),
+//   R   output adjoint in the R layout (A operand of the input adjoint), hidden layers only.
+struct BwdLds {
+  char *ZB, *ZP, *Q, *R;
+};
+
+__host__ __device__ constexpr size_t bwd_lds_bytes(int PB, int n_in, int n_out, bool with_prev) {
+  return (size_t)PB * n_out * 16 + (with_prev ? (size_t)PB * n_in * 16 : 0) + (size_t)n_in * q_stride(4 * PB) +
+         (with_prev ? (size_t)4 * PB * r_stride(n_out) : 0);
+}
+
+__device__ __forceinline__ BwdLds bwd_carve(char* smem, int PB, int n_in, int n_out, bool with_prev) {
+  BwdLds s;
+  s.ZB = smem;
+  s.ZP = s.ZB + (size_t)PB * n_out * 16;
+  s.Q = s.ZP + (with_prev ? (size_t)PB * n_in * 16 : 0);
+  s.R = s.Q + (size_t)n_in * q_stride(4 * PB);
+  return s;
+}
+
+// Start an asynchronous copy of `bytes` (a multiple of 1 KiB) contiguous bytes of device
+// memory into LDS: every wave moves 1 KiB per instruction, 16 bytes per lane landing at
+// consecutive LDS addresses.  Completion: s_waitcnt vmcnt(0), then a barrier.
+__device__ __forceinline__ void async_copy(char* dst, const char* src, int bytes) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int off = wave * 1024; off < bytes; off += kWaves * 1024)
+    __builtin_amdgcn_global_load_lds(src + off + lane * 16,
+                                     (__attribute__((address_space(3))) void*)(dst + off), 16, 0, 0);
+}
+
+__device__ __forceinline__ void wait_async() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Linear layer `layer`'s backward over `count` sub-tiles of PB points, sub-tile k being
+// number s0 + k * stride: weight-gradient sums (accw, bsum, kept by the caller), and for
+// layers with a predecessor the input adjoint and the activation adjoint (zb_out).  The
+// jets of sub-tile k + 1 are copied into LDS while sub-tile k is computed.  pts: points of
+// sub-tile 0 of the index space (Fourier embedding only).
 template <int PREC, int ACT, int NOB, int NIB, int PB>
-__device__ __forceinline__ void bwd_subtile(const NetDev& net, int layer, const float4* pts, int64_t cb0,
-                                            const float* zb_in, float* zb_out, const float* z_prev, char* smem,
-                                            f4 (&accw)[BwdShape<NOB, NIB, PB>::NOBW][BwdShape<NOB, NIB, PB>::NIBW],
-                                            float (&bsum)[BwdShape<NOB, NIB, PB>::NOBW]) {
+__device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const float4* pts, int64_t s0, int64_t stride,
+                                          int64_t count, const float* zb_in, float* zb_out, const float* z_prev,
+                                          char* smem,
+                                          f4 (&accw)[BwdShape<NOB, NIB, PB>::NOBW][BwdShape<NOB, NIB, PB>::NIBW],
+                                          float (&bsum)[BwdShape<NOB, NIB, PB>::NOBW]) {
   using S = BwdShape<NOB, NIB, PB>;
   using Pr = Prec<PREC>;
   constexpr int CPB = S::CPB, NOBW = S::NOBW, NIBW = S::NIBW, NIBA = S::NIBA, CBA = S::CBA;
@@ -946,95 +1051,112 @@ __device__ __forceinline__ void bwd_subtile(const NetDev& net, int layer, const 
   const int g = lane >> 4, l16 = lane & 15;
   const int n_in = ly.n_in, n_out = ly.n_out;
   const int nob = n_out / 16, nib = n_in / 16;
-  const int nbs_prev = n_in / 16;
   const bool has_prev = z_prev != nullptr;
   const int rs = r_stride(n_out);
   const int qs = q_stride(4 * PB);
-  char* Q = smem;                                   // layer-input jets, Q layout
-  char* R = smem + (size_t)n_in * qs;               // adjoint of z, R layout
+  const BwdLds L = bwd_carve(smem, PB, n_in, n_out, has_prev);
   const int wo = wave % WO, wi = wave / WO;
   const int wa = wave % WA, wca = wave / WA;
+  const int zb_bytes = CPB * nob * 1024, zp_bytes = CPB * nib * 1024;
+  auto zb_src = [&](int64_t s) { return reinterpret_cast<const char*>(zb_in) + s * zb_bytes; };
+  auto zp_src = [&](int64_t s) { return reinterpret_cast<const char*>(z_prev) + s * zp_bytes; };
+  auto frag = [&](const char* base, int cb, int nb, int nbs) {
+    return to_f4(*reinterpret_cast<const float4*>(base + ((size_t)(cb * nbs + nb) * 64 + lane) * 16));
+  };
 
+  if (count <= 0) return;
   __syncthreads();  // the previous user of the LDS is done
-  if (has_prev) {
-    // (1) adjoint of z (this layer's output) into the R layout
-    for (int f = wave; f < CPB * nob; f += kWaves) {
-      const int cb = f % CPB, ob = f / CPB;
-      const f4 zb = to_f4(*jet_frag(const_cast<float*>(zb_in), cb0 + cb, ob, nob, lane));
-      const int o = 16 * ob + l16;
-      char* base = R + (size_t)(16 * cb + 4 * g) * rs + (o >> 3) * 32;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Pr::put(base + (size_t)r * rs, o & 7, zb[r]);
-    }
-    __syncthreads();
-    // (2) adjoint of the layer input: abar[cp][i] = sum_o zbar[cp][o] W[o][i]
-    f4 acca[NIBA][CBA];
-#pragma unroll
-    for (int k = 0; k < NIBA; ++k)
-#pragma unroll
-      for (int c = 0; c < CBA; ++c) acca[k][c] = f4{0.f, 0.f, 0.f, 0.f};
-    {
-      int blk[NIBA];
-#pragma unroll
-      for (int k = 0; k < NIBA; ++k) blk[k] = min(wa + WA * k, nib - 1);
-      gemm_tile<PREC, NIBA, CBA>(acca, R, rs, wca * CBA, ly.wb, ly.kco, blk, lane);
-    }
-    // (3) one pass over the previous layer's pre-activations: recomputed activation jets
-    // into Q (operand of the weight gradient) and the activation adjoint
-#pragma unroll
-    for (int k = 0; k < NIBA; ++k) {
-      const int ib = wa + WA * k;
-      if (ib >= nib) continue;
-      const int n = 16 * ib + l16;
-#pragma unroll
-      for (int c = 0; c < CBA; ++c) {
-        const int cb = wca * CBA + c;
-        const f4 z = to_f4(*jet_frag(const_cast<float*>(z_prev), cb0 + cb, ib, nbs_prev, lane));
-        float s0, s1, s2, s3;
-        act_eval<ACT>(z.x, net.w0, s0, s1, s2, s3);
-        const f4 a = jet_act(z, s0, s1, s2, net.lapch, net.lap_mask);
-        int unit, pos0;
-        q_pos(cb, g, unit, pos0);
-        Pr::put4(Q + (size_t)n * qs + unit * 32, pos0, a);
-        const f4 zb = jet_act_adj(z, acca[k][c], s1, s2, s3, net.lapch, net.lap_mask);
-        *jet_frag(zb_out, cb0 + cb, ib, nbs_prev, lane) = to_float4(zb);
-        __builtin_amdgcn_sched_barrier(0);
+  async_copy(L.ZB, zb_src(s0), zb_bytes);
+  if (has_prev) async_copy(L.ZP, zp_src(s0), zp_bytes);
+
+  for (int64_t k = 0; k < count; ++k) {
+    const int64_t s = s0 + k * stride;
+    wait_async();
+    __syncthreads();  // sub-tile s is in ZB / ZP; the previous sub-tile is done with R and Q
+    // (1) output adjoint: R layout for the input adjoint, A operands of the weight gradient
+    if (has_prev) {
+      for (int f = wave; f < CPB * nob; f += kWaves) {
+        const int cb = f % CPB, ob = f / CPB;
+        const f4 zb = frag(L.ZB, cb, ob, nob);
+        const int o = 16 * ob + l16;
+        put_rows<PREC>(L.R + (size_t)(16 * cb + 4 * g) * rs + (o >> 3) * 32, rs, o, zb);
       }
     }
-  } else {
-    // Fourier-feature embedding of the sub-tile's points into Q
-    const int m = net.n_freq;
-    for (int idx = tid; idx < PB * m; idx += kThreads) {
-      const int p = idx / m, j = idx - (idx / m) * m;
-      f4 cj, sj;
-      rff_jets(net, pts[p], j, cj, sj);
-      const int cb = p >> 2, gg = p & 3;
-      int unit, pos0;
-      q_pos(cb, gg, unit, pos0);
-      Pr::put4(Q + (size_t)j * qs + unit * 32, pos0, cj);
-      Pr::put4(Q + (size_t)(m + j) * qs + unit * 32, pos0, sj);
-    }
-  }
-  __syncthreads();  // Q complete
-  // (4) weight gradient: W_bar[o][i] += sum_cp zbar[cp][o] a[cp][i]
-  // Out-of-range blocks are clamped to the last valid one; their sums are never stored.
-  for (int cc = 0; cc < CPB / 2; ++cc) {
-    Raw ao[NOBW];
+    Raw ao[CPB / 2][NOBW];
 #pragma unroll
-    for (int i = 0; i < NOBW; ++i) {
-      const int ob = min(wo + WO * i, nob - 1);
-      const float4 v0 = *jet_frag(const_cast<float*>(zb_in), cb0 + 2 * cc, ob, nob, lane);
-      const float4 v1 = *jet_frag(const_cast<float*>(zb_in), cb0 + 2 * cc + 1, ob, nob, lane);
-      const float f[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-      ao[i] = Pr::make(f);
-      bsum[i] += v0.x + v1.x;
-    }
+    for (int cc = 0; cc < CPB / 2; ++cc)
 #pragma unroll
-    for (int k = 0; k < NIBW; ++k) {
-      const Raw bq = lds_unit(Q, 16 * min(wi + S::WI * k, nib - 1) + l16, 4 * cc + g, qs);
+      for (int i = 0; i < NOBW; ++i) {
+        const int ob = min(wo + WO * i, nob - 1);  // clamped duplicates are never stored
+        const f4 v0 = frag(L.ZB, 2 * cc, ob, nob), v1 = frag(L.ZB, 2 * cc + 1, ob, nob);
+        const float f[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        ao[cc][i] = Pr::make(f);
+        bsum[i] += v0.x + v1.x;
+      }
+    __syncthreads();  // R complete; ZB no longer read
+    if (k + 1 < count) async_copy(L.ZB, zb_src(s + stride), zb_bytes);
+    const int64_t cb0 = s * CPB;
+    if (has_prev) {
+      // (2) adjoint of the layer input: abar[cp][i] = sum_o zbar[cp][o] W[o][i]
+      f4 acca[NIBA][CBA];
 #pragma unroll
-      for (int i = 0; i < NOBW; ++i) Pr::mma(accw[i][k], ao[i], bq);
+      for (int q = 0; q < NIBA; ++q)
+#pragma unroll
+        for (int c = 0; c < CBA; ++c) acca[q][c] = f4{0.f, 0.f, 0.f, 0.f};
+      {
+        int blk[NIBA];
+#pragma unroll
+        for (int q = 0; q < NIBA; ++q) blk[q] = min(wa + WA * q, nib - 1);
+        gemm_tile<PREC, NIBA, CBA>(acca, L.R, rs, wca * CBA, ly.wb, ly.kco, blk, lane);
+      }
+      // (3) one pass over the layer input's pre-activations: recomputed activation jets
+      // into Q (operand of the weight gradient) and the activation adjoint
+#pragma unroll
+      for (int q = 0; q < NIBA; ++q) {
+        const int ib = wa + WA * q;
+        if (ib >= nib) continue;
+        const int n = 16 * ib + l16;
+#pragma unroll
+        for (int c = 0; c < CBA; ++c) {
+          const int cb = wca * CBA + c;
+          const f4 z = frag(L.ZP, cb, ib, nib);
+          float s0v, s1v, s2v, s3v;
+          act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
+          const f4 a = jet_act(z, s0v, s1v, s2v, net.lapch, net.lap_mask);
+          int unit, pos0;
+          q_pos(cb, g, unit, pos0);
+          Pr::put4(L.Q + (size_t)n * qs + unit * 32, pos0, a);
+          const f4 zb = jet_act_adj(z, acca[q][c], s1v, s2v, s3v, net.lapch, net.lap_mask);
+          *jet_frag(zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    } else {
+      // Fourier-feature embedding of the sub-tile's points into Q
+      const int m = net.n_freq;
+      const float4* sp = pts + s * PB;
+      for (int idx = tid; idx < PB * m; idx += kThreads) {
+        const int p = idx / m, j = idx - (idx / m) * m;
+        f4 cj, sj;
+        rff_jets(net, sp[p], j, cj, sj);
+        const int cb = p >> 2, gg = p & 3;
+        int unit, pos0;
+        q_pos(cb, gg, unit, pos0);
+        Pr::put4(L.Q + (size_t)j * qs + unit * 32, pos0, cj);
+        Pr::put4(L.Q + (size_t)(m + j) * qs + unit * 32, pos0, sj);
+      }
     }
+    __syncthreads();  // Q complete; ZP no longer read
+    if (has_prev && k + 1 < count) async_copy(L.ZP, zp_src(s + stride), zp_bytes);
+    // (4) weight gradient: W_bar[o][i] += sum_cp zbar[cp][o] a[cp][i]
+#pragma unroll
+    for (int cc = 0; cc < CPB / 2; ++cc)
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q) {
+        const Raw bq = lds_unit(L.Q, 16 * min(wi + S::WI * q, nib - 1) + l16, 4 * cc + g, qs);
+#pragma unroll
+        for (int i = 0; i < NOBW; ++i) Pr::mma(accw[i][q], ao[cc][i], bq);
+      }
   }
 }
 
@@ -1082,9 +1204,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
   float bsum[S::NOBW];
 #pragma unroll
   for (int i = 0; i < S::NOBW; ++i) bsum[i] = 0.f;
-  for (int64_t sub = blockIdx.x; sub < A.n_sub; sub += gridDim.x)
-    bwd_subtile<PREC, ACT, NOB, NIB, PB>(A.net, A.layer, A.work.pts + sub * PB, sub * S::CPB, A.zb_in, A.zb_out,
-                                         A.z_prev, smem, accw, bsum);
+  const int64_t count = A.n_sub > blockIdx.x ? (A.n_sub - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+  bwd_range<PREC, ACT, NOB, NIB, PB>(A.net, A.layer, A.work.pts, blockIdx.x, gridDim.x, count, A.zb_in, A.zb_out,
+                                     A.z_prev, smem, accw, bsum);
   const LayerDev& ly = A.net.layer[A.layer];
   bwd_flush<NOB, NIB, PB>(accw, bsum, A.slots + (size_t)blockIdx.x * ly.n_out * (ly.n_in + 1), ly.n_out, ly.n_in);
 }
@@ -1150,7 +1272,7 @@ template <int PREC, int ACT, int H>
 __device__ __forceinline__ void run_item(const BatchArgs& A, const BatchInst& in, const BatchItem& it, int64_t item,
                                          char* smem) {
   constexpr int PF = H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128;
-  constexpr int PB = H == 256 ? 16 : H == 128 ? 32 : H == 64 ? 64 : 128;
+  constexpr int PB = 2048 / H;
   const NetDev& net = in.net;
   float* scratch = A.scratch + (size_t)blockIdx.x * A.scratch_per_wg;
   float* zs = scratch;
@@ -1193,9 +1315,8 @@ __device__ __forceinline__ void run_item(const BatchArgs& A, const BatchInst& in
     float bsum[S::NOBW];
 #pragma unroll
     for (int i = 0; i < S::NOBW; ++i) bsum[i] = 0.f;
-    for (int64_t sub = 0; sub < npts / PB; ++sub)
-      bwd_subtile<PREC, ACT, H / 16, H / 16, PB>(net, j, pts + sub * PB, sub * S::CPB, zb[cur], zb[cur ^ 1],
-                                                 zs + (j - 1) * in.zs_stride, smem, accw, bsum);
+    bwd_range<PREC, ACT, H / 16, H / 16, PB>(net, j, pts, 0, 1, npts / PB, zb[cur], zb[cur ^ 1],
+                                             zs + (j - 1) * in.zs_stride, smem, accw, bsum);
     bwd_flush<H / 16, H / 16, PB>(accw, bsum, gslot + in.eff_off[j], net.layer[j].n_out, net.layer[j].n_in);
     cur ^= 1;
   }
@@ -1379,8 +1500,8 @@ int bwd(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
 
 template <int PREC, int ACT, int H>
 int bwd_e(bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  constexpr int PB = H == 256 ? 16 : H == 128 ? 32 : H == 64 ? 64 : 128;
-  if (embed) return bwd<PREC, ACT, H / 16, 16, 16>(a, grid, lds, s);
+  constexpr int PB = 2048 / H;
+  if (embed) return bwd<PREC, ACT, H / 16, 16, H == 256 ? 8 : 16>(a, grid, lds, s);
   return bwd<PREC, ACT, H / 16, H / 16, PB>(a, grid, lds, s);
 }
 
@@ -1444,12 +1565,12 @@ int launch_zero_int(int* p, hipStream_t s) {
 
 size_t batched_lds(int kmax, int H) {
   const int PF = H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128;
-  const int PB = H == 256 ? 16 : H == 128 ? 32 : H == 64 ? 64 : 128;
+  const int PB = 2048 / H;
   const int WN = H / 16 < kWaves ? H / 16 : kWaves;
   const int WC = kWaves / WN;
   size_t f = (size_t)4 * PF * r_stride(kmax) + (size_t)PF * 16 + (size_t)PF * 12 * 4 * 2 + kWaves * 4 * 4 +
              kMaxTerms * 8 + (size_t)WC * 3 * H * 8 + 3 * 8;
-  size_t b = (size_t)H * q_stride(4 * PB) + (size_t)4 * PB * r_stride(H);
+  size_t b = bwd_lds_bytes(PB, H, H, true);
   size_t g = (size_t)kWaves * 256 * 4 * sizeof(float);
   size_t m = f > b ? f : b;
   return m > g ? m : g;
