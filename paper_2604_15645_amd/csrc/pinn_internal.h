@@ -14,6 +14,8 @@ constexpr int kMaxAnchors = 8;
 constexpr int kMaxTerms = 3 + kMaxAnchors;
 constexpr int kSegAlign = 128;  // every point segment starts at a multiple of this
 constexpr int kWaves = 8;
+constexpr int kRedThreads = 1024;  // reduction blocks: kRedGroups slot groups x 256 columns
+constexpr int kRedGroups = 4;
 constexpr int kThreads = 64 * kWaves;
 
 enum { kFP32 = 0, kBF16X3 = 1 };

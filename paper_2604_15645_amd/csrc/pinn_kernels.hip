@@ -1355,39 +1355,65 @@ __global__ __launch_bounds__(kThreads, 1) void k_batched(const BatchArgs A) {
 // dL/ds_o = sum_i W_oi dL/dW_oi (Sec. 2.6.2).
 
 __device__ __forceinline__ void reduce_row(const ReduceArgs& A, int o) {
-  double es = 1.0;
-  if (A.rwf) es = exp((double)A.params[A.off_s + o]);
+  // kRedThreads threads: kRedGroups groups of consecutive slots x kRedCols columns.  Each
+  // thread sums its group's slots in slot order, the groups are then added in group
+  // order: a fixed order, independent of timing.  Column n_in is the bias.
+  constexpr int NC = kRedThreads / kRedGroups;
+  __shared__ double part[kRedThreads];
+  __shared__ double red[NC];
+  const int tid = threadIdx.x, grp = tid / NC, col0 = tid % NC;
+  const int per = (A.n_slots + kRedGroups - 1) / kRedGroups;
+  const int s_lo = grp * per, s_hi = min(A.n_slots, s_lo + per);
+  const double es = A.rwf ? exp((double)A.params[A.off_s + o]) : 1.0;
   double ssum = 0.0;
-  for (int i = threadIdx.x; i < A.n_in; i += blockDim.x) {
+  for (int c0 = 0; c0 <= A.n_in; c0 += NC) {
+    const int col = c0 + col0;
     double t = 0.0;
-    for (int sl = 0; sl < A.n_slots; ++sl) t += A.slots[sl * A.slot_stride + (int64_t)o * A.n_in + i];
-    const double v = (double)A.params[A.off_w + (int64_t)o * A.n_in + i];
-    A.grad[A.off_w + (int64_t)o * A.n_in + i] = es * t;
-    ssum += t * es * v;
-  }
-  __shared__ double red[256];
-  red[threadIdx.x] = ssum;
-  __syncthreads();
-  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    if (col <= A.n_in) {
+      const double* p = A.slots + (col < A.n_in ? (int64_t)o * A.n_in + col : (int64_t)A.n_out * A.n_in + o);
+      int sl = s_lo;
+      for (; sl + 4 <= s_hi; sl += 4) {
+        const double v0 = p[sl * A.slot_stride], v1 = p[(sl + 1) * A.slot_stride];
+        const double v2 = p[(sl + 2) * A.slot_stride], v3 = p[(sl + 3) * A.slot_stride];
+        t += v0;
+        t += v1;
+        t += v2;
+        t += v3;
+      }
+      for (; sl < s_hi; ++sl) t += p[sl * A.slot_stride];
+    }
+    part[tid] = t;
+    __syncthreads();
+    if (grp == 0 && col <= A.n_in) {
+      double s = 0.0;
+      for (int q = 0; q < kRedGroups; ++q) s += part[q * NC + col0];
+      if (col < A.n_in) {
+        const double v = (double)A.params[A.off_w + (int64_t)o * A.n_in + col];
+        A.grad[A.off_w + (int64_t)o * A.n_in + col] = es * s;
+        ssum += s * es * v;
+      } else if (A.has_bias) {
+        A.grad[A.off_b + o] = s;
+      }
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    if (A.rwf) A.grad[A.off_s + o] = red[0];
-    if (A.has_bias) {
-      double t = 0.0;
-      for (int sl = 0; sl < A.n_slots; ++sl) t += A.slots[sl * A.slot_stride + (int64_t)A.n_out * A.n_in + o];
-      A.grad[A.off_b + o] = t;
+  if (A.rwf) {  // s_bar[o] = sum_i W[o][i] W_bar[o][i], fixed tree over the columns
+    if (grp == 0) red[col0] = ssum;
+    __syncthreads();
+    for (int st = NC / 2; st > 0; st >>= 1) {
+      if (tid < st) red[tid] += red[tid + st];
+      __syncthreads();
     }
+    if (tid == 0) A.grad[A.off_s + o] = red[0];
   }
 }
 
-__global__ void k_reduce_layer(const ReduceArgs A) {
+__global__ __launch_bounds__(kRedThreads) void k_reduce_layer(const ReduceArgs A) {
   if ((int)blockIdx.x < A.n_out) reduce_row(A, blockIdx.x);
 }
 
 // Per-instance reductions of the item slots: one block per (instance, layer, output row).
-__global__ void k_reduce_batched(const BatchReduceArgs A) {
+__global__ __launch_bounds__(kRedThreads) void k_reduce_batched(const BatchReduceArgs A) {
   const int64_t r = blockIdx.x;
   int lo = 0, hi = A.n_entries - 1;
   while (lo < hi) {  // last entry with row0 <= r
@@ -1411,33 +1437,56 @@ __global__ void k_reduce_batched(const BatchReduceArgs A) {
   reduce_row(a, (int)(r - e.row0));
 }
 
+// Loss terms of one instance per block: item partial sums added in item order by one
+// thread per term (an instance has at most a few hundred items).
 __global__ void k_reduce_loss_batched(const BatchLossArgs A) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.n_inst) return;
-  double total = 0.0;
-  for (int k = 0; k < A.n_res; ++k) {
+  const int i = blockIdx.x;
+  __shared__ double term[3];
+  const int k = threadIdx.x;
+  if (k < A.n_res) {
     double t = 0.0;
-    for (int s = 0; s < A.n_items[i]; ++s) t += A.loss_slots[(size_t)(A.item0[i] + s) * kMaxTerms + k];
+    const double* p = A.loss_slots + (size_t)A.item0[i] * kMaxTerms + k;
+    for (int s = 0; s < A.n_items[i]; ++s) t += p[(size_t)s * kMaxTerms];
     t *= A.w_res[i * 3 + k];
     A.losses[(size_t)i * (1 + A.n_res) + 1 + k] = t;
-    total += t;
+    term[k] = t;
   }
-  A.losses[(size_t)i * (1 + A.n_res)] = total;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double total = 0.0;
+    for (int q = 0; q < A.n_res; ++q) total += term[q];
+    A.losses[(size_t)i * (1 + A.n_res)] = total;
+  }
 }
 
 __global__ void k_zero_int(int* p) { *p = 0; }
 
-__global__ void k_reduce_loss(const LossArgs A) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double total = 0.0;
-  for (int k = 0; k < A.n_res + A.n_anchor; ++k) {
+// Loss terms: thread s sums slots s, s + 256, ... (in that order), then a fixed tree over
+// the 256 threads per term.
+__global__ __launch_bounds__(256) void k_reduce_loss(const LossArgs A) {
+  __shared__ double red[kMaxTerms][256];
+  const int tid = threadIdx.x;
+  const int nt = A.n_res + A.n_anchor;
+  for (int k = 0; k < nt; ++k) {
     double t = 0.0;
-    for (int sl = 0; sl < A.n_slots; ++sl) t += A.slots[(size_t)sl * kMaxTerms + k];
-    t *= k < A.n_res ? A.w_res[k] : A.w_anchor[k - A.n_res];
-    A.loss[1 + k] = t;
-    total += t;
+    for (int sl = tid; sl < A.n_slots; sl += 256) t += A.slots[(size_t)sl * kMaxTerms + k];
+    red[k][tid] = t;
   }
-  A.loss[0] = total;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st)
+      for (int k = 0; k < nt; ++k) red[k][tid] += red[k][tid + st];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double total = 0.0;
+    for (int k = 0; k < nt; ++k) {
+      const double t = red[k][0] * (k < A.n_res ? A.w_res[k] : A.w_anchor[k - A.n_res]);
+      A.loss[1 + k] = t;
+      total += t;
+    }
+    A.loss[0] = total;
+  }
 }
 
 // NaN / Inf scan of the parameters (opt-in check).
@@ -1598,22 +1647,22 @@ int launch_batched(int prec, int act, const BatchArgs& a, int grid, size_t lds, 
 }
 
 int launch_reduce_batched(const BatchReduceArgs& a, hipStream_t s) {
-  if (a.n_rows > 0) hipLaunchKernelGGL(k_reduce_batched, dim3((unsigned)a.n_rows), dim3(256), 0, s, a);
+  if (a.n_rows > 0) hipLaunchKernelGGL(k_reduce_batched, dim3((unsigned)a.n_rows), dim3(kRedThreads), 0, s, a);
   return status(hipGetLastError());
 }
 
 int launch_reduce_loss_batched(const BatchLossArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_loss_batched, dim3((a.n_inst + 63) / 64), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_reduce_loss_batched, dim3(a.n_inst), dim3(64), 0, s, a);
   return status(hipGetLastError());
 }
 
 int launch_reduce_layer(const ReduceArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_layer, dim3(a.n_out), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_reduce_layer, dim3(a.n_out), dim3(kRedThreads), 0, s, a);
   return status(hipGetLastError());
 }
 
 int launch_reduce_loss(const LossArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(256), 0, s, a);
   return status(hipGetLastError());
 }
 
