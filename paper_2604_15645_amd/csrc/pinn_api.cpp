@@ -116,6 +116,9 @@ int n_res_of(int pde_id) {
 }
 
 // Forward tile size: the largest of the width bucket's default that fits the LDS budget.
+// Kernel activation code: the activation, plus kLapFlag when jet channel 3 carries a Laplacian.
+int act_code(const pinn_net* net, const pinn_pde* pde) { return net->act | (pde->lap_mask ? kLapFlag : 0); }
+
 int default_fwd_p(int H) { return H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128; }
 int default_bwd_p(int H) { return 2048 / H; }
 int embed_bwd_p(int H) { return H == 256 ? 8 : 16; }
@@ -429,7 +432,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     a.kmax = p.kmax;
     a.with_grad = p.with_grad;
     a.residual = residual;
-    rc = timed("k_forward", stream, [&] { return launch_forward(prec, net->act, D.H, p.pf, a, p.grid_f, p.lds_f, stream); });
+    rc = timed("k_forward", stream, [&] { return launch_forward(prec, act_code(net, pde), D.H, p.pf, a, p.grid_f, p.lds_f, stream); });
     if (rc) return rc;
   }
   int cur = 0;
@@ -445,7 +448,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.zb_out = wk.zb[cur ^ 1];
       a.z_prev = wk.zs0 + (j - 1) * wk.zs_stride;
       a.slots = wk.layer_slots[j];
-      rc = timed("k_backward", stream, [&] { return launch_backward(prec, net->act, D.H, false, a, p.grid_b, p.lds_b, stream); });
+      rc = timed("k_backward", stream, [&] { return launch_backward(prec, act_code(net, pde), D.H, false, a, p.grid_b, p.lds_b, stream); });
       if (rc) return rc;
       cur ^= 1;
     }
@@ -460,7 +463,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.zb_out = nullptr;
       a.z_prev = nullptr;
       a.slots = wk.layer_slots[0];
-      rc = timed("k_backward_embed", stream, [&] { return launch_backward(prec, net->act, D.H, true, a, p.grid_b0, p.lds_b0, stream); });
+      rc = timed("k_backward_embed", stream, [&] { return launch_backward(prec, act_code(net, pde), D.H, true, a, p.grid_b0, p.lds_b0, stream); });
       if (rc) return rc;
     } else {
       Grad0Args a;
@@ -805,7 +808,7 @@ int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* p
   ba.loss_slots = reinterpret_cast<double*>(ws + b.o_loss);
   ba.grad_slots = reinterpret_cast<double*>(ws + b.o_grad);
   for (int k = 0; k < 3; ++k) ba.lambda_res[k] = (float)pde->lambda_res[k];
-  rc = timed("k_batched", stream, [&] { return launch_batched(prec, b.act, ba, b.grid, b.lds, stream); });
+  rc = timed("k_batched", stream, [&] { return launch_batched(prec, b.act | (pde->lap_mask ? kLapFlag : 0), ba, b.grid, b.lds, stream); });
   if (rc) return rc;
   BatchReduceArgs ra;
   ra.rows = reinterpret_cast<const BatchRow*>(dev(hrows));

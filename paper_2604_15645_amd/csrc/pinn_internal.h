@@ -20,6 +20,8 @@ constexpr int kThreads = 64 * kWaves;
 
 enum { kFP32 = 0, kBF16X3 = 1 };
 enum { kTanh = 0, kSin = 1 };
+// Kernel activation code: kTanh or kSin, plus kLapFlag when jet channel 3 is a Laplacian.
+enum { kLapFlag = 2 };
 enum { kBurgers = 1, kEuler1D = 2, kNS2D = 3, kMaxwell = 4 };
 
 // One linear layer as the kernels see it (all pointers into the workspace).

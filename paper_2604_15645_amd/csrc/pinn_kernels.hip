@@ -108,6 +108,22 @@ struct Prec<kFP32> {
 
 __device__ __forceinline__ __bf16 bf16_rne(float x) { return (__bf16)x; }
 
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+
+// x = hi + lo, hi = bf16(x), lo = bf16(x - hi), for two values at once: one packed
+// conversion per part, the hi parts widened back by shifts.
+__device__ __forceinline__ void split2(float x, float y, uint32_t& h, uint32_t& l) {
+  bf16x2 hv;
+  hv[0] = bf16_rne(x);
+  hv[1] = bf16_rne(y);
+  h = __builtin_bit_cast(uint32_t, hv);
+  const float xh = __uint_as_float(h << 16), yh = __uint_as_float(h & 0xffff0000u);
+  bf16x2 lv;
+  lv[0] = bf16_rne(x - xh);
+  lv[1] = bf16_rne(y - yh);
+  l = __builtin_bit_cast(uint32_t, lv);
+}
+
 template <>
 struct Prec<kBF16X3> {
   static __device__ __forceinline__ void mma(f4& acc, const Raw& x, const Raw& y) {
@@ -141,16 +157,12 @@ struct Prec<kBF16X3> {
                                                             __builtin_bit_cast(bf16x8, b[i].a), acc[i][c], 0, 0, 0);
   }
   static __device__ __forceinline__ Raw make(const float (&f)[8]) {
-    bf16x8 h, l;
+    uint32_t h[4], l[4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      __bf16 hj = bf16_rne(f[j]);
-      h[j] = hj;
-      l[j] = bf16_rne(f[j] - (float)hj);
-    }
+    for (int j = 0; j < 4; ++j) split2(f[2 * j], f[2 * j + 1], h[j], l[j]);
     Raw r;
-    r.a = __builtin_bit_cast(uint4, h);
-    r.b = __builtin_bit_cast(uint4, l);
+    r.a = make_uint4(h[0], h[1], h[2], h[3]);
+    r.b = make_uint4(l[0], l[1], l[2], l[3]);
     return r;
   }
   static __device__ __forceinline__ void put(char* unit, int pos, float x) {
@@ -159,25 +171,17 @@ struct Prec<kBF16X3> {
     reinterpret_cast<__bf16*>(unit + 16)[pos] = bf16_rne(x - (float)h);
   }
   static __device__ __forceinline__ void put2(char* unit, int pos, float x, float y) {
-    typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
-    bf16x2 h, l;
-    h[0] = bf16_rne(x);
-    h[1] = bf16_rne(y);
-    l[0] = bf16_rne(x - (float)h[0]);
-    l[1] = bf16_rne(y - (float)h[1]);
-    *reinterpret_cast<uint32_t*>(unit + 2 * pos) = __builtin_bit_cast(uint32_t, h);
-    *reinterpret_cast<uint32_t*>(unit + 16 + 2 * pos) = __builtin_bit_cast(uint32_t, l);
+    uint32_t h, l;
+    split2(x, y, h, l);
+    *reinterpret_cast<uint32_t*>(unit + 2 * pos) = h;
+    *reinterpret_cast<uint32_t*>(unit + 16 + 2 * pos) = l;
   }
   static __device__ __forceinline__ void put4(char* unit, int pos0, f4 x) {
-    bf16x4 h, l;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      __bf16 hj = bf16_rne(x[j]);
-      h[j] = hj;
-      l[j] = bf16_rne(x[j] - (float)hj);
-    }
-    *reinterpret_cast<uint2*>(unit + 2 * pos0) = __builtin_bit_cast(uint2, h);
-    *reinterpret_cast<uint2*>(unit + 16 + 2 * pos0) = __builtin_bit_cast(uint2, l);
+    uint32_t h0, l0, h1, l1;
+    split2(x[0], x[1], h0, l0);
+    split2(x[2], x[3], h1, l1);
+    *reinterpret_cast<uint2*>(unit + 2 * pos0) = make_uint2(h0, h1);
+    *reinterpret_cast<uint2*>(unit + 16 + 2 * pos0) = make_uint2(l0, l1);
   }
 };
 
@@ -214,6 +218,80 @@ __device__ __forceinline__ Raw lds_unit(const char* base, int row, int unit, int
   return r;
 }
 
+// Row strides of the two LDS tile layouts (bytes).  "R": rows cp, units over neurons.
+// "Q": rows neurons, units over cp in the order of the product accumulators.
+__host__ __device__ constexpr int r_stride(int width) { return width * 4 + 16; }
+__host__ __device__ constexpr int q_stride(int cp) { return cp * 4 + 16; }
+
+// ------------------------------------------------------------------ A-operand jet tiles
+// A tile holds the jets of P points x K neurons as the A operand of a product (rows
+// cp = 4 point + channel, reduction over neurons).  `ld` is the layout's leading size.
+//   FP32   "R" layout: rows cp (ld = row stride in bytes), 32-byte units of 8 neurons; a
+//          fragment is one unit.
+//   BF16X3 "T" layout: the 4 channels of a (point, neuron) are 4 consecutive bf16, hi and lo
+//          parts in two 1 KiB cells per 4 points x 32 neurons, cells ordered by neuron
+//          chunk then point group (ld = point groups of 4 in the tile).
+//          Stored with one 8-byte write per part; a fragment is 4 transposing LDS reads
+//          (ds_read_b64_tr_b16: within each 16-lane group, lane 4q + j receives element j of
+//          the 8 bytes read by lanes q, q + 4, q + 8 and q + 12).  The in-cell swizzle
+//          keeps both the writes of an accumulator block and the fragment reads free of
+//          bank conflicts per half wave.
+template <int PREC>
+struct Tile;
+
+template <>
+struct Tile<kFP32> {
+  static __device__ __forceinline__ int ld(int kmax, int P) { return r_stride(kmax); }
+  static __device__ __forceinline__ void put(char* X, int ld, int p, int n, f4 a) {
+    put_rows<kFP32>(X + (size_t)(4 * p) * ld + (n >> 3) * 32, ld, n, a);
+  }
+  static __device__ __forceinline__ Raw load(const char* X, int ld, int cb, int kc, int lane) {
+    return lds_unit(X, 16 * cb + (lane & 15), 4 * kc + (lane >> 4), ld);
+  }
+};
+
+// Byte offset of (point p mod 4, neuron n mod 32) inside a T-layout cell.
+__device__ __forceinline__ int t_cell_off(int p, int n) {
+  const int p0 = p & 1, p1 = (p >> 1) & 1;
+  const int n0 = n & 1, n1 = (n >> 1) & 1, n2 = (n >> 2) & 1, n3 = (n >> 3) & 1, n4 = (n >> 4) & 1;
+  const int slot = p0 | (n0 << 1) | (n1 << 2) | (n3 << 3) | ((n2 ^ p1) << 4);
+  return ((n4 << 1) | p1) * 256 + slot * 8;
+}
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint2 lds_tr16(const char* p) {
+  const v4s v = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (__attribute__((address_space(3))) v4s*)(const_cast<char*>(p)));
+  return __builtin_bit_cast(uint2, v);
+}
+
+template <>
+struct Tile<kBF16X3> {
+  static __device__ __forceinline__ int ld(int kmax, int P) { return P >> 2; }
+  static __device__ __forceinline__ char* cell(char* X, int ld, int pg, int nc) {
+    return X + (size_t)(nc * ld + pg) * 2048;
+  }
+  static __device__ __forceinline__ void put(char* X, int ld, int p, int n, f4 a) {
+    uint32_t h0, l0, h1, l1;
+    split2(a[0], a[1], h0, l0);
+    split2(a[2], a[3], h1, l1);
+    char* q = cell(X, ld, p >> 2, n >> 5) + t_cell_off(p, n);
+    *reinterpret_cast<uint2*>(q) = make_uint2(h0, h1);
+    *reinterpret_cast<uint2*>(q + 1024) = make_uint2(l0, l1);
+  }
+  static __device__ __forceinline__ Raw load(const char* X, int ld, int cb, int kc, int lane) {
+    const int g = lane >> 4, s = lane & 15;
+    const char* c = X + (size_t)(kc * ld + cb) * 2048;
+    const int o0 = t_cell_off(s, 8 * g + (s >> 2)), o1 = t_cell_off(s, 8 * g + 4 + (s >> 2));
+    const uint2 h0 = lds_tr16(c + o0), h1 = lds_tr16(c + o1);
+    const uint2 l0 = lds_tr16(c + 1024 + o0), l1 = lds_tr16(c + 1024 + o1);
+    Raw r;
+    r.a = make_uint4(h0.x, h0.y, h1.x, h1.y);
+    r.b = make_uint4(l0.x, l0.y, l1.x, l1.y);
+    return r;
+  }
+};
+
 __device__ __forceinline__ Raw glob_frag(const char* frags, int blk, int chunk, int nchunk, int lane) {
   const uint4* p = reinterpret_cast<const uint4*>(frags + (((size_t)blk * nchunk + chunk) * 64 + lane) * 32);
   Raw r;
@@ -222,10 +300,6 @@ __device__ __forceinline__ Raw glob_frag(const char* frags, int blk, int chunk, 
   return r;
 }
 
-// Row strides of the two LDS tile layouts (bytes).  "R": rows cp, units over neurons.
-// "Q": rows neurons, units over cp in the order of the product accumulators.
-__host__ __device__ constexpr int r_stride(int width) { return width * 4 + 16; }
-__host__ __device__ constexpr int q_stride(int cp) { return cp * 4 + 16; }
 
 // Q-layout position of a cp row inside its 32-row chunk: the accumulator of cp block cb,
 // lane group g, register r sits at 8 g + 4 (cb % 2) + r.
@@ -241,15 +315,14 @@ __device__ __forceinline__ float4* jet_frag(float* buf, int64_t cb, int nb, int 
 }
 
 // acc[i][c] += A(cp block cb0 + c) * W(block blk[i])^T over all reduction chunks: the A
-// operand comes from an R-layout tile in LDS, the B operand from fragment-major weights.
+// operand comes from a jet tile in LDS (Tile<PREC>), the B operand from fragment-major
+// weights.
 // Every block index must be valid (callers clamp them; results of clamped duplicates are
 // discarded), so the loop body has no branches and the products of one chunk issue back
 // to back over independent accumulators.
 template <int PREC, int NB, int CB>
-__device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int rs, int cb0,
+__device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int ld, int cb0,
                                           const char* frags, int kchunks, const int (&blk)[NB], int lane) {
-  const int g = lane >> 4, l16 = lane & 15;
-  const char* xa = X + (size_t)(16 * cb0 + l16) * rs + g * 32;
   const char* fb[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) fb[i] = frags + ((size_t)blk[i] * kchunks * 64 + lane) * 32;
@@ -287,11 +360,7 @@ __device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int 
     for (int c0 = 0; c0 < CB; c0 += CG) {
       Raw a[CG];
 #pragma unroll
-      for (int c = 0; c < CG; ++c) {
-        const uint4* p = reinterpret_cast<const uint4*>(xa + (size_t)(c0 + c) * 16 * rs + kc * 128);
-        a[c].a = p[0];
-        a[c].b = p[1];
-      }
+      for (int c = 0; c < CG; ++c) a[c] = Tile<PREC>::load(X, ld, cb0 + c0 + c, kc, lane);
       f4 (&part)[NB][CB] = acc;
       f4 sub[NB][CG];
 #pragma unroll
@@ -335,7 +404,7 @@ __device__ __forceinline__ void sincos_fast(float x, float& s, float& c) {
 
 template <int ACT>
 __device__ __forceinline__ void act_eval(float z, float w0, float& s0, float& s1, float& s2, float& s3) {
-  if (ACT == kTanh) {
+  if ((ACT & 1) == kTanh) {
     const float t = tanh_fast(z);
     const float d = 1.0f - t * t;
     s0 = t;
@@ -352,41 +421,43 @@ __device__ __forceinline__ void act_eval(float z, float w0, float& s0, float& s1
   }
 }
 
-// Jet of sigma(z): value s0, first derivatives s1 dz, Laplacian s2 sum_S (dz_k)^2 + s1 Lap z.
-__device__ __forceinline__ f4 jet_act(f4 z, float s0, float s1, float s2, int lapch, int lap_mask) {
+// Weights of the first-derivative channels in the Laplacian channel (channel 3): 1 for the
+// inputs in the Laplacian set, 0 otherwise; both 0 when channel 3 is a plain derivative
+// (three inputs) or unused.  Wave-uniform.
+__device__ __forceinline__ void lap_weights(const NetDev& net, float& w1, float& w2) {
+  const bool lap = net.lapch == 3;
+  w1 = lap && (net.lap_mask & 1) ? 1.0f : 0.0f;
+  w2 = lap && (net.lap_mask & 2) ? 1.0f : 0.0f;
+}
+
+// Jet of sigma(z): value s0, first derivatives s1 dz, and in channel 3 either the
+// derivative s1 dz_3 (LAP false: three inputs, or an unused channel) or the Laplacian
+// s2 sum_S (dz_k)^2 + s1 Lap z (LAP true; w1, w2 select the inputs in S).
+template <bool LAP>
+__device__ __forceinline__ f4 jet_act(f4 z, float s0, float s1, float s2, float w1, float w2) {
   f4 a;
   a.x = s0;
-  float q = 0.0f;
-  if (lap_mask & 1) q += z.y * z.y;
-  if (lap_mask & 2) q += z.z * z.z;
-  if (lap_mask & 4) q += z.w * z.w;
   a.y = s1 * z.y;
   a.z = s1 * z.z;
-  a.w = (lapch == 3) ? (s2 * q + s1 * z.w) : s1 * z.w;
+  a.w = s1 * z.w;
+  if (LAP) a.w = fmaf(s2, w1 * z.y * z.y + w2 * z.z * z.z, a.w);
   return a;
 }
 
 // Transpose of jet_act: adjoints of z given the adjoints abar of the activation jet.
-__device__ __forceinline__ f4 jet_act_adj(f4 z, f4 ab, float s1, float s2, float s3, int lapch, int lap_mask) {
+template <bool LAP>
+__device__ __forceinline__ f4 jet_act_adj(f4 z, f4 ab, float s1, float s2, float s3, float w1, float w2) {
   f4 zb;
-  float z0b = ab.x * s1;
-  if (lapch == 3) {
-    float q = 0.0f;
-    float lb = ab.w;
-    zb.y = ab.y * s1;
-    zb.z = ab.z * s1;
-    z0b += ab.y * s2 * z.y + ab.z * s2 * z.z;
-    if (lap_mask & 1) { q += z.y * z.y; zb.y += 2.0f * lb * s2 * z.y; }
-    if (lap_mask & 2) { q += z.z * z.z; zb.z += 2.0f * lb * s2 * z.z; }
-    z0b += lb * (s3 * q + s2 * z.w);
-    zb.w = lb * s1;
-  } else {
-    zb.y = ab.y * s1;
-    zb.z = ab.z * s1;
-    zb.w = ab.w * s1;
-    z0b += s2 * (ab.y * z.y + ab.z * z.z + ab.w * z.w);
+  zb.y = ab.y * s1;
+  zb.z = ab.z * s1;
+  zb.w = ab.w * s1;
+  zb.x = ab.x * s1 + s2 * (ab.y * z.y + ab.z * z.z + ab.w * z.w);
+  if (LAP) {
+    const float t = 2.0f * ab.w * s2;
+    zb.x = fmaf(ab.w * s3, w1 * z.y * z.y + w2 * z.z * z.z, zb.x);
+    zb.y = fmaf(t * w1, z.y, zb.y);
+    zb.z = fmaf(t * w2, z.z, zb.z);
   }
-  zb.x = z0b;
   return zb;
 }
 
@@ -696,7 +767,7 @@ struct TileSeg {
 // last hidden layer; cb_st: first cp block of this tile in those buffers.
 template <int PREC, int ACT, int H, int P>
 __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, const float4* pts, float* zs,
-                                         int64_t zs_stride, float* zb0, int64_t cb_st, const TileSeg& sg, int rs,
+                                         int64_t zs_stride, float* zb0, int64_t cb_st, const TileSeg& sg, int ld,
                                          bool with_grad, const FwdLds& s) {
   using S = FwdShape<H, P>;
   using Pr = Prec<PREC>;
@@ -707,6 +778,8 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
   const int wn = wave % WN, wc = wave / WN;
   const int L = net.L, dout = net.d_out;
   char* X = s.X;
+  float lw1, lw2;
+  lap_weights(net, lw1, lw2);
   const LayerDev& lout = net.layer[L];
 
   __syncthreads();  // the previous user of the LDS is done
@@ -742,14 +815,17 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
     }
   } else {
     // Fourier-feature jets into the R layout, then z = W gamma + b
+    // blocks of 4 points x 16 frequencies per wave: lane (g, l16) takes point 4 pb + g,
+    // frequency 16 jb + l16, the write pattern of an accumulator block
     const int m = net.n_freq;
-    for (int idx = tid; idx < P * m; idx += kThreads) {
-      const int p = idx / m, j = idx - (idx / m) * m;
+    const int nj = m >> 4;
+    for (int b = wave; b < (P / 4) * nj; b += kWaves) {
+      const int pb = b / nj, jb = b - (b / nj) * nj;
+      const int p = 4 * pb + g, j = 16 * jb + l16;
       f4 cj, sj;
       rff_jets(net, s.PT[p], j, cj, sj);
-      char* rowc = X + (size_t)(4 * p) * rs;
-      put_rows<PREC>(rowc + (j >> 3) * 32, rs, j, cj);
-      put_rows<PREC>(rowc + ((m + j) >> 3) * 32, rs, m + j, sj);
+      Tile<PREC>::put(X, ld, p, j, cj);
+      Tile<PREC>::put(X, ld, p, m + j, sj);
     }
     __syncthreads();
 #pragma unroll
@@ -760,7 +836,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       int blk[NBW];
 #pragma unroll
       for (int i = 0; i < NBW; ++i) blk[i] = min(wn + WN * i, l0.nbo - 1);
-      gemm_tile<PREC, NBW, CBW>(acc, X, rs, wc * CBW, l0.wf, l0.kci, blk, lane);
+      gemm_tile<PREC, NBW, CBW>(acc, X, ld, wc * CBW, l0.wf, l0.kci, blk, lane);
     }
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
@@ -797,8 +873,8 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
           const int cb = wc * CBW + c;
           float s0, s1, s2, s3;
           act_eval<ACT>(acc[i][c].x, net.w0, s0, s1, s2, s3);
-          const f4 a = jet_act(acc[i][c], s0, s1, s2, net.lapch, net.lap_mask);
-          put_rows<PREC>(X + (size_t)(16 * cb + 4 * g) * rs + (n >> 3) * 32, rs, n, a);
+          const f4 a = jet_act<(ACT & kLapFlag) != 0>(acc[i][c], s0, s1, s2, lw1, lw2);
+          Tile<PREC>::put(X, ld, 4 * cb + g, n, a);
           __builtin_amdgcn_sched_barrier(0);
         }
       }
@@ -814,7 +890,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
         int blk[NBW];
 #pragma unroll
         for (int i = 0; i < NBW; ++i) blk[i] = min(wn + WN * i, ln.nbo - 1);
-        gemm_tile<PREC, NBW, CBW>(acc, X, rs, wc * CBW, ln.wf, ln.kci, blk, lane);
+        gemm_tile<PREC, NBW, CBW>(acc, X, ld, wc * CBW, ln.wf, ln.kci, blk, lane);
       }
 #pragma unroll
       for (int i = 0; i < NBW; ++i) {
@@ -831,7 +907,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
     f4 y = f4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 0; kc < lout.kci; ++kc) {
       const Raw bw = glob_frag(lout.wf, 0, kc, lout.kci, lane);
-      const Raw a = lds_unit(X, 16 * cb + l16, 4 * kc + g, rs);
+      const Raw a = Tile<PREC>::load(X, ld, cb, kc, lane);
       Pr::mma(y, a, bw);
     }
     if (l16 < dout) {
@@ -926,7 +1002,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
         const f4 z = kLive ? acc[i][c] : to_f4(*jet_frag(zs + (L - 1) * zs_stride, cb_st + cb, nb, nbs, lane));
         float s0, s1, s2, s3;
         act_eval<ACT>(z.x, net.w0, s0, s1, s2, s3);
-        const f4 a = jet_act(z, s0, s1, s2, net.lapch, net.lap_mask);
+        const f4 a = jet_act<(ACT & kLapFlag) != 0>(z, s0, s1, s2, lw1, lw2);
         f4 ab = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int o = 0; o < 3; ++o) {
@@ -934,7 +1010,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
           ab += yb * wo[o];
           wsum[o] += yb.x * a.x + yb.y * a.y + yb.z * a.z + yb.w * a.w;
         }
-        const f4 zb = jet_act_adj(z, ab, s1, s2, s3, net.lapch, net.lap_mask);
+        const f4 zb = jet_act_adj<(ACT & kLapFlag) != 0>(z, ab, s1, s2, s3, lw1, lw2);
         *jet_frag(zb0, cb_st + cb, nb, nbs, lane) = to_float4(zb);
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -952,8 +1028,8 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
 template <int PREC, int ACT, int H, int P>
 __global__ __launch_bounds__(kThreads, 1) void k_forward(const FwdArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  const int rs = r_stride(A.kmax);
-  const FwdLds s = fwd_carve<H, P>(smem, rs);
+  const FwdLds s = fwd_carve<H, P>(smem, r_stride(A.kmax));
+  const int ld = Tile<PREC>::ld(A.kmax, P);
   fwd_begin<H, P>(s);
   for (int64_t tile = blockIdx.x; tile < A.n_tiles; tile += gridDim.x) {
     const int64_t p0 = tile * P;
@@ -968,7 +1044,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_forward(const FwdArgs A) {
     sg.lam = sid == 0 ? 0.0f : A.seg.lam_anchor[sid - 1];
     sg.residual = (sid == 0 && A.residual) ? A.residual + (p0 - A.seg.start[0]) * A.pde.n_res : nullptr;
     fwd_tile<PREC, ACT, H, P>(A.net, A.pde, A.work.pts + p0, A.work.zs0, A.work.zs_stride, A.work.zb[0],
-                              tile * (P / 4), sg, rs, A.with_grad != 0, s);
+                              tile * (P / 4), sg, ld, A.with_grad != 0, s);
   }
   fwd_end<H, P>(s, A.work.loss_slots + (size_t)blockIdx.x * kMaxTerms,
                 A.with_grad ? A.work.out_slots + (size_t)blockIdx.x * A.net.d_out * (A.net.layer[A.net.L].n_in + 1)
@@ -1052,7 +1128,9 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
   const int n_in = ly.n_in, n_out = ly.n_out;
   const int nob = n_out / 16, nib = n_in / 16;
   const bool has_prev = z_prev != nullptr;
-  const int rs = r_stride(n_out);
+  const int rld = Tile<PREC>::ld(n_out, PB);
+  float lw1, lw2;
+  lap_weights(net, lw1, lw2);
   const int qs = q_stride(4 * PB);
   const BwdLds L = bwd_carve(smem, PB, n_in, n_out, has_prev);
   const int wo = wave % WO, wi = wave / WO;
@@ -1079,7 +1157,7 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
         const int cb = f % CPB, ob = f / CPB;
         const f4 zb = frag(L.ZB, cb, ob, nob);
         const int o = 16 * ob + l16;
-        put_rows<PREC>(L.R + (size_t)(16 * cb + 4 * g) * rs + (o >> 3) * 32, rs, o, zb);
+        Tile<PREC>::put(L.R, rld, 4 * cb + g, o, zb);
       }
     }
     Raw ao[CPB / 2][NOBW];
@@ -1107,7 +1185,7 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
         int blk[NIBA];
 #pragma unroll
         for (int q = 0; q < NIBA; ++q) blk[q] = min(wa + WA * q, nib - 1);
-        gemm_tile<PREC, NIBA, CBA>(acca, L.R, rs, wca * CBA, ly.wb, ly.kco, blk, lane);
+        gemm_tile<PREC, NIBA, CBA>(acca, L.R, rld, wca * CBA, ly.wb, ly.kco, blk, lane);
       }
       // (3) one pass over the layer input's pre-activations: recomputed activation jets
       // into Q (operand of the weight gradient) and the activation adjoint
@@ -1122,11 +1200,11 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
           const f4 z = frag(L.ZP, cb, ib, nib);
           float s0v, s1v, s2v, s3v;
           act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
-          const f4 a = jet_act(z, s0v, s1v, s2v, net.lapch, net.lap_mask);
+          const f4 a = jet_act<(ACT & kLapFlag) != 0>(z, s0v, s1v, s2v, lw1, lw2);
           int unit, pos0;
           q_pos(cb, g, unit, pos0);
           Pr::put4(L.Q + (size_t)n * qs + unit * 32, pos0, a);
-          const f4 zb = jet_act_adj(z, acca[q][c], s1v, s2v, s3v, net.lapch, net.lap_mask);
+          const f4 zb = jet_act_adj<(ACT & kLapFlag) != 0>(z, acca[q][c], s1v, s2v, s3v, lw1, lw2);
           *jet_frag(zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -1285,8 +1363,8 @@ __device__ __forceinline__ void run_item(const BatchArgs& A, const BatchInst& in
   for (int c = 0; c < 3; ++c) pde.seed_scale[c] = 2.0f * A.lambda_res[c] / (float)in.n;
   // forward over the item's tiles
   {
-    const int rs = r_stride(in.kmax);
-    const FwdLds s = fwd_carve<H, PF>(smem, rs);
+    const FwdLds s = fwd_carve<H, PF>(smem, r_stride(in.kmax));
+    const int ld = Tile<PREC>::ld(in.kmax, PF);
     fwd_begin<H, PF>(s);
     for (int64_t t = 0; t < npts / PF; ++t) {
       const int64_t nv = in.n - (it.p0 + t * PF);
@@ -1298,7 +1376,7 @@ __device__ __forceinline__ void run_item(const BatchArgs& A, const BatchInst& in
       sg.out_mask = 0;
       sg.lam = 0.0f;
       sg.residual = nullptr;
-      fwd_tile<PREC, ACT, H, PF>(net, pde, pts + t * PF, zs, in.zs_stride, zb[0], t * (PF / 4), sg, rs, true, s);
+      fwd_tile<PREC, ACT, H, PF>(net, pde, pts + t * PF, zs, in.zs_stride, zb[0], t * (PF / 4), sg, ld, true, s);
     }
     const int nL = net.layer[net.L].n_in;
     fwd_end<H, PF>(s, loss_slot, gslot + in.eff_off[net.L], net.d_out, nL, true);
@@ -1588,18 +1666,35 @@ int launch_stage(int prec, const StageArgs& a, hipStream_t s) {
   return status(hipGetLastError());
 }
 
+template <int PREC>
+int fwd_a(int act, int H, int P, const FwdArgs& a, int grid, size_t lds, hipStream_t s) {
+  switch (act) {
+    case kTanh: return fwd_h<PREC, kTanh>(H, P, a, grid, lds, s);
+    case kSin: return fwd_h<PREC, kSin>(H, P, a, grid, lds, s);
+    case kTanh | kLapFlag: return fwd_h<PREC, kTanh | kLapFlag>(H, P, a, grid, lds, s);
+    case kSin | kLapFlag: return fwd_h<PREC, kSin | kLapFlag>(H, P, a, grid, lds, s);
+    default: return -2;
+  }
+}
+
+template <int PREC>
+int bwd_a(int act, int H, bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
+  switch (act) {
+    case kTanh: return bwd_h<PREC, kTanh>(H, embed, a, grid, lds, s);
+    case kSin: return bwd_h<PREC, kSin>(H, embed, a, grid, lds, s);
+    case kTanh | kLapFlag: return bwd_h<PREC, kTanh | kLapFlag>(H, embed, a, grid, lds, s);
+    case kSin | kLapFlag: return bwd_h<PREC, kSin | kLapFlag>(H, embed, a, grid, lds, s);
+    default: return -2;
+  }
+}
+
 int launch_forward(int prec, int act, int H, int P, const FwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  if (prec == kFP32)
-    return act == kTanh ? fwd_h<kFP32, kTanh>(H, P, a, grid, lds, s) : fwd_h<kFP32, kSin>(H, P, a, grid, lds, s);
-  return act == kTanh ? fwd_h<kBF16X3, kTanh>(H, P, a, grid, lds, s) : fwd_h<kBF16X3, kSin>(H, P, a, grid, lds, s);
+  return prec == kFP32 ? fwd_a<kFP32>(act, H, P, a, grid, lds, s) : fwd_a<kBF16X3>(act, H, P, a, grid, lds, s);
 }
 
 int launch_backward(int prec, int act, int H, bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  if (prec == kFP32)
-    return act == kTanh ? bwd_h<kFP32, kTanh>(H, embed, a, grid, lds, s)
-                        : bwd_h<kFP32, kSin>(H, embed, a, grid, lds, s);
-  return act == kTanh ? bwd_h<kBF16X3, kTanh>(H, embed, a, grid, lds, s)
-                      : bwd_h<kBF16X3, kSin>(H, embed, a, grid, lds, s);
+  return prec == kFP32 ? bwd_a<kFP32>(act, H, embed, a, grid, lds, s)
+                       : bwd_a<kBF16X3>(act, H, embed, a, grid, lds, s);
 }
 
 int launch_grad0(const Grad0Args& a, int grid, hipStream_t s) {
@@ -1625,25 +1720,27 @@ size_t batched_lds(int kmax, int H) {
   return m > g ? m : g;
 }
 
-int launch_batched(int prec, int act, const BatchArgs& a, int grid, size_t lds, hipStream_t s) {
-  const void* k;
-  if (prec == kFP32)
-    k = act == kTanh ? reinterpret_cast<const void*>(k_batched<kFP32, kTanh>)
-                     : reinterpret_cast<const void*>(k_batched<kFP32, kSin>);
-  else
-    k = act == kTanh ? reinterpret_cast<const void*>(k_batched<kBF16X3, kTanh>)
-                     : reinterpret_cast<const void*>(k_batched<kBF16X3, kSin>);
-  if (lds > 65536 &&
-      hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-    return -5;
-  if (prec == kFP32) {
-    if (act == kTanh) hipLaunchKernelGGL((k_batched<kFP32, kTanh>), dim3(grid), dim3(kThreads), lds, s, a);
-    else hipLaunchKernelGGL((k_batched<kFP32, kSin>), dim3(grid), dim3(kThreads), lds, s, a);
-  } else {
-    if (act == kTanh) hipLaunchKernelGGL((k_batched<kBF16X3, kTanh>), dim3(grid), dim3(kThreads), lds, s, a);
-    else hipLaunchKernelGGL((k_batched<kBF16X3, kSin>), dim3(grid), dim3(kThreads), lds, s, a);
-  }
+template <int PREC, int ACT>
+int batched_k(const BatchArgs& a, int grid, size_t lds, hipStream_t s) {
+  auto k = k_batched<PREC, ACT>;
+  if (set_lds(k, lds)) return -5;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, a);
   return status(hipGetLastError());
+}
+
+template <int PREC>
+int batched_a(int act, const BatchArgs& a, int grid, size_t lds, hipStream_t s) {
+  switch (act) {
+    case kTanh: return batched_k<PREC, kTanh>(a, grid, lds, s);
+    case kSin: return batched_k<PREC, kSin>(a, grid, lds, s);
+    case kTanh | kLapFlag: return batched_k<PREC, kTanh | kLapFlag>(a, grid, lds, s);
+    case kSin | kLapFlag: return batched_k<PREC, kSin | kLapFlag>(a, grid, lds, s);
+    default: return -2;
+  }
+}
+
+int launch_batched(int prec, int act, const BatchArgs& a, int grid, size_t lds, hipStream_t s) {
+  return prec == kFP32 ? batched_a<kFP32>(act, a, grid, lds, s) : batched_a<kBF16X3>(act, a, grid, lds, s);
 }
 
 int launch_reduce_batched(const BatchReduceArgs& a, hipStream_t s) {
