@@ -151,6 +151,8 @@ struct Plan {
   int64_t n_pad;
   int pf, pb;             // forward tile points, backward sub-tile points (hidden layers)
   int kmax;
+  int pb0;
+  bool wide, wide0;       // wide bf16x3 backward for the hidden layers / the embedding layer
   int64_t n_tiles, n_sub, n_sub0;
   int grid_f, grid_b, grid_b0, grid_g0;
   size_t lds_f, lds_b, lds_b0;
@@ -206,14 +208,22 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   }
   if (fwd_lds(p.pf, p.kmax, D.H) > kLdsBudget) p.pf = 16;
   if (fwd_lds(p.pf, p.kmax, D.H) > kLdsBudget) return PINN_E_UNSUPPORTED;
-  p.pb = default_bwd_p(D.H);
+  // layer backward: the wide bf16x3 kernel when the layer input width is a multiple of
+  // 128 (hidden widths 128 / 256; Fourier embeddings of 64 / 128 frequencies)
+  bool wide = prec == PINN_PREC_BF16X3 && D.H >= 128;
+  for (int j = 1; j < D.L; ++j) wide = wide && D.n_in[j] % 128 == 0;
+  const bool wide0 = prec == PINN_PREC_BF16X3 && net->n_freq > 0 && (D.e / 16) % 8 == 0;
+  p.wide = wide;
+  p.wide0 = wide0;
+  p.pb = wide ? wide_pb(D.H) : default_bwd_p(D.H);
+  p.pb0 = wide0 ? wide_pb(D.H) : embed_bwd_p(D.H);
   p.lds_f = fwd_lds(p.pf, p.kmax, D.H);
-  p.lds_b = bwd_lds(p.pb, D.H, D.H, true);
-  p.lds_b0 = bwd_lds(embed_bwd_p(D.H), 256, D.H, false);
+  p.lds_b = wide ? (size_t)2 * p.pb * D.H * 16 : bwd_lds(p.pb, D.H, D.H, true);
+  p.lds_b0 = wide0 ? (size_t)2 * p.pb0 * D.H * 16 : bwd_lds(p.pb0, 256, D.H, false);
   if (p.lds_b > kLdsBudget || p.lds_b0 > kLdsBudget) return PINN_E_UNSUPPORTED;
   p.n_tiles = p.n_pad / p.pf;
   p.n_sub = p.n_pad / p.pb;
-  p.n_sub0 = p.n_pad / embed_bwd_p(D.H);
+  p.n_sub0 = p.n_pad / p.pb0;
   int cap = kGridCap;
   if (tune && tune->grid > 0) cap = tune->grid;
   p.grid_f = (int)std::min<int64_t>(p.n_tiles, cap);
@@ -448,6 +458,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.zb_out = wk.zb[cur ^ 1];
       a.z_prev = wk.zs0 + (j - 1) * wk.zs_stride;
       a.slots = wk.layer_slots[j];
+      a.wide = p.wide;
       rc = timed("k_backward", stream, [&] { return launch_backward(prec, act_code(net, pde), D.H, false, a, p.grid_b, p.lds_b, stream); });
       if (rc) return rc;
       cur ^= 1;
@@ -463,6 +474,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.zb_out = nullptr;
       a.z_prev = nullptr;
       a.slots = wk.layer_slots[0];
+      a.wide = p.wide0;
       rc = timed("k_backward_embed", stream, [&] { return launch_backward(prec, act_code(net, pde), D.H, true, a, p.grid_b0, p.lds_b0, stream); });
       if (rc) return rc;
     } else {

@@ -117,6 +117,7 @@ struct BwdArgs {
   float* zb_out;        // adjoint of the previous hidden layer's pre-activation (or null)
   const float* z_prev;  // stash of the previous hidden layer (null for layer 0)
   double* slots;        // [gridDim][n_out * (n_in + 1)]
+  int wide;             // use the wide bf16x3 kernel (input width a multiple of 128)
 };
 
 struct Grad0Args {
@@ -206,6 +207,9 @@ struct BatchLossArgs {
   int n_inst, n_res;
   double* losses;            // [n_inst][1 + n_res]
 };
+
+// Sub-tile points of the wide bf16x3 layer backward (input width a multiple of 128).
+constexpr int wide_pb(int H) { return H >= 256 ? 16 : 32; }
 
 // Launchers (pinn_kernels.hip).  Each returns a pinn_status value.
 int launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t s);

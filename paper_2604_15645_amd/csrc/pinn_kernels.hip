@@ -1289,6 +1289,226 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
   bwd_flush<NOB, NIB, PB>(accw, bsum, A.slots + (size_t)blockIdx.x * ly.n_out * (ly.n_in + 1), ly.n_out, ly.n_in);
 }
 
+// ================================================================== backward (one layer, wide)
+
+// Layer backward for bf16x3 when the layer input width is a multiple of 128 (8 waves x
+// 16-column blocks).  Wave w owns input blocks ib = w + 8 k: it computes the input adjoint
+// (and, for a hidden layer, the activation adjoint) for those columns over the whole
+// sub-tile, and the weight-gradient columns of those blocks for every output row.  The
+// weight-gradient product then takes its B operand (activation jets of the layer input,
+// in accumulator order) straight from the wave's registers and its A operand (output
+// adjoint, 8 cp per lane) from the R tile by plain 8-byte reads, so no second LDS tile is
+// needed and sub-tiles can be twice as large as in bwd_range.
+// LDS: STG and R (T layout), both PB x (16 NOB) x 16 bytes.  STG holds, in turn, the staged
+// output-adjoint fragments of the sub-tile (copied in during the previous sub-tile's weight
+// gradient) and the staged layer-input pre-activations (copied in during the input-adjoint
+// product).
+template <int NOB, int NIB, int PB>
+struct WideShape {
+  static constexpr int CPB = PB / 4;
+  static constexpr int NIBW = NIB / 8;             // input blocks per wave (upper bound)
+  static constexpr int NOBC = (NOB + 7) / 8;       // output blocks converted per wave
+  static_assert(NIB % 8 == 0 && CPB % 2 == 0, "wide backward shape");
+};
+
+__host__ __device__ constexpr size_t wide_lds_bytes(int PB, int n_out) { return (size_t)2 * PB * n_out * 16; }
+
+// A operand of the weight gradient for output block ob and cp chunk cc (points 8 cc ..
+// 8 cc + 7): lane (g, l16) takes output o = 16 ob + l16 and the 4 channels of points
+// 8 cc + g and 8 cc + 4 + g -- the cp order of the accumulator fragments.
+__device__ __forceinline__ Raw wide_zbar_op(const char* R, int ld, int ob, int cc, int lane) {
+  const int g = lane >> 4, o = 16 * ob + (lane & 15);
+  const int p0 = 8 * cc + g, p1 = p0 + 4;
+  const char* c0 = R + (size_t)((o >> 5) * ld + (p0 >> 2)) * 2048 + t_cell_off(p0, o);
+  const char* c1 = R + (size_t)((o >> 5) * ld + (p1 >> 2)) * 2048 + t_cell_off(p1, o);
+  const uint2 h0 = *reinterpret_cast<const uint2*>(c0), h1 = *reinterpret_cast<const uint2*>(c1);
+  const uint2 l0 = *reinterpret_cast<const uint2*>(c0 + 1024), l1 = *reinterpret_cast<const uint2*>(c1 + 1024);
+  Raw r;
+  r.a = make_uint4(h0.x, h0.y, h1.x, h1.y);
+  r.b = make_uint4(l0.x, l0.y, l1.x, l1.y);
+  return r;
+}
+
+template <int ACT, int NOB, int NIB, int PB>
+__device__ __forceinline__ void bwd_wide_range(const NetDev& net, int layer, const float4* pts, int64_t s0,
+                                               int64_t stride, int64_t count, const float* zb_in, float* zb_out,
+                                               const float* z_prev, char* smem,
+                                               f4 (&accw)[NOB][WideShape<NOB, NIB, PB>::NIBW],
+                                               float (&bsum)[WideShape<NOB, NIB, PB>::NOBC]) {
+  using S = WideShape<NOB, NIB, PB>;
+  using Pr = Prec<kBF16X3>;
+  using T = Tile<kBF16X3>;
+  constexpr int CPB = S::CPB, NIBW = S::NIBW, NOBC = S::NOBC;
+  constexpr bool kLap = (ACT & kLapFlag) != 0;
+  const LayerDev& ly = net.layer[layer];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, l16 = lane & 15;
+  const int n_in = ly.n_in, n_out = ly.n_out;
+  const int nob = n_out / 16, nib = n_in / 16;
+  const bool has_prev = z_prev != nullptr;
+  const int rld = T::ld(n_out, PB);
+  float lw1, lw2;
+  lap_weights(net, lw1, lw2);
+  char* STG = smem;
+  char* R = smem + (size_t)PB * NOB * 256;  // STG sized for the widest layer of the kernel
+  const int zb_bytes = CPB * nob * 1024, zp_bytes = CPB * nib * 1024;
+  auto zb_src = [&](int64_t s) { return reinterpret_cast<const char*>(zb_in) + s * zb_bytes; };
+
+  if (count <= 0) return;
+  __syncthreads();  // the previous user of the LDS is done
+  async_copy(STG, zb_src(s0), zb_bytes);
+
+  for (int64_t k = 0; k < count; ++k) {
+    const int64_t s = s0 + k * stride;
+    const int64_t cb0 = s * CPB;
+    wait_async();
+    __syncthreads();  // sub-tile s staged; the previous sub-tile is done with R
+    // (1) output adjoint into R (T layout); bias sums of the converted output blocks
+#pragma unroll
+    for (int q = 0; q < NOBC; ++q) {
+      const int ob = wave + 8 * q;
+      if (ob < nob) {
+#pragma unroll
+        for (int cb = 0; cb < CPB; ++cb) {
+          const f4 zb = to_f4(*reinterpret_cast<const float4*>(STG + ((size_t)(cb * nob + ob) * 64 + lane) * 16));
+          T::put(R, rld, 4 * cb + g, 16 * ob + l16, zb);
+          bsum[q] += zb.x;
+        }
+      }
+    }
+    __syncthreads();  // R complete; STG free
+    // (2)-(3) per owned input block: layer-input jets a (B operand of the weight gradient)
+    // and, for a hidden layer, the input adjoint and the activation adjoint
+    Raw aop[NIBW][CPB / 2];
+    if (has_prev) {
+      async_copy(STG, reinterpret_cast<const char*>(z_prev) + s * zp_bytes, zp_bytes);
+      f4 acca[NIBW][CPB];
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q)
+#pragma unroll
+        for (int cb = 0; cb < CPB; ++cb) acca[q][cb] = f4{0.f, 0.f, 0.f, 0.f};
+      {
+        int blk[NIBW];
+#pragma unroll
+        for (int q = 0; q < NIBW; ++q) blk[q] = wave + 8 * q;
+        gemm_tile<kBF16X3, NIBW, CPB>(acca, R, rld, 0, ly.wb, ly.kco, blk, lane);
+      }
+      wait_async();
+      __syncthreads();  // pre-activations of sub-tile s staged
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q) {
+        const int ib = wave + 8 * q;
+#pragma unroll
+        for (int cc = 0; cc < CPB / 2; ++cc) {
+          float f[8];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int cb = 2 * cc + h;
+            const f4 z = to_f4(*reinterpret_cast<const float4*>(STG + ((size_t)(cb * nib + ib) * 64 + lane) * 16));
+            float s0v, s1v, s2v, s3v;
+            act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
+            const f4 a = jet_act<kLap>(z, s0v, s1v, s2v, lw1, lw2);
+            f[4 * h] = a.x;
+            f[4 * h + 1] = a.y;
+            f[4 * h + 2] = a.z;
+            f[4 * h + 3] = a.w;
+            const f4 zb = jet_act_adj<kLap>(z, acca[q][cb], s1v, s2v, s3v, lw1, lw2);
+            *jet_frag(zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
+          }
+          aop[q][cc] = Pr::make(f);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    } else {
+      // Fourier-feature jets of the owned columns: column i < m is cos(x B_i), i >= m sin
+      const int m = net.n_freq;
+      const float4* sp = pts + s * PB;
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q) {
+        const int i = 16 * min(wave + 8 * q, nib - 1) + l16;
+        const int j = i < m ? i : i - m;
+#pragma unroll
+        for (int cc = 0; cc < CPB / 2; ++cc) {
+          float f[8];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            f4 cj, sj;
+            rff_jets(net, sp[4 * (2 * cc + h) + g], j, cj, sj);
+            const f4 a = i < m ? cj : sj;
+            f[4 * h] = a.x;
+            f[4 * h + 1] = a.y;
+            f[4 * h + 2] = a.z;
+            f[4 * h + 3] = a.w;
+          }
+          aop[q][cc] = Pr::make(f);
+        }
+      }
+    }
+    __syncthreads();  // STG no longer read
+    if (k + 1 < count) async_copy(STG, zb_src(s + stride), zb_bytes);
+    // (4) weight gradient: W_bar[o][i] += sum_cp zbar[cp][o] a[cp][i] for the owned columns
+#pragma unroll
+    for (int cc = 0; cc < CPB / 2; ++cc)
+#pragma unroll
+      for (int ob = 0; ob < NOB; ++ob) {
+        const Raw ao = wide_zbar_op(R, rld, min(ob, nob - 1), cc, lane);
+#pragma unroll
+        for (int q = 0; q < NIBW; ++q) Pr::mma(accw[ob][q], ao, aop[q][cc]);
+      }
+  }
+}
+
+// Weight-gradient sums of the wide backward into a slot [n_out][n_in] then [n_out].
+template <int NOB, int NIB, int PB>
+__device__ __forceinline__ void bwd_wide_flush(const f4 (&accw)[NOB][WideShape<NOB, NIB, PB>::NIBW],
+                                               const float (&bsum)[WideShape<NOB, NIB, PB>::NOBC], double* slot,
+                                               int n_out, int n_in) {
+  using S = WideShape<NOB, NIB, PB>;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, l16 = lane & 15;
+  const int nob = n_out / 16, nib = n_in / 16;
+#pragma unroll
+  for (int ob = 0; ob < NOB; ++ob) {
+    if (ob >= nob) continue;
+#pragma unroll
+    for (int q = 0; q < S::NIBW; ++q) {
+      const int ib = wave + 8 * q;
+      if (ib >= nib) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) slot[(size_t)(16 * ob + 4 * g + r) * n_in + 16 * ib + l16] = (double)accw[ob][q][r];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < S::NOBC; ++q) {
+    const int ob = wave + 8 * q;
+    float v = bsum[q];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (ob < nob && g == 0) slot[(size_t)n_out * n_in + 16 * ob + l16] = (double)v;
+  }
+}
+
+template <int ACT, int NOB, int NIB, int PB>
+__global__ __launch_bounds__(kThreads, 1) void k_backward_wide(const BwdArgs A) {
+  using S = WideShape<NOB, NIB, PB>;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  f4 accw[NOB][S::NIBW];
+#pragma unroll
+  for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+    for (int q = 0; q < S::NIBW; ++q) accw[ob][q] = f4{0.f, 0.f, 0.f, 0.f};
+  float bsum[S::NOBC];
+#pragma unroll
+  for (int q = 0; q < S::NOBC; ++q) bsum[q] = 0.f;
+  const int64_t count = A.n_sub > blockIdx.x ? (A.n_sub - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+  bwd_wide_range<ACT, NOB, NIB, PB>(A.net, A.layer, A.work.pts, blockIdx.x, gridDim.x, count, A.zb_in, A.zb_out,
+                                    A.z_prev, smem, accw, bsum);
+  const LayerDev& ly = A.net.layer[A.layer];
+  bwd_wide_flush<NOB, NIB, PB>(accw, bsum, A.slots + (size_t)blockIdx.x * ly.n_out * (ly.n_in + 1), ly.n_out, ly.n_in);
+}
+
 // ================================================================== first layer, identity
 
 // W_bar[o][k] = sum_points (zbar0[o] x_k + zbar_{1+k}[o]), b_bar[o] = sum zbar0[o]: the
@@ -1625,8 +1845,26 @@ int bwd(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
   return status(hipGetLastError());
 }
 
+template <int ACT, int NOB, int NIB, int PB>
+int bwd_wide(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
+  auto k = k_backward_wide<ACT, NOB, NIB, PB>;
+  if (set_lds(k, lds)) return -5;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, a);
+  return status(hipGetLastError());
+}
+
 template <int PREC, int ACT, int H>
 int bwd_e(bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
+  if constexpr (PREC == kBF16X3) {
+    // wide path (chosen by the plan): input widths that are multiples of 128
+    constexpr int PW = wide_pb(H);
+    if (a.wide) {
+      if (a.net.layer[a.layer].n_in % 128 != 0) return -2;
+      if (embed) return bwd_wide<ACT, H / 16, 16, PW>(a, grid, lds, s);
+      if constexpr (H >= 128) return bwd_wide<ACT, H / 16, H / 16, PW>(a, grid, lds, s);
+      return -2;
+    }
+  }
   constexpr int PB = 2048 / H;
   if (embed) return bwd<PREC, ACT, H / 16, 16, H == 256 ? 8 : 16>(a, grid, lds, s);
   return bwd<PREC, ACT, H / 16, H / 16, PB>(a, grid, lds, s);
