@@ -153,6 +153,7 @@ struct Plan {
   int kmax;
   int pb0;
   bool wide, wide0;       // wide bf16x3 backward for the hidden layers / the embedding layer
+  bool split;             // split-role bf16x3 backward for the hidden layers
   int64_t n_tiles, n_sub, n_sub0;
   int grid_f, grid_b, grid_b0, grid_g0;
   size_t lds_f, lds_b, lds_b0;
@@ -215,6 +216,9 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   const bool wide0 = prec == PINN_PREC_BF16X3 && net->n_freq > 0 && (D.e / 16) % 8 == 0;
   p.wide = wide;
   p.wide0 = wide0;
+  // split roles: uniform hidden width H (128 or 256); the grid is a multiple of 16
+  p.split = wide;
+  for (int j = 1; j < D.L; ++j) p.split = p.split && D.n_in[j] == D.H && D.n_out[j] == D.H;
   p.pb = wide ? wide_pb(D.H) : default_bwd_p(D.H);
   p.pb0 = wide0 ? wide_pb(D.H) : embed_bwd_p(D.H);
   p.lds_f = fwd_lds(p.pf, p.kmax, D.H);
@@ -228,6 +232,10 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   if (tune && tune->grid > 0) cap = tune->grid;
   p.grid_f = (int)std::min<int64_t>(p.n_tiles, cap);
   p.grid_b = (int)std::min<int64_t>(p.n_sub, cap);
+  if (p.split) {  // two roles of G work-groups each, G a multiple of 8
+    const int64_t G = std::min<int64_t>(align_up(std::min<int64_t>(p.n_sub, cap / 2), 8), std::max(8, cap / 2 / 8 * 8));
+    p.grid_b = (int)(2 * G);
+  }
   p.grid_b0 = (int)std::min<int64_t>(p.n_sub0, cap);
   p.grid_g0 = (int)std::min<int64_t>(std::max<int64_t>(1, p.n_pad / 4 / 64), 128);
   // workspace layout
@@ -458,7 +466,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.zb_out = wk.zb[cur ^ 1];
       a.z_prev = wk.zs0 + (j - 1) * wk.zs_stride;
       a.slots = wk.layer_slots[j];
-      a.wide = p.wide;
+      a.wide = p.split ? 2 : p.wide;
       rc = timed("k_backward", stream, [&] { return launch_backward(prec, act_code(net, pde), D.H, false, a, p.grid_b, p.lds_b, stream); });
       if (rc) return rc;
       cur ^= 1;
@@ -505,7 +513,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
         a.n_slots = p.grid_f;
       } else {
         a.slots = wk.layer_slots[l];
-        a.n_slots = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : p.grid_g0) : p.grid_b;
+        a.n_slots = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : p.grid_g0) : (p.split ? p.grid_b / 2 : p.grid_b);
       }
       rc = timed("k_reduce_layer", stream, [&] { return launch_reduce_layer(a, stream); });
       if (rc) return rc;

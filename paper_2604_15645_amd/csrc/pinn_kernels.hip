@@ -685,6 +685,19 @@ __global__ void k_fill(double* p, int64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
+__device__ __forceinline__ void wait_async() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Work-group barrier for LDS traffic: this wave's LDS operations complete (lgkmcnt 0), then
+// s_barrier.  Unlike __syncthreads it does not wait for the wave's outstanding vector-memory
+// operations (global stores, staged copies), which keep running across the barrier; the
+// empty asm statements keep the compiler from moving memory accesses across it.
+__device__ __forceinline__ void barrier_lds() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // gfx9 encoding: vmcnt 63, expcnt 7, lgkmcnt 0
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // ================================================================== forward
 
 // Compile-time shape of the forward tile: hidden width bound H, tile points P.
@@ -782,9 +795,9 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
   lap_weights(net, lw1, lw2);
   const LayerDev& lout = net.layer[L];
 
-  __syncthreads();  // the previous user of the LDS is done
+  barrier_lds();  // the previous user of the LDS is done
   for (int p = tid; p < P; p += kThreads) s.PT[p] = pts[p];
-  __syncthreads();
+  barrier_lds();
 
   f4 acc[NBW][CBW];
   // ---- layer 0
@@ -827,7 +840,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       Tile<PREC>::put(X, ld, p, j, cj);
       Tile<PREC>::put(X, ld, p, m + j, sj);
     }
-    __syncthreads();
+    barrier_lds();
 #pragma unroll
     for (int i = 0; i < NBW; ++i)
 #pragma unroll
@@ -862,7 +875,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
             *jet_frag(zsj, cb_st + wc * CBW + c, nb, nbs, lane) = to_float4(acc[i][c]);
       }
     }
-    __syncthreads();  // every wave is done reading the layer input from X
+    barrier_lds();  // every wave is done reading the layer input from X
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
       const int nb = wn + WN * i;
@@ -879,7 +892,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
         }
       }
     }
-    __syncthreads();
+    barrier_lds();
     if (j + 1 < L) {
       const LayerDev& ln = net.layer[j + 1];
 #pragma unroll
@@ -916,7 +929,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       *reinterpret_cast<float4*>(dst) = to_float4(y);
     }
   }
-  __syncthreads();
+  barrier_lds();
 
   // ---- residual (or supervision misfit), loss partial sums and the output-jet seed
   float part[3] = {0.f, 0.f, 0.f};
@@ -965,7 +978,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
     const float v = wave_sum(part[k]);
     if (lane == 0) s.RED[wave * 4 + k] = v;
   }
-  __syncthreads();
+  barrier_lds();
   if (tid == 0) {
     const int nterm = sg.kind == 0 ? pde.n_res : 1;
     for (int k = 0; k < nterm; ++k) {
@@ -1104,7 +1117,6 @@ __device__ __forceinline__ void async_copy(char* dst, const char* src, int bytes
                                      (__attribute__((address_space(3))) void*)(dst + off), 16, 0, 0);
 }
 
-__device__ __forceinline__ void wait_async() { __builtin_amdgcn_s_waitcnt(0); }
 
 // Linear layer `layer`'s backward over `count` sub-tiles of PB points, sub-tile k being
 // number s0 + k * stride: weight-gradient sums (accw, bsum, kept by the caller), and for
@@ -1150,7 +1162,7 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
   for (int64_t k = 0; k < count; ++k) {
     const int64_t s = s0 + k * stride;
     wait_async();
-    __syncthreads();  // sub-tile s is in ZB / ZP; the previous sub-tile is done with R and Q
+    barrier_lds();  // sub-tile s is in ZB / ZP; the previous sub-tile is done with R and Q
     // (1) output adjoint: R layout for the input adjoint, A operands of the weight gradient
     if (has_prev) {
       for (int f = wave; f < CPB * nob; f += kWaves) {
@@ -1171,7 +1183,7 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
         ao[cc][i] = Pr::make(f);
         bsum[i] += v0.x + v1.x;
       }
-    __syncthreads();  // R complete; ZB no longer read
+    barrier_lds();  // R complete; ZB no longer read
     if (k + 1 < count) async_copy(L.ZB, zb_src(s + stride), zb_bytes);
     const int64_t cb0 = s * CPB;
     if (has_prev) {
@@ -1224,7 +1236,7 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
         Pr::put4(L.Q + (size_t)(m + j) * qs + unit * 32, pos0, sj);
       }
     }
-    __syncthreads();  // Q complete; ZP no longer read
+    barrier_lds();  // Q complete; ZP no longer read
     if (has_prev && k + 1 < count) async_copy(L.ZP, zp_src(s + stride), zp_bytes);
     // (4) weight gradient: W_bar[o][i] += sum_cp zbar[cp][o] a[cp][i]
 #pragma unroll
@@ -1363,7 +1375,7 @@ __device__ __forceinline__ void bwd_wide_range(const NetDev& net, int layer, con
     const int64_t s = s0 + k * stride;
     const int64_t cb0 = s * CPB;
     wait_async();
-    __syncthreads();  // sub-tile s staged; the previous sub-tile is done with R
+    barrier_lds();  // sub-tile s staged; the previous sub-tile is done with R
     // (1) output adjoint into R (T layout); bias sums of the converted output blocks
 #pragma unroll
     for (int q = 0; q < NOBC; ++q) {
@@ -1377,7 +1389,7 @@ __device__ __forceinline__ void bwd_wide_range(const NetDev& net, int layer, con
         }
       }
     }
-    __syncthreads();  // R complete; STG free
+    barrier_lds();  // R complete; STG free
     // (2)-(3) per owned input block: layer-input jets a (B operand of the weight gradient)
     // and, for a hidden layer, the input adjoint and the activation adjoint
     Raw aop[NIBW][CPB / 2];
@@ -1395,7 +1407,7 @@ __device__ __forceinline__ void bwd_wide_range(const NetDev& net, int layer, con
         gemm_tile<kBF16X3, NIBW, CPB>(acca, R, rld, 0, ly.wb, ly.kco, blk, lane);
       }
       wait_async();
-      __syncthreads();  // pre-activations of sub-tile s staged
+      barrier_lds();  // pre-activations of sub-tile s staged
 #pragma unroll
       for (int q = 0; q < NIBW; ++q) {
         const int ib = wave + 8 * q;
@@ -1445,7 +1457,7 @@ __device__ __forceinline__ void bwd_wide_range(const NetDev& net, int layer, con
         }
       }
     }
-    __syncthreads();  // STG no longer read
+    barrier_lds();  // STG no longer read
     if (k + 1 < count) async_copy(STG, zb_src(s + stride), zb_bytes);
     // (4) weight gradient: W_bar[o][i] += sum_cp zbar[cp][o] a[cp][i] for the owned columns
 #pragma unroll
@@ -1507,6 +1519,209 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_wide(const BwdArgs A) 
                                     A.z_prev, smem, accw, bsum);
   const LayerDev& ly = A.net.layer[A.layer];
   bwd_wide_flush<NOB, NIB, PB>(accw, bsum, A.slots + (size_t)blockIdx.x * ly.n_out * (ly.n_in + 1), ly.n_out, ly.n_in);
+}
+
+// ================================================================== backward (one layer, split roles)
+
+// Hidden-layer backward for bf16x3 at input widths that are multiples of 128, with the
+// work-groups split into two roles that sweep the same sub-tiles:
+//   role 0  input adjoint and activation adjoint (abar = zbar W, then zbar_prev), with the
+//           layer's weight fragments held in registers for the whole launch (no weight
+//           traffic per sub-tile);
+//   role 1  weight gradient W_bar += zbar^T a_prev and bias gradient, the sums held in
+//           registers over the work-group's sub-tiles.
+// Each role keeps half the matrix-core work of a sub-tile.  Work-groups b and b + 8 (one
+// of each role) take the same sub-tiles; dispatch places them on the same XCD, so the
+// second reader of a sub-tile's jets finds them in cache.  Both roles stage the output
+// adjoint of the next sub-tile into LDS (STG) and load the pre-activations of the current
+// one into registers before they are needed; vector-memory counters complete in issue
+// order, and the loop waits only for what it needs (role 0 leaves its adjoint stores
+// outstanding across the wait).
+template <int NOB, int NIB, int PB>
+struct SplitShape {
+  static constexpr int CPB = PB / 4;
+  static constexpr int NIBW = NIB / 8;   // input blocks per wave
+  static constexpr int NOBC = NOB / 8;   // output blocks converted per wave
+  static constexpr int KC = NOB / 2;     // reduction chunks of the input adjoint (n_out / 32)
+  static constexpr int NSTORE = NIBW * CPB;  // adjoint stores per lane and sub-tile
+  static_assert(NIB % 8 == 0 && NOB % 8 == 0 && CPB % 2 == 0, "split backward shape");
+};
+
+// s_waitcnt with only the vector-memory count bounded (gfx9 encoding: vmcnt in bits 3:0
+// and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+template <int ACT, int NOB, int NIB, int PB>
+__global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A) {
+  using S = SplitShape<NOB, NIB, PB>;
+  using Pr = Prec<kBF16X3>;
+  using T = Tile<kBF16X3>;
+  constexpr int CPB = S::CPB, NIBW = S::NIBW, NOBC = S::NOBC, KC = S::KC;
+  constexpr bool kLap = (ACT & kLapFlag) != 0;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const NetDev& net = A.net;
+  const LayerDev& ly = net.layer[A.layer];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, l16 = lane & 15;
+  const int n_in = ly.n_in, n_out = ly.n_out;
+  const int nib = n_in / 16, nob = n_out / 16;
+  const int rld = T::ld(n_out, PB);
+  float lw1, lw2;
+  lap_weights(net, lw1, lw2);
+  char* STG = smem;
+  char* R = smem + (size_t)PB * NOB * 256;
+  const int zb_bytes = CPB * nob * 1024;
+  // role and index within the role (blocks b and b + 8 share a sub-tile sequence)
+  const int b = blockIdx.x;
+  const int role = (b >> 3) & 1;
+  const int rb = ((b >> 4) << 3) | (b & 7);
+  const int G = gridDim.x >> 1;
+  const int64_t count = A.n_sub > rb ? (A.n_sub - rb + G - 1) / G : 0;
+  auto zb_src = [&](int64_t s) { return reinterpret_cast<const char*>(A.zb_in) + s * zb_bytes; };
+  f4 zp[NIBW][CPB];
+  auto load_zp = [&](int64_t s) {
+#pragma unroll
+    for (int q = 0; q < NIBW; ++q)
+#pragma unroll
+      for (int cb = 0; cb < CPB; ++cb)
+        zp[q][cb] = to_f4(*jet_frag(const_cast<float*>(A.z_prev), s * CPB + cb, wave + 8 * q, nib, lane));
+  };
+  auto convert = [&](float* bsum) {  // STG -> R (T layout), bias sums of the converted blocks
+#pragma unroll
+    for (int q = 0; q < NOBC; ++q) {
+      const int ob = wave + 8 * q;
+#pragma unroll
+      for (int cb = 0; cb < CPB; ++cb) {
+        const f4 zb = to_f4(*reinterpret_cast<const float4*>(STG + ((size_t)(cb * nob + ob) * 64 + lane) * 16));
+        T::put(R, rld, 4 * cb + g, 16 * ob + l16, zb);
+        if (bsum) bsum[q] += zb.x;
+      }
+    }
+  };
+  if (count > 0) async_copy(STG, zb_src(rb), zb_bytes);
+
+  if (role == 0) {
+    // ---- input adjoint and activation adjoint
+    Raw wreg[NIBW][KC];  // B operand fragments of the owned input blocks, all chunks
+#pragma unroll
+    for (int q = 0; q < NIBW; ++q)
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) wreg[q][kc] = glob_frag(ly.wb, wave + 8 * q, kc, KC, lane);
+    for (int64_t k = 0; k < count; ++k) {
+      const int64_t s = rb + k * G;
+      const int64_t cb0 = s * CPB;
+      if (k == 0)
+        wait_vm<0>();
+      else
+        wait_vm<S::NSTORE>();  // the staged adjoint; the previous sub-tile's stores may run on
+      barrier_lds();
+      load_zp(s);
+      convert(nullptr);
+      barrier_lds();  // R complete; STG free
+      if (k + 1 < count) async_copy(STG, zb_src(s + G), zb_bytes);
+      f4 acca[NIBW][CPB];
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q)
+#pragma unroll
+        for (int cb = 0; cb < CPB; ++cb) acca[q][cb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        Raw a[CPB];
+#pragma unroll
+        for (int cb = 0; cb < CPB; ++cb) a[cb] = T::load(R, rld, cb, kc, lane);
+        Raw bq[NIBW];
+#pragma unroll
+        for (int q = 0; q < NIBW; ++q) bq[q] = wreg[q][kc];
+        Pr::template mma_tile<NIBW, CPB>(acca, a, bq);
+      }
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q) {
+        const int ib = wave + 8 * q;
+#pragma unroll
+        for (int cb = 0; cb < CPB; ++cb) {
+          const f4 z = zp[q][cb];
+          float s0v, s1v, s2v, s3v;
+          act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
+          const f4 zb = jet_act_adj<kLap>(z, acca[q][cb], s1v, s2v, s3v, lw1, lw2);
+          *jet_frag(A.zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
+        }
+      }
+    }
+  } else {
+    // ---- weight and bias gradient
+    f4 accw[NOB][NIBW];
+#pragma unroll
+    for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q) accw[ob][q] = f4{0.f, 0.f, 0.f, 0.f};
+    float bsum[NOBC];
+#pragma unroll
+    for (int q = 0; q < NOBC; ++q) bsum[q] = 0.f;
+    for (int64_t k = 0; k < count; ++k) {
+      const int64_t s = rb + k * G;
+      wait_vm<0>();
+      barrier_lds();  // sub-tile s staged; the previous sub-tile is done with R
+      load_zp(s);
+      convert(bsum);
+      barrier_lds();  // R complete; STG free
+      if (k + 1 < count) async_copy(STG, zb_src(s + G), zb_bytes);
+      Raw aop[NIBW][CPB / 2];
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q)
+#pragma unroll
+        for (int cc = 0; cc < CPB / 2; ++cc) {
+          float f[8];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const f4 z = zp[q][2 * cc + h];
+            float s0v, s1v, s2v, s3v;
+            act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
+            const f4 a = jet_act<kLap>(z, s0v, s1v, s2v, lw1, lw2);
+            f[4 * h] = a.x;
+            f[4 * h + 1] = a.y;
+            f[4 * h + 2] = a.z;
+            f[4 * h + 3] = a.w;
+          }
+          aop[q][cc] = Pr::make(f);
+        }
+#pragma unroll
+      for (int cc = 0; cc < CPB / 2; ++cc) {
+        Raw ao = wide_zbar_op(R, rld, 0, cc, lane);
+#pragma unroll
+        for (int ob = 0; ob < NOB; ++ob) {
+          Raw an = ao;
+          if (ob + 1 < NOB) an = wide_zbar_op(R, rld, ob + 1, cc, lane);
+#pragma unroll
+          for (int q = 0; q < NIBW; ++q) Pr::mma(accw[ob][q], ao, aop[q][cc]);
+          ao = an;
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+    // flush: slot rb, [n_out][n_in] then [n_out]
+    double* slot = A.slots + (size_t)rb * n_out * (n_in + 1);
+#pragma unroll
+    for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q) {
+        const int ib = wave + 8 * q;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) slot[(size_t)(16 * ob + 4 * g + r) * n_in + 16 * ib + l16] = (double)accw[ob][q][r];
+      }
+#pragma unroll
+    for (int q = 0; q < NOBC; ++q) {
+      const int ob = wave + 8 * q;
+      float v = bsum[q];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      if (g == 0) slot[(size_t)n_out * n_in + 16 * ob + l16] = (double)v;
+    }
+  }
 }
 
 // ================================================================== first layer, identity
@@ -1853,8 +2068,26 @@ int bwd_wide(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
   return status(hipGetLastError());
 }
 
+template <int ACT, int H>
+int bwd_split(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
+  if constexpr (H >= 128) {
+    auto k = k_backward_split<ACT, H / 16, H / 16, wide_pb(H)>;
+    if (set_lds(k, lds)) return -5;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, a);
+    return status(hipGetLastError());
+  }
+  return -2;
+}
+
 template <int PREC, int ACT, int H>
 int bwd_e(bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
+  if constexpr (PREC == kBF16X3) {
+    if (a.wide == 2 && !embed) {
+      // split-role kernel: layer widths must be exactly H (uniform hidden layers)
+      if (a.net.layer[a.layer].n_in != H || a.net.layer[a.layer].n_out != H || grid % 16 != 0) return -2;
+      return bwd_split<ACT, H>(a, grid, lds, s);
+    }
+  }
   if constexpr (PREC == kBF16X3) {
     // wide path (chosen by the plan): input widths that are multiples of 128
     constexpr int PW = wide_pb(H);
