@@ -60,6 +60,25 @@ def kernel_flops(net, pde, n_points):
     return out, step * n_points
 
 
+def measured_traffic(config, kernel):
+    """HBM bytes per launch of `kernel` on this workload from the committed counter summary
+    (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by the copy calibration), or None when no
+    summary exists or the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_bf16x3_traffic.json" % config)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_2604_15645_amd", "csrc", "pinn_kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    k = rec.get("kernels", {}).get(kernel)
+    if rec.get("source_sha256") != sha or k is None:
+        return None
+    return k["hbm_bytes_per_launch"]
+
+
 def make_inputs(name, n_points, dev):
     import numpy as np
     import torch
@@ -115,7 +134,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="maxwell", help="burgers | euler | ns | maxwell")
     ap.add_argument("--points", type=int, default=0, help="override the point count")
-    ap.add_argument("--sample", type=int, default=16384, help="CPU-baseline / parity prefix")
+    ap.add_argument("--sample", type=int, default=65536, help="CPU-baseline / parity prefix")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -167,7 +186,8 @@ def main():
         achieved = n_prod * alg / (avg_ms / 1e3)
         roof = {"kernel": dom, "bound": "mfma", "achieved": achieved / 1e12,
                 "peak": PEAK["bf16"] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK["bf16"], "traffic": None,
+                "frac": achieved / PEAK["bf16"],
+                "traffic": measured_traffic(name, dom) if n_points == synth.CONFIGS[name]["n_points"] else None,
                 "alg_flops_per_launch": alg, "n_prod": n_prod, "avg_launch_ms": avg_ms}
 
     result = {
