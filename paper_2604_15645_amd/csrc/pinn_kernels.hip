@@ -1665,10 +1665,28 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
     for (int64_t k = 0; k < count; ++k) {
       const int64_t s = rb + k * G;
       wait_vm<0>();
-      barrier_lds();  // sub-tile s staged; the previous sub-tile is done with R
+      barrier_lds();  // sub-tile s staged; the previous sub-tile is done with ZT
       load_zp(s);
-      convert(bsum);
-      barrier_lds();  // R complete; STG free
+      // output adjoint as weight-gradient A operands in the ZT layout: for output block ob
+      // and cp chunk cc, lane (g, l16) holds 8 cp of output 16 ob + l16 (points 8 cc + g,
+      // 8 cc + 4 + g, accumulator order), bf16 hi then lo, 32 bytes per lane
+#pragma unroll
+      for (int q = 0; q < NOBC; ++q) {
+        const int ob = wave + 8 * q;
+#pragma unroll
+        for (int cc = 0; cc < CPB / 2; ++cc) {
+          const float* f0 = reinterpret_cast<const float*>(STG + ((size_t)((2 * cc) * nob + ob) * 64 + lane) * 16);
+          const float* f1 = reinterpret_cast<const float*>(STG + ((size_t)((2 * cc + 1) * nob + ob) * 64 + lane) * 16);
+          const float4 v0 = *reinterpret_cast<const float4*>(f0), v1 = *reinterpret_cast<const float4*>(f1);
+          const float f[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+          const Raw op = Pr::make(f);
+          uint4* d = reinterpret_cast<uint4*>(R + ((size_t)(ob * (CPB / 2) + cc) * 64 + lane) * 32);
+          d[0] = op.a;
+          d[1] = op.b;
+          bsum[q] += v0.x + v1.x;
+        }
+      }
+      barrier_lds();  // ZT complete; STG free
       if (k + 1 < count) async_copy(STG, zb_src(s + G), zb_bytes);
       Raw aop[NIBW][CPB / 2];
 #pragma unroll
@@ -1691,11 +1709,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
         }
 #pragma unroll
       for (int cc = 0; cc < CPB / 2; ++cc) {
-        Raw ao = wide_zbar_op(R, rld, 0, cc, lane);
+        Raw ao = lds_unit(R, 0 * (CPB / 2) + cc, lane, 64 * 32);
 #pragma unroll
         for (int ob = 0; ob < NOB; ++ob) {
           Raw an = ao;
-          if (ob + 1 < NOB) an = wide_zbar_op(R, rld, ob + 1, cc, lane);
+          if (ob + 1 < NOB) an = lds_unit(R, (ob + 1) * (CPB / 2) + cc, lane, 64 * 32);
 #pragma unroll
           for (int q = 0; q < NIBW; ++q) Pr::mma(accw[ob][q], ao, aop[q][cc]);
           ao = an;
