@@ -482,7 +482,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.zb_out = nullptr;
       a.z_prev = nullptr;
       a.slots = wk.layer_slots[0];
-      a.wide = p.wide0;
+      a.wide = p.wide0 ? (D.n_out[0] == D.H && D.H >= 64 ? 3 : 1) : 0;
       rc = timed("k_backward_embed", stream, [&] { return launch_backward(prec, act_code(net, pde), D.H, true, a, p.grid_b0, p.lds_b0, stream); });
       if (rc) return rc;
     } else {

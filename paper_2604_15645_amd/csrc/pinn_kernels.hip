@@ -1541,10 +1541,10 @@ template <int NOB, int NIB, int PB>
 struct SplitShape {
   static constexpr int CPB = PB / 4;
   static constexpr int NIBW = NIB / 8;   // input blocks per wave
-  static constexpr int NOBC = NOB / 8;   // output blocks converted per wave
+  static constexpr int NOBC = (NOB + 7) / 8;  // output blocks converted per wave
   static constexpr int KC = NOB / 2;     // reduction chunks of the input adjoint (n_out / 32)
   static constexpr int NSTORE = NIBW * CPB;  // adjoint stores per lane and sub-tile
-  static_assert(NIB % 8 == 0 && NOB % 8 == 0 && CPB % 2 == 0, "split backward shape");
+  static_assert(NIB % 8 == 0 && CPB % 2 == 0, "split backward shape");
 };
 
 // s_waitcnt with only the vector-memory count bounded (gfx9 encoding: vmcnt in bits 3:0
@@ -1555,7 +1555,60 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
-template <int ACT, int NOB, int NIB, int PB>
+// Input-adjoint product of the split backward's first role, with the copy of the next
+// sub-tile's adjoint into STG started first.  STG and R are distinct LDS regions; the
+// restrict qualifiers let the compiler's wait insertion see that the tile reads do not
+// depend on the copy.
+template <int NIBW, int CPB, int KC>
+__device__ __forceinline__ void split_adjoint_product(f4 (&acca)[NIBW][CPB], char* __restrict__ STG,
+                                                      const char* __restrict__ R, int rld,
+                                                      const Raw (&wreg)[NIBW][KC], const char* next, int bytes,
+                                                      int lane) {
+  if (next) async_copy(STG, next, bytes);
+#pragma unroll
+  for (int q = 0; q < NIBW; ++q)
+#pragma unroll
+    for (int cb = 0; cb < CPB; ++cb) acca[q][cb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+    Raw a[CPB];
+#pragma unroll
+    for (int cb = 0; cb < CPB; ++cb) a[cb] = Tile<kBF16X3>::load(R, rld, cb, kc, lane);
+    Raw bq[NIBW];
+#pragma unroll
+    for (int q = 0; q < NIBW; ++q) bq[q] = wreg[q][kc];
+    Prec<kBF16X3>::template mma_tile<NIBW, CPB>(acca, a, bq);
+  }
+  // work that waits on vector memory (the pre-activations) stays after the product, so the
+  // copy started above runs under it
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Weight-gradient product of the split backward's second role (A operands from the ZT
+// tile, B operands in registers), with the copy of the next sub-tile's adjoint into STG
+// started first; the restrict qualifiers tell the compiler's wait insertion that the ZT
+// reads do not depend on the copy.
+template <int NOB, int NIBW, int CPB>
+__device__ __forceinline__ void split_weight_grad_product(f4 (&accw)[NOB][NIBW], const Raw (&aop)[NIBW][CPB / 2],
+                                                          char* __restrict__ STG, const char* __restrict__ ZT,
+                                                          const char* next, int bytes, int lane) {
+  if (next) async_copy(STG, next, bytes);
+#pragma unroll
+  for (int cc = 0; cc < CPB / 2; ++cc) {
+    Raw ao = lds_unit(ZT, cc, lane, 64 * 32);
+#pragma unroll
+    for (int ob = 0; ob < NOB; ++ob) {
+      Raw an = ao;
+      if (ob + 1 < NOB) an = lds_unit(ZT, (ob + 1) * (CPB / 2) + cc, lane, 64 * 32);
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q) Prec<kBF16X3>::mma(accw[ob][q], ao, aop[q][cc]);
+      ao = an;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+template <int ACT, int NOB, int NIB, int PB, bool EMB>
 __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A) {
   using S = SplitShape<NOB, NIB, PB>;
   using Pr = Prec<kBF16X3>;
@@ -1577,10 +1630,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
   char* R = smem + (size_t)PB * NOB * 256;
   const int zb_bytes = CPB * nob * 1024;
   // role and index within the role (blocks b and b + 8 share a sub-tile sequence)
+  // (EMB: the Fourier-embedding layer -- weight gradient only, every work-group)
   const int b = blockIdx.x;
-  const int role = (b >> 3) & 1;
-  const int rb = ((b >> 4) << 3) | (b & 7);
-  const int G = gridDim.x >> 1;
+  const int role = EMB ? 1 : (b >> 3) & 1;
+  const int rb = EMB ? b : ((b >> 4) << 3) | (b & 7);
+  const int G = EMB ? gridDim.x : gridDim.x >> 1;
   const int64_t count = A.n_sub > rb ? (A.n_sub - rb + G - 1) / G : 0;
   auto zb_src = [&](int64_t s) { return reinterpret_cast<const char*>(A.zb_in) + s * zb_bytes; };
   f4 zp[NIBW][CPB];
@@ -1595,6 +1649,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
 #pragma unroll
     for (int q = 0; q < NOBC; ++q) {
       const int ob = wave + 8 * q;
+      if (ob >= NOB) continue;
 #pragma unroll
       for (int cb = 0; cb < CPB; ++cb) {
         const f4 zb = to_f4(*reinterpret_cast<const float4*>(STG + ((size_t)(cb * nob + ob) * 64 + lane) * 16));
@@ -1605,13 +1660,14 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
   };
   if (count > 0) async_copy(STG, zb_src(rb), zb_bytes);
 
-  if (role == 0) {
+  if (!EMB && role == 0) {
     // ---- input adjoint and activation adjoint
     Raw wreg[NIBW][KC];  // B operand fragments of the owned input blocks, all chunks
 #pragma unroll
     for (int q = 0; q < NIBW; ++q)
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) wreg[q][kc] = glob_frag(ly.wb, wave + 8 * q, kc, KC, lane);
+    wait_vm<0>();  // resident from here on: no wait for them inside the loop
     for (int64_t k = 0; k < count; ++k) {
       const int64_t s = rb + k * G;
       const int64_t cb0 = s * CPB;
@@ -1620,25 +1676,12 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
       else
         wait_vm<S::NSTORE>();  // the staged adjoint; the previous sub-tile's stores may run on
       barrier_lds();
-      load_zp(s);
       convert(nullptr);
+      load_zp(s);  // after the staged reads: waiting for these must not wait for the next copy
       barrier_lds();  // R complete; STG free
-      if (k + 1 < count) async_copy(STG, zb_src(s + G), zb_bytes);
       f4 acca[NIBW][CPB];
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-#pragma unroll
-        for (int cb = 0; cb < CPB; ++cb) acca[q][cb] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kc = 0; kc < KC; ++kc) {
-        Raw a[CPB];
-#pragma unroll
-        for (int cb = 0; cb < CPB; ++cb) a[cb] = T::load(R, rld, cb, kc, lane);
-        Raw bq[NIBW];
-#pragma unroll
-        for (int q = 0; q < NIBW; ++q) bq[q] = wreg[q][kc];
-        Pr::template mma_tile<NIBW, CPB>(acca, a, bq);
-      }
+      split_adjoint_product<NIBW, CPB, KC>(acca, STG, R, rld, wreg, k + 1 < count ? zb_src(s + G) : nullptr,
+                                           zb_bytes, lane);
 #pragma unroll
       for (int q = 0; q < NIBW; ++q) {
         const int ib = wave + 8 * q;
@@ -1662,17 +1705,18 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
     float bsum[NOBC];
 #pragma unroll
     for (int q = 0; q < NOBC; ++q) bsum[q] = 0.f;
+    if (!EMB && count > 0) load_zp(rb);
     for (int64_t k = 0; k < count; ++k) {
       const int64_t s = rb + k * G;
       wait_vm<0>();
-      barrier_lds();  // sub-tile s staged; the previous sub-tile is done with ZT
-      load_zp(s);
+      barrier_lds();  // sub-tile s staged and its pre-activations loaded; ZT free
       // output adjoint as weight-gradient A operands in the ZT layout: for output block ob
       // and cp chunk cc, lane (g, l16) holds 8 cp of output 16 ob + l16 (points 8 cc + g,
       // 8 cc + 4 + g, accumulator order), bf16 hi then lo, 32 bytes per lane
 #pragma unroll
       for (int q = 0; q < NOBC; ++q) {
         const int ob = wave + 8 * q;
+        if (ob >= NOB) continue;
 #pragma unroll
         for (int cc = 0; cc < CPB / 2; ++cc) {
           const float* f0 = reinterpret_cast<const float*>(STG + ((size_t)((2 * cc) * nob + ob) * 64 + lane) * 16);
@@ -1687,7 +1731,6 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
         }
       }
       barrier_lds();  // ZT complete; STG free
-      if (k + 1 < count) async_copy(STG, zb_src(s + G), zb_bytes);
       Raw aop[NIBW][CPB / 2];
 #pragma unroll
       for (int q = 0; q < NIBW; ++q)
@@ -1696,10 +1739,20 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
           float f[8];
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
-            const f4 z = zp[q][2 * cc + h];
-            float s0v, s1v, s2v, s3v;
-            act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
-            const f4 a = jet_act<kLap>(z, s0v, s1v, s2v, lw1, lw2);
+            f4 a;
+            if constexpr (EMB) {
+              // Fourier-feature jets: column i < m is cos(x B_i), column i >= m sin(x B_{i-m})
+              const int m = net.n_freq;
+              const int i = 16 * (wave + 8 * q) + l16;
+              f4 cj, sj;
+              rff_jets(net, A.work.pts[(int64_t)s * PB + 4 * (2 * cc + h) + g], i < m ? i : i - m, cj, sj);
+              a = i < m ? cj : sj;
+            } else {
+              const f4 z = zp[q][2 * cc + h];
+              float s0v, s1v, s2v, s3v;
+              act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
+              a = jet_act<kLap>(z, s0v, s1v, s2v, lw1, lw2);
+            }
             f[4 * h] = a.x;
             f[4 * h + 1] = a.y;
             f[4 * h + 2] = a.z;
@@ -1707,19 +1760,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
           }
           aop[q][cc] = Pr::make(f);
         }
-#pragma unroll
-      for (int cc = 0; cc < CPB / 2; ++cc) {
-        Raw ao = lds_unit(R, 0 * (CPB / 2) + cc, lane, 64 * 32);
-#pragma unroll
-        for (int ob = 0; ob < NOB; ++ob) {
-          Raw an = ao;
-          if (ob + 1 < NOB) an = lds_unit(R, (ob + 1) * (CPB / 2) + cc, lane, 64 * 32);
-#pragma unroll
-          for (int q = 0; q < NIBW; ++q) Pr::mma(accw[ob][q], ao, aop[q][cc]);
-          ao = an;
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      }
+      if (!EMB && k + 1 < count) load_zp(s + G);  // the next sub-tile's pre-activations load under the product
+      split_weight_grad_product<NOB, NIBW, CPB>(accw, aop, STG, R, k + 1 < count ? zb_src(s + G) : nullptr,
+                                                zb_bytes, lane);
     }
     // flush: slot rb, [n_out][n_in] then [n_out]
     double* slot = A.slots + (size_t)rb * n_out * (n_in + 1);
@@ -1737,7 +1780,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
       float v = bsum[q];
       v += __shfl_xor(v, 16, 64);
       v += __shfl_xor(v, 32, 64);
-      if (g == 0) slot[(size_t)n_out * n_in + 16 * ob + l16] = (double)v;
+      if (g == 0 && ob < NOB) slot[(size_t)n_out * n_in + 16 * ob + l16] = (double)v;
     }
   }
 }
@@ -2086,13 +2129,28 @@ int bwd_wide(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
   return status(hipGetLastError());
 }
 
+template <int ACT, int NOB, int NIB, int PB, bool EMB>
+int split_k(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
+  auto k = k_backward_split<ACT, NOB, NIB, PB, EMB>;
+  if (set_lds(k, lds)) return -5;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, a);
+  return status(hipGetLastError());
+}
+
 template <int ACT, int H>
 int bwd_split(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  if constexpr (H >= 128) {
-    auto k = k_backward_split<ACT, H / 16, H / 16, wide_pb(H)>;
-    if (set_lds(k, lds)) return -5;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, a);
-    return status(hipGetLastError());
+  if constexpr (H >= 128) return split_k<ACT, H / 16, H / 16, wide_pb(H), false>(a, grid, lds, s);
+  return -2;
+}
+
+// Fourier-embedding layer (weight gradient only): embedding width 128 or 256.
+template <int ACT, int H>
+int bwd_split_embed(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
+  const int n_in = a.net.layer[0].n_in, n_out = a.net.layer[0].n_out;
+  if (n_out != H || n_in % 128 != 0) return -2;
+  if constexpr (H >= 64) {
+    if (n_in == 128) return split_k<ACT, H / 16, 8, wide_pb(H), true>(a, grid, lds, s);
+    if (n_in == 256) return split_k<ACT, H / 16, 16, wide_pb(H), true>(a, grid, lds, s);
   }
   return -2;
 }
@@ -2105,6 +2163,7 @@ int bwd_e(bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
       if (a.net.layer[a.layer].n_in != H || a.net.layer[a.layer].n_out != H || grid % 16 != 0) return -2;
       return bwd_split<ACT, H>(a, grid, lds, s);
     }
+    if (a.wide == 3 && embed) return bwd_split_embed<ACT, H>(a, grid, lds, s);
   }
   if constexpr (PREC == kBF16X3) {
     // wide path (chosen by the plan): input widths that are multiples of 128
