@@ -137,6 +137,8 @@ def main():
     ap.add_argument("--sample", type=int, default=65536, help="CPU-baseline / parity prefix")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--tile-points", type=int, default=0, help="forward tile points (0 = the library's)")
+    ap.add_argument("--grid", type=int, default=0, help="work-group cap (0 = the library's)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -166,7 +168,8 @@ def main():
     net, pde = case["net"], case["pde"]
     n_total = n_points + sum(len(a["points"]) for a in case["anchors"])
 
-    ms16, k16, out16 = time_steps(case, params, B, pts, anchors, "bf16x3", args.steps, args.warmup)
+    tune = {"tile_points": args.tile_points, "grid": args.grid} if args.tile_points or args.grid else None
+    ms16, k16, out16 = time_steps(case, params, B, pts, anchors, "bf16x3", args.steps, args.warmup, tune)
     fp32 = None
     if not args.no_fp32:
         ms32, k32, out32 = time_steps(case, params, B, pts, anchors, "fp32",
@@ -204,7 +207,8 @@ def main():
         "dtype": "bf16x3",
         "data": "synthetic",
         "config": {"workload": "%s: %s" % (name, describe(net, pde, n_points)),
-                   "points": n_points, "params": synth.param_count(net), "parallelism": "none"},
+                   "points": n_points, "params": synth.param_count(net), "parallelism": "none",
+                   **({"tune": tune} if tune else {})},
         "step_alg_tflop": step_flops / 1e12,
         "step_mfma_frac": n_prod * step_flops / (ms16 / 1e3) / PEAK["bf16"],
         "kernels_ms": {k: v[1] / v[0] for k, v in k16.items()},

@@ -230,7 +230,10 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   p.n_sub0 = p.n_pad / p.pb0;
   int cap = kGridCap;
   if (tune && tune->grid > 0) cap = tune->grid;
-  p.grid_f = (int)std::min<int64_t>(p.n_tiles, cap);
+  // 16-point forward tiles are compiled for two resident work-groups per compute unit
+  // (at most 128 registers per lane); give the launch twice the work-groups when their LDS fits.
+  const int cap_f = p.pf <= 16 && 2 * p.lds_f <= kLdsBudget && !(tune && tune->grid > 0) ? 2 * cap : cap;
+  p.grid_f = (int)std::min<int64_t>(p.n_tiles, cap_f);
   p.grid_b = (int)std::min<int64_t>(p.n_sub, cap);
   if (p.split) {  // two roles of G work-groups each, G a multiple of 8
     const int64_t G = std::min<int64_t>(align_up(std::min<int64_t>(p.n_sub, cap / 2), 8), std::max(8, cap / 2 / 8 * 8));

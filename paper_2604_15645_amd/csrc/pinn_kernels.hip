@@ -320,42 +320,30 @@ __device__ __forceinline__ float4* jet_frag(float* buf, int64_t cb, int nb, int 
 // Every block index must be valid (callers clamp them; results of clamped duplicates are
 // discarded), so the loop body has no branches and the products of one chunk issue back
 // to back over independent accumulators.
-template <int PREC, int NB, int CB>
+template <int PREC, int NB, int CB, int CGMAX = 8, bool PREFETCH = false>
 __device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int ld, int cb0,
                                           const char* frags, int kchunks, const int (&blk)[NB], int lane) {
   const char* fb[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) fb[i] = frags + ((size_t)blk[i] * kchunks * 64 + lane) * 32;
-  constexpr int CG = CB > 8 ? 8 : CB;  // A fragments live at a time
+  constexpr int CG = CB > CGMAX ? CGMAX : CB;  // A fragments live at a time
   static_assert(CB % CG == 0, "cp blocks per wave");
-  Raw bw[NB];
-#if PINN_PREFETCH_B
-  // weight fragments of chunk kc + 1 are loaded while chunk kc is multiplied
-#pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    const uint4* p = reinterpret_cast<const uint4*>(fb[i]);
-    bw[i].a = p[0];
-    bw[i].b = p[1];
-  }
-#endif
-  for (int kc = 0; kc < kchunks; ++kc) {
-#if PINN_PREFETCH_B
-    Raw bn[NB];
-    const int kn = kc + 1 < kchunks ? kc + 1 : kc;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const uint4* p = reinterpret_cast<const uint4*>(fb[i] + (size_t)kn * 2048);
-      bn[i].a = p[0];
-      bn[i].b = p[1];
-    }
-#else
+  auto load_b = [&](Raw (&b)[NB], int kc) {
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const uint4* p = reinterpret_cast<const uint4*>(fb[i] + (size_t)kc * 2048);
-      bw[i].a = p[0];
-      bw[i].b = p[1];
+      b[i].a = p[0];
+      b[i].b = p[1];
     }
-#endif
+  };
+  Raw bw[NB];
+  if (PREFETCH) load_b(bw, 0);  // weight fragments of chunk kc + 1 load while chunk kc multiplies
+  for (int kc = 0; kc < kchunks; ++kc) {
+    Raw bn[NB];
+    if (PREFETCH)
+      load_b(bn, kc + 1 < kchunks ? kc + 1 : kc);
+    else
+      load_b(bw, kc);
 #pragma unroll
     for (int c0 = 0; c0 < CB; c0 += CG) {
       Raw a[CG];
@@ -373,10 +361,10 @@ __device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int 
 #pragma unroll
         for (int c = 0; c < CG; ++c) part[i][c0 + c] = sub[i][c];
     }
-#if PINN_PREFETCH_B
+    if (PREFETCH) {
 #pragma unroll
-    for (int i = 0; i < NB; ++i) bw[i] = bn[i];
-#endif
+      for (int i = 0; i < NB; ++i) bw[i] = bn[i];
+    }
   }
 }
 
@@ -849,7 +837,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       int blk[NBW];
 #pragma unroll
       for (int i = 0; i < NBW; ++i) blk[i] = min(wn + WN * i, l0.nbo - 1);
-      gemm_tile<PREC, NBW, CBW>(acc, X, ld, wc * CBW, l0.wf, l0.kci, blk, lane);
+      gemm_tile<PREC, NBW, CBW, 8, true>(acc, X, ld, wc * CBW, l0.wf, l0.kci, blk, lane);
     }
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
@@ -903,7 +891,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
         int blk[NBW];
 #pragma unroll
         for (int i = 0; i < NBW; ++i) blk[i] = min(wn + WN * i, ln.nbo - 1);
-        gemm_tile<PREC, NBW, CBW>(acc, X, ld, wc * CBW, ln.wf, ln.kci, blk, lane);
+        gemm_tile<PREC, NBW, CBW, 8, true>(acc, X, ld, wc * CBW, ln.wf, ln.kci, blk, lane);
       }
 #pragma unroll
       for (int i = 0; i < NBW; ++i) {
@@ -1039,7 +1027,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
 }
 
 template <int PREC, int ACT, int H, int P>
-__global__ __launch_bounds__(kThreads, 1) void k_forward(const FwdArgs A) {
+__global__ __launch_bounds__(kThreads, P <= 16 ? 4 : 1) void k_forward(const FwdArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const FwdLds s = fwd_carve<H, P>(smem, r_stride(A.kmax));
   const int ld = Tile<PREC>::ld(A.kmax, P);
