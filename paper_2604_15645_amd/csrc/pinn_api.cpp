@@ -133,6 +133,7 @@ size_t fwd_lds(int P, int kmax, int H) {
   b += kWaves * 4 * 4;                           // RED
   b += kMaxTerms * 8;                            // LOSS
   b += (size_t)WC * 3 * H * 8 + 3 * 8;           // WL, BL
+  b += kFourierLds;                              // BF
   return b;
 }
 // Layer backward: staged output adjoint (and staged input pre-activations), Q tile, and
@@ -223,17 +224,14 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   p.pb0 = wide0 ? wide_pb(D.H) : embed_bwd_p(D.H);
   p.lds_f = fwd_lds(p.pf, p.kmax, D.H);
   p.lds_b = wide ? (size_t)2 * p.pb * D.H * 16 : bwd_lds(p.pb, D.H, D.H, true);
-  p.lds_b0 = wide0 ? (size_t)2 * p.pb0 * D.H * 16 : bwd_lds(p.pb0, 256, D.H, false);
+  p.lds_b0 = wide0 ? (size_t)2 * p.pb0 * D.H * 16 + kFourierLds : bwd_lds(p.pb0, 256, D.H, false);
   if (p.lds_b > kLdsBudget || p.lds_b0 > kLdsBudget) return PINN_E_UNSUPPORTED;
   p.n_tiles = p.n_pad / p.pf;
   p.n_sub = p.n_pad / p.pb;
   p.n_sub0 = p.n_pad / p.pb0;
   int cap = kGridCap;
   if (tune && tune->grid > 0) cap = tune->grid;
-  // 16-point forward tiles are compiled for two resident work-groups per compute unit
-  // (at most 128 registers per lane); give the launch twice the work-groups when their LDS fits.
-  const int cap_f = p.pf <= 16 && 2 * p.lds_f <= kLdsBudget && !(tune && tune->grid > 0) ? 2 * cap : cap;
-  p.grid_f = (int)std::min<int64_t>(p.n_tiles, cap_f);
+  p.grid_f = (int)std::min<int64_t>(p.n_tiles, cap);
   p.grid_b = (int)std::min<int64_t>(p.n_sub, cap);
   if (p.split) {  // two roles of G work-groups each, G a multiple of 8
     const int64_t G = std::min<int64_t>(align_up(std::min<int64_t>(p.n_sub, cap / 2), 8), std::max(8, cap / 2 / 8 * 8));

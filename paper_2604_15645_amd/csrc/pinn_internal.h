@@ -17,6 +17,8 @@ constexpr int kWaves = 8;
 constexpr int kRedThreads = 1024;  // reduction blocks: kRedGroups slot groups x 256 columns
 constexpr int kRedGroups = 4;
 constexpr int kThreads = 64 * kWaves;
+constexpr int kMaxFreq = 128;                     // Fourier frequencies (2 m <= 256)
+constexpr int kFourierLds = 3 * kMaxFreq * 4;     // LDS bytes of a staged Fourier matrix
 
 enum { kFP32 = 0, kBF16X3 = 1 };
 enum { kTanh = 0, kSin = 1 };

@@ -314,15 +314,44 @@ __device__ __forceinline__ float4* jet_frag(float* buf, int64_t cb, int nb, int 
   return reinterpret_cast<float4*>(buf) + ((cb * nbs + nb) * 64 + lane);
 }
 
+// Jet-fragment stores of one tile through a buffer resource over the tile's bytes: a store
+// switched off by a wave-uniform condition goes to an offset past the end, which the
+// hardware drops, instead of behind a branch.  The number of vector-memory operations a wave
+// has issued then does not depend on the condition, so later waits for loads issued before
+// these stores can leave the stores in flight.
+struct FragStore {
+  __amdgpu_buffer_rsrc_t r;
+  int nbs;
+  __device__ __forceinline__ FragStore(float* buf, int64_t cb0, int ncb, int nbs_) : nbs(nbs_) {
+    r = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<float4*>(buf) + cb0 * nbs_ * 64, (short)0,
+                                          ncb * nbs_ * 1024, 0x00020000);
+  }
+  // cp block cb (relative to cb0), neuron block nb, stored only when ok
+  __device__ __forceinline__ void put(int cb, int nb, int lane, f4 v, bool ok) const {
+    typedef __attribute__((ext_vector_type(4))) unsigned u4v;
+    // the condition goes through a register the compiler cannot see into, so that it selects
+    // the offset instead of duplicating the code around a branch
+    int okv = ok;
+    asm volatile("" : "+v"(okv));
+    const unsigned off = okv ? (unsigned)(((cb * nbs + nb) * 64 + lane) * 16) : 0x80000000u;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, v), r, off, 0, 0);
+  }
+};
+
 // acc[i][c] += A(cp block cb0 + c) * W(block blk[i])^T over all reduction chunks: the A
 // operand comes from a jet tile in LDS (Tile<PREC>), the B operand from fragment-major
 // weights.
 // Every block index must be valid (callers clamp them; results of clamped duplicates are
 // discarded), so the loop body has no branches and the products of one chunk issue back
 // to back over independent accumulators.
-template <int PREC, int NB, int CB, int CGMAX = 8, bool PREFETCH = false>
+// PRE: the weight fragments of chunks 0 and 1 (chunk 0 again when there is one chunk) come
+// in pre0 / pre1, loaded by the caller before its own stores, so that waiting for them does
+// not wait for those stores (vector-memory counters complete in issue order).
+template <int PREC, int NB, int CB, int CGMAX = 8, bool PREFETCH = false, bool PRE = false>
 __device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int ld, int cb0,
-                                          const char* frags, int kchunks, const int (&blk)[NB], int lane) {
+                                          const char* frags, int kchunks, const int (&blk)[NB], int lane,
+                                          const Raw (&pre0)[NB], const Raw (&pre1)[NB]) {
+  static_assert(!PRE || PREFETCH, "preloaded chunks need the prefetching loop");
   const char* fb[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) fb[i] = frags + ((size_t)blk[i] * kchunks * 64 + lane) * 32;
@@ -337,13 +366,22 @@ __device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int 
     }
   };
   Raw bw[NB];
-  if (PREFETCH) load_b(bw, 0);  // weight fragments of chunk kc + 1 load while chunk kc multiplies
+  if (PRE) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) bw[i] = pre0[i];
+  } else if (PREFETCH) {
+    load_b(bw, 0);  // weight fragments of chunk kc + 1 load while chunk kc multiplies
+  }
   for (int kc = 0; kc < kchunks; ++kc) {
     Raw bn[NB];
-    if (PREFETCH)
+    if (PRE && kc == 0) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) bn[i] = pre1[i];
+    } else if (PREFETCH) {
       load_b(bn, kc + 1 < kchunks ? kc + 1 : kc);
-    else
+    } else {
       load_b(bw, kc);
+    }
 #pragma unroll
     for (int c0 = 0; c0 < CB; c0 += CG) {
       Raw a[CG];
@@ -365,6 +403,24 @@ __device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int 
 #pragma unroll
       for (int i = 0; i < NB; ++i) bw[i] = bn[i];
     }
+  }
+}
+
+template <int PREC, int NB, int CB, int CGMAX = 8, bool PREFETCH = false>
+__device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int ld, int cb0,
+                                          const char* frags, int kchunks, const int (&blk)[NB], int lane) {
+  Raw none[NB];
+  gemm_tile<PREC, NB, CB, CGMAX, PREFETCH, false>(acc, X, ld, cb0, frags, kchunks, blk, lane, none, none);
+}
+
+// Weight fragments of chunks 0 and 1 of blocks blk (chunk 0 twice when there is one chunk).
+template <int NB>
+__device__ __forceinline__ void load_first_chunks(Raw (&b0)[NB], Raw (&b1)[NB], const char* frags, int kchunks,
+                                                  const int (&blk)[NB], int lane) {
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    b0[i] = glob_frag(frags, blk[i], 0, kchunks, lane);
+    b1[i] = glob_frag(frags, blk[i], kchunks > 1 ? 1 : 0, kchunks, lane);
   }
 }
 
@@ -560,9 +616,9 @@ __device__ __forceinline__ int seg_of(const SegDev& seg, int64_t p) {
 
 // Fourier-feature jets of feature j (< m) for point x: cos block and sin block, channels
 // 0..3 (Sec. 2.6.1: gamma = [cos(xB), sin(xB)], derivatives by the chain rule).
-__device__ __forceinline__ void rff_jets(const NetDev& net, const float4 x, int j, f4& cj, f4& sj) {
+// B: the Fourier matrix, d_in x n_freq (global memory or a staged copy in LDS)
+__device__ __forceinline__ void rff_jets(const NetDev& net, const float* B, const float4 x, int j, f4& cj, f4& sj) {
   const int m = net.n_freq;
-  const float* B = net.B;
   float b0 = B[j], b1 = net.d_in > 1 ? B[m + j] : 0.0f, b2 = net.d_in > 2 ? B[2 * m + j] : 0.0f;
   float v = x.x * b0 + x.y * b1 + x.z * b2;
   float bl = 0.0f;
@@ -710,6 +766,7 @@ struct FwdLds {
   double* LOSS;  // [kMaxTerms] sums of squares (FP64, per work item)
   double* WL;    // [WC][3][H] output-layer weight-gradient sums
   double* BL;    // [3] output-layer bias-gradient sums
+  float* BF;     // Fourier matrix, d_in x n_freq (staged once per launch)
 };
 
 template <int H, int P>
@@ -723,13 +780,16 @@ __device__ __forceinline__ FwdLds fwd_carve(char* smem, int rs) {
   s.LOSS = reinterpret_cast<double*>(s.RED + kWaves * 4);
   s.WL = s.LOSS + kMaxTerms;
   s.BL = s.WL + FwdShape<H, P>::WC * 3 * H;
+  s.BF = reinterpret_cast<float*>(s.BL + 3);
   return s;
 }
 
+// Zero the per-launch sums and stage the Fourier matrix (read by every tile's embedding).
 template <int H, int P>
-__device__ __forceinline__ void fwd_begin(const FwdLds& s) {
+__device__ __forceinline__ void fwd_begin(const FwdLds& s, const NetDev& net) {
   for (int i = threadIdx.x; i < kMaxTerms; i += kThreads) s.LOSS[i] = 0.0;
   for (int i = threadIdx.x; i < FwdShape<H, P>::WC * 3 * H + 3; i += kThreads) s.WL[i] = 0.0;
+  for (int i = threadIdx.x; i < net.d_in * net.n_freq; i += kThreads) s.BF[i] = net.B[i];
 }
 
 // Write the accumulated sums of a run of tiles: loss terms, and (with the gradient) the
@@ -824,7 +884,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       const int pb = b / nj, jb = b - (b / nj) * nj;
       const int p = 4 * pb + g, j = 16 * jb + l16;
       f4 cj, sj;
-      rff_jets(net, s.PT[p], j, cj, sj);
+      rff_jets(net, s.BF, s.PT[p], j, cj, sj);
       Tile<PREC>::put(X, ld, p, j, cj);
       Tile<PREC>::put(X, ld, p, m + j, sj);
     }
@@ -848,71 +908,104 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
     }
   }
 
+  // Small tiles keep the last hidden layer's pre-activation jets in the accumulators until
+  // the output layer's backward below; no later kernel reads that layer's stash, so it is
+  // written only when the jets are read back from it here.
+  constexpr bool kLive = CBW <= 8;
+  // Early weight loads (the next layer's first chunks before the stash stores, the output
+  // layer's chunks all at once) cost registers; the bf16x3 shapes with at most 8 cp blocks
+  // per wave have them to spare.
+  constexpr bool kPre = PREC == kBF16X3 && CBW <= 8;
+
   // ---- hidden layers: acc holds z of layer j
   for (int j = 0; j < L; ++j) {
     const LayerDev& lj = net.layer[j];
     const int nbs = lj.n_out / 16;
-    if (with_grad) {
-      float* zsj = zs + j * zs_stride;
+    // the next layer's first weight chunks and biases load before this layer's stash stores,
+    // so that the next product's first waits leave those stores in flight
+    Raw pre0[NBW], pre1[NBW];
+    int nblk[NBW];
+    float nbias[NBW];
+    const bool next = j + 1 < L;
+    if (next) {
+      const LayerDev& ln = net.layer[j + 1];
 #pragma unroll
       for (int i = 0; i < NBW; ++i) {
         const int nb = wn + WN * i;
-        if (nb < nbs)
-#pragma unroll
-          for (int c = 0; c < CBW; ++c)
-            *jet_frag(zsj, cb_st + wc * CBW + c, nb, nbs, lane) = to_float4(acc[i][c]);
+        nblk[i] = min(nb, ln.nbo - 1);
+        nbias[i] = nb < ln.nbo ? ln.b[16 * nb + l16] : 0.0f;
       }
+      if (kPre) load_first_chunks<NBW>(pre0, pre1, ln.wf, ln.kci, nblk, lane);
     }
     barrier_lds();  // every wave is done reading the layer input from X
+    // activation jets into X, each fragment's stash store issued beside its activation (the
+    // stores overlap the vector-ALU work instead of forming a burst of their own); the stores
+    // are issued unconditionally and switched off by offset (FragStore)
+    {
+      const bool keep = with_grad && !(kLive && j == L - 1);
+      const FragStore st(zs + j * zs_stride, cb_st, CPB, nbs);
 #pragma unroll
-    for (int i = 0; i < NBW; ++i) {
-      const int nb = wn + WN * i;
-      if (nb < nbs) {
+      for (int i = 0; i < NBW; ++i) {
+        const int nb = wn + WN * i;
         const int n = 16 * nb + l16;
 #pragma unroll
         for (int c = 0; c < CBW; ++c) {
           const int cb = wc * CBW + c;
-          float s0, s1, s2, s3;
-          act_eval<ACT>(acc[i][c].x, net.w0, s0, s1, s2, s3);
-          const f4 a = jet_act<(ACT & kLapFlag) != 0>(acc[i][c], s0, s1, s2, lw1, lw2);
-          Tile<PREC>::put(X, ld, 4 * cb + g, n, a);
+          st.put(cb, nb, lane, acc[i][c], keep && nb < nbs);
+          if (nb < nbs) {
+            float s0, s1, s2, s3;
+            act_eval<ACT>(acc[i][c].x, net.w0, s0, s1, s2, s3);
+            const f4 a = jet_act<(ACT & kLapFlag) != 0>(acc[i][c], s0, s1, s2, lw1, lw2);
+            Tile<PREC>::put(X, ld, 4 * cb + g, n, a);
+          }
           __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
     barrier_lds();
-    if (j + 1 < L) {
+    if (next) {
       const LayerDev& ln = net.layer[j + 1];
 #pragma unroll
       for (int i = 0; i < NBW; ++i)
 #pragma unroll
         for (int c = 0; c < CBW; ++c) acc[i][c] = f4{0.f, 0.f, 0.f, 0.f};
-      {
-        int blk[NBW];
+      gemm_tile<PREC, NBW, CBW, 8, true, kPre>(acc, X, ld, wc * CBW, ln.wf, ln.kci, nblk, lane, pre0, pre1);
 #pragma unroll
-        for (int i = 0; i < NBW; ++i) blk[i] = min(wn + WN * i, ln.nbo - 1);
-        gemm_tile<PREC, NBW, CBW, 8, true>(acc, X, ld, wc * CBW, ln.wf, ln.kci, blk, lane);
-      }
+      for (int i = 0; i < NBW; ++i)
 #pragma unroll
-      for (int i = 0; i < NBW; ++i) {
-        const int nb = wn + WN * i;
-        const float bn = nb < ln.nbo ? ln.b[16 * nb + l16] : 0.0f;
-#pragma unroll
-        for (int c = 0; c < CBW; ++c) acc[i][c].x += bn;
-      }
+        for (int c = 0; c < CBW; ++c) acc[i][c].x += nbias[i];
     }
   }
 
-  // ---- output layer (d_out <= 3 columns of one 16-wide block): waves over cp blocks
+  // ---- output layer (d_out <= 3 columns of one 16-wide block): waves over cp blocks; all
+  // weight chunks (at most 8: input width <= 256) are requested before the first is used
+  constexpr int kOutChunks = kPre ? 8 : 1;
+  Raw ow[kOutChunks];
+  if (kPre) {
+#pragma unroll
+    for (int kc = 0; kc < kOutChunks; ++kc)
+      if (kc < lout.kci) ow[kc] = glob_frag(lout.wf, 0, kc, lout.kci, lane);
+  }
+  const float obias = l16 < dout ? lout.b[l16] : 0.0f;
   for (int cb = wave; cb < CPB; cb += kWaves) {
     f4 y = f4{0.f, 0.f, 0.f, 0.f};
-    for (int kc = 0; kc < lout.kci; ++kc) {
-      const Raw bw = glob_frag(lout.wf, 0, kc, lout.kci, lane);
-      const Raw a = Tile<PREC>::load(X, ld, cb, kc, lane);
-      Pr::mma(y, a, bw);
+    if (kPre) {
+#pragma unroll
+      for (int kc = 0; kc < kOutChunks; ++kc) {
+        if (kc < lout.kci) {
+          const Raw a = Tile<PREC>::load(X, ld, cb, kc, lane);
+          Pr::mma(y, a, ow[kc]);
+        }
+      }
+    } else {
+      for (int kc = 0; kc < lout.kci; ++kc) {
+        const Raw bw = glob_frag(lout.wf, 0, kc, lout.kci, lane);
+        const Raw a = Tile<PREC>::load(X, ld, cb, kc, lane);
+        Pr::mma(y, a, bw);
+      }
     }
     if (l16 < dout) {
-      y.x += lout.b[l16];
+      y.x += obias;
       float* dst = s.YJ + ((4 * cb + g) * 3 + l16) * 4;
       *reinterpret_cast<float4*>(dst) = to_float4(y);
     }
@@ -995,7 +1088,6 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       for (int o = 0; o < 3; ++o) wo[o] = o < dout ? lout.w[o * nL + n] : 0.0f;
       // pre-activation jets of the last hidden layer: still in the accumulators when the
       // tile is small, else read back from the stash (fewer live registers)
-      constexpr bool kLive = CBW <= 8;
 #pragma unroll(kLive ? CBW : 1)
       for (int c = 0; c < CBW; ++c) {
         const int cb = wc * CBW + c;
@@ -1027,11 +1119,11 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
 }
 
 template <int PREC, int ACT, int H, int P>
-__global__ __launch_bounds__(kThreads, P <= 16 ? 4 : 1) void k_forward(const FwdArgs A) {
+__global__ __launch_bounds__(kThreads, 1) void k_forward(const FwdArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const FwdLds s = fwd_carve<H, P>(smem, r_stride(A.kmax));
   const int ld = Tile<PREC>::ld(A.kmax, P);
-  fwd_begin<H, P>(s);
+  fwd_begin<H, P>(s, A.net);
   for (int64_t tile = blockIdx.x; tile < A.n_tiles; tile += gridDim.x) {
     const int64_t p0 = tile * P;
     const int sid = seg_of(A.seg, p0);
@@ -1216,7 +1308,7 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
       for (int idx = tid; idx < PB * m; idx += kThreads) {
         const int p = idx / m, j = idx - (idx / m) * m;
         f4 cj, sj;
-        rff_jets(net, sp[p], j, cj, sj);
+        rff_jets(net, net.B, sp[p], j, cj, sj);
         const int cb = p >> 2, gg = p & 3;
         int unit, pos0;
         q_pos(cb, gg, unit, pos0);
@@ -1434,7 +1526,7 @@ __device__ __forceinline__ void bwd_wide_range(const NetDev& net, int layer, con
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             f4 cj, sj;
-            rff_jets(net, sp[4 * (2 * cc + h) + g], j, cj, sj);
+            rff_jets(net, net.B, sp[4 * (2 * cc + h) + g], j, cj, sj);
             const f4 a = i < m ? cj : sj;
             f[4 * h] = a.x;
             f[4 * h + 1] = a.y;
@@ -1616,6 +1708,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
   lap_weights(net, lw1, lw2);
   char* STG = smem;
   char* R = smem + (size_t)PB * NOB * 256;
+  float* BF = reinterpret_cast<float*>(R + (size_t)PB * NOB * 256);  // Fourier matrix (EMB)
+  if (EMB)
+    for (int i = threadIdx.x; i < net.d_in * net.n_freq; i += kThreads) BF[i] = net.B[i];
   const int zb_bytes = CPB * nob * 1024;
   // role and index within the role (blocks b and b + 8 share a sub-tile sequence)
   // (EMB: the Fourier-embedding layer -- weight gradient only, every work-group)
@@ -1733,7 +1828,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
               const int m = net.n_freq;
               const int i = 16 * (wave + 8 * q) + l16;
               f4 cj, sj;
-              rff_jets(net, A.work.pts[(int64_t)s * PB + 4 * (2 * cc + h) + g], i < m ? i : i - m, cj, sj);
+              rff_jets(net, BF, A.work.pts[(int64_t)s * PB + 4 * (2 * cc + h) + g], i < m ? i : i - m, cj, sj);
               a = i < m ? cj : sj;
             } else {
               const f4 z = zp[q][2 * cc + h];
@@ -1849,7 +1944,7 @@ __device__ __forceinline__ void run_item(const BatchArgs& A, const BatchInst& in
   {
     const FwdLds s = fwd_carve<H, PF>(smem, r_stride(in.kmax));
     const int ld = Tile<PREC>::ld(in.kmax, PF);
-    fwd_begin<H, PF>(s);
+    fwd_begin<H, PF>(s, net);
     for (int64_t t = 0; t < npts / PF; ++t) {
       const int64_t nv = in.n - (it.p0 + t * PF);
       TileSeg sg;
@@ -2249,7 +2344,7 @@ size_t batched_lds(int kmax, int H) {
   const int WN = H / 16 < kWaves ? H / 16 : kWaves;
   const int WC = kWaves / WN;
   size_t f = (size_t)4 * PF * r_stride(kmax) + (size_t)PF * 16 + (size_t)PF * 12 * 4 * 2 + kWaves * 4 * 4 +
-             kMaxTerms * 8 + (size_t)WC * 3 * H * 8 + 3 * 8;
+             kMaxTerms * 8 + (size_t)WC * 3 * H * 8 + 3 * 8 + kFourierLds;
   size_t b = bwd_lds_bytes(PB, H, H, true);
   size_t g = (size_t)kWaves * 256 * 4 * sizeof(float);
   size_t m = f > b ? f : b;
