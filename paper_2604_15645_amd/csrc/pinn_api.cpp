@@ -125,12 +125,13 @@ int embed_bwd_p(int H) { return H == 256 ? 8 : 16; }
 constexpr size_t kLdsBudget = 160 * 1024;
 
 size_t fwd_lds(int P, int kmax, int H) {
-  const int WN = std::min(8, H / 16);
-  const int WC = 8 / WN;
-  size_t b = (size_t)4 * P * (kmax * 4 + 16);  // X
+  const int NW = fwd_waves(H, P);
+  const int WN = std::min(NW, H / 16);
+  const int WC = NW / WN;
+  size_t b = (size_t)4 * P * (kmax * 4 + 16) * (fwd_double_x(P) ? 2 : 1);  // X (one or two)
   b += (size_t)P * 16;                           // PT
   b += (size_t)P * 12 * 4 * 2;                   // YJ, YB
-  b += kWaves * 4 * 4;                           // RED
+  b += NW * 4 * 4;                               // RED
   b += kMaxTerms * 8;                            // LOSS
   b += (size_t)WC * 3 * H * 8 + 3 * 8;           // WL, BL
   b += kFourierLds;                              // BF
@@ -231,7 +232,8 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   p.n_sub0 = p.n_pad / p.pb0;
   int cap = kGridCap;
   if (tune && tune->grid > 0) cap = tune->grid;
-  p.grid_f = (int)std::min<int64_t>(p.n_tiles, cap);
+  // (several resident forward work-groups per compute unit for the small-wave shapes)
+  p.grid_f = (int)std::min<int64_t>(p.n_tiles, tune && tune->grid > 0 ? cap : cap * fwd_wg_per_cu(D.H, p.pf));
   p.grid_b = (int)std::min<int64_t>(p.n_sub, cap);
   if (p.split) {  // two roles of G work-groups each, G a multiple of 8
     const int64_t G = std::min<int64_t>(align_up(std::min<int64_t>(p.n_sub, cap / 2), 8), std::max(8, cap / 2 / 8 * 8));

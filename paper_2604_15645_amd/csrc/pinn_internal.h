@@ -213,6 +213,15 @@ struct BatchLossArgs {
 // Sub-tile points of the wide bf16x3 layer backward (input width a multiple of 128).
 constexpr int wide_pb(int H) { return H >= 256 ? 16 : 32; }
 
+// Waves per work-group of the forward kernel for hidden width H and tile points P.
+constexpr int fwd_waves(int H, int P) { return kWaves; }
+// Resident forward work-groups per compute unit.
+constexpr int fwd_wg_per_cu(int H, int P) { return kWaves / fwd_waves(H, P); }
+// 16-point forward tiles keep two layer-input tiles in LDS: layer j's activations go to one
+// while layer j's product may still read the other, so a wave that finishes its product
+// starts its activations without waiting for the slower waves.
+constexpr bool fwd_double_x(int P) { return P <= 16; }
+
 // Launchers (pinn_kernels.hip).  Each returns a pinn_status value.
 int launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t s);
 int launch_points(const PointsArgs& a, hipStream_t s);

@@ -347,11 +347,80 @@ struct FragStore {
 // PRE: the weight fragments of chunks 0 and 1 (chunk 0 again when there is one chunk) come
 // in pre0 / pre1, loaded by the caller before its own stores, so that waiting for them does
 // not wait for those stores (vector-memory counters complete in issue order).
+// bf16x3 form of the tile product with every operand requested well before its use: the A
+// fragment of cp block c for chunk kc + 1 is read from LDS as soon as the three products of
+// chunk kc that use it have issued (the other blocks' products cover the LDS latency), and
+// the weight fragments of chunk kc + 2 load while chunk kc multiplies, from two register
+// sets in turn.  Per accumulator the products keep the order of Prec::mma (lo*hi, hi*lo,
+// hi*hi), so results equal those of the plain loop bit for bit.
+template <int NB, int CB, bool PRE>
+__device__ __forceinline__ void gemm_tile_rot(f4 (&acc)[NB][CB], const char* X, int ld, int cb0,
+                                              const char* frags, int kchunks, const int (&blk)[NB], int lane,
+                                              const Raw (&pre0)[NB], const Raw (&pre1)[NB]) {
+  using T = Tile<kBF16X3>;
+  const char* fb[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) fb[i] = frags + ((size_t)blk[i] * kchunks * 64 + lane) * 32;
+  auto load_b = [&](Raw (&b)[NB], int kc) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const uint4* p = reinterpret_cast<const uint4*>(fb[i] + (size_t)kc * 2048);
+      b[i].a = p[0];
+      b[i].b = p[1];
+    }
+  };
+  Raw b0[NB], b1[NB], a[CB];
+  if (PRE) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      b0[i] = pre0[i];
+      b1[i] = pre1[i];
+    }
+  } else {
+    load_b(b0, 0);
+    load_b(b1, kchunks > 1 ? 1 : 0);
+  }
+#pragma unroll
+  for (int c = 0; c < CB; ++c) a[c] = T::load(X, ld, cb0 + c, 0, lane);
+  auto step = [&](const Raw (&b)[NB], int kc) {
+    const int kn = kc + 1 < kchunks ? kc + 1 : kc;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[c].b),
+                                                            __builtin_bit_cast(bf16x8, b[i].a), acc[i][c], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[c].a),
+                                                            __builtin_bit_cast(bf16x8, b[i].b), acc[i][c], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[c].a),
+                                                            __builtin_bit_cast(bf16x8, b[i].a), acc[i][c], 0, 0, 0);
+      a[c] = T::load(X, ld, cb0 + c, kn, lane);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  for (int kc = 0; kc < kchunks; kc += 2) {
+    step(b0, kc);
+    load_b(b0, kc + 2 < kchunks ? kc + 2 : kchunks - 1);
+    if (kc + 1 < kchunks) {
+      step(b1, kc + 1);
+      load_b(b1, kc + 3 < kchunks ? kc + 3 : kchunks - 1);
+    }
+  }
+}
+
 template <int PREC, int NB, int CB, int CGMAX = 8, bool PREFETCH = false, bool PRE = false>
 __device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int ld, int cb0,
                                           const char* frags, int kchunks, const int (&blk)[NB], int lane,
                                           const Raw (&pre0)[NB], const Raw (&pre1)[NB]) {
   static_assert(!PRE || PREFETCH, "preloaded chunks need the prefetching loop");
+  if constexpr (PREC == kBF16X3 && PREFETCH && CB <= CGMAX) {
+    gemm_tile_rot<NB, CB, PRE>(acc, X, ld, cb0, frags, kchunks, blk, lane, pre0, pre1);
+    return;
+  }
   const char* fb[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) fb[i] = frags + ((size_t)blk[i] * kchunks * 64 + lane) * 32;
@@ -745,12 +814,12 @@ __device__ __forceinline__ void barrier_lds() {
 // ================================================================== forward
 
 // Compile-time shape of the forward tile: hidden width bound H, tile points P.
-template <int H, int P>
+template <int H, int P, int NW = kWaves>
 struct FwdShape {
   static constexpr int CPB = P / 4;                    // 16-row cp blocks per tile
   static constexpr int NBMAX = H / 16;                 // neuron blocks
-  static constexpr int WN = NBMAX < kWaves ? NBMAX : kWaves;
-  static constexpr int WC = kWaves / WN;
+  static constexpr int WN = NBMAX < NW ? NBMAX : NW;
+  static constexpr int WC = NW / WN;
   static constexpr int NBW = (NBMAX + WN - 1) / WN;    // neuron blocks per wave
   static constexpr int CBW = CPB / WC;                 // cp blocks per wave
   static_assert(CPB % WC == 0, "tile too small for the wave split");
@@ -758,55 +827,59 @@ struct FwdShape {
 
 // LDS of the forward tile body.
 struct FwdLds {
-  char* X;       // R-layout tile (4P rows)
+  char* X;       // layer-input tile (4P rows)
+  char* X2;      // second layer-input tile (16-point tiles), else X
   float4* PT;    // tile points
   float* YJ;     // [P][3][4] output jets
   float* YB;     // [P][3][4] output-jet adjoints
-  float* RED;    // [kWaves][4] wave partial sums
+  float* RED;    // [waves][4] wave partial sums
   double* LOSS;  // [kMaxTerms] sums of squares (FP64, per work item)
   double* WL;    // [WC][3][H] output-layer weight-gradient sums
   double* BL;    // [3] output-layer bias-gradient sums
   float* BF;     // Fourier matrix, d_in x n_freq (staged once per launch)
 };
 
-template <int H, int P>
+template <int H, int P, int NW = kWaves>
 __device__ __forceinline__ FwdLds fwd_carve(char* smem, int rs) {
   FwdLds s;
   s.X = smem;
-  s.PT = reinterpret_cast<float4*>(smem + (size_t)4 * P * rs);
+  s.X2 = fwd_double_x(P) ? smem + (size_t)4 * P * rs : smem;
+  s.PT = reinterpret_cast<float4*>(smem + (size_t)4 * P * rs * (fwd_double_x(P) ? 2 : 1));
   s.YJ = reinterpret_cast<float*>(s.PT + P);
   s.YB = s.YJ + P * 12;
   s.RED = s.YB + P * 12;
-  s.LOSS = reinterpret_cast<double*>(s.RED + kWaves * 4);
+  s.LOSS = reinterpret_cast<double*>(s.RED + NW * 4);
   s.WL = s.LOSS + kMaxTerms;
-  s.BL = s.WL + FwdShape<H, P>::WC * 3 * H;
+  s.BL = s.WL + FwdShape<H, P, NW>::WC * 3 * H;
   s.BF = reinterpret_cast<float*>(s.BL + 3);
   return s;
 }
 
 // Zero the per-launch sums and stage the Fourier matrix (read by every tile's embedding).
-template <int H, int P>
+template <int H, int P, int NW = kWaves>
 __device__ __forceinline__ void fwd_begin(const FwdLds& s, const NetDev& net) {
-  for (int i = threadIdx.x; i < kMaxTerms; i += kThreads) s.LOSS[i] = 0.0;
-  for (int i = threadIdx.x; i < FwdShape<H, P>::WC * 3 * H + 3; i += kThreads) s.WL[i] = 0.0;
-  for (int i = threadIdx.x; i < net.d_in * net.n_freq; i += kThreads) s.BF[i] = net.B[i];
+  constexpr int NT = 64 * NW;
+  for (int i = threadIdx.x; i < kMaxTerms; i += NT) s.LOSS[i] = 0.0;
+  for (int i = threadIdx.x; i < FwdShape<H, P, NW>::WC * 3 * H + 3; i += NT) s.WL[i] = 0.0;
+  for (int i = threadIdx.x; i < net.d_in * net.n_freq; i += NT) s.BF[i] = net.B[i];
 }
 
 // Write the accumulated sums of a run of tiles: loss terms, and (with the gradient) the
 // output layer's weight and bias sums in its [d_out][n_L] then [d_out] layout.
-template <int H, int P>
+template <int H, int P, int NW = kWaves>
 __device__ __forceinline__ void fwd_end(const FwdLds& s, double* loss_slot, double* out_slot, int dout, int nL,
                                         bool with_grad) {
+  constexpr int NT = 64 * NW;
   __syncthreads();
-  for (int i = threadIdx.x; i < kMaxTerms; i += kThreads) loss_slot[i] = s.LOSS[i];
+  for (int i = threadIdx.x; i < kMaxTerms; i += NT) loss_slot[i] = s.LOSS[i];
   if (with_grad) {
-    for (int i = threadIdx.x; i < dout * nL; i += kThreads) {
+    for (int i = threadIdx.x; i < dout * nL; i += NT) {
       const int o = i / nL, n = i - o * nL;
       double t = 0.0;
-      for (int c = 0; c < FwdShape<H, P>::WC; ++c) t += s.WL[(c * 3 + o) * H + n];
+      for (int c = 0; c < FwdShape<H, P, NW>::WC; ++c) t += s.WL[(c * 3 + o) * H + n];
       out_slot[i] = t;
     }
-    for (int o = threadIdx.x; o < dout; o += kThreads) out_slot[dout * nL + o] = s.BL[o];
+    for (int o = threadIdx.x; o < dout; o += NT) out_slot[dout * nL + o] = s.BL[o];
   }
 }
 
@@ -826,11 +899,13 @@ struct TileSeg {
 // seed and (with the gradient) the output layer's backward.  pts: the tile's points;
 // zs: stash of hidden layer 0 with zs_stride floats between layers; zb0: adjoint of the
 // last hidden layer; cb_st: first cp block of this tile in those buffers.
-template <int PREC, int ACT, int H, int P>
+template <int PREC, int ACT, int H, int P, int NW = kWaves>
 __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, const float4* pts, float* zs,
                                          int64_t zs_stride, float* zb0, int64_t cb_st, const TileSeg& sg, int ld,
                                          bool with_grad, const FwdLds& s) {
-  using S = FwdShape<H, P>;
+  using S = FwdShape<H, P, NW>;
+  constexpr int NT = 64 * NW;
+  static_assert(P <= NT, "one thread per tile point");
   using Pr = Prec<PREC>;
   constexpr int CPB = S::CPB, NBW = S::NBW, CBW = S::CBW, WN = S::WN;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -844,7 +919,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
   const LayerDev& lout = net.layer[L];
 
   barrier_lds();  // the previous user of the LDS is done
-  for (int p = tid; p < P; p += kThreads) s.PT[p] = pts[p];
+  for (int p = tid; p < P; p += NT) s.PT[p] = pts[p];
   barrier_lds();
 
   f4 acc[NBW][CBW];
@@ -880,7 +955,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
     // frequency 16 jb + l16, the write pattern of an accumulator block
     const int m = net.n_freq;
     const int nj = m >> 4;
-    for (int b = wave; b < (P / 4) * nj; b += kWaves) {
+    for (int b = wave; b < (P / 4) * nj; b += NW) {
       const int pb = b / nj, jb = b - (b / nj) * nj;
       const int p = 4 * pb + g, j = 16 * jb + l16;
       f4 cj, sj;
@@ -915,7 +990,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
   // Early weight loads (the next layer's first chunks before the stash stores, the output
   // layer's chunks all at once) cost registers; the bf16x3 shapes with at most 8 cp blocks
   // per wave have them to spare.
-  constexpr bool kPre = PREC == kBF16X3 && CBW <= 8;
+  constexpr bool kPre = PREC == kBF16X3 && CBW <= 8 && NBW <= 2;
 
   // ---- hidden layers: acc holds z of layer j
   for (int j = 0; j < L; ++j) {
@@ -937,8 +1012,11 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       }
       if (kPre) load_first_chunks<NBW>(pre0, pre1, ln.wf, ln.kci, nblk, lane);
     }
-    barrier_lds();  // every wave is done reading the layer input from X
-    // activation jets into X, each fragment's stash store issued beside its activation (the
+    // layer j's activations go to XA; with one tile (XA == X) every wave must first be done
+    // reading the layer input from it, with two they go to the tile the product did not read
+    char* XA = (j & 1) ? X : s.X2;
+    if (!fwd_double_x(P)) barrier_lds();
+    // activation jets into XA, each fragment's stash store issued beside its activation (the
     // stores overlap the vector-ALU work instead of forming a burst of their own); the stores
     // are issued unconditionally and switched off by offset (FragStore)
     {
@@ -956,7 +1034,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
             float s0, s1, s2, s3;
             act_eval<ACT>(acc[i][c].x, net.w0, s0, s1, s2, s3);
             const f4 a = jet_act<(ACT & kLapFlag) != 0>(acc[i][c], s0, s1, s2, lw1, lw2);
-            Tile<PREC>::put(X, ld, 4 * cb + g, n, a);
+            Tile<PREC>::put(XA, ld, 4 * cb + g, n, a);
           }
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -969,7 +1047,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       for (int i = 0; i < NBW; ++i)
 #pragma unroll
         for (int c = 0; c < CBW; ++c) acc[i][c] = f4{0.f, 0.f, 0.f, 0.f};
-      gemm_tile<PREC, NBW, CBW, 8, true, kPre>(acc, X, ld, wc * CBW, ln.wf, ln.kci, nblk, lane, pre0, pre1);
+      gemm_tile<PREC, NBW, CBW, 8, true, kPre>(acc, XA, ld, wc * CBW, ln.wf, ln.kci, nblk, lane, pre0, pre1);
 #pragma unroll
       for (int i = 0; i < NBW; ++i)
 #pragma unroll
@@ -980,6 +1058,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
   // ---- output layer (d_out <= 3 columns of one 16-wide block): waves over cp blocks; all
   // weight chunks (at most 8: input width <= 256) are requested before the first is used
   constexpr int kOutChunks = kPre ? 8 : 1;
+  const char* XL = ((L - 1) & 1) ? X : s.X2;  // the last hidden layer's activations
   Raw ow[kOutChunks];
   if (kPre) {
 #pragma unroll
@@ -987,20 +1066,20 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       if (kc < lout.kci) ow[kc] = glob_frag(lout.wf, 0, kc, lout.kci, lane);
   }
   const float obias = l16 < dout ? lout.b[l16] : 0.0f;
-  for (int cb = wave; cb < CPB; cb += kWaves) {
+  for (int cb = wave; cb < CPB; cb += NW) {
     f4 y = f4{0.f, 0.f, 0.f, 0.f};
     if (kPre) {
 #pragma unroll
       for (int kc = 0; kc < kOutChunks; ++kc) {
         if (kc < lout.kci) {
-          const Raw a = Tile<PREC>::load(X, ld, cb, kc, lane);
+          const Raw a = Tile<PREC>::load(XL, ld, cb, kc, lane);
           Pr::mma(y, a, ow[kc]);
         }
       }
     } else {
       for (int kc = 0; kc < lout.kci; ++kc) {
         const Raw bw = glob_frag(lout.wf, 0, kc, lout.kci, lane);
-        const Raw a = Tile<PREC>::load(X, ld, cb, kc, lane);
+        const Raw a = Tile<PREC>::load(XL, ld, cb, kc, lane);
         Pr::mma(y, a, bw);
       }
     }
@@ -1064,7 +1143,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
     const int nterm = sg.kind == 0 ? pde.n_res : 1;
     for (int k = 0; k < nterm; ++k) {
       double t = 0.0;
-      for (int w = 0; w < kWaves; ++w) t += (double)s.RED[w * 4 + k];
+      for (int w = 0; w < NW; ++w) t += (double)s.RED[w * 4 + k];
       s.LOSS[sg.term + k] += t;
     }
   }
@@ -1118,12 +1197,12 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
   }
 }
 
-template <int PREC, int ACT, int H, int P>
-__global__ __launch_bounds__(kThreads, 1) void k_forward(const FwdArgs A) {
+template <int PREC, int ACT, int H, int P, int NW = fwd_waves(H, P)>
+__global__ __launch_bounds__(64 * NW, 8 / NW) void k_forward(const FwdArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  const FwdLds s = fwd_carve<H, P>(smem, r_stride(A.kmax));
+  const FwdLds s = fwd_carve<H, P, NW>(smem, r_stride(A.kmax));
   const int ld = Tile<PREC>::ld(A.kmax, P);
-  fwd_begin<H, P>(s, A.net);
+  fwd_begin<H, P, NW>(s, A.net);
   for (int64_t tile = blockIdx.x; tile < A.n_tiles; tile += gridDim.x) {
     const int64_t p0 = tile * P;
     const int sid = seg_of(A.seg, p0);
@@ -1136,10 +1215,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_forward(const FwdArgs A) {
     sg.out_mask = sid == 0 ? 0 : A.seg.out_mask[sid - 1];
     sg.lam = sid == 0 ? 0.0f : A.seg.lam_anchor[sid - 1];
     sg.residual = (sid == 0 && A.residual) ? A.residual + (p0 - A.seg.start[0]) * A.pde.n_res : nullptr;
-    fwd_tile<PREC, ACT, H, P>(A.net, A.pde, A.work.pts + p0, A.work.zs0, A.work.zs_stride, A.work.zb[0],
-                              tile * (P / 4), sg, ld, A.with_grad != 0, s);
+    fwd_tile<PREC, ACT, H, P, NW>(A.net, A.pde, A.work.pts + p0, A.work.zs0, A.work.zs_stride, A.work.zb[0],
+                                  tile * (P / 4), sg, ld, A.with_grad != 0, s);
   }
-  fwd_end<H, P>(s, A.work.loss_slots + (size_t)blockIdx.x * kMaxTerms,
+  fwd_end<H, P, NW>(s, A.work.loss_slots + (size_t)blockIdx.x * kMaxTerms,
                 A.with_grad ? A.work.out_slots + (size_t)blockIdx.x * A.net.d_out * (A.net.layer[A.net.L].n_in + 1)
                             : nullptr,
                 A.net.d_out, A.net.layer[A.net.L].n_in, A.with_grad != 0);
@@ -2173,7 +2252,7 @@ template <int PREC, int ACT, int H, int P>
 int fwd(const FwdArgs& a, int grid, size_t lds, hipStream_t s) {
   auto k = k_forward<PREC, ACT, H, P>;
   if (set_lds(k, lds)) return -5;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, a);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * fwd_waves(H, P)), lds, s, a);
   return status(hipGetLastError());
 }
 

@@ -75,6 +75,18 @@ def test_parity_configs(oracle, dev, name, n, prec):
     check(run_gpu(case, dev, prec), run_oracle(oracle, case), prec, name)
 
 
+@pytest.mark.parametrize("grid", [0, 8])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("name,n", CASES)
+def test_parity_small_forward_tiles(oracle, dev, name, n, prec, grid):
+    """16-point forward tiles (at width 256: work-groups of four waves, two per compute unit),
+    with the default work-group count and with 8 work-groups looping over many tiles."""
+    from paper_2604_15645_amd import synth
+    case = synth.make_case(name, n_points=n + 37, seed=2000 + n, perturb=True)
+    got = run_gpu(case, dev, prec, tune={"tile_points": 16, "grid": grid})
+    check(got, run_oracle(oracle, case), prec, "%s-p16-g%d" % (name, grid))
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_forward_only_matches(oracle, dev, prec):
     from paper_2604_15645_amd import synth
