@@ -265,6 +265,18 @@ __device__ __forceinline__ uint2 lds_tr16(const char* p) {
   return __builtin_bit_cast(uint2, v);
 }
 
+// LDS byte address of a pointer into the work-group's LDS, masked to the 18 bits an LDS
+// address has: with the high bits known to be zero the compiler folds constant offsets
+// added to it into the immediate offset of the LDS instruction instead of adding them per
+// access.
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char*)p & 0x3FFFFu;
+}
+__device__ __forceinline__ uint2 lds_tr16_at(uint32_t a) {
+  const v4s v = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) v4s*)(uintptr_t)a);
+  return __builtin_bit_cast(uint2, v);
+}
+
 template <>
 struct Tile<kBF16X3> {
   static __device__ __forceinline__ int ld(int kmax, int P) { return P >> 2; }
@@ -281,10 +293,11 @@ struct Tile<kBF16X3> {
   }
   static __device__ __forceinline__ Raw load(const char* X, int ld, int cb, int kc, int lane) {
     const int g = lane >> 4, s = lane & 15;
-    const char* c = X + (size_t)(kc * ld + cb) * 2048;
-    const int o0 = t_cell_off(s, 8 * g + (s >> 2)), o1 = t_cell_off(s, 8 * g + 4 + (s >> 2));
-    const uint2 h0 = lds_tr16(c + o0), h1 = lds_tr16(c + o1);
-    const uint2 l0 = lds_tr16(c + 1024 + o0), l1 = lds_tr16(c + 1024 + o1);
+    const uint32_t c = (uint32_t)(kc * ld + cb) * 2048;
+    const uint32_t x0 = (lds_addr(X) + t_cell_off(s, 8 * g + (s >> 2))) & 0x3FFFFu;
+    const uint32_t x1 = (lds_addr(X) + t_cell_off(s, 8 * g + 4 + (s >> 2))) & 0x3FFFFu;
+    const uint2 h0 = lds_tr16_at(x0 + c), h1 = lds_tr16_at(x1 + c);
+    const uint2 l0 = lds_tr16_at(x0 + c + 1024), l1 = lds_tr16_at(x1 + c + 1024);
     Raw r;
     r.a = make_uint4(h0.x, h0.y, h1.x, h1.y);
     r.b = make_uint4(l0.x, l0.y, l1.x, l1.y);
@@ -1728,15 +1741,30 @@ __device__ __forceinline__ void split_adjoint_product(f4 (&acca)[NIBW][CPB], cha
   for (int q = 0; q < NIBW; ++q)
 #pragma unroll
     for (int cb = 0; cb < CPB; ++cb) acca[q][cb] = f4{0.f, 0.f, 0.f, 0.f};
+  // the A fragment of cp block cb for chunk kc + 1 is read as soon as the products of chunk
+  // kc that use it have issued; per accumulator the order of Prec::mma is kept
+  Raw a[CPB];
+#pragma unroll
+  for (int cb = 0; cb < CPB; ++cb) a[cb] = Tile<kBF16X3>::load(R, rld, cb, 0, lane);
 #pragma unroll
   for (int kc = 0; kc < KC; ++kc) {
-    Raw a[CPB];
 #pragma unroll
-    for (int cb = 0; cb < CPB; ++cb) a[cb] = Tile<kBF16X3>::load(R, rld, cb, kc, lane);
-    Raw bq[NIBW];
+    for (int cb = 0; cb < CPB; ++cb) {
 #pragma unroll
-    for (int q = 0; q < NIBW; ++q) bq[q] = wreg[q][kc];
-    Prec<kBF16X3>::template mma_tile<NIBW, CPB>(acca, a, bq);
+      for (int q = 0; q < NIBW; ++q)
+        acca[q][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[cb].b),
+                                                              __builtin_bit_cast(bf16x8, wreg[q][kc].a), acca[q][cb], 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q)
+        acca[q][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[cb].a),
+                                                              __builtin_bit_cast(bf16x8, wreg[q][kc].b), acca[q][cb], 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q)
+        acca[q][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[cb].a),
+                                                              __builtin_bit_cast(bf16x8, wreg[q][kc].a), acca[q][cb], 0, 0, 0);
+      if (kc + 1 < KC) a[cb] = Tile<kBF16X3>::load(R, rld, cb, kc + 1, lane);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
   // work that waits on vector memory (the pre-activations) stays after the product, so the
   // copy started above runs under it
@@ -1752,16 +1780,30 @@ __device__ __forceinline__ void split_weight_grad_product(f4 (&accw)[NOB][NIBW],
                                                           char* __restrict__ STG, const char* __restrict__ ZT,
                                                           const char* next, int bytes, int lane) {
   if (next) async_copy(STG, next, bytes);
+  // A operands (one 2 KiB unit per output block) read D blocks ahead of their products, from a
+  // ring of D register sets; per accumulator the order of Prec::mma is kept
+  constexpr int D = NOB < 3 ? NOB : 3;
 #pragma unroll
   for (int cc = 0; cc < CPB / 2; ++cc) {
-    Raw ao = lds_unit(ZT, cc, lane, 64 * 32);
+    Raw u[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) u[d] = lds_unit(ZT, d * (CPB / 2) + cc, lane, 64 * 32);
 #pragma unroll
     for (int ob = 0; ob < NOB; ++ob) {
-      Raw an = ao;
-      if (ob + 1 < NOB) an = lds_unit(ZT, (ob + 1) * (CPB / 2) + cc, lane, 64 * 32);
+      const Raw ao = u[ob % D];
 #pragma unroll
-      for (int q = 0; q < NIBW; ++q) Prec<kBF16X3>::mma(accw[ob][q], ao, aop[q][cc]);
-      ao = an;
+      for (int q = 0; q < NIBW; ++q)
+        accw[ob][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ao.b),
+                                                              __builtin_bit_cast(bf16x8, aop[q][cc].a), accw[ob][q], 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q)
+        accw[ob][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ao.a),
+                                                              __builtin_bit_cast(bf16x8, aop[q][cc].b), accw[ob][q], 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q)
+        accw[ob][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ao.a),
+                                                              __builtin_bit_cast(bf16x8, aop[q][cc].a), accw[ob][q], 0, 0, 0);
+      if (ob + D < NOB) u[ob % D] = lds_unit(ZT, (ob + D) * (CPB / 2) + cc, lane, 64 * 32);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
