@@ -60,6 +60,27 @@ def kernel_flops(net, pde, n_points):
     return out, step * n_points
 
 
+def kernel_bytes(net, pde, n_points):
+    """Algorithmic HBM bytes per launch of each kernel kind: the jets that must cross HBM
+    between the kernels (C FP32 channels per neuron and point), plus the points.
+
+    Forward: points in, pre-activation jets of the hidden layers the backward reads (all but
+    the last) out, adjoint jets of the last hidden layer out.  Hidden-layer backward: the
+    layer's output adjoint and its input pre-activations in, the input adjoint out.
+    Embedding-layer backward: its output adjoint and the points in."""
+    from paper_2604_15645_amd import synth
+    C = channels(net, pde)
+    dims = synth.layer_dims(net)
+    jet = 4 * C
+    widths = [no for no, _ in dims[:-1]]
+    out = {"k_forward": (16 + jet * (sum(widths[:-1]) + widths[-1])) * n_points}
+    if len(dims) > 2:
+        no, ni = dims[1]
+        out["k_backward"] = jet * (no + 2 * ni) * n_points
+    out["k_backward_embed"] = (jet * dims[0][0] + 16) * n_points
+    return out
+
+
 def measured_traffic(config, kernel):
     """HBM bytes per launch of `kernel` on this workload from the committed counter summary
     (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by the copy calibration), or None when no
@@ -177,21 +198,33 @@ def main():
         fp32 = {"value": n_points / (ms32 / 1e3), "ms_per_step": ms32,
                 "kernels_ms": {k: v[1] / v[0] for k, v in k32.items()}}
 
-    # roofline of the dominant kernel (largest summed time per step)
+    # roofline of the dominant kernel (largest summed time per step): the bound is the
+    # resource whose peak gives the longer lower limit on the launch (HBM bytes at 8 TB/s or
+    # bf16 matrix-core FLOPs at 2.5 PFLOP/s); the other resource's figures are reported too
     flops, step_flops = kernel_flops(net, pde, n_total)
+    nbytes = kernel_bytes(net, pde, n_total)
     dom = max(k16, key=lambda k: k16[k][1])
     launches, tot = k16[dom]
     avg_ms = tot / launches
     alg = flops.get(dom, 0)
+    alg_b = nbytes.get(dom, 0)
     n_prod = 3  # BF16X3: three bf16 matrix-core products per logical FP32 product
     roof = None
-    if alg:
-        achieved = n_prod * alg / (avg_ms / 1e3)
-        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved / 1e12,
-                "peak": PEAK["bf16"] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK["bf16"],
-                "traffic": measured_traffic(name, dom) if n_points == synth.CONFIGS[name]["n_points"] else None,
-                "alg_flops_per_launch": alg, "n_prod": n_prod, "avg_launch_ms": avg_ms}
+    if alg and alg_b:
+        mfma = n_prod * alg / (avg_ms / 1e3)
+        hbm = alg_b / (avg_ms / 1e3)
+        hbm_bound = alg_b / HBM_PEAK >= n_prod * alg / PEAK["bf16"]
+        traffic = measured_traffic(name, dom) if n_points == synth.CONFIGS[name]["n_points"] else None
+        if hbm_bound:
+            roof = {"kernel": dom, "bound": "hbm", "achieved": hbm / 1e9, "peak": HBM_PEAK / 1e9,
+                    "unit": "GB/s", "frac": hbm / HBM_PEAK, "traffic": traffic,
+                    "mfma_achieved_tflops": mfma / 1e12, "mfma_frac": mfma / PEAK["bf16"]}
+        else:
+            roof = {"kernel": dom, "bound": "mfma", "achieved": mfma / 1e12, "peak": PEAK["bf16"] / 1e12,
+                    "unit": "TFLOP/s", "frac": mfma / PEAK["bf16"], "traffic": traffic,
+                    "hbm_achieved_gbs": hbm / 1e9, "hbm_frac": hbm / HBM_PEAK}
+        roof.update({"alg_bytes_per_launch": alg_b, "alg_flops_per_launch": alg, "n_prod": n_prod,
+                     "avg_launch_ms": avg_ms})
 
     result = {
         "metric": METRIC,

@@ -13,7 +13,8 @@ ARCH = "gfx950"
 
 HIP_FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-munsafe-fp-atomics",
-    # packed FP32 VALU instructions stay off (see DESIGN notes on correctness)
+    # packed FP32 VALU instructions stay off: some of their forms have given wrong results
+    # on this hardware without any error
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
 ]

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <set>
@@ -119,6 +120,12 @@ int n_res_of(int pde_id) {
 // Kernel activation code: the activation, plus kLapFlag when jet channel 3 carries a Laplacian.
 int act_code(const pinn_net* net, const pinn_pde* pde) { return net->act | (pde->lap_mask ? kLapFlag : 0); }
 
+// Launch numbers of the split backward (pacing words carry them; they only grow).
+unsigned long long next_launch_id() {
+  static std::atomic<unsigned long long> n{1};
+  return n.fetch_add(1, std::memory_order_relaxed);
+}
+
 int default_fwd_p(int H) { return H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128; }
 int default_bwd_p(int H) { return 2048 / H; }
 int embed_bwd_p(int H) { return H == 256 ? 8 : 16; }
@@ -162,7 +169,7 @@ struct Plan {
   bool with_grad;
   // workspace offsets
   int64_t o_pts, o_wf[kMaxLayers], o_wb[kMaxLayers], o_w[kMaxLayers], o_b[kMaxLayers];
-  int64_t o_zs[kMaxHidden], o_zb[2], o_loss, o_out, o_layer[kMaxLayers], o_flag;
+  int64_t o_zs[kMaxHidden], o_zb[2], o_loss, o_out, o_layer[kMaxLayers], o_flag, o_pace;
   int64_t zs_stride;
   int64_t bytes;
 };
@@ -255,6 +262,7 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   }
   p.o_loss = take((int64_t)p.grid_f * kMaxTerms * 8);
   p.o_flag = take(16);
+  p.o_pace = take((int64_t)std::max(p.grid_b, 1) * 8);  // split-backward pacing words (any content)
   if (p.with_grad) {
     p.zs_stride = p.n_pad * 4 * D.hmax;
     p.o_zs[0] = take(p.zs_stride * D.L * 4);
@@ -470,6 +478,8 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.z_prev = wk.zs0 + (j - 1) * wk.zs_stride;
       a.slots = wk.layer_slots[j];
       a.wide = p.split ? 2 : p.wide;
+      a.pace = reinterpret_cast<unsigned long long*>(ws + p.o_pace);
+      a.launch = next_launch_id();
       rc = timed("k_backward", stream, [&] { return launch_backward(prec, act_code(net, pde), D.H, false, a, p.grid_b, p.lds_b, stream); });
       if (rc) return rc;
       cur ^= 1;

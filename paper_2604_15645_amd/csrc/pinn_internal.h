@@ -120,6 +120,10 @@ struct BwdArgs {
   const float* z_prev;  // stash of the previous hidden layer (null for layer 0)
   double* slots;        // [gridDim][n_out * (n_in + 1)]
   int wide;             // use the wide bf16x3 kernel (input width a multiple of 128)
+  // split roles: progress of each weight-gradient work-group, (launch << 20) + sub-tile
+  // index, read by its input-adjoint partner to stay at most one sub-tile ahead
+  unsigned long long* pace;
+  unsigned long long launch;
 };
 
 struct Grad0Args {

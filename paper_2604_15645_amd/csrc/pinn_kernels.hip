@@ -1809,6 +1809,8 @@ __device__ __forceinline__ void split_weight_grad_product(f4 (&accw)[NOB][NIBW],
   }
 }
 
+constexpr int kPaceSpin = 512;  // polls of a pacing wait before it goes on regardless
+
 template <int ACT, int NOB, int NIB, int PB, bool EMB>
 __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A) {
   using S = SplitShape<NOB, NIB, PB>;
@@ -1872,6 +1874,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) wreg[q][kc] = glob_frag(ly.wb, wave + 8 * q, kc, KC, lane);
     wait_vm<0>();  // resident from here on: no wait for them inside the loop
+    bool held = false;  // the partner had not reached the previous sub-tile when last read
     for (int64_t k = 0; k < count; ++k) {
       const int64_t s = rb + k * G;
       const int64_t cb0 = s * CPB;
@@ -1879,9 +1882,21 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
         wait_vm<0>();
       else
         wait_vm<S::NSTORE>();  // the staged adjoint; the previous sub-tile's stores may run on
+      if (held && threadIdx.x == 0) {
+        // pacing: this role reads each sub-tile first and its partner must find the jets
+        // still in L2, so it runs at most one sub-tile ahead of the partner (a bounded wait:
+        // it goes on regardless after kPaceSpin polls)
+        const unsigned long long want = (A.launch << 20) + (unsigned long long)(k - 1);
+        for (int it = 0; it < kPaceSpin; ++it) {
+          if (__hip_atomic_load(&A.pace[rb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want) break;
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
       barrier_lds();
       convert(nullptr);
       load_zp(s);  // after the staged reads: waiting for these must not wait for the next copy
+      unsigned long long seen = ~0ull;
+      if (A.pace) seen = __hip_atomic_load(&A.pace[rb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       barrier_lds();  // R complete; STG free
       f4 acca[NIBW][CPB];
       split_adjoint_product<NIBW, CPB, KC>(acca, STG, R, rld, wreg, k + 1 < count ? zb_src(s + G) : nullptr,
@@ -1898,6 +1913,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
           *jet_frag(A.zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
         }
       }
+      // read beside the pre-activations, compared once they are in use
+      held = A.pace && seen < (A.launch << 20) + (unsigned long long)k;
     }
   } else {
     // ---- weight and bias gradient
@@ -1913,6 +1930,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
     for (int64_t k = 0; k < count; ++k) {
       const int64_t s = rb + k * G;
       wait_vm<0>();
+      // progress for the partner's pacing: sub-tile s read, the next one about to be
+      if (!EMB && A.pace && threadIdx.x == 0)
+        __hip_atomic_store(&A.pace[rb], (A.launch << 20) + (unsigned long long)k, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
       barrier_lds();  // sub-tile s staged and its pre-activations loaded; ZT free
       // output adjoint as weight-gradient A operands in the ZT layout: for output block ob
       // and cp chunk cc, lane (g, l16) holds 8 cp of output 16 ob + l16 (points 8 cc + g,

@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle on the same seeded inputs.
 
-Tolerances (normwise, relative; see DESIGN.md): FP32 <= 1e-5 and BF16X3 <= 1e-4 on every
+Tolerances (normwise, relative): FP32 <= 1e-5 and BF16X3 <= 1e-4 on every
 residual component, every loss term and the whole parameter gradient."""
 import numpy as np
 import pytest
