@@ -247,7 +247,7 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
     p.grid_b = (int)(2 * G);
   }
   p.grid_b0 = (int)std::min<int64_t>(p.n_sub0, cap);
-  p.grid_g0 = (int)std::min<int64_t>(std::max<int64_t>(1, p.n_pad / 4 / 64), 128);
+  p.grid_g0 = (int)std::min<int64_t>(std::max<int64_t>(1, p.n_pad / 4 / 64), kGridCap);
   // workspace layout
   int64_t o = 0;
   auto take = [&](int64_t bytes) { int64_t r = o; o = align_up(o + bytes, kAlign); return r; };

@@ -2022,19 +2022,33 @@ __device__ __forceinline__ void grad0_range(const float* zb, const float4* pts, 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nob = n_out / 16;
   __syncthreads();
-  for (int ob = 0; ob < nob; ++ob) {
-    float s[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int64_t cb = cb_lo + wave; cb < cb_hi; cb += kWaves) {
-      const float4 z = *jet_frag(const_cast<float*>(zb), cb, ob, nob, lane);
-      const float4 x = pts[4 * cb + g];
-      s[0] += z.x * x.x + z.y;
-      s[1] += z.x * x.y + z.z;
-      s[2] += z.x * x.z + z.w;
-      s[3] += z.x;
+  // every cp block once, all neuron blocks of it together (up to 16 independent loads in
+  // flight per wave); per neuron block the sums run over the cp blocks in order
+  constexpr int kMaxOb = 16;  // n_out <= 256
+  float s[kMaxOb][4];
+#pragma unroll
+  for (int ob = 0; ob < kMaxOb; ++ob)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[ob][k] = 0.f;
+  for (int64_t cb = cb_lo + wave; cb < cb_hi; cb += kWaves) {
+    const float4 x = pts[4 * cb + g];
+#pragma unroll
+    for (int ob = 0; ob < kMaxOb; ++ob) {
+      if (ob < nob) {
+        const float4 z = *jet_frag(const_cast<float*>(zb), cb, ob, nob, lane);
+        s[ob][0] += z.x * x.x + z.y;
+        s[ob][1] += z.x * x.y + z.z;
+        s[ob][2] += z.x * x.z + z.w;
+        s[ob][3] += z.x;
+      }
     }
+  }
+#pragma unroll
+  for (int ob = 0; ob < kMaxOb; ++ob) {
+    if (ob >= nob) continue;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      float v = s[k];
+      float v = s[ob][k];
       v += __shfl_xor(v, 16, 64);
       v += __shfl_xor(v, 32, 64);
       if (g == 0) red[(wave * 256 + 16 * ob + l16) * 4 + k] = v;
