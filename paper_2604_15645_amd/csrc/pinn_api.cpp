@@ -142,6 +142,7 @@ size_t fwd_lds(int P, int kmax, int H) {
   b += kMaxTerms * 8;                            // LOSS
   b += (size_t)WC * 3 * H * 8 + 3 * 8;           // WL, BL
   b += kFourierLds;                              // BF
+  b += kOutLds + 16;                             // OW (16-byte aligned)
   return b;
 }
 // Layer backward: staged output adjoint (and staged input pre-activations), Q tile, and

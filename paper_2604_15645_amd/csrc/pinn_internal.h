@@ -19,6 +19,7 @@ constexpr int kRedGroups = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kMaxFreq = 128;                     // Fourier frequencies (2 m <= 256)
 constexpr int kFourierLds = 3 * kMaxFreq * 4;     // LDS bytes of a staged Fourier matrix
+constexpr int kOutLds = 8 * 4 * 3 * 32;           // LDS bytes of the staged output-layer fragments
 
 enum { kFP32 = 0, kBF16X3 = 1 };
 enum { kTanh = 0, kSin = 1 };

@@ -850,6 +850,8 @@ struct FwdLds {
   double* WL;    // [WC][3][H] output-layer weight-gradient sums
   double* BL;    // [3] output-layer bias-gradient sums
   float* BF;     // Fourier matrix, d_in x n_freq (staged once per launch)
+  char* OW;      // output-layer weight fragments of the lanes that carry an output:
+                 // [chunk < 8][g < 4][output < 3][32 B] (staged once per launch)
 };
 
 template <int H, int P, int NW = kWaves>
@@ -865,6 +867,7 @@ __device__ __forceinline__ FwdLds fwd_carve(char* smem, int rs) {
   s.WL = s.LOSS + kMaxTerms;
   s.BL = s.WL + FwdShape<H, P, NW>::WC * 3 * H;
   s.BF = reinterpret_cast<float*>(s.BL + 3);
+  s.OW = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(s.BF + 3 * kMaxFreq) + 15) & ~(uintptr_t)15);
   return s;
 }
 
@@ -875,6 +878,15 @@ __device__ __forceinline__ void fwd_begin(const FwdLds& s, const NetDev& net) {
   for (int i = threadIdx.x; i < kMaxTerms; i += NT) s.LOSS[i] = 0.0;
   for (int i = threadIdx.x; i < FwdShape<H, P, NW>::WC * 3 * H + 3; i += NT) s.WL[i] = 0.0;
   for (int i = threadIdx.x; i < net.d_in * net.n_freq; i += NT) s.BF[i] = net.B[i];
+  // output layer: of each 16-lane group only lanes 0 .. d_out - 1 carry a column
+  const LayerDev& lo = net.layer[net.L];
+  for (int i = threadIdx.x; i < kOutLds / 4; i += NT) {
+    const int w = i & 7, r = i >> 3, o = r % 3, g = (r / 3) & 3, kc = r / 12;
+    uint32_t v = 0;
+    if (kc < lo.kci && o < net.d_out)
+      v = reinterpret_cast<const uint32_t*>(lo.wf + ((size_t)kc * 64 + 16 * g + o) * 32)[w];
+    reinterpret_cast<uint32_t*>(s.OW)[i] = v;
+  }
 }
 
 // Write the accumulated sums of a run of tiles: loss terms, and (with the gradient) the
@@ -1068,33 +1080,19 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
     }
   }
 
-  // ---- output layer (d_out <= 3 columns of one 16-wide block): waves over cp blocks; all
-  // weight chunks (at most 8: input width <= 256) are requested before the first is used
-  constexpr int kOutChunks = kPre ? 8 : 1;
+  // ---- output layer (d_out <= 3 columns of one 16-wide block): waves over cp blocks, the
+  // weight fragments from their staged copy in LDS (zero on the lanes without an output)
   const char* XL = ((L - 1) & 1) ? X : s.X2;  // the last hidden layer's activations
-  Raw ow[kOutChunks];
-  if (kPre) {
-#pragma unroll
-    for (int kc = 0; kc < kOutChunks; ++kc)
-      if (kc < lout.kci) ow[kc] = glob_frag(lout.wf, 0, kc, lout.kci, lane);
-  }
   const float obias = l16 < dout ? lout.b[l16] : 0.0f;
   for (int cb = wave; cb < CPB; cb += NW) {
     f4 y = f4{0.f, 0.f, 0.f, 0.f};
-    if (kPre) {
-#pragma unroll
-      for (int kc = 0; kc < kOutChunks; ++kc) {
-        if (kc < lout.kci) {
-          const Raw a = Tile<PREC>::load(XL, ld, cb, kc, lane);
-          Pr::mma(y, a, ow[kc]);
-        }
-      }
-    } else {
-      for (int kc = 0; kc < lout.kci; ++kc) {
-        const Raw bw = glob_frag(lout.wf, 0, kc, lout.kci, lane);
-        const Raw a = Tile<PREC>::load(XL, ld, cb, kc, lane);
-        Pr::mma(y, a, bw);
-      }
+    for (int kc = 0; kc < lout.kci; ++kc) {
+      const Raw a = Tile<PREC>::load(XL, ld, cb, kc, lane);
+      Raw bw;
+      bw.a = make_uint4(0, 0, 0, 0);
+      bw.b = bw.a;
+      if (l16 < 3) bw = *reinterpret_cast<const Raw*>(s.OW + ((kc * 4 + g) * 3 + l16) * 32);
+      Pr::mma(y, a, bw);
     }
     if (l16 < dout) {
       y.x += obias;
@@ -2500,7 +2498,7 @@ size_t batched_lds(int kmax, int H) {
   const int WN = H / 16 < kWaves ? H / 16 : kWaves;
   const int WC = kWaves / WN;
   size_t f = (size_t)4 * PF * r_stride(kmax) + (size_t)PF * 16 + (size_t)PF * 12 * 4 * 2 + kWaves * 4 * 4 +
-             kMaxTerms * 8 + (size_t)WC * 3 * H * 8 + 3 * 8 + kFourierLds;
+             kMaxTerms * 8 + (size_t)WC * 3 * H * 8 + 3 * 8 + kFourierLds + kOutLds + 16;
   size_t b = bwd_lds_bytes(PB, H, H, true);
   size_t g = (size_t)kWaves * 256 * 4 * sizeof(float);
   size_t m = f > b ? f : b;
