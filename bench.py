@@ -9,7 +9,8 @@ Default workload: 2D Maxwell (E_z, H_x, H_y) network with 128 Fourier frequencie
 single-GPU configuration of the benchmark set.  The BF16X3 path is the reported value;
 the plain FP32 matrix-core path is timed beside it.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the benchmark runs on one GPU (how the
+points would shard over several is a design note, not a run).
 """
 import argparse
 import json
@@ -165,8 +166,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only (--gpus 1); multi-GPU runs are not part of this "
-              "build", file=sys.stderr)
+        print("bench.py runs on one GPU only (--gpus 1): the fused step is measured on one GPU's "
+              "share of the points; runs on several GPUs are not provided", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
