@@ -138,7 +138,7 @@ size_t fwd_lds(int P, int kmax, int H) {
   size_t b = (size_t)4 * P * (kmax * 4 + 16) * (fwd_double_x(P) ? 2 : 1);  // X (one or two)
   b += (size_t)P * 16;                           // PT
   b += (size_t)P * 12 * 4 * 2;                   // YJ, YB
-  b += NW * 4 * 4;                               // RED
+  b += NW * 8 * 4;                               // RED
   b += kMaxTerms * 8;                            // LOSS
   b += (size_t)WC * 3 * H * 8 + 3 * 8;           // WL, BL
   b += kFourierLds;                              // BF

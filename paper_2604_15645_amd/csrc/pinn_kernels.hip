@@ -845,7 +845,7 @@ struct FwdLds {
   float4* PT;    // tile points
   float* YJ;     // [P][3][4] output jets
   float* YB;     // [P][3][4] output-jet adjoints
-  float* RED;    // [waves][4] wave partial sums
+  float* RED;    // [waves][8] wave partial sums (loss terms, then output-bias adjoints)
   double* LOSS;  // [kMaxTerms] sums of squares (FP64, per work item)
   double* WL;    // [WC][3][H] output-layer weight-gradient sums
   double* BL;    // [3] output-layer bias-gradient sums
@@ -863,7 +863,7 @@ __device__ __forceinline__ FwdLds fwd_carve(char* smem, int rs) {
   s.YJ = reinterpret_cast<float*>(s.PT + P);
   s.YB = s.YJ + P * 12;
   s.RED = s.YB + P * 12;
-  s.LOSS = reinterpret_cast<double*>(s.RED + NW * 4);
+  s.LOSS = reinterpret_cast<double*>(s.RED + NW * 8);
   s.WL = s.LOSS + kMaxTerms;
   s.BL = s.WL + FwdShape<H, P, NW>::WC * 3 * H;
   s.BF = reinterpret_cast<float*>(s.BL + 3);
@@ -1104,6 +1104,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
 
   // ---- residual (or supervision misfit), loss partial sums and the output-jet seed
   float part[3] = {0.f, 0.f, 0.f};
+  float ybv[3] = {0.f, 0.f, 0.f};  // value-channel output adjoints: the output bias gradient
   if (tid < P) {
     const int p = tid;
     float y[3][4], yb[3][4];
@@ -1141,21 +1142,32 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
         for (int c = 0; c < 4; ++c) yb[o][c] = 0.0f;
     }
 #pragma unroll
-    for (int o = 0; o < 3; ++o)
+    for (int o = 0; o < 3; ++o) {
       *reinterpret_cast<float4*>(s.YB + (p * 3 + o) * 4) = make_float4(yb[o][0], yb[o][1], yb[o][2], yb[o][3]);
+      ybv[o] = yb[o][0];
+    }
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const float v = wave_sum(part[k]);
-    if (lane == 0) s.RED[wave * 4 + k] = v;
+    const float u = wave_sum(ybv[k]);
+    if (lane == 0) {
+      s.RED[wave * 8 + k] = v;
+      s.RED[wave * 8 + 4 + k] = u;
+    }
   }
   barrier_lds();
-  if (tid == 0) {
+  {
+    // one thread per loss term and per output bias, each summing the waves in order
     const int nterm = sg.kind == 0 ? pde.n_res : 1;
-    for (int k = 0; k < nterm; ++k) {
+    if (tid < nterm) {
       double t = 0.0;
-      for (int w = 0; w < NW; ++w) t += (double)s.RED[w * 4 + k];
-      s.LOSS[sg.term + k] += t;
+      for (int w = 0; w < NW; ++w) t += (double)s.RED[w * 8 + tid];
+      s.LOSS[sg.term + tid] += t;
+    } else if (with_grad && tid >= 4 && tid < 4 + dout) {
+      double t = 0.0;
+      for (int w = 0; w < NW; ++w) t += (double)s.RED[w * 8 + tid];
+      s.BL[tid - 4] += t;
     }
   }
 
@@ -1163,11 +1175,6 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
   if (with_grad) {
     const int nL = lout.n_in;
     const int nbs = nL / 16;
-    if (tid < dout) {
-      float t = 0.0f;
-      for (int p = 0; p < P; ++p) t += s.YB[(p * 3 + tid) * 4];
-      s.BL[tid] += (double)t;
-    }
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
       const int nb = wn + WN * i;
@@ -2497,7 +2504,7 @@ size_t batched_lds(int kmax, int H) {
   const int PB = 2048 / H;
   const int WN = H / 16 < kWaves ? H / 16 : kWaves;
   const int WC = kWaves / WN;
-  size_t f = (size_t)4 * PF * r_stride(kmax) + (size_t)PF * 16 + (size_t)PF * 12 * 4 * 2 + kWaves * 4 * 4 +
+  size_t f = (size_t)4 * PF * r_stride(kmax) + (size_t)PF * 16 + (size_t)PF * 12 * 4 * 2 + kWaves * 8 * 4 +
              kMaxTerms * 8 + (size_t)WC * 3 * H * 8 + 3 * 8 + kFourierLds + kOutLds + 16;
   size_t b = bwd_lds_bytes(PB, H, H, true);
   size_t g = (size_t)kWaves * 256 * 4 * sizeof(float);
