@@ -360,80 +360,11 @@ struct FragStore {
 // PRE: the weight fragments of chunks 0 and 1 (chunk 0 again when there is one chunk) come
 // in pre0 / pre1, loaded by the caller before its own stores, so that waiting for them does
 // not wait for those stores (vector-memory counters complete in issue order).
-// bf16x3 form of the tile product with every operand requested well before its use: the A
-// fragment of cp block c for chunk kc + 1 is read from LDS as soon as the three products of
-// chunk kc that use it have issued (the other blocks' products cover the LDS latency), and
-// the weight fragments of chunk kc + 2 load while chunk kc multiplies, from two register
-// sets in turn.  Per accumulator the products keep the order of Prec::mma (lo*hi, hi*lo,
-// hi*hi), so results equal those of the plain loop bit for bit.
-template <int NB, int CB, bool PRE>
-__device__ __forceinline__ void gemm_tile_rot(f4 (&acc)[NB][CB], const char* X, int ld, int cb0,
-                                              const char* frags, int kchunks, const int (&blk)[NB], int lane,
-                                              const Raw (&pre0)[NB], const Raw (&pre1)[NB]) {
-  using T = Tile<kBF16X3>;
-  const char* fb[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) fb[i] = frags + ((size_t)blk[i] * kchunks * 64 + lane) * 32;
-  auto load_b = [&](Raw (&b)[NB], int kc) {
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const uint4* p = reinterpret_cast<const uint4*>(fb[i] + (size_t)kc * 2048);
-      b[i].a = p[0];
-      b[i].b = p[1];
-    }
-  };
-  Raw b0[NB], b1[NB], a[CB];
-  if (PRE) {
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      b0[i] = pre0[i];
-      b1[i] = pre1[i];
-    }
-  } else {
-    load_b(b0, 0);
-    load_b(b1, kchunks > 1 ? 1 : 0);
-  }
-#pragma unroll
-  for (int c = 0; c < CB; ++c) a[c] = T::load(X, ld, cb0 + c, 0, lane);
-  auto step = [&](const Raw (&b)[NB], int kc) {
-    const int kn = kc + 1 < kchunks ? kc + 1 : kc;
-#pragma unroll
-    for (int c = 0; c < CB; ++c) {
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[c].b),
-                                                            __builtin_bit_cast(bf16x8, b[i].a), acc[i][c], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[c].a),
-                                                            __builtin_bit_cast(bf16x8, b[i].b), acc[i][c], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[c].a),
-                                                            __builtin_bit_cast(bf16x8, b[i].a), acc[i][c], 0, 0, 0);
-      a[c] = T::load(X, ld, cb0 + c, kn, lane);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  };
-  for (int kc = 0; kc < kchunks; kc += 2) {
-    step(b0, kc);
-    load_b(b0, kc + 2 < kchunks ? kc + 2 : kchunks - 1);
-    if (kc + 1 < kchunks) {
-      step(b1, kc + 1);
-      load_b(b1, kc + 3 < kchunks ? kc + 3 : kchunks - 1);
-    }
-  }
-}
-
 template <int PREC, int NB, int CB, int CGMAX = 8, bool PREFETCH = false, bool PRE = false>
 __device__ __forceinline__ void gemm_tile(f4 (&acc)[NB][CB], const char* X, int ld, int cb0,
                                           const char* frags, int kchunks, const int (&blk)[NB], int lane,
                                           const Raw (&pre0)[NB], const Raw (&pre1)[NB]) {
   static_assert(!PRE || PREFETCH, "preloaded chunks need the prefetching loop");
-  if constexpr (PREC == kBF16X3 && PREFETCH && CB <= CGMAX) {
-    gemm_tile_rot<NB, CB, PRE>(acc, X, ld, cb0, frags, kchunks, blk, lane, pre0, pre1);
-    return;
-  }
   const char* fb[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) fb[i] = frags + ((size_t)blk[i] * kchunks * 64 + lane) * 32;
