@@ -4,10 +4,19 @@ A step is one pinn_residual_bwd call over the whole synthetic collocation set: e
 jets, every hidden layer, output layer, PDE residual, loss, and dL/dtheta for every
 parameter.  Inputs are resident in device memory before the timed region starts.
 
-Default workload: 2D Maxwell (E_z, H_x, H_y) network with 128 Fourier frequencies
+Headline workload: 2D Maxwell (E_z, H_x, H_y) network with 128 Fourier frequencies
 (sigma = 2) and 6 x 256 sine layers, 1,048,576 uniform points on [0,1]^3 -- the largest
 single-GPU configuration of the benchmark set.  The BF16X3 path is the reported value;
-the plain FP32 matrix-core path is timed beside it.
+the plain FP32 matrix-core path is timed beside it.  The other configurations (Burgers,
+1D Euler, Navier-Stokes, and the 64-network Burgers sweep in one persistent launch) are
+timed in the same run and reported as extra keys of the same JSON line.
+
+Roofline: the contractions are dense matrix products, so the bound is the matrix-core
+rate.  For bf16x3 every logical product is three BF16 products, so the achieved rate is
+3 x algorithmic FLOPs / time against the 2.5 PFLOP/s dense BF16 peak; FP32 is algorithmic
+FLOPs / time against 157.3 TFLOP/s.  Algorithmic FLOPs per point: 2 C n_in n_out per
+linear layer in the forward (2 d_in n_out for an identity-embedding first layer), the same
+again for each weight gradient and for each input adjoint (none for the first layer).
 
 Prints one JSON line.  --gpus above 1 is refused: the benchmark runs on one GPU (how the
 points would shard over several is a design note, not a run).
@@ -26,6 +35,8 @@ METRIC = "collocation points/sec for fused residual+grad step, BF16x3 vs FP32 at
 PEAK = {"bf16": 2.5e15, "fp32": 157.3e12}   # dense matrix-core peaks, FLOP/s
 HBM_PEAK = 8.0e12
 TOL = {"fp32": 1e-5, "bf16x3": 1e-4}
+N_PROD = {"bf16x3": 3, "fp32": 1}
+PEAK_OF = {"bf16x3": "bf16", "fp32": "fp32"}
 
 
 def channels(net, pde):
@@ -62,13 +73,9 @@ def kernel_flops(net, pde, n_points):
 
 
 def kernel_bytes(net, pde, n_points):
-    """Algorithmic HBM bytes per launch of each kernel kind: the jets that must cross HBM
-    between the kernels (C FP32 channels per neuron and point), plus the points.
-
-    Forward: points in, pre-activation jets of the hidden layers the backward reads (all but
-    the last) out, adjoint jets of the last hidden layer out.  Hidden-layer backward: the
-    layer's output adjoint and its input pre-activations in, the input adjoint out.
-    Embedding-layer backward: its output adjoint and the points in."""
+    """HBM bytes per launch of each kernel kind that this design moves between kernels
+    (the pre-activation stash and the adjoints, C FP32 channels per neuron and point, plus
+    the points): the traffic of the layer-by-layer backward, not a property of the method."""
     from paper_2604_15645_amd import synth
     C = channels(net, pde)
     dims = synth.layer_dims(net)
@@ -82,21 +89,30 @@ def kernel_bytes(net, pde, n_points):
     return out
 
 
+def source_sha256():
+    """Hash of the kernel and host sources (the counter summaries record the one they were
+    taken on)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2604_15645_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
 def measured_traffic(config, kernel):
     """HBM bytes per launch of `kernel` on this workload from the committed counter summary
     (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by the copy calibration), or None when no
-    summary exists or the kernel source has changed since the counters were taken."""
-    import hashlib
+    summary exists or the sources have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "%s_bf16x3_traffic.json" % config)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    src = os.path.join(ROOT, "paper_2604_15645_amd", "csrc", "pinn_kernels.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
     k = rec.get("kernels", {}).get(kernel)
-    if rec.get("source_sha256") != sha or k is None:
+    if rec.get("source_sha256") != source_sha256() or k is None:
         return None
     return k["hbm_bytes_per_launch"]
 
@@ -111,12 +127,13 @@ def make_inputs(name, n_points, dev):
     return case, t(case["params"]), t(case["B"]), t(case["points"]), anchors
 
 
-def time_steps(case, params, B, pts, anchors, prec, steps, warmup, tune=None):
+def time_steps(case, params, B, pts, anchors, prec, steps, warmup, tune=None, per_kernel=True):
+    """Mean ms per step over `steps` calls after `warmup` calls (HIP events on the stream
+    the library launches on), the per-kernel record of the timed calls, and the outputs."""
     import torch
     from paper_2604_15645_amd import binding
     net, pde = case["net"], case["pde"]
     ws = binding.Workspace(pts.device)
-    out = {}
     r = binding.residual_step(net, pde, params, B, pts, anchors, prec=prec, residual=True,
                               workspace=ws, tune=tune)
     out = dict(r)
@@ -125,7 +142,7 @@ def time_steps(case, params, B, pts, anchors, prec, steps, warmup, tune=None):
                               out=out, tune=tune)
     torch.cuda.synchronize()
     binding.timing_collect()          # drop anything recorded before the timed region
-    binding.timing_enable(True)
+    binding.timing_enable(per_kernel)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
@@ -136,9 +153,8 @@ def time_steps(case, params, B, pts, anchors, prec, steps, warmup, tune=None):
     binding.timing_enable(False)
     kernels = binding.timing_collect()
     ms = e0.elapsed_time(e1) / steps
-    res = {k: v for k, v in out.items()}
     del ws
-    return ms, kernels, res
+    return ms, kernels, out
 
 
 def relerr(a, b):
@@ -147,6 +163,107 @@ def relerr(a, b):
     b = np.asarray(b, dtype=np.float64).ravel()
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def parity(out, ref):
+    import numpy as np
+    lo = out["loss"].cpu().numpy()
+    return {"residual": relerr(out["residual"].cpu().numpy(), ref["residual"]),
+            "loss": float(np.max(np.abs(lo - ref["loss"]) / np.abs(ref["loss"]))),
+            "grad": relerr(out["grad"].cpu().numpy(), ref["grad"])}
+
+
+def bench_config(name, dev, steps, warmup, sample, fp32=True):
+    """One single-network configuration at full size: both precisions, matrix-core
+    fractions of the whole step, and parity on a prefix of the points (oracle)."""
+    import torch
+    from oracle import oracle
+    from paper_2604_15645_amd import binding, synth
+    case, params, B, pts, anchors = make_inputs(name, None, dev)
+    net, pde = case["net"], case["pde"]
+    n = len(case["points"])
+    n_total = n + sum(len(a["points"]) for a in case["anchors"])
+    _, step_flops = kernel_flops(net, pde, n_total)
+    rec = {"workload": describe(net, pde, n), "points": n}
+    precs = ("bf16x3", "fp32") if fp32 else ("bf16x3",)
+    m = min(sample, n)
+    ref = oracle.loss_grad(net, pde, case["params"], case["B"], case["points"][:m], case["anchors"])
+    for prec in precs:
+        ms, _, _ = time_steps(case, params, B, pts, anchors, prec, steps, warmup, per_kernel=False)
+        o = binding.residual_step(net, pde, params, B, pts[:m].contiguous(), anchors, prec=prec)
+        torch.cuda.synchronize()
+        rec[prec] = {"ms_per_step": ms, "points_per_s": n / (ms / 1e3),
+                     "mfma_frac": N_PROD[prec] * step_flops / (ms / 1e3) / PEAK[PEAK_OF[prec]],
+                     "parity": dict(parity(o, ref), tol=TOL[prec], sample_points=m)}
+    if fp32:
+        rec["speedup_bf16x3_vs_fp32"] = rec["fp32"]["ms_per_step"] / rec["bf16x3"]["ms_per_step"]
+    return rec
+
+
+def bench_sweep(dev, steps, warmup):
+    """The 64 Burgers networks of uneven width, depth and point count in one persistent
+    launch (pinn_batched_bwd), against the same networks as 64 separate calls."""
+    import numpy as np
+    import torch
+    from oracle import oracle
+    from paper_2604_15645_amd import binding, synth
+    insts = synth.make_sweep()
+    nets = [c["net"] for c in insts]
+    pde = insts[0]["pde"]
+    params = [torch.from_numpy(c["params"]).to(dev) for c in insts]
+    pts = [torch.from_numpy(c["points"]).to(dev) for c in insts]
+    n_tot = sum(len(c["points"]) for c in insts)
+    flops = sum(kernel_flops(c["net"], c["pde"], len(c["points"]))[1] for c in insts)
+    rec = {"workload": "64 Burgers networks, widths 32-256, depths 3-6, %d points in all" % n_tot,
+           "points": n_tot, "alg_tflop": flops / 1e12}
+    # parity: the smallest instance of each width class, whole gradient against the oracle
+    pick = {}
+    for i, c in enumerate(insts):
+        w = c["net"]["widths"][0]
+        if w not in pick or len(c["points"]) < len(insts[pick[w]]["points"]):
+            pick[w] = i
+    refs = {i: oracle.loss_grad(insts[i]["net"], pde, insts[i]["params"], None, insts[i]["points"],
+                                want_residual=False) for i in sorted(pick.values())}
+    for prec in ("bf16x3", "fp32"):
+        ws = binding.Workspace(dev)
+        run = lambda: binding.batched_step(nets, pde, params, pts, prec=prec, workspace=ws)
+        out = run()
+        for _ in range(max(0, warmup - 1)):
+            run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            out = run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        # the same networks as separate calls, one after the other
+        ws1 = binding.Workspace(dev)
+        single = lambda: [binding.residual_step(c["net"], pde, params[i], None, pts[i], (), prec=prec,
+                                                residual=False, workspace=ws1)
+                          for i, c in enumerate(insts)]
+        single()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(max(1, steps // 4)):
+            single()
+        e1.record()
+        torch.cuda.synchronize()
+        ms1 = e0.elapsed_time(e1) / max(1, steps // 4)
+        losses = out["losses"].cpu().numpy()
+        worst = {"loss": 0.0, "grad": 0.0}
+        for i, ref in refs.items():
+            worst["loss"] = max(worst["loss"], float(np.max(np.abs(losses[i] - ref["loss"]) /
+                                                            np.abs(ref["loss"]))))
+            worst["grad"] = max(worst["grad"], relerr(out["grads"][i].cpu().numpy(), ref["grad"]))
+        rec[prec] = {"ms_per_step": ms, "points_per_s": n_tot / (ms / 1e3),
+                     "mfma_frac": N_PROD[prec] * flops / (ms / 1e3) / PEAK[PEAK_OF[prec]],
+                     "separate_calls_ms": ms1, "speedup_vs_separate_calls": ms1 / ms,
+                     "parity": dict(worst, tol=TOL[prec],
+                                    instances=[int(i) for i in sorted(refs)])}
+        del ws, ws1
+    return rec
 
 
 def main():
@@ -159,6 +276,8 @@ def main():
     ap.add_argument("--sample", type=int, default=65536, help="CPU-baseline / parity prefix")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-others", action="store_true",
+                    help="skip the other configurations and the batched sweep")
     ap.add_argument("--tile-points", type=int, default=0, help="forward tile points (0 = the library's)")
     ap.add_argument("--grid", type=int, default=0, help="work-group cap (0 = the library's)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -189,43 +308,41 @@ def main():
     case, params, B, pts, anchors = make_inputs(name, n_points, dev)
     net, pde = case["net"], case["pde"]
     n_total = n_points + sum(len(a["points"]) for a in case["anchors"])
+    print("bench: %s, %d points" % (name, n_points), file=sys.stderr, flush=True)
 
     tune = {"tile_points": args.tile_points, "grid": args.grid} if args.tile_points or args.grid else None
     ms16, k16, out16 = time_steps(case, params, B, pts, anchors, "bf16x3", args.steps, args.warmup, tune)
     fp32 = None
     if not args.no_fp32:
-        ms32, k32, out32 = time_steps(case, params, B, pts, anchors, "fp32",
-                                      max(2, args.steps // 4), min(args.warmup, 2))
+        ms32, k32, _ = time_steps(case, params, B, pts, anchors, "fp32",
+                                  max(2, args.steps // 4), min(args.warmup, 2))
         fp32 = {"value": n_points / (ms32 / 1e3), "ms_per_step": ms32,
                 "kernels_ms": {k: v[1] / v[0] for k, v in k32.items()}}
+    print("bench: timed", file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel (largest summed time per step): the bound is the
-    # resource whose peak gives the longer lower limit on the launch (HBM bytes at 8 TB/s or
-    # bf16 matrix-core FLOPs at 2.5 PFLOP/s); the other resource's figures are reported too
+    # matrix-core roofline of the dominant kernel (largest summed time per step), from the
+    # library's own per-launch events on the stream its kernels run on
     flops, step_flops = kernel_flops(net, pde, n_total)
     nbytes = kernel_bytes(net, pde, n_total)
     dom = max(k16, key=lambda k: k16[k][1])
     launches, tot = k16[dom]
     avg_ms = tot / launches
     alg = flops.get(dom, 0)
-    alg_b = nbytes.get(dom, 0)
-    n_prod = 3  # BF16X3: three bf16 matrix-core products per logical FP32 product
+    n_prod = N_PROD["bf16x3"]
     roof = None
-    if alg and alg_b:
+    if alg:
         mfma = n_prod * alg / (avg_ms / 1e3)
-        hbm = alg_b / (avg_ms / 1e3)
-        hbm_bound = alg_b / HBM_PEAK >= n_prod * alg / PEAK["bf16"]
-        traffic = measured_traffic(name, dom) if n_points == synth.CONFIGS[name]["n_points"] else None
-        if hbm_bound:
-            roof = {"kernel": dom, "bound": "hbm", "achieved": hbm / 1e9, "peak": HBM_PEAK / 1e9,
-                    "unit": "GB/s", "frac": hbm / HBM_PEAK, "traffic": traffic,
-                    "mfma_achieved_tflops": mfma / 1e12, "mfma_frac": mfma / PEAK["bf16"]}
-        else:
-            roof = {"kernel": dom, "bound": "mfma", "achieved": mfma / 1e12, "peak": PEAK["bf16"] / 1e12,
-                    "unit": "TFLOP/s", "frac": mfma / PEAK["bf16"], "traffic": traffic,
-                    "hbm_achieved_gbs": hbm / 1e9, "hbm_frac": hbm / HBM_PEAK}
-        roof.update({"alg_bytes_per_launch": alg_b, "alg_flops_per_launch": alg, "n_prod": n_prod,
-                     "avg_launch_ms": avg_ms})
+        is_full = n_points == synth.CONFIGS[name]["n_points"] and tune is None
+        roof = {"kernel": dom, "bound": "mfma", "achieved": mfma / 1e12, "peak": PEAK["bf16"] / 1e12,
+                "unit": "TFLOP/s", "frac": mfma / PEAK["bf16"],
+                "traffic": measured_traffic(name, dom) if is_full else None,
+                "alg_flops_per_launch": alg, "n_prod": n_prod, "avg_launch_ms": avg_ms,
+                "launches_per_step": launches / args.steps,
+                "step_frac": n_prod * step_flops / (ms16 / 1e3) / PEAK["bf16"]}
+        if nbytes.get(dom):
+            roof["stash_bytes_per_launch"] = nbytes[dom]
+            roof["stash_gbs"] = nbytes[dom] / (avg_ms / 1e3) / 1e9
+            roof["stash_hbm_frac"] = nbytes[dom] / (avg_ms / 1e3) / HBM_PEAK
 
     result = {
         "metric": METRIC,
@@ -257,32 +374,46 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import oracle
         m = min(args.sample, n_points)
-        sample = dict(case, points=case["points"][:m])
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
         t0 = time.time()
-        ref = oracle.loss_grad(net, pde, case["params"], case["B"], sample["points"],
+        ref = oracle.loss_grad(net, pde, case["params"], case["B"], case["points"][:m],
                                case["anchors"], n_threads=threads)
         dt = time.time() - t0
+        m1 = min(m, 1024)
+        t0 = time.time()
+        oracle.loss_grad(net, pde, case["params"], case["B"], case["points"][:m1], case["anchors"],
+                         n_threads=1)
+        dt1 = time.time() - t0
         result["cpu_baseline"] = {"value": m / dt, "unit": "points/s", "cores": threads,
                                   "kind": "oracle",
                                   "sample": "first %d of the %d points (+%d supervision points), "
                                             "FP64 loss and gradient, %.1f s" %
-                                            (m, n_points, n_total - n_points, dt)}
+                                            (m, n_points, n_total - n_points, dt),
+                                  "single_thread": {"value": m1 / dt1, "unit": "points/s",
+                                                    "sample": "first %d points, %.1f s" % (m1, dt1)}}
         # parity at the benchmark's own shape: the prefix through the GPU path
         par = {}
         ptsm = pts[:m].contiguous()
         for prec in ("bf16x3", "fp32"):
             o = binding.residual_step(net, pde, params, B, ptsm, anchors, prec=prec)
             torch.cuda.synchronize()
-            g = o["grad"].cpu().numpy()
-            lo = o["loss"].cpu().numpy()
-            rs = o["residual"].cpu().numpy()
-            par[prec] = {"residual": relerr(rs, ref["residual"]),
-                         "loss": float(np.max(np.abs(lo - ref["loss"]) / np.abs(ref["loss"]))),
-                         "grad": relerr(g, ref["grad"]), "tol": TOL[prec]}
+            par[prec] = dict(parity(o, ref), tol=TOL[prec])
         full = out16["residual"].cpu().numpy()[:m]
         par["bf16x3_full_run_residual"] = relerr(full, ref["residual"])
         result["parity_vs_oracle"] = par
+        print("bench: cpu baseline and parity done", file=sys.stderr, flush=True)
+
+    if not args.no_others and not args.points and tune is None:
+        others = {}
+        for other in ("burgers", "euler", "ns", "maxwell"):
+            if other == name:
+                continue
+            others[other] = bench_config(other, dev, args.steps, args.warmup, 8192,
+                                         fp32=not args.no_fp32)
+            print("bench: %s done" % other, file=sys.stderr, flush=True)
+        result["configs"] = others
+        result["sweep"] = bench_sweep(dev, max(3, args.steps // 2), args.warmup)
+        print("bench: sweep done", file=sys.stderr, flush=True)
     print(json.dumps(result))
 
 

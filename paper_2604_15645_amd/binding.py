@@ -209,6 +209,31 @@ def _check_dev(t, name, dtype=torch.float32):
         raise ValueError("%s must be a contiguous %s tensor" % (name, dtype))
 
 
+def _check_shapes(net_spec, params, B, points, anchors=()):
+    """Sizes the C ABI cannot see: a mis-sized buffer would be read out of bounds on the
+    device, so every size is checked here before any library call (ValueError)."""
+    d_in, d_out = int(net_spec["d_in"]), int(net_spec["d_out"])
+    n_freq = int(net_spec.get("n_freq", 0))
+    want = param_count(net_spec)
+    if params.dim() != 1 or params.numel() != want:
+        raise ValueError("params must be a flat tensor of %d values, got shape %s"
+                         % (want, tuple(params.shape)))
+    if points.dim() != 2 or points.shape[1] != d_in:
+        raise ValueError("points must have shape (n, %d), got %s" % (d_in, tuple(points.shape)))
+    if n_freq > 0:
+        if B is None or B.numel() != d_in * n_freq:
+            raise ValueError("fourier_B must hold d_in x n_freq = %d values" % (d_in * n_freq))
+    elif B is not None:
+        raise ValueError("fourier_B given for a network without Fourier features")
+    for i, a in enumerate(anchors):
+        ap, at = a["points"], a["targets"]
+        if ap.dim() != 2 or ap.shape[1] != d_in:
+            raise ValueError("anchor %d points must have shape (n, %d)" % (i, d_in))
+        if at.numel() != ap.shape[0] * d_out:
+            raise ValueError("anchor %d targets must hold n x d_out = %d values"
+                             % (i, ap.shape[0] * d_out))
+
+
 def residual_step(net_spec, pde_spec, params, B, points, anchors=(), prec="bf16x3", grad=True,
                   residual=True, tune=None, flags=0, workspace=None, out=None):
     """One call of pinn_residual_bwd (grad=True) or pinn_residual_fwd.
@@ -223,6 +248,7 @@ def residual_step(net_spec, pde_spec, params, B, points, anchors=(), prec="bf16x
     for a in anchors:
         _check_dev(a["points"], "anchor points")
         _check_dev(a["targets"], "anchor targets")
+    _check_shapes(net_spec, params, B, points, anchors)
     dev = points.device
     n, p = net_struct(net_spec), pde_struct(pde_spec)
     arr = _anchor_array(anchors)
@@ -303,9 +329,12 @@ def batched_step(net_specs, pde_spec, params, points, prec="bf16x3", tune_table=
     params[i], points[i]: FP32 device tensors.  Returns dict(losses = FP64 [n_inst, 1 + n_res],
     grads = list of FP64 [n_params_i])."""
     n = len(net_specs)
+    if len(params) != n or len(points) != n:
+        raise ValueError("one params and one points tensor per network")
     for i in range(n):
         _check_dev(params[i], "params[%d]" % i)
         _check_dev(points[i], "points[%d]" % i)
+        _check_shapes(net_specs[i], params[i], None, points[i])
     dev = points[0].device
     nets, npts, tt = _batch_structs(net_specs, [p.shape[0] for p in points], tune_table)
     p = pde_struct(pde_spec)

@@ -87,8 +87,8 @@ int check_pde(const pinn_net* net, const pinn_pde* pde) {
   for (int k = 0; k < 4; ++k)
     if (!std::isfinite(pde->coef[k])) return PINN_E_INVALID;
   switch (pde->pde_id) {
-    case PINN_PDE_BURGERS:
-      if (net->d_in != 2 || !(pde->lap_mask & 1)) return PINN_E_UNSUPPORTED;
+    case PINN_PDE_BURGERS:  // the Laplacian channel must be u_xx alone
+      if (net->d_in != 2 || pde->lap_mask != 1) return PINN_E_UNSUPPORTED;
       return PINN_OK;
     case PINN_PDE_EULER1D:
       if (net->d_in != 2 || net->d_out != 3 || !(pde->coef[0] > 1.0)) return PINN_E_UNSUPPORTED;

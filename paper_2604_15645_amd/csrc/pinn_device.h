@@ -1,5 +1,9 @@
-// pinn_kernels.hip -- gfx950 kernels of the fused PINN residual + gradient step.
-//
+// pinn_device.h -- device code shared by the gfx950 kernels of the fused PINN residual +
+// gradient step: operand formats and matrix-core products, LDS tile layouts, activation
+// and PDE-residual jets, and the forward / layer-backward bodies that several kernels use.
+// Included by the kernel translation units only.
+#pragma once
+
 // Data model.  Every point carries 4 jet channels: value, first derivatives in the inputs
 // (d_in of them) and, when the PDE needs it, the Laplacian over the inputs in lap_mask;
 // unused channels stay zero.  A tile of P points is a (4P x width) matrix whose rows are
@@ -17,28 +21,23 @@
 // of a lane are the 4 channels of one (point, neuron): the activation jet update is
 // lane-local.
 //
-// Kernels:
-//   k_stage     effective weights W = diag(exp s) V (Sec. 2.6.2) and operand fragments;
-//   k_points    gathers residual and supervision points into one padded buffer;
-//   k_forward   per tile: embedding jets, hidden layers, output layer, residual, loss
-//               partial sums, residual adjoint seed and the output layer's backward;
-//               stores the pre-activation jets of every hidden layer;
-//   k_backward  one linear layer's backward over a contiguous range of tiles: weight
-//               gradient (kept in registers over the whole range), adjoint of the layer
-//               input and the activation adjoint;
-//   k_grad0     identity-embedding first layer's weight gradient;
-//   k_reduce_*  fixed-order FP64 reductions of the per-work-group partial sums.
+// Kernels (one translation unit each group, so that they compile in parallel):
+//   k_misc.hip      k_stage (effective weights W = diag(exp s) V, Sec. 2.6.2, and operand
+//                   fragments), k_points (residual and supervision points gathered into one
+//                   padded buffer), k_grad0 (identity-embedding first layer's weight
+//                   gradient), k_reduce_* (fixed-order FP64 reductions of the per-work-group
+//                   partial sums);
+//   k_forward.hip   per tile: embedding jets, hidden layers, output layer, residual, loss
+//                   partial sums, residual adjoint seed and the output layer's backward;
+//                   stores the pre-activation jets of the hidden layers the backward reads;
+//   k_backward.hip  one linear layer's backward over a range of sub-tiles: weight gradient
+//                   (kept in registers over the range), adjoint of the layer input and the
+//                   activation adjoint;
+//   k_batched.hip   many independent networks in one persistent launch.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "pinn_internal.h"
-
-#ifndef PINN_R_PAIR
-#define PINN_R_PAIR 1
-#endif
-#ifndef PINN_PREFETCH_B
-#define PINN_PREFETCH_B 0
-#endif
 
 namespace pinn {
 
@@ -197,17 +196,12 @@ __device__ __forceinline__ float swap_pair(float x) {
 // every pair must be active.
 template <int PREC>
 __device__ __forceinline__ void put_rows(char* base, int rs, int n, f4 a) {
-#if PINN_R_PAIR
   const bool odd = n & 1;
   const float r0 = swap_pair(odd ? a[0] : a[2]);
   const float r1 = swap_pair(odd ? a[1] : a[3]);
   const int row = odd ? 2 : 0, pos = n & 6;
   Prec<PREC>::put2(base + (size_t)row * rs, pos, odd ? r0 : a[0], odd ? a[2] : r0);
   Prec<PREC>::put2(base + (size_t)(row + 1) * rs, pos, odd ? r1 : a[1], odd ? a[3] : r1);
-#else
-#pragma unroll
-  for (int r = 0; r < 4; ++r) Prec<PREC>::put(base + (size_t)r * rs, n & 7, a[r]);
-#endif
 }
 
 __device__ __forceinline__ Raw lds_unit(const char* base, int row, int unit, int stride) {
@@ -658,90 +652,6 @@ __device__ __forceinline__ void rff_jets(const NetDev& net, const float* B, cons
   }
 }
 
-// ================================================================== staging
-
-// Effective weights and operand fragments of every layer.  One thread per (fragment,
-// lane) of either kind, plus the plain FP32 copies.
-
-__device__ __forceinline__ float eff_w(const StageArgs& a, int l, int o, int i) {
-  if (o >= a.n_out[l] || i >= a.n_in[l]) return 0.0f;
-  float v = a.params[a.off_w[l] + (int64_t)o * a.n_in[l] + i];
-  if (a.rwf) v *= expf(a.params[a.off_s[l] + o]);
-  return v;
-}
-
-template <int PREC>
-__global__ void k_stage(const StageArgs a) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.cum[a.n_layers]) return;
-  int l = 0;
-  while (t >= a.cum[l + 1]) ++l;
-  t -= a.cum[l];
-  const int ni = a.n_in[l], no = a.n_out[l];
-  const int nbo = (no + 15) / 16, kci = (ni + 31) / 32;
-  const int nbi = (ni + 15) / 16, kco = (no + 31) / 32;
-  const int64_t nf = (int64_t)nbo * kci * 64, nb = (int64_t)nbi * kco * 64;
-  const int64_t nplain = (int64_t)no * ni;
-  if (t < nf) {  // forward fragment lane: neuron 16 blk + lane % 16, inputs 32 ch + 8 (lane/16) + j
-    int lane = (int)(t % 64);
-    int64_t f = t / 64;
-    int ch = (int)(f % kci), blk = (int)(f / kci);
-    float v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = eff_w(a, l, 16 * blk + lane % 16, 32 * ch + 8 * (lane / 16) + j);
-    Raw r = Prec<PREC>::make(v);
-    uint4* p = reinterpret_cast<uint4*>(a.wf[l] + t * 32);
-    p[0] = r.a;
-    p[1] = r.b;
-    return;
-  }
-  t -= nf;
-  if (t < nb) {  // backward fragment lane: input 16 blk + lane % 16, outputs 32 ch + 8 (lane/16) + j
-    int lane = (int)(t % 64);
-    int64_t f = t / 64;
-    int ch = (int)(f % kco), blk = (int)(f / kco);
-    float v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = eff_w(a, l, 32 * ch + 8 * (lane / 16) + j, 16 * blk + lane % 16);
-    Raw r = Prec<PREC>::make(v);
-    uint4* p = reinterpret_cast<uint4*>(a.wb[l] + t * 32);
-    p[0] = r.a;
-    p[1] = r.b;
-    return;
-  }
-  t -= nb;
-  if (t < nplain) {
-    a.w[l][t] = eff_w(a, l, (int)(t / ni), (int)(t % ni));
-    return;
-  }
-  t -= nplain;
-  if (t < no) a.b[l][t] = a.has_bias ? a.params[a.off_b[l] + t] : 0.0f;
-}
-
-// Gather residual and supervision points into one padded (x, y, t, 0) buffer.
-
-__global__ void k_points(const PointsArgs a) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.n_pad) return;
-  int s = 0;
-  for (int k = 1; k < a.n_seg; ++k)
-    if (p >= a.start[k]) s = k;
-  int64_t i = p - a.start[s];
-  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (i < a.n[s]) {
-    const float* x = a.src[s] + i * a.d_in;
-    v.x = x[0];
-    if (a.d_in > 1) v.y = x[1];
-    if (a.d_in > 2) v.z = x[2];
-  }
-  a.dst[p] = v;
-}
-
-__global__ void k_fill(double* p, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0;
-}
-
 __device__ __forceinline__ void wait_async() { __builtin_amdgcn_s_waitcnt(0); }
 
 // Work-group barrier for LDS traffic: this wave's LDS operations complete (lgkmcnt 0), then
@@ -1146,33 +1056,6 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
   }
 }
 
-template <int PREC, int ACT, int H, int P, int NW = fwd_waves(H, P)>
-__global__ __launch_bounds__(64 * NW, 8 / NW) void k_forward(const FwdArgs A) {
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  const FwdLds s = fwd_carve<H, P, NW>(smem, r_stride(A.kmax));
-  const int ld = Tile<PREC>::ld(A.kmax, P);
-  fwd_begin<H, P, NW>(s, A.net);
-  for (int64_t tile = blockIdx.x; tile < A.n_tiles; tile += gridDim.x) {
-    const int64_t p0 = tile * P;
-    const int sid = seg_of(A.seg, p0);
-    const int64_t nv = A.seg.start[sid] + A.seg.n[sid] - p0;
-    TileSeg sg;
-    sg.nvalid = nv < 0 ? 0 : (nv > P ? P : (int)nv);
-    sg.kind = sid == 0 ? 0 : 1;
-    sg.term = sid == 0 ? 0 : A.pde.n_res + (sid - 1);
-    sg.targets = sid == 0 ? nullptr : A.seg.targets[sid - 1] + (p0 - A.seg.start[sid]) * A.net.d_out;
-    sg.out_mask = sid == 0 ? 0 : A.seg.out_mask[sid - 1];
-    sg.lam = sid == 0 ? 0.0f : A.seg.lam_anchor[sid - 1];
-    sg.residual = (sid == 0 && A.residual) ? A.residual + (p0 - A.seg.start[0]) * A.pde.n_res : nullptr;
-    fwd_tile<PREC, ACT, H, P, NW>(A.net, A.pde, A.work.pts + p0, A.work.zs0, A.work.zs_stride, A.work.zb[0],
-                                  tile * (P / 4), sg, ld, A.with_grad != 0, s);
-  }
-  fwd_end<H, P, NW>(s, A.work.loss_slots + (size_t)blockIdx.x * kMaxTerms,
-                A.with_grad ? A.work.out_slots + (size_t)blockIdx.x * A.net.d_out * (A.net.layer[A.net.L].n_in + 1)
-                            : nullptr,
-                A.net.d_out, A.net.layer[A.net.L].n_in, A.with_grad != 0);
-}
-
 // ================================================================== backward (one layer)
 
 template <int NOB, int NIB, int PB>
@@ -1390,562 +1273,6 @@ __device__ __forceinline__ void bwd_flush(const f4 (&accw)[BwdShape<NOB, NIB, PB
   }
 }
 
-template <int PREC, int ACT, int NOB, int NIB, int PB>
-__global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
-  using S = BwdShape<NOB, NIB, PB>;
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  f4 accw[S::NOBW][S::NIBW];
-#pragma unroll
-  for (int i = 0; i < S::NOBW; ++i)
-#pragma unroll
-    for (int k = 0; k < S::NIBW; ++k) accw[i][k] = f4{0.f, 0.f, 0.f, 0.f};
-  float bsum[S::NOBW];
-#pragma unroll
-  for (int i = 0; i < S::NOBW; ++i) bsum[i] = 0.f;
-  const int64_t count = A.n_sub > blockIdx.x ? (A.n_sub - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
-  bwd_range<PREC, ACT, NOB, NIB, PB>(A.net, A.layer, A.work.pts, blockIdx.x, gridDim.x, count, A.zb_in, A.zb_out,
-                                     A.z_prev, smem, accw, bsum);
-  const LayerDev& ly = A.net.layer[A.layer];
-  bwd_flush<NOB, NIB, PB>(accw, bsum, A.slots + (size_t)blockIdx.x * ly.n_out * (ly.n_in + 1), ly.n_out, ly.n_in);
-}
-
-// ================================================================== backward (one layer, wide)
-
-// Layer backward for bf16x3 when the layer input width is a multiple of 128 (8 waves x
-// 16-column blocks).  Wave w owns input blocks ib = w + 8 k: it computes the input adjoint
-// (and, for a hidden layer, the activation adjoint) for those columns over the whole
-// sub-tile, and the weight-gradient columns of those blocks for every output row.  The
-// weight-gradient product then takes its B operand (activation jets of the layer input,
-// in accumulator order) straight from the wave's registers and its A operand (output
-// adjoint, 8 cp per lane) from the R tile by plain 8-byte reads, so no second LDS tile is
-// needed and sub-tiles can be twice as large as in bwd_range.
-// LDS: STG and R (T layout), both PB x (16 NOB) x 16 bytes.  STG holds, in turn, the staged
-// output-adjoint fragments of the sub-tile (copied in during the previous sub-tile's weight
-// gradient) and the staged layer-input pre-activations (copied in during the input-adjoint
-// product).
-template <int NOB, int NIB, int PB>
-struct WideShape {
-  static constexpr int CPB = PB / 4;
-  static constexpr int NIBW = NIB / 8;             // input blocks per wave (upper bound)
-  static constexpr int NOBC = (NOB + 7) / 8;       // output blocks converted per wave
-  static_assert(NIB % 8 == 0 && CPB % 2 == 0, "wide backward shape");
-};
-
-__host__ __device__ constexpr size_t wide_lds_bytes(int PB, int n_out) { return (size_t)2 * PB * n_out * 16; }
-
-// A operand of the weight gradient for output block ob and cp chunk cc (points 8 cc ..
-// 8 cc + 7): lane (g, l16) takes output o = 16 ob + l16 and the 4 channels of points
-// 8 cc + g and 8 cc + 4 + g -- the cp order of the accumulator fragments.
-__device__ __forceinline__ Raw wide_zbar_op(const char* R, int ld, int ob, int cc, int lane) {
-  const int g = lane >> 4, o = 16 * ob + (lane & 15);
-  const int p0 = 8 * cc + g, p1 = p0 + 4;
-  const char* c0 = R + (size_t)((o >> 5) * ld + (p0 >> 2)) * 2048 + t_cell_off(p0, o);
-  const char* c1 = R + (size_t)((o >> 5) * ld + (p1 >> 2)) * 2048 + t_cell_off(p1, o);
-  const uint2 h0 = *reinterpret_cast<const uint2*>(c0), h1 = *reinterpret_cast<const uint2*>(c1);
-  const uint2 l0 = *reinterpret_cast<const uint2*>(c0 + 1024), l1 = *reinterpret_cast<const uint2*>(c1 + 1024);
-  Raw r;
-  r.a = make_uint4(h0.x, h0.y, h1.x, h1.y);
-  r.b = make_uint4(l0.x, l0.y, l1.x, l1.y);
-  return r;
-}
-
-template <int ACT, int NOB, int NIB, int PB>
-__device__ __forceinline__ void bwd_wide_range(const NetDev& net, int layer, const float4* pts, int64_t s0,
-                                               int64_t stride, int64_t count, const float* zb_in, float* zb_out,
-                                               const float* z_prev, char* smem,
-                                               f4 (&accw)[NOB][WideShape<NOB, NIB, PB>::NIBW],
-                                               float (&bsum)[WideShape<NOB, NIB, PB>::NOBC]) {
-  using S = WideShape<NOB, NIB, PB>;
-  using Pr = Prec<kBF16X3>;
-  using T = Tile<kBF16X3>;
-  constexpr int CPB = S::CPB, NIBW = S::NIBW, NOBC = S::NOBC;
-  constexpr bool kLap = (ACT & kLapFlag) != 0;
-  const LayerDev& ly = net.layer[layer];
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int g = lane >> 4, l16 = lane & 15;
-  const int n_in = ly.n_in, n_out = ly.n_out;
-  const int nob = n_out / 16, nib = n_in / 16;
-  const bool has_prev = z_prev != nullptr;
-  const int rld = T::ld(n_out, PB);
-  float lw1, lw2;
-  lap_weights(net, lw1, lw2);
-  char* STG = smem;
-  char* R = smem + (size_t)PB * NOB * 256;  // STG sized for the widest layer of the kernel
-  const int zb_bytes = CPB * nob * 1024, zp_bytes = CPB * nib * 1024;
-  auto zb_src = [&](int64_t s) { return reinterpret_cast<const char*>(zb_in) + s * zb_bytes; };
-
-  if (count <= 0) return;
-  __syncthreads();  // the previous user of the LDS is done
-  async_copy(STG, zb_src(s0), zb_bytes);
-
-  for (int64_t k = 0; k < count; ++k) {
-    const int64_t s = s0 + k * stride;
-    const int64_t cb0 = s * CPB;
-    wait_async();
-    barrier_lds();  // sub-tile s staged; the previous sub-tile is done with R
-    // (1) output adjoint into R (T layout); bias sums of the converted output blocks
-#pragma unroll
-    for (int q = 0; q < NOBC; ++q) {
-      const int ob = wave + 8 * q;
-      if (ob < nob) {
-#pragma unroll
-        for (int cb = 0; cb < CPB; ++cb) {
-          const f4 zb = to_f4(*reinterpret_cast<const float4*>(STG + ((size_t)(cb * nob + ob) * 64 + lane) * 16));
-          T::put(R, rld, 4 * cb + g, 16 * ob + l16, zb);
-          bsum[q] += zb.x;
-        }
-      }
-    }
-    barrier_lds();  // R complete; STG free
-    // (2)-(3) per owned input block: layer-input jets a (B operand of the weight gradient)
-    // and, for a hidden layer, the input adjoint and the activation adjoint
-    Raw aop[NIBW][CPB / 2];
-    if (has_prev) {
-      async_copy(STG, reinterpret_cast<const char*>(z_prev) + s * zp_bytes, zp_bytes);
-      f4 acca[NIBW][CPB];
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-#pragma unroll
-        for (int cb = 0; cb < CPB; ++cb) acca[q][cb] = f4{0.f, 0.f, 0.f, 0.f};
-      {
-        int blk[NIBW];
-#pragma unroll
-        for (int q = 0; q < NIBW; ++q) blk[q] = wave + 8 * q;
-        gemm_tile<kBF16X3, NIBW, CPB>(acca, R, rld, 0, ly.wb, ly.kco, blk, lane);
-      }
-      wait_async();
-      barrier_lds();  // pre-activations of sub-tile s staged
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q) {
-        const int ib = wave + 8 * q;
-#pragma unroll
-        for (int cc = 0; cc < CPB / 2; ++cc) {
-          float f[8];
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int cb = 2 * cc + h;
-            const f4 z = to_f4(*reinterpret_cast<const float4*>(STG + ((size_t)(cb * nib + ib) * 64 + lane) * 16));
-            float s0v, s1v, s2v, s3v;
-            act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
-            const f4 a = jet_act<kLap>(z, s0v, s1v, s2v, lw1, lw2);
-            f[4 * h] = a.x;
-            f[4 * h + 1] = a.y;
-            f[4 * h + 2] = a.z;
-            f[4 * h + 3] = a.w;
-            const f4 zb = jet_act_adj<kLap>(z, acca[q][cb], s1v, s2v, s3v, lw1, lw2);
-            *jet_frag(zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
-          }
-          aop[q][cc] = Pr::make(f);
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      }
-    } else {
-      // Fourier-feature jets of the owned columns: column i < m is cos(x B_i), i >= m sin
-      const int m = net.n_freq;
-      const float4* sp = pts + s * PB;
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q) {
-        const int i = 16 * min(wave + 8 * q, nib - 1) + l16;
-        const int j = i < m ? i : i - m;
-#pragma unroll
-        for (int cc = 0; cc < CPB / 2; ++cc) {
-          float f[8];
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            f4 cj, sj;
-            rff_jets(net, net.B, sp[4 * (2 * cc + h) + g], j, cj, sj);
-            const f4 a = i < m ? cj : sj;
-            f[4 * h] = a.x;
-            f[4 * h + 1] = a.y;
-            f[4 * h + 2] = a.z;
-            f[4 * h + 3] = a.w;
-          }
-          aop[q][cc] = Pr::make(f);
-        }
-      }
-    }
-    barrier_lds();  // STG no longer read
-    if (k + 1 < count) async_copy(STG, zb_src(s + stride), zb_bytes);
-    // (4) weight gradient: W_bar[o][i] += sum_cp zbar[cp][o] a[cp][i] for the owned columns
-#pragma unroll
-    for (int cc = 0; cc < CPB / 2; ++cc)
-#pragma unroll
-      for (int ob = 0; ob < NOB; ++ob) {
-        const Raw ao = wide_zbar_op(R, rld, min(ob, nob - 1), cc, lane);
-#pragma unroll
-        for (int q = 0; q < NIBW; ++q) Pr::mma(accw[ob][q], ao, aop[q][cc]);
-      }
-  }
-}
-
-// Weight-gradient sums of the wide backward into a slot [n_out][n_in] then [n_out].
-template <int NOB, int NIB, int PB>
-__device__ __forceinline__ void bwd_wide_flush(const f4 (&accw)[NOB][WideShape<NOB, NIB, PB>::NIBW],
-                                               const float (&bsum)[WideShape<NOB, NIB, PB>::NOBC], double* slot,
-                                               int n_out, int n_in) {
-  using S = WideShape<NOB, NIB, PB>;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int g = lane >> 4, l16 = lane & 15;
-  const int nob = n_out / 16, nib = n_in / 16;
-#pragma unroll
-  for (int ob = 0; ob < NOB; ++ob) {
-    if (ob >= nob) continue;
-#pragma unroll
-    for (int q = 0; q < S::NIBW; ++q) {
-      const int ib = wave + 8 * q;
-      if (ib >= nib) continue;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) slot[(size_t)(16 * ob + 4 * g + r) * n_in + 16 * ib + l16] = (double)accw[ob][q][r];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < S::NOBC; ++q) {
-    const int ob = wave + 8 * q;
-    float v = bsum[q];
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    if (ob < nob && g == 0) slot[(size_t)n_out * n_in + 16 * ob + l16] = (double)v;
-  }
-}
-
-template <int ACT, int NOB, int NIB, int PB>
-__global__ __launch_bounds__(kThreads, 1) void k_backward_wide(const BwdArgs A) {
-  using S = WideShape<NOB, NIB, PB>;
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  f4 accw[NOB][S::NIBW];
-#pragma unroll
-  for (int ob = 0; ob < NOB; ++ob)
-#pragma unroll
-    for (int q = 0; q < S::NIBW; ++q) accw[ob][q] = f4{0.f, 0.f, 0.f, 0.f};
-  float bsum[S::NOBC];
-#pragma unroll
-  for (int q = 0; q < S::NOBC; ++q) bsum[q] = 0.f;
-  const int64_t count = A.n_sub > blockIdx.x ? (A.n_sub - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
-  bwd_wide_range<ACT, NOB, NIB, PB>(A.net, A.layer, A.work.pts, blockIdx.x, gridDim.x, count, A.zb_in, A.zb_out,
-                                    A.z_prev, smem, accw, bsum);
-  const LayerDev& ly = A.net.layer[A.layer];
-  bwd_wide_flush<NOB, NIB, PB>(accw, bsum, A.slots + (size_t)blockIdx.x * ly.n_out * (ly.n_in + 1), ly.n_out, ly.n_in);
-}
-
-// ================================================================== backward (one layer, split roles)
-
-// Hidden-layer backward for bf16x3 at input widths that are multiples of 128, with the
-// work-groups split into two roles that sweep the same sub-tiles:
-//   role 0  input adjoint and activation adjoint (abar = zbar W, then zbar_prev), with the
-//           layer's weight fragments held in registers for the whole launch (no weight
-//           traffic per sub-tile);
-//   role 1  weight gradient W_bar += zbar^T a_prev and bias gradient, the sums held in
-//           registers over the work-group's sub-tiles.
-// Each role keeps half the matrix-core work of a sub-tile.  Work-groups b and b + 8 (one
-// of each role) take the same sub-tiles; dispatch places them on the same XCD, so the
-// second reader of a sub-tile's jets finds them in cache.  Both roles stage the output
-// adjoint of the next sub-tile into LDS (STG) and load the pre-activations of the current
-// one into registers before they are needed; vector-memory counters complete in issue
-// order, and the loop waits only for what it needs (role 0 leaves its adjoint stores
-// outstanding across the wait).
-template <int NOB, int NIB, int PB>
-struct SplitShape {
-  static constexpr int CPB = PB / 4;
-  static constexpr int NIBW = NIB / 8;   // input blocks per wave
-  static constexpr int NOBC = (NOB + 7) / 8;  // output blocks converted per wave
-  static constexpr int KC = NOB / 2;     // reduction chunks of the input adjoint (n_out / 32)
-  static constexpr int NSTORE = NIBW * CPB;  // adjoint stores per lane and sub-tile
-  static_assert(NIB % 8 == 0 && CPB % 2 == 0, "split backward shape");
-};
-
-// s_waitcnt with only the vector-memory count bounded (gfx9 encoding: vmcnt in bits 3:0
-// and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima).
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
-}
-
-// Input-adjoint product of the split backward's first role, with the copy of the next
-// sub-tile's adjoint into STG started first.  STG and R are distinct LDS regions; the
-// restrict qualifiers let the compiler's wait insertion see that the tile reads do not
-// depend on the copy.
-template <int NIBW, int CPB, int KC>
-__device__ __forceinline__ void split_adjoint_product(f4 (&acca)[NIBW][CPB], char* __restrict__ STG,
-                                                      const char* __restrict__ R, int rld,
-                                                      const Raw (&wreg)[NIBW][KC], const char* next, int bytes,
-                                                      int lane) {
-  if (next) async_copy(STG, next, bytes);
-#pragma unroll
-  for (int q = 0; q < NIBW; ++q)
-#pragma unroll
-    for (int cb = 0; cb < CPB; ++cb) acca[q][cb] = f4{0.f, 0.f, 0.f, 0.f};
-  // the A fragment of cp block cb for chunk kc + 1 is read as soon as the products of chunk
-  // kc that use it have issued; per accumulator the order of Prec::mma is kept
-  Raw a[CPB];
-#pragma unroll
-  for (int cb = 0; cb < CPB; ++cb) a[cb] = Tile<kBF16X3>::load(R, rld, cb, 0, lane);
-#pragma unroll
-  for (int kc = 0; kc < KC; ++kc) {
-#pragma unroll
-    for (int cb = 0; cb < CPB; ++cb) {
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-        acca[q][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[cb].b),
-                                                              __builtin_bit_cast(bf16x8, wreg[q][kc].a), acca[q][cb], 0, 0, 0);
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-        acca[q][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[cb].a),
-                                                              __builtin_bit_cast(bf16x8, wreg[q][kc].b), acca[q][cb], 0, 0, 0);
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-        acca[q][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[cb].a),
-                                                              __builtin_bit_cast(bf16x8, wreg[q][kc].a), acca[q][cb], 0, 0, 0);
-      if (kc + 1 < KC) a[cb] = Tile<kBF16X3>::load(R, rld, cb, kc + 1, lane);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-  // work that waits on vector memory (the pre-activations) stays after the product, so the
-  // copy started above runs under it
-  __builtin_amdgcn_sched_barrier(0);
-}
-
-// Weight-gradient product of the split backward's second role (A operands from the ZT
-// tile, B operands in registers), with the copy of the next sub-tile's adjoint into STG
-// started first; the restrict qualifiers tell the compiler's wait insertion that the ZT
-// reads do not depend on the copy.
-template <int NOB, int NIBW, int CPB>
-__device__ __forceinline__ void split_weight_grad_product(f4 (&accw)[NOB][NIBW], const Raw (&aop)[NIBW][CPB / 2],
-                                                          char* __restrict__ STG, const char* __restrict__ ZT,
-                                                          const char* next, int bytes, int lane) {
-  if (next) async_copy(STG, next, bytes);
-  // A operands (one 2 KiB unit per output block) read D blocks ahead of their products, from a
-  // ring of D register sets; per accumulator the order of Prec::mma is kept
-  constexpr int D = NOB < 3 ? NOB : 3;
-#pragma unroll
-  for (int cc = 0; cc < CPB / 2; ++cc) {
-    Raw u[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) u[d] = lds_unit(ZT, d * (CPB / 2) + cc, lane, 64 * 32);
-#pragma unroll
-    for (int ob = 0; ob < NOB; ++ob) {
-      const Raw ao = u[ob % D];
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-        accw[ob][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ao.b),
-                                                              __builtin_bit_cast(bf16x8, aop[q][cc].a), accw[ob][q], 0, 0, 0);
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-        accw[ob][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ao.a),
-                                                              __builtin_bit_cast(bf16x8, aop[q][cc].b), accw[ob][q], 0, 0, 0);
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-        accw[ob][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ao.a),
-                                                              __builtin_bit_cast(bf16x8, aop[q][cc].a), accw[ob][q], 0, 0, 0);
-      if (ob + D < NOB) u[ob % D] = lds_unit(ZT, (ob + D) * (CPB / 2) + cc, lane, 64 * 32);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-}
-
-constexpr int kPaceSpin = 512;  // polls of a pacing wait before it goes on regardless
-
-template <int ACT, int NOB, int NIB, int PB, bool EMB>
-__global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A) {
-  using S = SplitShape<NOB, NIB, PB>;
-  using Pr = Prec<kBF16X3>;
-  using T = Tile<kBF16X3>;
-  constexpr int CPB = S::CPB, NIBW = S::NIBW, NOBC = S::NOBC, KC = S::KC;
-  constexpr bool kLap = (ACT & kLapFlag) != 0;
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  const NetDev& net = A.net;
-  const LayerDev& ly = net.layer[A.layer];
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int g = lane >> 4, l16 = lane & 15;
-  const int n_in = ly.n_in, n_out = ly.n_out;
-  const int nib = n_in / 16, nob = n_out / 16;
-  const int rld = T::ld(n_out, PB);
-  float lw1, lw2;
-  lap_weights(net, lw1, lw2);
-  char* STG = smem;
-  char* R = smem + (size_t)PB * NOB * 256;
-  float* BF = reinterpret_cast<float*>(R + (size_t)PB * NOB * 256);  // Fourier matrix (EMB)
-  if (EMB)
-    for (int i = threadIdx.x; i < net.d_in * net.n_freq; i += kThreads) BF[i] = net.B[i];
-  const int zb_bytes = CPB * nob * 1024;
-  // role and index within the role (blocks b and b + 8 share a sub-tile sequence)
-  // (EMB: the Fourier-embedding layer -- weight gradient only, every work-group)
-  const int b = blockIdx.x;
-  const int role = EMB ? 1 : (b >> 3) & 1;
-  const int rb = EMB ? b : ((b >> 4) << 3) | (b & 7);
-  const int G = EMB ? gridDim.x : gridDim.x >> 1;
-  const int64_t count = A.n_sub > rb ? (A.n_sub - rb + G - 1) / G : 0;
-  auto zb_src = [&](int64_t s) { return reinterpret_cast<const char*>(A.zb_in) + s * zb_bytes; };
-  f4 zp[NIBW][CPB];
-  auto load_zp = [&](int64_t s) {
-#pragma unroll
-    for (int q = 0; q < NIBW; ++q)
-#pragma unroll
-      for (int cb = 0; cb < CPB; ++cb)
-        zp[q][cb] = to_f4(*jet_frag(const_cast<float*>(A.z_prev), s * CPB + cb, wave + 8 * q, nib, lane));
-  };
-  auto convert = [&](float* bsum) {  // STG -> R (T layout), bias sums of the converted blocks
-#pragma unroll
-    for (int q = 0; q < NOBC; ++q) {
-      const int ob = wave + 8 * q;
-      if (ob >= NOB) continue;
-#pragma unroll
-      for (int cb = 0; cb < CPB; ++cb) {
-        const f4 zb = to_f4(*reinterpret_cast<const float4*>(STG + ((size_t)(cb * nob + ob) * 64 + lane) * 16));
-        T::put(R, rld, 4 * cb + g, 16 * ob + l16, zb);
-        if (bsum) bsum[q] += zb.x;
-      }
-    }
-  };
-  if (count > 0) async_copy(STG, zb_src(rb), zb_bytes);
-
-  if (!EMB && role == 0) {
-    // ---- input adjoint and activation adjoint
-    Raw wreg[NIBW][KC];  // B operand fragments of the owned input blocks, all chunks
-#pragma unroll
-    for (int q = 0; q < NIBW; ++q)
-#pragma unroll
-      for (int kc = 0; kc < KC; ++kc) wreg[q][kc] = glob_frag(ly.wb, wave + 8 * q, kc, KC, lane);
-    wait_vm<0>();  // resident from here on: no wait for them inside the loop
-    bool held = false;  // the partner had not reached the previous sub-tile when last read
-    for (int64_t k = 0; k < count; ++k) {
-      const int64_t s = rb + k * G;
-      const int64_t cb0 = s * CPB;
-      if (k == 0)
-        wait_vm<0>();
-      else
-        wait_vm<S::NSTORE>();  // the staged adjoint; the previous sub-tile's stores may run on
-      if (held && threadIdx.x == 0) {
-        // pacing: this role reads each sub-tile first and its partner must find the jets
-        // still in L2, so it runs at most one sub-tile ahead of the partner (a bounded wait:
-        // it goes on regardless after kPaceSpin polls)
-        const unsigned long long want = (A.launch << 20) + (unsigned long long)(k - 1);
-        for (int it = 0; it < kPaceSpin; ++it) {
-          if (__hip_atomic_load(&A.pace[rb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want) break;
-          __builtin_amdgcn_s_sleep(2);
-        }
-      }
-      barrier_lds();
-      convert(nullptr);
-      load_zp(s);  // after the staged reads: waiting for these must not wait for the next copy
-      unsigned long long seen = ~0ull;
-      if (A.pace) seen = __hip_atomic_load(&A.pace[rb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      barrier_lds();  // R complete; STG free
-      f4 acca[NIBW][CPB];
-      split_adjoint_product<NIBW, CPB, KC>(acca, STG, R, rld, wreg, k + 1 < count ? zb_src(s + G) : nullptr,
-                                           zb_bytes, lane);
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q) {
-        const int ib = wave + 8 * q;
-#pragma unroll
-        for (int cb = 0; cb < CPB; ++cb) {
-          const f4 z = zp[q][cb];
-          float s0v, s1v, s2v, s3v;
-          act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
-          const f4 zb = jet_act_adj<kLap>(z, acca[q][cb], s1v, s2v, s3v, lw1, lw2);
-          *jet_frag(A.zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
-        }
-      }
-      // read beside the pre-activations, compared once they are in use
-      held = A.pace && seen < (A.launch << 20) + (unsigned long long)k;
-    }
-  } else {
-    // ---- weight and bias gradient
-    f4 accw[NOB][NIBW];
-#pragma unroll
-    for (int ob = 0; ob < NOB; ++ob)
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q) accw[ob][q] = f4{0.f, 0.f, 0.f, 0.f};
-    float bsum[NOBC];
-#pragma unroll
-    for (int q = 0; q < NOBC; ++q) bsum[q] = 0.f;
-    if (!EMB && count > 0) load_zp(rb);
-    for (int64_t k = 0; k < count; ++k) {
-      const int64_t s = rb + k * G;
-      wait_vm<0>();
-      // progress for the partner's pacing: sub-tile s read, the next one about to be
-      if (!EMB && A.pace && threadIdx.x == 0)
-        __hip_atomic_store(&A.pace[rb], (A.launch << 20) + (unsigned long long)k, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      barrier_lds();  // sub-tile s staged and its pre-activations loaded; ZT free
-      // output adjoint as weight-gradient A operands in the ZT layout: for output block ob
-      // and cp chunk cc, lane (g, l16) holds 8 cp of output 16 ob + l16 (points 8 cc + g,
-      // 8 cc + 4 + g, accumulator order), bf16 hi then lo, 32 bytes per lane
-#pragma unroll
-      for (int q = 0; q < NOBC; ++q) {
-        const int ob = wave + 8 * q;
-        if (ob >= NOB) continue;
-#pragma unroll
-        for (int cc = 0; cc < CPB / 2; ++cc) {
-          const float* f0 = reinterpret_cast<const float*>(STG + ((size_t)((2 * cc) * nob + ob) * 64 + lane) * 16);
-          const float* f1 = reinterpret_cast<const float*>(STG + ((size_t)((2 * cc + 1) * nob + ob) * 64 + lane) * 16);
-          const float4 v0 = *reinterpret_cast<const float4*>(f0), v1 = *reinterpret_cast<const float4*>(f1);
-          const float f[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-          const Raw op = Pr::make(f);
-          uint4* d = reinterpret_cast<uint4*>(R + ((size_t)(ob * (CPB / 2) + cc) * 64 + lane) * 32);
-          d[0] = op.a;
-          d[1] = op.b;
-          bsum[q] += v0.x + v1.x;
-        }
-      }
-      barrier_lds();  // ZT complete; STG free
-      Raw aop[NIBW][CPB / 2];
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-#pragma unroll
-        for (int cc = 0; cc < CPB / 2; ++cc) {
-          float f[8];
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            f4 a;
-            if constexpr (EMB) {
-              // Fourier-feature jets: column i < m is cos(x B_i), column i >= m sin(x B_{i-m})
-              const int m = net.n_freq;
-              const int i = 16 * (wave + 8 * q) + l16;
-              f4 cj, sj;
-              rff_jets(net, BF, A.work.pts[(int64_t)s * PB + 4 * (2 * cc + h) + g], i < m ? i : i - m, cj, sj);
-              a = i < m ? cj : sj;
-            } else {
-              const f4 z = zp[q][2 * cc + h];
-              float s0v, s1v, s2v, s3v;
-              act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
-              a = jet_act<kLap>(z, s0v, s1v, s2v, lw1, lw2);
-            }
-            f[4 * h] = a.x;
-            f[4 * h + 1] = a.y;
-            f[4 * h + 2] = a.z;
-            f[4 * h + 3] = a.w;
-          }
-          aop[q][cc] = Pr::make(f);
-        }
-      if (!EMB && k + 1 < count) load_zp(s + G);  // the next sub-tile's pre-activations load under the product
-      split_weight_grad_product<NOB, NIBW, CPB>(accw, aop, STG, R, k + 1 < count ? zb_src(s + G) : nullptr,
-                                                zb_bytes, lane);
-    }
-    // flush: slot rb, [n_out][n_in] then [n_out]
-    double* slot = A.slots + (size_t)rb * n_out * (n_in + 1);
-#pragma unroll
-    for (int ob = 0; ob < NOB; ++ob)
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q) {
-        const int ib = wave + 8 * q;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) slot[(size_t)(16 * ob + 4 * g + r) * n_in + 16 * ib + l16] = (double)accw[ob][q][r];
-      }
-#pragma unroll
-    for (int q = 0; q < NOBC; ++q) {
-      const int ob = wave + 8 * q;
-      float v = bsum[q];
-      v += __shfl_xor(v, 16, 64);
-      v += __shfl_xor(v, 32, 64);
-      if (g == 0 && ob < NOB) slot[(size_t)n_out * n_in + 16 * ob + l16] = (double)v;
-    }
-  }
-}
-
 // ================================================================== first layer, identity
 
 // W_bar[o][k] = sum_points (zbar0[o] x_k + zbar_{1+k}[o]), b_bar[o] = sum zbar0[o]: the
@@ -2000,490 +1327,14 @@ __device__ __forceinline__ void grad0_range(const float* zb, const float4* pts, 
   }
 }
 
-__global__ __launch_bounds__(kThreads, 1) void k_grad0(const Grad0Args A) {
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  const int64_t per = (A.n_cb + gridDim.x - 1) / gridDim.x;
-  const int64_t lo = (int64_t)blockIdx.x * per;
-  const int64_t hi = lo + per < A.n_cb ? lo + per : A.n_cb;
-  grad0_range(A.zb, A.pts, A.n_out, A.d_in, lo, hi, A.slots + (size_t)blockIdx.x * A.n_out * (A.d_in + 1),
-              reinterpret_cast<float*>(smem));
-}
-
-// ================================================================== many networks, one launch
-
-// Work item i: instance items[i].inst, padded points [p0, p1) of that instance (multiples
-// of 128).  A work-group takes items from the counter in the order `order` (longest first),
-// runs the forward over the item's tiles and then every layer's backward over the same
-// points, keeping each layer's weight-gradient sums in registers over the item, and writes
-// them with the loss sums to the item's own FP64 slots.  Slots are per item, so the
-// result does not depend on which work-group ran which item.
-template <int PREC, int ACT, int H>
-__device__ __forceinline__ void run_item(const BatchArgs& A, const BatchInst& in, const BatchItem& it, int64_t item,
-                                         char* smem) {
-  constexpr int PF = H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128;
-  constexpr int PB = 2048 / H;
-  const NetDev& net = in.net;
-  float* scratch = A.scratch + (size_t)blockIdx.x * A.scratch_per_wg;
-  float* zs = scratch;
-  float* zb[2] = {scratch + in.zb_off[0], scratch + in.zb_off[1]};
-  const float4* pts = A.pts + in.pts_off + it.p0;
-  const int64_t npts = it.p1 - it.p0;
-  double* loss_slot = A.loss_slots + (size_t)item * kMaxTerms;
-  double* gslot = A.grad_slots + it.slot_off;
-  PdeDev pde = A.pde;
-  for (int c = 0; c < 3; ++c) pde.seed_scale[c] = 2.0f * A.lambda_res[c] / (float)in.n;
-  // forward over the item's tiles
-  {
-    const FwdLds s = fwd_carve<H, PF>(smem, r_stride(in.kmax));
-    const int ld = Tile<PREC>::ld(in.kmax, PF);
-    fwd_begin<H, PF>(s, net);
-    for (int64_t t = 0; t < npts / PF; ++t) {
-      const int64_t nv = in.n - (it.p0 + t * PF);
-      TileSeg sg;
-      sg.nvalid = nv < 0 ? 0 : (nv > PF ? PF : (int)nv);
-      sg.kind = 0;
-      sg.term = 0;
-      sg.targets = nullptr;
-      sg.out_mask = 0;
-      sg.lam = 0.0f;
-      sg.residual = nullptr;
-      fwd_tile<PREC, ACT, H, PF>(net, pde, pts + t * PF, zs, in.zs_stride, zb[0], t * (PF / 4), sg, ld, true, s);
-    }
-    const int nL = net.layer[net.L].n_in;
-    fwd_end<H, PF>(s, loss_slot, gslot + in.eff_off[net.L], net.d_out, nL, true);
-  }
-  // backward, hidden layers last to first
-  int cur = 0;
-  for (int j = net.L - 1; j >= 1; --j) {
-    using S = BwdShape<H / 16, H / 16, PB>;
-    f4 accw[S::NOBW][S::NIBW];
-#pragma unroll
-    for (int i = 0; i < S::NOBW; ++i)
-#pragma unroll
-      for (int k = 0; k < S::NIBW; ++k) accw[i][k] = f4{0.f, 0.f, 0.f, 0.f};
-    float bsum[S::NOBW];
-#pragma unroll
-    for (int i = 0; i < S::NOBW; ++i) bsum[i] = 0.f;
-    bwd_range<PREC, ACT, H / 16, H / 16, PB>(net, j, pts, 0, 1, npts / PB, zb[cur], zb[cur ^ 1],
-                                             zs + (j - 1) * in.zs_stride, smem, accw, bsum);
-    bwd_flush<H / 16, H / 16, PB>(accw, bsum, gslot + in.eff_off[j], net.layer[j].n_out, net.layer[j].n_in);
-    cur ^= 1;
-  }
-  // first layer (identity embedding)
-  grad0_range(zb[cur], pts, net.layer[0].n_out, net.d_in, 0, npts / 4, gslot + in.eff_off[0],
-              reinterpret_cast<float*>(smem));
-  __syncthreads();
-}
-
-template <int PREC, int ACT>
-__global__ __launch_bounds__(kThreads, 1) void k_batched(const BatchArgs A) {
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-  __shared__ int s_q;
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) s_q = atomicAdd(A.counter, 1);
-    __syncthreads();
-    const int q = __builtin_amdgcn_readfirstlane(s_q);
-    if (q >= A.n_items) break;
-    const int64_t item = A.order[q];
-    const BatchItem it = A.items[item];
-    const BatchInst& in = A.inst[it.inst];
-    switch (in.H) {
-      case 32: run_item<PREC, ACT, 32>(A, in, it, item, smem); break;
-      case 64: run_item<PREC, ACT, 64>(A, in, it, item, smem); break;
-      case 128: run_item<PREC, ACT, 128>(A, in, it, item, smem); break;
-      default: run_item<PREC, ACT, 256>(A, in, it, item, smem); break;
-    }
-  }
-}
-
-// ================================================================== reductions
-
-// Sum the per-work-group FP64 slots of one layer in slot order, then map to the parameter
-// layout: with factorised weights W = diag(exp s) V, dL/dV = exp(s) dL/dW and
-// dL/ds_o = sum_i W_oi dL/dW_oi (Sec. 2.6.2).
-
-__device__ __forceinline__ void reduce_row(const ReduceArgs& A, int o) {
-  // kRedThreads threads: kRedGroups groups of consecutive slots x kRedCols columns.  Each
-  // thread sums its group's slots in slot order, the groups are then added in group
-  // order: a fixed order, independent of timing.  Column n_in is the bias.
-  constexpr int NC = kRedThreads / kRedGroups;
-  __shared__ double part[kRedThreads];
-  __shared__ double red[NC];
-  const int tid = threadIdx.x, grp = tid / NC, col0 = tid % NC;
-  const int per = (A.n_slots + kRedGroups - 1) / kRedGroups;
-  const int s_lo = grp * per, s_hi = min(A.n_slots, s_lo + per);
-  const double es = A.rwf ? exp((double)A.params[A.off_s + o]) : 1.0;
-  double ssum = 0.0;
-  for (int c0 = 0; c0 <= A.n_in; c0 += NC) {
-    const int col = c0 + col0;
-    double t = 0.0;
-    if (col <= A.n_in) {
-      const double* p = A.slots + (col < A.n_in ? (int64_t)o * A.n_in + col : (int64_t)A.n_out * A.n_in + o);
-      int sl = s_lo;
-      for (; sl + 4 <= s_hi; sl += 4) {
-        const double v0 = p[sl * A.slot_stride], v1 = p[(sl + 1) * A.slot_stride];
-        const double v2 = p[(sl + 2) * A.slot_stride], v3 = p[(sl + 3) * A.slot_stride];
-        t += v0;
-        t += v1;
-        t += v2;
-        t += v3;
-      }
-      for (; sl < s_hi; ++sl) t += p[sl * A.slot_stride];
-    }
-    part[tid] = t;
-    __syncthreads();
-    if (grp == 0 && col <= A.n_in) {
-      double s = 0.0;
-      for (int q = 0; q < kRedGroups; ++q) s += part[q * NC + col0];
-      if (col < A.n_in) {
-        const double v = (double)A.params[A.off_w + (int64_t)o * A.n_in + col];
-        A.grad[A.off_w + (int64_t)o * A.n_in + col] = es * s;
-        ssum += s * es * v;
-      } else if (A.has_bias) {
-        A.grad[A.off_b + o] = s;
-      }
-    }
-    __syncthreads();
-  }
-  if (A.rwf) {  // s_bar[o] = sum_i W[o][i] W_bar[o][i], fixed tree over the columns
-    if (grp == 0) red[col0] = ssum;
-    __syncthreads();
-    for (int st = NC / 2; st > 0; st >>= 1) {
-      if (tid < st) red[tid] += red[tid + st];
-      __syncthreads();
-    }
-    if (tid == 0) A.grad[A.off_s + o] = red[0];
-  }
-}
-
-__global__ __launch_bounds__(kRedThreads) void k_reduce_layer(const ReduceArgs A) {
-  if ((int)blockIdx.x < A.n_out) reduce_row(A, blockIdx.x);
-}
-
-// Per-instance reductions of the item slots: one block per (instance, layer, output row).
-__global__ __launch_bounds__(kRedThreads) void k_reduce_batched(const BatchReduceArgs A) {
-  const int64_t r = blockIdx.x;
-  int lo = 0, hi = A.n_entries - 1;
-  while (lo < hi) {  // last entry with row0 <= r
-    const int mid = (lo + hi + 1) / 2;
-    if (A.rows[mid].row0 <= r) lo = mid; else hi = mid - 1;
-  }
-  const BatchRow e = A.rows[lo];
-  ReduceArgs a;
-  a.slots = A.grad_slots + e.slot0;
-  a.n_slots = e.n_items;
-  a.slot_stride = e.slot_stride;
-  a.n_out = e.n_out;
-  a.n_in = e.n_in;
-  a.rwf = e.rwf;
-  a.has_bias = e.has_bias;
-  a.params = e.params;
-  a.off_w = e.off_w;
-  a.off_s = e.off_s;
-  a.off_b = e.off_b;
-  a.grad = e.grad;
-  reduce_row(a, (int)(r - e.row0));
-}
-
-// Loss terms of one instance per block: item partial sums added in item order by one
-// thread per term (an instance has at most a few hundred items).
-__global__ void k_reduce_loss_batched(const BatchLossArgs A) {
-  const int i = blockIdx.x;
-  __shared__ double term[3];
-  const int k = threadIdx.x;
-  if (k < A.n_res) {
-    double t = 0.0;
-    const double* p = A.loss_slots + (size_t)A.item0[i] * kMaxTerms + k;
-    for (int s = 0; s < A.n_items[i]; ++s) t += p[(size_t)s * kMaxTerms];
-    t *= A.w_res[i * 3 + k];
-    A.losses[(size_t)i * (1 + A.n_res) + 1 + k] = t;
-    term[k] = t;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double total = 0.0;
-    for (int q = 0; q < A.n_res; ++q) total += term[q];
-    A.losses[(size_t)i * (1 + A.n_res)] = total;
-  }
-}
-
-__global__ void k_zero_int(int* p) { *p = 0; }
-
-// Loss terms: thread s sums slots s, s + 256, ... (in that order), then a fixed tree over
-// the 256 threads per term.
-__global__ __launch_bounds__(256) void k_reduce_loss(const LossArgs A) {
-  __shared__ double red[kMaxTerms][256];
-  const int tid = threadIdx.x;
-  const int nt = A.n_res + A.n_anchor;
-  for (int k = 0; k < nt; ++k) {
-    double t = 0.0;
-    for (int sl = tid; sl < A.n_slots; sl += 256) t += A.slots[(size_t)sl * kMaxTerms + k];
-    red[k][tid] = t;
-  }
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (tid < st)
-      for (int k = 0; k < nt; ++k) red[k][tid] += red[k][tid + st];
-    __syncthreads();
-  }
-  if (tid == 0) {
-    double total = 0.0;
-    for (int k = 0; k < nt; ++k) {
-      const double t = red[k][0] * (k < A.n_res ? A.w_res[k] : A.w_anchor[k - A.n_res]);
-      A.loss[1 + k] = t;
-      total += t;
-    }
-    A.loss[0] = total;
-  }
-}
-
-// NaN / Inf scan of the parameters (opt-in check).
-__global__ void k_zero_flag(int* flag) { *flag = 0; }
-
-__global__ void k_check_finite(const float* p, int64_t n, int* flag) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && !isfinite(p[i])) *flag = 1;
-}
-
-
-// ================================================================== launchers
-
-namespace {
-
+// Launch helpers.
+// Dynamic LDS above 64 KiB has to be allowed per kernel.
 template <typename K>
-int set_lds(K kernel, size_t bytes) {
-  // Dynamic LDS above 64 KiB has to be allowed per kernel.
+inline int set_lds(K kernel, size_t bytes) {
   if (bytes <= 65536) return 0;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess ? 0 : -5;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes) == hipSuccess ? 0 : -5;
 }
-
-int status(hipError_t e) { return e == hipSuccess ? 0 : -5; }
-
-template <int PREC, int ACT, int H, int P>
-int fwd(const FwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  auto k = k_forward<PREC, ACT, H, P>;
-  if (set_lds(k, lds)) return -5;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * fwd_waves(H, P)), lds, s, a);
-  return status(hipGetLastError());
-}
-
-template <int PREC, int ACT, int H>
-int fwd_p(int P, const FwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  constexpr int PD = H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128;
-  if (P == PD) return fwd<PREC, ACT, H, PD>(a, grid, lds, s);
-  if (P == 16) return fwd<PREC, ACT, H, 16>(a, grid, lds, s);
-  return -2;
-}
-
-template <int PREC, int ACT>
-int fwd_h(int H, int P, const FwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  switch (H) {
-    case 32: return fwd_p<PREC, ACT, 32>(P, a, grid, lds, s);
-    case 64: return fwd_p<PREC, ACT, 64>(P, a, grid, lds, s);
-    case 128: return fwd_p<PREC, ACT, 128>(P, a, grid, lds, s);
-    case 256: return fwd_p<PREC, ACT, 256>(P, a, grid, lds, s);
-    default: return -2;
-  }
-}
-
-template <int PREC, int ACT, int NOB, int NIB, int PB>
-int bwd(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  auto k = k_backward<PREC, ACT, NOB, NIB, PB>;
-  if (set_lds(k, lds)) return -5;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, a);
-  return status(hipGetLastError());
-}
-
-template <int ACT, int NOB, int NIB, int PB>
-int bwd_wide(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  auto k = k_backward_wide<ACT, NOB, NIB, PB>;
-  if (set_lds(k, lds)) return -5;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, a);
-  return status(hipGetLastError());
-}
-
-template <int ACT, int NOB, int NIB, int PB, bool EMB>
-int split_k(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  auto k = k_backward_split<ACT, NOB, NIB, PB, EMB>;
-  if (set_lds(k, lds)) return -5;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, a);
-  return status(hipGetLastError());
-}
-
-template <int ACT, int H>
-int bwd_split(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  if constexpr (H >= 128) return split_k<ACT, H / 16, H / 16, wide_pb(H), false>(a, grid, lds, s);
-  return -2;
-}
-
-// Fourier-embedding layer (weight gradient only): embedding width 128 or 256.
-template <int ACT, int H>
-int bwd_split_embed(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  const int n_in = a.net.layer[0].n_in, n_out = a.net.layer[0].n_out;
-  if (n_out != H || n_in % 128 != 0) return -2;
-  if constexpr (H >= 64) {
-    if (n_in == 128) return split_k<ACT, H / 16, 8, wide_pb(H), true>(a, grid, lds, s);
-    if (n_in == 256) return split_k<ACT, H / 16, 16, wide_pb(H), true>(a, grid, lds, s);
-  }
-  return -2;
-}
-
-template <int PREC, int ACT, int H>
-int bwd_e(bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  if constexpr (PREC == kBF16X3) {
-    if (a.wide == 2 && !embed) {
-      // split-role kernel: layer widths must be exactly H (uniform hidden layers)
-      if (a.net.layer[a.layer].n_in != H || a.net.layer[a.layer].n_out != H || grid % 16 != 0) return -2;
-      return bwd_split<ACT, H>(a, grid, lds, s);
-    }
-    if (a.wide == 3 && embed) return bwd_split_embed<ACT, H>(a, grid, lds, s);
-  }
-  if constexpr (PREC == kBF16X3) {
-    // wide path (chosen by the plan): input widths that are multiples of 128
-    constexpr int PW = wide_pb(H);
-    if (a.wide) {
-      if (a.net.layer[a.layer].n_in % 128 != 0) return -2;
-      if (embed) return bwd_wide<ACT, H / 16, 16, PW>(a, grid, lds, s);
-      if constexpr (H >= 128) return bwd_wide<ACT, H / 16, H / 16, PW>(a, grid, lds, s);
-      return -2;
-    }
-  }
-  constexpr int PB = 2048 / H;
-  if (embed) return bwd<PREC, ACT, H / 16, 16, H == 256 ? 8 : 16>(a, grid, lds, s);
-  return bwd<PREC, ACT, H / 16, H / 16, PB>(a, grid, lds, s);
-}
-
-template <int PREC, int ACT>
-int bwd_h(int H, bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  switch (H) {
-    case 32: return bwd_e<PREC, ACT, 32>(embed, a, grid, lds, s);
-    case 64: return bwd_e<PREC, ACT, 64>(embed, a, grid, lds, s);
-    case 128: return bwd_e<PREC, ACT, 128>(embed, a, grid, lds, s);
-    case 256: return bwd_e<PREC, ACT, 256>(embed, a, grid, lds, s);
-    default: return -2;
-  }
-}
-
-}  // namespace
-
-int launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, s, flag);
-  if (n > 0) hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, flag);
-  return status(hipGetLastError());
-}
-
-int launch_points(const PointsArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_points, dim3((unsigned)((a.n_pad + 255) / 256)), dim3(256), 0, s, a);
-  return status(hipGetLastError());
-}
-
-int launch_stage(int prec, const StageArgs& a, hipStream_t s) {
-  const int64_t n = a.cum[a.n_layers];
-  const dim3 grid((unsigned)((n + 255) / 256));
-  if (prec == kFP32)
-    hipLaunchKernelGGL(k_stage<kFP32>, grid, dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_stage<kBF16X3>, grid, dim3(256), 0, s, a);
-  return status(hipGetLastError());
-}
-
-template <int PREC>
-int fwd_a(int act, int H, int P, const FwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  switch (act) {
-    case kTanh: return fwd_h<PREC, kTanh>(H, P, a, grid, lds, s);
-    case kSin: return fwd_h<PREC, kSin>(H, P, a, grid, lds, s);
-    case kTanh | kLapFlag: return fwd_h<PREC, kTanh | kLapFlag>(H, P, a, grid, lds, s);
-    case kSin | kLapFlag: return fwd_h<PREC, kSin | kLapFlag>(H, P, a, grid, lds, s);
-    default: return -2;
-  }
-}
-
-template <int PREC>
-int bwd_a(int act, int H, bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  switch (act) {
-    case kTanh: return bwd_h<PREC, kTanh>(H, embed, a, grid, lds, s);
-    case kSin: return bwd_h<PREC, kSin>(H, embed, a, grid, lds, s);
-    case kTanh | kLapFlag: return bwd_h<PREC, kTanh | kLapFlag>(H, embed, a, grid, lds, s);
-    case kSin | kLapFlag: return bwd_h<PREC, kSin | kLapFlag>(H, embed, a, grid, lds, s);
-    default: return -2;
-  }
-}
-
-int launch_forward(int prec, int act, int H, int P, const FwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  return prec == kFP32 ? fwd_a<kFP32>(act, H, P, a, grid, lds, s) : fwd_a<kBF16X3>(act, H, P, a, grid, lds, s);
-}
-
-int launch_backward(int prec, int act, int H, bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  return prec == kFP32 ? bwd_a<kFP32>(act, H, embed, a, grid, lds, s)
-                       : bwd_a<kBF16X3>(act, H, embed, a, grid, lds, s);
-}
-
-int launch_grad0(const Grad0Args& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_grad0, dim3(grid), dim3(kThreads), kWaves * 256 * 4 * sizeof(float), s, a);
-  return status(hipGetLastError());
-}
-
-int launch_zero_int(int* p, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, p);
-  return status(hipGetLastError());
-}
-
-size_t batched_lds(int kmax, int H) {
-  const int PF = H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128;
-  const int PB = 2048 / H;
-  const int WN = H / 16 < kWaves ? H / 16 : kWaves;
-  const int WC = kWaves / WN;
-  size_t f = (size_t)4 * PF * r_stride(kmax) + (size_t)PF * 16 + (size_t)PF * 12 * 4 * 2 + kWaves * 8 * 4 +
-             kMaxTerms * 8 + (size_t)WC * 3 * H * 8 + 3 * 8 + kFourierLds + kOutLds + 16;
-  size_t b = bwd_lds_bytes(PB, H, H, true);
-  size_t g = (size_t)kWaves * 256 * 4 * sizeof(float);
-  size_t m = f > b ? f : b;
-  return m > g ? m : g;
-}
-
-template <int PREC, int ACT>
-int batched_k(const BatchArgs& a, int grid, size_t lds, hipStream_t s) {
-  auto k = k_batched<PREC, ACT>;
-  if (set_lds(k, lds)) return -5;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, a);
-  return status(hipGetLastError());
-}
-
-template <int PREC>
-int batched_a(int act, const BatchArgs& a, int grid, size_t lds, hipStream_t s) {
-  switch (act) {
-    case kTanh: return batched_k<PREC, kTanh>(a, grid, lds, s);
-    case kSin: return batched_k<PREC, kSin>(a, grid, lds, s);
-    case kTanh | kLapFlag: return batched_k<PREC, kTanh | kLapFlag>(a, grid, lds, s);
-    case kSin | kLapFlag: return batched_k<PREC, kSin | kLapFlag>(a, grid, lds, s);
-    default: return -2;
-  }
-}
-
-int launch_batched(int prec, int act, const BatchArgs& a, int grid, size_t lds, hipStream_t s) {
-  return prec == kFP32 ? batched_a<kFP32>(act, a, grid, lds, s) : batched_a<kBF16X3>(act, a, grid, lds, s);
-}
-
-int launch_reduce_batched(const BatchReduceArgs& a, hipStream_t s) {
-  if (a.n_rows > 0) hipLaunchKernelGGL(k_reduce_batched, dim3((unsigned)a.n_rows), dim3(kRedThreads), 0, s, a);
-  return status(hipGetLastError());
-}
-
-int launch_reduce_loss_batched(const BatchLossArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_loss_batched, dim3(a.n_inst), dim3(64), 0, s, a);
-  return status(hipGetLastError());
-}
-
-int launch_reduce_layer(const ReduceArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_layer, dim3(a.n_out), dim3(kRedThreads), 0, s, a);
-  return status(hipGetLastError());
-}
-
-int launch_reduce_loss(const LossArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(256), 0, s, a);
-  return status(hipGetLastError());
-}
+inline int launch_status(hipError_t e) { return e == hipSuccess ? 0 : -5; }
 
 }  // namespace pinn

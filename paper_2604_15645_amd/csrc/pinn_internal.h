@@ -1,5 +1,5 @@
 // pinn_internal.h -- descriptors shared by the host planner (pinn_api.cpp) and the HIP
-// kernels (pinn_kernels.hip).  Not part of the public C ABI.
+// kernels (k_*.hip, pinn_device.h).  Not part of the public C ABI.
 #pragma once
 #include <stdint.h>
 #include <stddef.h>
@@ -227,7 +227,7 @@ constexpr int fwd_wg_per_cu(int H, int P) { return kWaves / fwd_waves(H, P); }
 // starts its activations without waiting for the slower waves.
 constexpr bool fwd_double_x(int P) { return P <= 16; }
 
-// Launchers (pinn_kernels.hip).  Each returns a pinn_status value.
+// Launchers (k_*.hip).  Each returns a pinn_status value.
 int launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t s);
 int launch_points(const PointsArgs& a, hipStream_t s);
 int launch_stage(int prec, const StageArgs& a, hipStream_t s);

@@ -65,6 +65,8 @@ def test_validation_errors(lib):
     assert code_of(lambda: ws(dict(net, widths=[0, 32]), pde)) == -1
     assert code_of(lambda: ws(net, dict(pde, pde="ns2d"))) == -2          # ns needs 3 outputs
     assert code_of(lambda: ws(net, dict(pde, lap_mask=0))) == -2          # burgers needs u_xx
+    assert code_of(lambda: ws(net, dict(pde, lap_mask=3))) == -2          # ... and u_xx alone
+    assert code_of(lambda: ws(net, dict(pde, lap_mask=2))) == -2
     assert code_of(lambda: ws(net, dict(pde, lap_mask=8))) == -1          # input 3 does not exist
     assert code_of(lambda: ws(dict(net, widths=[48, 48]), pde)) == -2     # widths: multiples of 32
     assert code_of(lambda: ws(dict(net, widths=[512]), pde)) == -2        # at most 256 wide
@@ -124,3 +126,38 @@ def test_workspace_grows_with_points_and_gradient():
     assert b > a and f < b
     # the stash of every hidden layer dominates: 5 layers x 4 channels x 128 x 4 B per point
     assert b >= 100000 * 5 * 4 * 128 * 4
+
+
+def test_binding_rejects_mis_sized_buffers():
+    """The C ABI cannot see buffer sizes: the binding checks every one before a call."""
+    import torch
+    for name in ("burgers", "euler", "maxwell"):
+        c = synth.make_case(name, n_points=10)
+        net = c["net"]
+        p = torch.from_numpy(c["params"])
+        x = torch.from_numpy(c["points"])
+        B = None if c["B"] is None else torch.from_numpy(c["B"])
+        binding._check_shapes(net, p, B, x)                       # the right sizes pass
+        with pytest.raises(ValueError):
+            binding._check_shapes(net, p[:-1], B, x)              # one parameter short
+        with pytest.raises(ValueError):
+            binding._check_shapes(net, torch.cat([p, p[:1]]), B, x)
+        with pytest.raises(ValueError):
+            binding._check_shapes(net, p, B, x[:, :1].contiguous())  # wrong input dimension
+        with pytest.raises(ValueError):
+            binding._check_shapes(net, p, B, x.reshape(-1))
+        if B is not None:
+            with pytest.raises(ValueError):
+                binding._check_shapes(net, p, B[:, :-1].contiguous(), x)
+            with pytest.raises(ValueError):
+                binding._check_shapes(net, p, None, x)
+        else:
+            with pytest.raises(ValueError):
+                binding._check_shapes(net, p, torch.zeros(4), x)
+    c = synth.make_case("burgers", n_points=10)
+    p, x = torch.from_numpy(c["params"]), torch.from_numpy(c["points"])
+    a = [dict(points=torch.from_numpy(c["anchors"][0]["points"]),
+              targets=torch.from_numpy(c["anchors"][0]["targets"]))]
+    binding._check_shapes(c["net"], p, None, x, a)
+    with pytest.raises(ValueError):
+        binding._check_shapes(c["net"], p, None, x, [dict(a[0], targets=a[0]["targets"][:-1])])

@@ -96,11 +96,47 @@ def test_forward_only_matches(oracle, dev, prec):
     check(got, run_oracle(oracle, case, grad=False), prec, "ns-fwd")
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("n", [1, 5, 129])
-def test_tiny_and_ragged_point_counts(oracle, dev, n):
+def test_tiny_and_ragged_point_counts(oracle, dev, n, prec):
     from paper_2604_15645_amd import synth
     case = synth.make_case("euler", n_points=n, seed=40 + n, perturb=True)
-    check(run_gpu(case, dev, "fp32"), run_oracle(oracle, case), "fp32", "euler-n%d" % n)
+    check(run_gpu(case, dev, prec), run_oracle(oracle, case), prec, "euler-n%d" % n)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("name", ["burgers", "euler", "ns", "maxwell"])
+def test_constant_output_network_is_exact(dev, name, prec):
+    """With the output weights zero the outputs are the (non-zero) output biases, every
+    derivative vanishes, and so do the residual of every PDE, the loss and the whole
+    gradient -- exactly, with every hidden layer still evaluated."""
+    from paper_2604_15645_amd import synth
+    case = synth.make_case(name, n_points=333, seed=5, perturb=True, anchors=False)
+    no, ni = synth.layer_dims(case["net"])[-1]
+    tail = no * ni + (no if case["net"].get("rwf") else 0) + no
+    p = case["params"].copy()
+    p[len(p) - tail:len(p) - tail + no * ni] = 0.0
+    p[len(p) - no:] = np.array([1.5, 0.4, 2.0], dtype=np.float32)[:no]   # rho, p > 0 for Euler
+    case["params"] = p
+    got = run_gpu(case, dev, prec)
+    assert np.all(got["residual"] == 0.0), name
+    assert np.all(got["loss"] == 0.0), name
+    assert np.all(got["grad"] == 0.0), name
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("name,masks", [("ns", (5, 6)), ("euler", (2, 7)), ("maxwell", (4, 3))])
+def test_multi_output_supervision(oracle, dev, name, masks, prec):
+    """Value supervision of outputs other than output 0 (every out_mask bit)."""
+    from paper_2604_15645_amd import synth
+    case = synth.make_case(name, n_points=400, seed=61, perturb=True)
+    rng = np.random.Generator(np.random.PCG64(62))
+    d_in = case["net"]["d_in"]
+    case["anchors"] = [dict(points=rng.uniform(0, 1, size=(90 + 41 * k, d_in)).astype(np.float32),
+                            targets=rng.normal(size=(90 + 41 * k, 3)).astype(np.float32),
+                            out_mask=m, **{"lambda": 0.5 + k})
+                       for k, m in enumerate(masks)]
+    check(run_gpu(case, dev, prec), run_oracle(oracle, case), prec, "%s-mask" % name)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])

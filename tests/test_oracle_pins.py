@@ -294,6 +294,42 @@ def test_oracle_matches_torch_autograd(oracle, pde, variant):
     assert relerr(got["grad"], grad) < 1e-11
 
 
+@pytest.mark.parametrize("pde,masks", [("ns2d", (5, 6)), ("euler1d", (2, 7)), ("maxwell", (4, 3))])
+def test_multi_output_supervision_matches_torch_autograd(oracle, pde, masks):
+    """Value supervision on networks with three outputs (Sec. 2.3: one mean square per
+    supervised quantity): every out_mask bit, not only output 0, against the autograd
+    formulation, and the gradient against central differences of the oracle's loss."""
+    net = small_net(pde, widths=(7, 6), act="tanh", n_freq=3 if pde != "ns2d" else 0, w0=1.0)
+    r = rng(31)
+    params = synth.init_params(net, r, perturb=True).astype(np.float64)
+    B = r.normal(0, 1.2, size=(net["d_in"], net["n_freq"])) if net["n_freq"] else None
+    pts = r.uniform(0.05, 0.95, size=(19, net["d_in"]))
+    if pde == "euler1d":
+        params[-3:] += np.array([2.0, 0.3, 1.5])
+    anchors = [dict(points=r.uniform(0.0, 1.0, size=(6 + k, net["d_in"])),
+                    targets=r.normal(size=(6 + k, 3)), out_mask=m, **{"lambda": 0.6 + 0.5 * k})
+               for k, m in enumerate(masks)]
+    spec = dict(PDES[pde], lambda_res=[1.0, 0.7, 1.3])
+    got = oracle.loss_grad(net, spec, params, B, pts, anchors)
+    loss, res, grad = torch_loss(net, spec, params, B, pts, anchors)
+    assert relerr(got["loss"], loss) < 1e-12
+    assert relerr(got["grad"], grad) < 1e-11
+    # each supervision term differs from the term with only output 0 supervised
+    only0 = [dict(a, out_mask=1) for a in anchors]
+    base = oracle.loss_grad(net, spec, params, B, pts, only0)
+    for k in range(len(anchors)):
+        assert abs(got["loss"][4 + k] - base["loss"][4 + k]) > 1e-6 * abs(got["loss"][4 + k])
+    # central differences of the oracle's own loss along random directions
+    for j in range(3):
+        v = r.normal(size=params.size)
+        h = 1e-5
+        lp = oracle.loss_grad(net, spec, params + h * v, B, pts, anchors, want_grad=False)["loss"][0]
+        lm = oracle.loss_grad(net, spec, params - h * v, B, pts, anchors, want_grad=False)["loss"][0]
+        fd = (lp - lm) / (2 * h)
+        an = float(got["grad"] @ v)
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (j, fd, an)
+
+
 # ------------------------------------------------------------ residual stage alone
 
 def analytic_jets(fields, syms, lap_syms, pts):
