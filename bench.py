@@ -7,7 +7,9 @@ parameter.  Inputs are resident in device memory before the timed region starts.
 Headline workload: 2D Maxwell (E_z, H_x, H_y) network with 128 Fourier frequencies
 (sigma = 2) and 6 x 256 sine layers, 1,048,576 uniform points on [0,1]^3 -- the largest
 single-GPU configuration of the benchmark set.  The BF16X3 path is the reported value;
-the plain FP32 matrix-core path is timed beside it.  The other configurations (Burgers,
+the same three-product split with IEEE half parts (FP16X3, same matrix-core rate, 22
+instead of 16 significant bits per operand) and the plain FP32 matrix-core path are timed
+beside it.  The other configurations (Burgers,
 1D Euler, Navier-Stokes, and the 64-network Burgers sweep in one persistent launch) are
 timed in the same run and reported as extra keys of the same JSON line.
 
@@ -34,9 +36,9 @@ if ROOT not in sys.path:
 METRIC = "collocation points/sec for fused residual+grad step, BF16x3 vs FP32 at 1e-4 rel err"
 PEAK = {"bf16": 2.5e15, "fp32": 157.3e12}   # dense matrix-core peaks, FLOP/s
 HBM_PEAK = 8.0e12
-TOL = {"fp32": 1e-5, "bf16x3": 1e-4}
-N_PROD = {"bf16x3": 3, "fp32": 1}
-PEAK_OF = {"bf16x3": "bf16", "fp32": "fp32"}
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "fp16x3": 1e-4}
+N_PROD = {"bf16x3": 3, "fp16x3": 3, "fp32": 1}
+PEAK_OF = {"bf16x3": "bf16", "fp16x3": "bf16", "fp32": "fp32"}   # FP16 dense peak = BF16
 
 
 def channels(net, pde):
@@ -185,7 +187,7 @@ def bench_config(name, dev, steps, warmup, sample, fp32=True):
     n_total = n + sum(len(a["points"]) for a in case["anchors"])
     _, step_flops = kernel_flops(net, pde, n_total)
     rec = {"workload": describe(net, pde, n), "points": n}
-    precs = ("bf16x3", "fp32") if fp32 else ("bf16x3",)
+    precs = ("bf16x3", "fp16x3", "fp32") if fp32 else ("bf16x3", "fp16x3")
     m = min(sample, n)
     ref = oracle.loss_grad(net, pde, case["params"], case["B"], case["points"][:m], case["anchors"])
     for prec in precs:
@@ -224,7 +226,7 @@ def bench_sweep(dev, steps, warmup):
             pick[w] = i
     refs = {i: oracle.loss_grad(insts[i]["net"], pde, insts[i]["params"], None, insts[i]["points"],
                                 want_residual=False) for i in sorted(pick.values())}
-    for prec in ("bf16x3", "fp32"):
+    for prec in ("bf16x3", "fp16x3", "fp32"):
         ws = binding.Workspace(dev)
         run = lambda: binding.batched_step(nets, pde, params, pts, prec=prec, workspace=ws)
         out = run()
@@ -312,6 +314,9 @@ def main():
 
     tune = {"tile_points": args.tile_points, "grid": args.grid} if args.tile_points or args.grid else None
     ms16, k16, out16 = time_steps(case, params, B, pts, anchors, "bf16x3", args.steps, args.warmup, tune)
+    ms_h, k_h, _ = time_steps(case, params, B, pts, anchors, "fp16x3", args.steps, args.warmup, tune)
+    fp16x3 = {"value": n_points / (ms_h / 1e3), "ms_per_step": ms_h,
+              "kernels_ms": {k: v[1] / v[0] for k, v in k_h.items()}}
     fp32 = None
     if not args.no_fp32:
         ms32, k32, _ = time_steps(case, params, B, pts, anchors, "fp32",
@@ -366,6 +371,8 @@ def main():
         "kernel_launches_per_step": {k: v[0] / args.steps for k, v in k16.items()},
         "roofline": roof,
     }
+    fp16x3["step_mfma_frac"] = n_prod * step_flops / (fp16x3["ms_per_step"] / 1e3) / PEAK["bf16"]
+    result["fp16x3"] = fp16x3
     if fp32:
         result["fp32"] = fp32
         result["fp32"]["step_mfma_frac_fp32"] = step_flops / (fp32["ms_per_step"] / 1e3) / PEAK["fp32"]
@@ -394,7 +401,7 @@ def main():
         # parity at the benchmark's own shape: the prefix through the GPU path
         par = {}
         ptsm = pts[:m].contiguous()
-        for prec in ("bf16x3", "fp32"):
+        for prec in ("bf16x3", "fp16x3", "fp32"):
             o = binding.residual_step(net, pde, params, B, ptsm, anchors, prec=prec)
             torch.cuda.synchronize()
             par[prec] = dict(parity(o, ref), tol=TOL[prec])

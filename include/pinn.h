@@ -65,9 +65,24 @@ typedef enum { PINN_ACT_TANH = 0, PINN_ACT_SIN = 1 } pinn_act;
 
 typedef enum {
   PINN_PREC_FP32 = 0,   /* FP32 matrix cores (v_mfma_f32_16x16x4_f32), FP32 accumulate   */
-  PINN_PREC_BF16X3 = 1  /* each product a*b as hi*hi + hi*lo + lo*hi with a = hi + lo,
+  PINN_PREC_BF16X3 = 1, /* each product a*b as hi*hi + hi*lo + lo*hi with a = hi + lo,
                            hi = bf16(a), lo = bf16(a - hi), BF16 matrix cores, FP32
-                           accumulate                                                    */
+                           accumulate.  hi + lo holds 16 significant bits, so each
+                           operand is represented to about 2^-16 relative; a residual
+                           much smaller than the terms it is formed from (strong
+                           cancellation) loses accuracy in proportion.                  */
+  PINN_PREC_BF16 = 2,   /* one BF16 product per product (8 significant bits): not
+                           implemented -- the derivative jets of a residual need more;
+                           returns PINN_E_UNSUPPORTED                                   */
+  PINN_PREC_FP64 = 3,   /* reserved                                                     */
+  PINN_PREC_FP16X3 = 4  /* as BF16X3 with IEEE half parts, hi = fp16(a), lo = fp16(a - hi),
+                           FP16 matrix cores (the same rate as BF16): 22 significant bits,
+                           operands represented to about 2^-22.  Half precision has a
+                           narrow range: every adjoint is scaled by a power of two from its
+                           largest magnitude before it is split (exact, undone on the
+                           result); activation jets and weights are split unscaled and must
+                           stay below 65504 in magnitude (the result is otherwise not
+                           finite); parts below 2^-14 keep an absolute resolution of 2^-24. */
 } pinn_prec;
 
 /* Opt-in flags (bitwise or). */

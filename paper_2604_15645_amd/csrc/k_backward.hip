@@ -20,10 +20,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
 #pragma unroll
   for (int i = 0; i < S::NOBW; ++i) bsum[i] = 0.f;
   const int64_t count = A.n_sub > blockIdx.x ? (A.n_sub - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+  const float asc = adj_scale<PREC>(A.work.amax[A.layer]);
+  float amx = 0.0f;
   bwd_range<PREC, ACT, NOB, NIB, PB>(A.net, A.layer, A.work.pts, blockIdx.x, gridDim.x, count, A.zb_in, A.zb_out,
-                                     A.z_prev, smem, accw, bsum);
+                                     A.z_prev, smem, accw, bsum, asc, amx);
+  if constexpr (PREC == kFP16X3)
+    if (A.z_prev) amax_publish(amx, &A.work.amax[A.layer - 1]);
   const LayerDev& ly = A.net.layer[A.layer];
-  bwd_flush<NOB, NIB, PB>(accw, bsum, A.slots + (size_t)blockIdx.x * ly.n_out * (ly.n_in + 1), ly.n_out, ly.n_in);
+  bwd_flush<NOB, NIB, PB>(accw, bsum, A.slots + (size_t)blockIdx.x * ly.n_out * (ly.n_in + 1), ly.n_out, ly.n_in,
+                          1.0f / asc);
 }
 
 // ================================================================== backward (one layer, wide)
@@ -66,15 +71,15 @@ __device__ __forceinline__ Raw wide_zbar_op(const char* R, int ld, int ob, int c
   return r;
 }
 
-template <int ACT, int NOB, int NIB, int PB>
+template <int PREC, int ACT, int NOB, int NIB, int PB>
 __device__ __forceinline__ void bwd_wide_range(const NetDev& net, int layer, const float4* pts, int64_t s0,
                                                int64_t stride, int64_t count, const float* zb_in, float* zb_out,
                                                const float* z_prev, char* smem,
                                                f4 (&accw)[NOB][WideShape<NOB, NIB, PB>::NIBW],
-                                               float (&bsum)[WideShape<NOB, NIB, PB>::NOBC]) {
+                                               float (&bsum)[WideShape<NOB, NIB, PB>::NOBC], float asc, float& amx) {
   using S = WideShape<NOB, NIB, PB>;
-  using Pr = Prec<kBF16X3>;
-  using T = Tile<kBF16X3>;
+  using Pr = Prec<PREC>;
+  using T = Tile<PREC>;
   constexpr int CPB = S::CPB, NIBW = S::NIBW, NOBC = S::NOBC;
   constexpr bool kLap = (ACT & kLapFlag) != 0;
   const LayerDev& ly = net.layer[layer];
@@ -109,7 +114,7 @@ __device__ __forceinline__ void bwd_wide_range(const NetDev& net, int layer, con
 #pragma unroll
         for (int cb = 0; cb < CPB; ++cb) {
           const f4 zb = to_f4(*reinterpret_cast<const float4*>(STG + ((size_t)(cb * nob + ob) * 64 + lane) * 16));
-          T::put(R, rld, 4 * cb + g, 16 * ob + l16, zb);
+          T::put(R, rld, 4 * cb + g, 16 * ob + l16, ascale<PREC>(zb, asc));
           bsum[q] += zb.x;
         }
       }
@@ -129,7 +134,7 @@ __device__ __forceinline__ void bwd_wide_range(const NetDev& net, int layer, con
         int blk[NIBW];
 #pragma unroll
         for (int q = 0; q < NIBW; ++q) blk[q] = wave + 8 * q;
-        gemm_tile<kBF16X3, NIBW, CPB>(acca, R, rld, 0, ly.wb, ly.kco, blk, lane);
+        gemm_tile<PREC, NIBW, CPB>(acca, R, rld, 0, ly.wb, ly.kco, blk, lane);
       }
       wait_async();
       barrier_lds();  // pre-activations of sub-tile s staged
@@ -150,8 +155,9 @@ __device__ __forceinline__ void bwd_wide_range(const NetDev& net, int layer, con
             f[4 * h + 1] = a.y;
             f[4 * h + 2] = a.z;
             f[4 * h + 3] = a.w;
-            const f4 zb = jet_act_adj<kLap>(z, acca[q][cb], s1v, s2v, s3v, lw1, lw2);
+            const f4 zb = jet_act_adj<kLap>(z, ascale<PREC>(acca[q][cb], 1.0f / asc), s1v, s2v, s3v, lw1, lw2);
             *jet_frag(zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
+            if constexpr (PREC == kFP16X3) amx = fmaxf(amx, jet_absmax(zb));
           }
           aop[q][cc] = Pr::make(f);
           __builtin_amdgcn_sched_barrier(0);
@@ -200,7 +206,7 @@ __device__ __forceinline__ void bwd_wide_range(const NetDev& net, int layer, con
 template <int NOB, int NIB, int PB>
 __device__ __forceinline__ void bwd_wide_flush(const f4 (&accw)[NOB][WideShape<NOB, NIB, PB>::NIBW],
                                                const float (&bsum)[WideShape<NOB, NIB, PB>::NOBC], double* slot,
-                                               int n_out, int n_in) {
+                                               int n_out, int n_in, float inv) {
   using S = WideShape<NOB, NIB, PB>;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -214,7 +220,8 @@ __device__ __forceinline__ void bwd_wide_flush(const f4 (&accw)[NOB][WideShape<N
       const int ib = wave + 8 * q;
       if (ib >= nib) continue;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) slot[(size_t)(16 * ob + 4 * g + r) * n_in + 16 * ib + l16] = (double)accw[ob][q][r];
+      for (int r = 0; r < 4; ++r)
+        slot[(size_t)(16 * ob + 4 * g + r) * n_in + 16 * ib + l16] = (double)accw[ob][q][r] * (double)inv;
     }
   }
 #pragma unroll
@@ -227,7 +234,7 @@ __device__ __forceinline__ void bwd_wide_flush(const f4 (&accw)[NOB][WideShape<N
   }
 }
 
-template <int ACT, int NOB, int NIB, int PB>
+template <int PREC, int ACT, int NOB, int NIB, int PB>
 __global__ __launch_bounds__(kThreads, 1) void k_backward_wide(const BwdArgs A) {
   using S = WideShape<NOB, NIB, PB>;
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -240,10 +247,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_wide(const BwdArgs A) 
 #pragma unroll
   for (int q = 0; q < S::NOBC; ++q) bsum[q] = 0.f;
   const int64_t count = A.n_sub > blockIdx.x ? (A.n_sub - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
-  bwd_wide_range<ACT, NOB, NIB, PB>(A.net, A.layer, A.work.pts, blockIdx.x, gridDim.x, count, A.zb_in, A.zb_out,
-                                    A.z_prev, smem, accw, bsum);
+  const float asc = adj_scale<PREC>(A.work.amax[A.layer]);
+  float amx = 0.0f;
+  bwd_wide_range<PREC, ACT, NOB, NIB, PB>(A.net, A.layer, A.work.pts, blockIdx.x, gridDim.x, count, A.zb_in,
+                                          A.zb_out, A.z_prev, smem, accw, bsum, asc, amx);
+  if constexpr (PREC == kFP16X3)
+    if (A.z_prev) amax_publish(amx, &A.work.amax[A.layer - 1]);
   const LayerDev& ly = A.net.layer[A.layer];
-  bwd_wide_flush<NOB, NIB, PB>(accw, bsum, A.slots + (size_t)blockIdx.x * ly.n_out * (ly.n_in + 1), ly.n_out, ly.n_in);
+  bwd_wide_flush<NOB, NIB, PB>(accw, bsum, A.slots + (size_t)blockIdx.x * ly.n_out * (ly.n_in + 1), ly.n_out, ly.n_in,
+                               1.0f / asc);
 }
 
 // ================================================================== backward (one layer, split roles)
@@ -284,7 +296,7 @@ __device__ __forceinline__ void wait_vm() {
 // sub-tile's adjoint into STG started first.  STG and R are distinct LDS regions; the
 // restrict qualifiers let the compiler's wait insertion see that the tile reads do not
 // depend on the copy.
-template <int NIBW, int CPB, int KC>
+template <int PREC, int NIBW, int CPB, int KC>
 __device__ __forceinline__ void split_adjoint_product(f4 (&acca)[NIBW][CPB], char* __restrict__ STG,
                                                       const char* __restrict__ R, int rld,
                                                       const Raw (&wreg)[NIBW][KC], const char* next, int bytes,
@@ -298,24 +310,18 @@ __device__ __forceinline__ void split_adjoint_product(f4 (&acca)[NIBW][CPB], cha
   // kc that use it have issued; per accumulator the order of Prec::mma is kept
   Raw a[CPB];
 #pragma unroll
-  for (int cb = 0; cb < CPB; ++cb) a[cb] = Tile<kBF16X3>::load(R, rld, cb, 0, lane);
+  for (int cb = 0; cb < CPB; ++cb) a[cb] = Tile<PREC>::load(R, rld, cb, 0, lane);
 #pragma unroll
   for (int kc = 0; kc < KC; ++kc) {
 #pragma unroll
     for (int cb = 0; cb < CPB; ++cb) {
 #pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-        acca[q][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[cb].b),
-                                                              __builtin_bit_cast(bf16x8, wreg[q][kc].a), acca[q][cb], 0, 0, 0);
+      for (int q = 0; q < NIBW; ++q) acca[q][cb] = Half<PREC>::mfma(a[cb].b, wreg[q][kc].a, acca[q][cb]);
 #pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-        acca[q][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[cb].a),
-                                                              __builtin_bit_cast(bf16x8, wreg[q][kc].b), acca[q][cb], 0, 0, 0);
+      for (int q = 0; q < NIBW; ++q) acca[q][cb] = Half<PREC>::mfma(a[cb].a, wreg[q][kc].b, acca[q][cb]);
 #pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-        acca[q][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[cb].a),
-                                                              __builtin_bit_cast(bf16x8, wreg[q][kc].a), acca[q][cb], 0, 0, 0);
-      if (kc + 1 < KC) a[cb] = Tile<kBF16X3>::load(R, rld, cb, kc + 1, lane);
+      for (int q = 0; q < NIBW; ++q) acca[q][cb] = Half<PREC>::mfma(a[cb].a, wreg[q][kc].a, acca[q][cb]);
+      if (kc + 1 < KC) a[cb] = Tile<PREC>::load(R, rld, cb, kc + 1, lane);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -328,7 +334,7 @@ __device__ __forceinline__ void split_adjoint_product(f4 (&acca)[NIBW][CPB], cha
 // tile, B operands in registers), with the copy of the next sub-tile's adjoint into STG
 // started first; the restrict qualifiers tell the compiler's wait insertion that the ZT
 // reads do not depend on the copy.
-template <int NOB, int NIBW, int CPB>
+template <int PREC, int NOB, int NIBW, int CPB>
 __device__ __forceinline__ void split_weight_grad_product(f4 (&accw)[NOB][NIBW], const Raw (&aop)[NIBW][CPB / 2],
                                                           char* __restrict__ STG, const char* __restrict__ ZT,
                                                           const char* next, int bytes, int lane) {
@@ -345,17 +351,11 @@ __device__ __forceinline__ void split_weight_grad_product(f4 (&accw)[NOB][NIBW],
     for (int ob = 0; ob < NOB; ++ob) {
       const Raw ao = u[ob % D];
 #pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-        accw[ob][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ao.b),
-                                                              __builtin_bit_cast(bf16x8, aop[q][cc].a), accw[ob][q], 0, 0, 0);
+      for (int q = 0; q < NIBW; ++q) accw[ob][q] = Half<PREC>::mfma(ao.b, aop[q][cc].a, accw[ob][q]);
 #pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-        accw[ob][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ao.a),
-                                                              __builtin_bit_cast(bf16x8, aop[q][cc].b), accw[ob][q], 0, 0, 0);
+      for (int q = 0; q < NIBW; ++q) accw[ob][q] = Half<PREC>::mfma(ao.a, aop[q][cc].b, accw[ob][q]);
 #pragma unroll
-      for (int q = 0; q < NIBW; ++q)
-        accw[ob][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ao.a),
-                                                              __builtin_bit_cast(bf16x8, aop[q][cc].a), accw[ob][q], 0, 0, 0);
+      for (int q = 0; q < NIBW; ++q) accw[ob][q] = Half<PREC>::mfma(ao.a, aop[q][cc].a, accw[ob][q]);
       if (ob + D < NOB) u[ob % D] = lds_unit(ZT, (ob + D) * (CPB / 2) + cc, lane, 64 * 32);
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -364,11 +364,11 @@ __device__ __forceinline__ void split_weight_grad_product(f4 (&accw)[NOB][NIBW],
 
 constexpr int kPaceSpin = 512;  // polls of a pacing wait before it goes on regardless
 
-template <int ACT, int NOB, int NIB, int PB, bool EMB>
+template <int PREC, int ACT, int NOB, int NIB, int PB, bool EMB>
 __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A) {
   using S = SplitShape<NOB, NIB, PB>;
-  using Pr = Prec<kBF16X3>;
-  using T = Tile<kBF16X3>;
+  using Pr = Prec<PREC>;
+  using T = Tile<PREC>;
   constexpr int CPB = S::CPB, NIBW = S::NIBW, NOBC = S::NOBC, KC = S::KC;
   constexpr bool kLap = (ACT & kLapFlag) != 0;
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -388,6 +388,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
   if (EMB)
     for (int i = threadIdx.x; i < net.d_in * net.n_freq; i += kThreads) BF[i] = net.B[i];
   const int zb_bytes = CPB * nob * 1024;
+  const float asc = adj_scale<PREC>(A.work.amax[A.layer]);
   // role and index within the role (blocks b and b + 8 share a sub-tile sequence)
   // (EMB: the Fourier-embedding layer -- weight gradient only, every work-group)
   const int b = blockIdx.x;
@@ -412,7 +413,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
 #pragma unroll
       for (int cb = 0; cb < CPB; ++cb) {
         const f4 zb = to_f4(*reinterpret_cast<const float4*>(STG + ((size_t)(cb * nob + ob) * 64 + lane) * 16));
-        T::put(R, rld, 4 * cb + g, 16 * ob + l16, zb);
+        T::put(R, rld, 4 * cb + g, 16 * ob + l16, ascale<PREC>(zb, asc));
         if (bsum) bsum[q] += zb.x;
       }
     }
@@ -428,6 +429,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
       for (int kc = 0; kc < KC; ++kc) wreg[q][kc] = glob_frag(ly.wb, wave + 8 * q, kc, KC, lane);
     wait_vm<0>();  // resident from here on: no wait for them inside the loop
     bool held = false;  // the partner had not reached the previous sub-tile when last read
+    float amx = 0.0f;
     for (int64_t k = 0; k < count; ++k) {
       const int64_t s = rb + k * G;
       const int64_t cb0 = s * CPB;
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
       if (A.pace) seen = __hip_atomic_load(&A.pace[rb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       barrier_lds();  // R complete; STG free
       f4 acca[NIBW][CPB];
-      split_adjoint_product<NIBW, CPB, KC>(acca, STG, R, rld, wreg, k + 1 < count ? zb_src(s + G) : nullptr,
+      split_adjoint_product<PREC, NIBW, CPB, KC>(acca, STG, R, rld, wreg, k + 1 < count ? zb_src(s + G) : nullptr,
                                            zb_bytes, lane);
 #pragma unroll
       for (int q = 0; q < NIBW; ++q) {
@@ -462,13 +464,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
           const f4 z = zp[q][cb];
           float s0v, s1v, s2v, s3v;
           act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
-          const f4 zb = jet_act_adj<kLap>(z, acca[q][cb], s1v, s2v, s3v, lw1, lw2);
+          const f4 zb = jet_act_adj<kLap>(z, ascale<PREC>(acca[q][cb], 1.0f / asc), s1v, s2v, s3v, lw1, lw2);
           *jet_frag(A.zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
+          if constexpr (PREC == kFP16X3) amx = fmaxf(amx, jet_absmax(zb));
         }
       }
       // read beside the pre-activations, compared once they are in use
       held = A.pace && seen < (A.launch << 20) + (unsigned long long)k;
     }
+    if constexpr (PREC == kFP16X3) amax_publish(amx, &A.work.amax[A.layer - 1]);
   } else {
     // ---- weight and bias gradient
     f4 accw[NOB][NIBW];
@@ -500,7 +504,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
           const float* f0 = reinterpret_cast<const float*>(STG + ((size_t)((2 * cc) * nob + ob) * 64 + lane) * 16);
           const float* f1 = reinterpret_cast<const float*>(STG + ((size_t)((2 * cc + 1) * nob + ob) * 64 + lane) * 16);
           const float4 v0 = *reinterpret_cast<const float4*>(f0), v1 = *reinterpret_cast<const float4*>(f1);
-          const float f[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+          const float f[8] = {ascale<PREC>(v0.x, asc), ascale<PREC>(v0.y, asc), ascale<PREC>(v0.z, asc),
+                              ascale<PREC>(v0.w, asc), ascale<PREC>(v1.x, asc), ascale<PREC>(v1.y, asc),
+                              ascale<PREC>(v1.z, asc), ascale<PREC>(v1.w, asc)};
           const Raw op = Pr::make(f);
           uint4* d = reinterpret_cast<uint4*>(R + ((size_t)(ob * (CPB / 2) + cc) * 64 + lane) * 32);
           d[0] = op.a;
@@ -539,7 +545,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
           aop[q][cc] = Pr::make(f);
         }
       if (!EMB && k + 1 < count) load_zp(s + G);  // the next sub-tile's pre-activations load under the product
-      split_weight_grad_product<NOB, NIBW, CPB>(accw, aop, STG, R, k + 1 < count ? zb_src(s + G) : nullptr,
+      split_weight_grad_product<PREC, NOB, NIBW, CPB>(accw, aop, STG, R, k + 1 < count ? zb_src(s + G) : nullptr,
                                                 zb_bytes, lane);
     }
     // flush: slot rb, [n_out][n_in] then [n_out]
@@ -550,7 +556,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
       for (int q = 0; q < NIBW; ++q) {
         const int ib = wave + 8 * q;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) slot[(size_t)(16 * ob + 4 * g + r) * n_in + 16 * ib + l16] = (double)accw[ob][q][r];
+        for (int r = 0; r < 4; ++r)
+          slot[(size_t)(16 * ob + 4 * g + r) * n_in + 16 * ib + l16] = (double)accw[ob][q][r] * (double)(1.0f / asc);
       }
 #pragma unroll
     for (int q = 0; q < NOBC; ++q) {
@@ -576,57 +583,57 @@ int bwd(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
   return launch_status(hipGetLastError());
 }
 
-template <int ACT, int NOB, int NIB, int PB>
+template <int PREC, int ACT, int NOB, int NIB, int PB>
 int bwd_wide(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  auto k = k_backward_wide<ACT, NOB, NIB, PB>;
+  auto k = k_backward_wide<PREC, ACT, NOB, NIB, PB>;
   if (set_lds(k, lds)) return -5;
   hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, a);
   return launch_status(hipGetLastError());
 }
 
-template <int ACT, int NOB, int NIB, int PB, bool EMB>
+template <int PREC, int ACT, int NOB, int NIB, int PB, bool EMB>
 int split_k(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  auto k = k_backward_split<ACT, NOB, NIB, PB, EMB>;
+  auto k = k_backward_split<PREC, ACT, NOB, NIB, PB, EMB>;
   if (set_lds(k, lds)) return -5;
   hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, a);
   return launch_status(hipGetLastError());
 }
 
-template <int ACT, int H>
+template <int PREC, int ACT, int H>
 int bwd_split(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  if constexpr (H >= 128) return split_k<ACT, H / 16, H / 16, wide_pb(H), false>(a, grid, lds, s);
+  if constexpr (H >= 128) return split_k<PREC, ACT, H / 16, H / 16, wide_pb(H), false>(a, grid, lds, s);
   return -2;
 }
 
 // Fourier-embedding layer (weight gradient only): embedding width 128 or 256.
-template <int ACT, int H>
+template <int PREC, int ACT, int H>
 int bwd_split_embed(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
   const int n_in = a.net.layer[0].n_in, n_out = a.net.layer[0].n_out;
   if (n_out != H || n_in % 128 != 0) return -2;
   if constexpr (H >= 64) {
-    if (n_in == 128) return split_k<ACT, H / 16, 8, wide_pb(H), true>(a, grid, lds, s);
-    if (n_in == 256) return split_k<ACT, H / 16, 16, wide_pb(H), true>(a, grid, lds, s);
+    if (n_in == 128) return split_k<PREC, ACT, H / 16, 8, wide_pb(H), true>(a, grid, lds, s);
+    if (n_in == 256) return split_k<PREC, ACT, H / 16, 16, wide_pb(H), true>(a, grid, lds, s);
   }
   return -2;
 }
 
 template <int PREC, int ACT, int H>
 int bwd_e(bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  if constexpr (PREC == kBF16X3) {
+  if constexpr (is_split(PREC)) {
     if (a.wide == 2 && !embed) {
       // split-role kernel: layer widths must be exactly H (uniform hidden layers)
       if (a.net.layer[a.layer].n_in != H || a.net.layer[a.layer].n_out != H || grid % 16 != 0) return -2;
-      return bwd_split<ACT, H>(a, grid, lds, s);
+      return bwd_split<PREC, ACT, H>(a, grid, lds, s);
     }
-    if (a.wide == 3 && embed) return bwd_split_embed<ACT, H>(a, grid, lds, s);
+    if (a.wide == 3 && embed) return bwd_split_embed<PREC, ACT, H>(a, grid, lds, s);
   }
-  if constexpr (PREC == kBF16X3) {
+  if constexpr (is_split(PREC)) {
     // wide path (chosen by the plan): input widths that are multiples of 128
     constexpr int PW = wide_pb(H);
     if (a.wide) {
       if (a.net.layer[a.layer].n_in % 128 != 0) return -2;
-      if (embed) return bwd_wide<ACT, H / 16, 16, PW>(a, grid, lds, s);
-      if constexpr (H >= 128) return bwd_wide<ACT, H / 16, H / 16, PW>(a, grid, lds, s);
+      if (embed) return bwd_wide<PREC, ACT, H / 16, 16, PW>(a, grid, lds, s);
+      if constexpr (H >= 128) return bwd_wide<PREC, ACT, H / 16, H / 16, PW>(a, grid, lds, s);
       return -2;
     }
   }
@@ -660,8 +667,9 @@ int bwd_a(int act, int H, bool embed, const BwdArgs& a, int grid, size_t lds, hi
 }
 
 int launch_backward(int prec, int act, int H, bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  return prec == kFP32 ? bwd_a<kFP32>(act, H, embed, a, grid, lds, s)
-                       : bwd_a<kBF16X3>(act, H, embed, a, grid, lds, s);
+  if (prec == kFP32) return bwd_a<kFP32>(act, H, embed, a, grid, lds, s);
+  if (prec == kFP16X3) return bwd_a<kFP16X3>(act, H, embed, a, grid, lds, s);
+  return bwd_a<kBF16X3>(act, H, embed, a, grid, lds, s);
 }
 
 }  // namespace pinn

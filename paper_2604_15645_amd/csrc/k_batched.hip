@@ -14,9 +14,21 @@ namespace pinn {
 // points, keeping each layer's weight-gradient sums in registers over the item, and writes
 // them with the loss sums to the item's own FP64 slots.  Slots are per item, so the
 // result does not depend on which work-group ran which item.
+// Largest value of m over the work-group (every thread calls it; red: kWaves floats).
+__device__ __forceinline__ float wg_max(float m, float* red) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  float r = red[0];
+  for (int w = 1; w < kWaves; ++w) r = fmaxf(r, red[w]);
+  return r;
+}
+
 template <int PREC, int ACT, int H>
 __device__ __forceinline__ void run_item(const BatchArgs& A, const BatchInst& in, const BatchItem& it, int64_t item,
-                                         char* smem) {
+                                         char* smem, float* red) {
   constexpr int PF = H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128;
   constexpr int PB = 2048 / H;
   const NetDev& net = in.net;
@@ -29,7 +41,9 @@ __device__ __forceinline__ void run_item(const BatchArgs& A, const BatchInst& in
   double* gslot = A.grad_slots + it.slot_off;
   PdeDev pde = A.pde;
   for (int c = 0; c < 3; ++c) pde.seed_scale[c] = 2.0f * A.lambda_res[c] / (float)in.n;
-  // forward over the item's tiles
+  // forward over the item's tiles; amx: largest magnitude of the adjoint the forward writes
+  // (FP16X3 scales each layer's adjoint by the item's own largest magnitude)
+  float amx = 0.0f;
   {
     const FwdLds s = fwd_carve<H, PF>(smem, r_stride(in.kmax));
     const int ld = Tile<PREC>::ld(in.kmax, PF);
@@ -44,7 +58,8 @@ __device__ __forceinline__ void run_item(const BatchArgs& A, const BatchInst& in
       sg.out_mask = 0;
       sg.lam = 0.0f;
       sg.residual = nullptr;
-      fwd_tile<PREC, ACT, H, PF>(net, pde, pts + t * PF, zs, in.zs_stride, zb[0], t * (PF / 4), sg, ld, true, s);
+      fwd_tile<PREC, ACT, H, PF>(net, pde, pts + t * PF, zs, in.zs_stride, zb[0], t * (PF / 4), sg, ld, true, s,
+                                 amx);
     }
     const int nL = net.layer[net.L].n_in;
     fwd_end<H, PF>(s, loss_slot, gslot + in.eff_off[net.L], net.d_out, nL, true);
@@ -61,9 +76,13 @@ __device__ __forceinline__ void run_item(const BatchArgs& A, const BatchInst& in
     float bsum[S::NOBW];
 #pragma unroll
     for (int i = 0; i < S::NOBW; ++i) bsum[i] = 0.f;
+    float asc = 1.0f;
+    if constexpr (PREC == kFP16X3) asc = adj_scale<PREC>(__float_as_uint(wg_max(amx, red)));
+    amx = 0.0f;
     bwd_range<PREC, ACT, H / 16, H / 16, PB>(net, j, pts, 0, 1, npts / PB, zb[cur], zb[cur ^ 1],
-                                             zs + (j - 1) * in.zs_stride, smem, accw, bsum);
-    bwd_flush<H / 16, H / 16, PB>(accw, bsum, gslot + in.eff_off[j], net.layer[j].n_out, net.layer[j].n_in);
+                                             zs + (j - 1) * in.zs_stride, smem, accw, bsum, asc, amx);
+    bwd_flush<H / 16, H / 16, PB>(accw, bsum, gslot + in.eff_off[j], net.layer[j].n_out, net.layer[j].n_in,
+                                  1.0f / asc);
     cur ^= 1;
   }
   // first layer (identity embedding)
@@ -76,6 +95,7 @@ template <int PREC, int ACT>
 __global__ __launch_bounds__(kThreads, 1) void k_batched(const BatchArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   __shared__ int s_q;
+  __shared__ float s_red[kWaves];
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) s_q = atomicAdd(A.counter, 1);
@@ -86,10 +106,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_batched(const BatchArgs A) {
     const BatchItem it = A.items[item];
     const BatchInst& in = A.inst[it.inst];
     switch (in.H) {
-      case 32: run_item<PREC, ACT, 32>(A, in, it, item, smem); break;
-      case 64: run_item<PREC, ACT, 64>(A, in, it, item, smem); break;
-      case 128: run_item<PREC, ACT, 128>(A, in, it, item, smem); break;
-      default: run_item<PREC, ACT, 256>(A, in, it, item, smem); break;
+      case 32: run_item<PREC, ACT, 32>(A, in, it, item, smem, s_red); break;
+      case 64: run_item<PREC, ACT, 64>(A, in, it, item, smem, s_red); break;
+      case 128: run_item<PREC, ACT, 128>(A, in, it, item, smem, s_red); break;
+      default: run_item<PREC, ACT, 256>(A, in, it, item, smem, s_red); break;
     }
   }
 }
@@ -130,7 +150,9 @@ int batched_a(int act, const BatchArgs& a, int grid, size_t lds, hipStream_t s) 
 }
 
 int launch_batched(int prec, int act, const BatchArgs& a, int grid, size_t lds, hipStream_t s) {
-  return prec == kFP32 ? batched_a<kFP32>(act, a, grid, lds, s) : batched_a<kBF16X3>(act, a, grid, lds, s);
+  if (prec == kFP32) return batched_a<kFP32>(act, a, grid, lds, s);
+  if (prec == kFP16X3) return batched_a<kFP16X3>(act, a, grid, lds, s);
+  return batched_a<kBF16X3>(act, a, grid, lds, s);
 }
 
 }  // namespace pinn

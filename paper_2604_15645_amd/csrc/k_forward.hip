@@ -13,6 +13,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void k_forward(const FwdArgs A) {
   const FwdLds s = fwd_carve<H, P, NW>(smem, r_stride(A.kmax));
   const int ld = Tile<PREC>::ld(A.kmax, P);
   fwd_begin<H, P, NW>(s, A.net);
+  float amx = 0.0f;
   for (int64_t tile = blockIdx.x; tile < A.n_tiles; tile += gridDim.x) {
     const int64_t p0 = tile * P;
     const int sid = seg_of(A.seg, p0);
@@ -26,8 +27,10 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void k_forward(const FwdArgs A) {
     sg.lam = sid == 0 ? 0.0f : A.seg.lam_anchor[sid - 1];
     sg.residual = (sid == 0 && A.residual) ? A.residual + (p0 - A.seg.start[0]) * A.pde.n_res : nullptr;
     fwd_tile<PREC, ACT, H, P, NW>(A.net, A.pde, A.work.pts + p0, A.work.zs0, A.work.zs_stride, A.work.zb[0],
-                                  tile * (P / 4), sg, ld, A.with_grad != 0, s);
+                                  tile * (P / 4), sg, ld, A.with_grad != 0, s, amx);
   }
+  if constexpr (PREC == kFP16X3)
+    if (A.with_grad) amax_publish(amx, &A.work.amax[A.net.L - 1]);
   fwd_end<H, P, NW>(s, A.work.loss_slots + (size_t)blockIdx.x * kMaxTerms,
                 A.with_grad ? A.work.out_slots + (size_t)blockIdx.x * A.net.d_out * (A.net.layer[A.net.L].n_in + 1)
                             : nullptr,
@@ -80,7 +83,9 @@ int fwd_a(int act, int H, int P, const FwdArgs& a, int grid, size_t lds, hipStre
 }
 
 int launch_forward(int prec, int act, int H, int P, const FwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  return prec == kFP32 ? fwd_a<kFP32>(act, H, P, a, grid, lds, s) : fwd_a<kBF16X3>(act, H, P, a, grid, lds, s);
+  if (prec == kFP32) return fwd_a<kFP32>(act, H, P, a, grid, lds, s);
+  if (prec == kFP16X3) return fwd_a<kFP16X3>(act, H, P, a, grid, lds, s);
+  return fwd_a<kBF16X3>(act, H, P, a, grid, lds, s);
 }
 
 }  // namespace pinn

@@ -71,6 +71,7 @@ __global__ void k_stage(const StageArgs a) {
 
 __global__ void k_points(const PointsArgs a) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < a.n_zero) a.zero[p] = 0u;
   if (p >= a.n_pad) return;
   int s = 0;
   for (int k = 1; k < a.n_seg; ++k)
@@ -255,7 +256,8 @@ int launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t s) {
 }
 
 int launch_points(const PointsArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_points, dim3((unsigned)((a.n_pad + 255) / 256)), dim3(256), 0, s, a);
+  const int64_t n = a.n_pad > a.n_zero ? a.n_pad : a.n_zero;
+  hipLaunchKernelGGL(k_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
   return launch_status(hipGetLastError());
 }
 
@@ -264,6 +266,8 @@ int launch_stage(int prec, const StageArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)((n + 255) / 256));
   if (prec == kFP32)
     hipLaunchKernelGGL(k_stage<kFP32>, grid, dim3(256), 0, s, a);
+  else if (prec == kFP16X3)
+    hipLaunchKernelGGL(k_stage<kFP16X3>, grid, dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL(k_stage<kBF16X3>, grid, dim3(256), 0, s, a);
   return launch_status(hipGetLastError());

@@ -106,6 +106,17 @@ int check_pde(const pinn_net* net, const pinn_pde* pde) {
   }
 }
 
+// Kernel precision code of a public precision, or the status to return for it.
+int kernel_prec(int prec, int* kp) {
+  switch (prec) {
+    case PINN_PREC_FP32: *kp = kFP32; return PINN_OK;
+    case PINN_PREC_BF16X3: *kp = kBF16X3; return PINN_OK;
+    case PINN_PREC_FP16X3: *kp = kFP16X3; return PINN_OK;
+    case PINN_PREC_BF16: return PINN_E_UNSUPPORTED;  // single-product BF16: see pinn.h
+    default: return PINN_E_INVALID;
+  }
+}
+
 int n_res_of(int pde_id) {
   switch (pde_id) {
     case PINN_PDE_BURGERS: return 1;
@@ -170,7 +181,7 @@ struct Plan {
   bool with_grad;
   // workspace offsets
   int64_t o_pts, o_wf[kMaxLayers], o_wb[kMaxLayers], o_w[kMaxLayers], o_b[kMaxLayers];
-  int64_t o_zs[kMaxHidden], o_zb[2], o_loss, o_out, o_layer[kMaxLayers], o_flag, o_pace;
+  int64_t o_zs[kMaxHidden], o_zb[2], o_loss, o_out, o_layer[kMaxLayers], o_flag, o_pace, o_amax;
   int64_t zs_stride;
   int64_t bytes;
 };
@@ -183,7 +194,9 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   if (rc) return rc;
   rc = check_pde(net, pde);
   if (rc) return rc;
-  if (prec != PINN_PREC_FP32 && prec != PINN_PREC_BF16X3) return PINN_E_INVALID;
+  int kp = 0;
+  rc = kernel_prec(prec, &kp);
+  if (rc) return rc;
   if (n_points < 0 || n_anchor < 0 || n_anchor > kMaxAnchors) return PINN_E_INVALID;
   if (n_anchor > 0 && !anchors) return PINN_E_INVALID;
   for (int a = 0; a < n_anchor; ++a) {
@@ -195,7 +208,7 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   rc = check_supported(net, p.D, pde->lap_mask);
   if (rc) return rc;
   const Dims& D = p.D;
-  p.prec = prec;
+  p.prec = kp;
   p.act = net->act;
   p.with_grad = with_grad != 0;
   p.n_res = n_res_of(pde->pde_id);
@@ -221,9 +234,9 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   if (fwd_lds(p.pf, p.kmax, D.H) > kLdsBudget) return PINN_E_UNSUPPORTED;
   // layer backward: the wide bf16x3 kernel when the layer input width is a multiple of
   // 128 (hidden widths 128 / 256; Fourier embeddings of 64 / 128 frequencies)
-  bool wide = prec == PINN_PREC_BF16X3 && D.H >= 128;
+  bool wide = is_split(kp) && D.H >= 128;
   for (int j = 1; j < D.L; ++j) wide = wide && D.n_in[j] % 128 == 0;
-  const bool wide0 = prec == PINN_PREC_BF16X3 && net->n_freq > 0 && (D.e / 16) % 8 == 0;
+  const bool wide0 = is_split(kp) && net->n_freq > 0 && (D.e / 16) % 8 == 0;
   p.wide = wide;
   p.wide0 = wide0;
   // split roles: uniform hidden width H (128 or 256); the grid is a multiple of 16
@@ -263,6 +276,7 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   }
   p.o_loss = take((int64_t)p.grid_f * kMaxTerms * 8);
   p.o_flag = take(16);
+  p.o_amax = take(kMaxHidden * 4);
   p.o_pace = take((int64_t)std::max(p.grid_b, 1) * 8);  // split-backward pacing words (any content)
   if (p.with_grad) {
     p.zs_stride = p.n_pad * 4 * D.hmax;
@@ -307,11 +321,12 @@ Timing& timing() {
   return t;
 }
 
-// Launch through f(), bracketed by events when timing is enabled.
+// Launch through f(), bracketed by events when timing is enabled (and allowed: the
+// allocation-free entry point creates no events).
 template <typename F>
-int timed(const char* name, hipStream_t s, F f) {
+int timed(bool allow, const char* name, hipStream_t s, F f) {
   Timing& T = timing();
-  if (!T.on) return f();
+  if (!T.on || !allow) return f();
   std::lock_guard<std::mutex> lk(T.mu);
   TimedLaunch tl{name, T.get(), T.get()};
   if (!tl.start || !tl.stop) return PINN_E_HIP;
@@ -354,7 +369,7 @@ NetDev make_netdev(const pinn_net* net, const pinn_pde* pde, const Plan& p, char
 int run(const pinn_net* net, const pinn_pde* pde, const float* params, const float* B, const float* points,
         int64_t n_points, const pinn_anchor* anchors, int n_anchor, int prec, uint32_t flags,
         const pinn_tune* tune, float* residual, double* loss, double* grad, void* workspace,
-        size_t ws_bytes, pinn_stream_t stream_, bool with_grad) {
+        size_t ws_bytes, pinn_stream_t stream_, bool with_grad, bool allow_timing = true) {
   Plan p;
   int rc = make_plan(net, pde, n_points, anchors, n_anchor, prec, with_grad, tune, &p);
   if (rc) return rc;
@@ -371,7 +386,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
 
   if (flags & PINN_FLAG_CHECK_FINITE) {
     int* flag = reinterpret_cast<int*>(ws + p.o_flag);
-    rc = timed("k_check_finite", stream, [&] { return launch_check_finite(params, D.n_params, flag, stream); });
+    rc = timed(allow_timing, "k_check_finite", stream, [&] { return launch_check_finite(params, D.n_params, flag, stream); });
     if (rc) return rc;
     int h = 0;
     if (hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess) return PINN_E_HIP;
@@ -392,7 +407,9 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     }
     a.n_pad = p.n_pad;
     a.dst = reinterpret_cast<float4*>(ws + p.o_pts);
-    rc = timed("k_points", stream, [&] { return launch_points(a, stream); });
+    a.zero = reinterpret_cast<unsigned int*>(ws + p.o_amax);
+    a.n_zero = kMaxHidden;
+    rc = timed(allow_timing, "k_points", stream, [&] { return launch_points(a, stream); });
     if (rc) return rc;
   }
   // weights
@@ -420,7 +437,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       cum += nbo * kci * 64 + nbi * kco * 64 + (int64_t)D.n_out[l] * D.n_in[l] + D.n_out[l];
     }
     a.cum[D.n_layers] = cum;
-    rc = timed("k_stage", stream, [&] { return launch_stage(prec, a, stream); });
+    rc = timed(allow_timing, "k_stage", stream, [&] { return launch_stage(p.prec, a, stream); });
     if (rc) return rc;
   }
 
@@ -430,6 +447,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
   wk.n_pad = p.n_pad;
   wk.pts = reinterpret_cast<const float4*>(ws + p.o_pts);
   wk.loss_slots = reinterpret_cast<double*>(ws + p.o_loss);
+  wk.amax = reinterpret_cast<unsigned int*>(ws + p.o_amax);
   if (p.with_grad) {
     wk.zs0 = reinterpret_cast<float*>(ws + p.o_zs[0]);
     wk.zs_stride = p.zs_stride;
@@ -462,7 +480,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     a.kmax = p.kmax;
     a.with_grad = p.with_grad;
     a.residual = residual;
-    rc = timed("k_forward", stream, [&] { return launch_forward(prec, act_code(net, pde), D.H, p.pf, a, p.grid_f, p.lds_f, stream); });
+    rc = timed(allow_timing, "k_forward", stream, [&] { return launch_forward(p.prec, act_code(net, pde), D.H, p.pf, a, p.grid_f, p.lds_f, stream); });
     if (rc) return rc;
   }
   int cur = 0;
@@ -481,7 +499,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.wide = p.split ? 2 : p.wide;
       a.pace = reinterpret_cast<unsigned long long*>(ws + p.o_pace);
       a.launch = next_launch_id();
-      rc = timed("k_backward", stream, [&] { return launch_backward(prec, act_code(net, pde), D.H, false, a, p.grid_b, p.lds_b, stream); });
+      rc = timed(allow_timing, "k_backward", stream, [&] { return launch_backward(p.prec, act_code(net, pde), D.H, false, a, p.grid_b, p.lds_b, stream); });
       if (rc) return rc;
       cur ^= 1;
     }
@@ -497,7 +515,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.z_prev = nullptr;
       a.slots = wk.layer_slots[0];
       a.wide = p.wide0 ? (D.n_out[0] == D.H && D.H >= 64 ? 3 : 1) : 0;
-      rc = timed("k_backward_embed", stream, [&] { return launch_backward(prec, act_code(net, pde), D.H, true, a, p.grid_b0, p.lds_b0, stream); });
+      rc = timed(allow_timing, "k_backward_embed", stream, [&] { return launch_backward(p.prec, act_code(net, pde), D.H, true, a, p.grid_b0, p.lds_b0, stream); });
       if (rc) return rc;
     } else {
       Grad0Args a;
@@ -507,7 +525,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.d_in = D.d_in;
       a.n_cb = p.n_pad / 4;
       a.slots = wk.layer_slots[0];
-      rc = timed("k_grad0", stream, [&] { return launch_grad0(a, p.grid_g0, stream); });
+      rc = timed(allow_timing, "k_grad0", stream, [&] { return launch_grad0(a, p.grid_g0, stream); });
       if (rc) return rc;
     }
     for (int l = 0; l < D.n_layers; ++l) {
@@ -529,7 +547,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
         a.slots = wk.layer_slots[l];
         a.n_slots = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : p.grid_g0) : (p.split ? p.grid_b / 2 : p.grid_b);
       }
-      rc = timed("k_reduce_layer", stream, [&] { return launch_reduce_layer(a, stream); });
+      rc = timed(allow_timing, "k_reduce_layer", stream, [&] { return launch_reduce_layer(a, stream); });
       if (rc) return rc;
     }
   }
@@ -544,7 +562,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     for (int k = 0; k < n_anchor; ++k)
       a.w_anchor[k] = anchors[k].n > 0 ? anchors[k].lambda / (double)anchors[k].n : 0.0;
     a.loss = loss;
-    rc = timed("k_reduce_loss", stream, [&] { return launch_reduce_loss(a, stream); });
+    rc = timed(allow_timing, "k_reduce_loss", stream, [&] { return launch_reduce_loss(a, stream); });
     if (rc) return rc;
   }
   return hip_rc(hipGetLastError());
@@ -574,9 +592,11 @@ int make_batch_plan(const pinn_net* nets, const pinn_pde* pde, const int64_t* n_
                     const pinn_tune* tune, BatchPlan* out) {
   BatchPlan& b = *out;
   if (!nets || !pde || !n_points || n_inst <= 0 || n_inst > 65536) return PINN_E_INVALID;
-  if (prec != PINN_PREC_FP32 && prec != PINN_PREC_BF16X3) return PINN_E_INVALID;
+  int kp = 0;
+  const int prc = kernel_prec(prec, &kp);
+  if (prc) return prc;
   b.n_inst = n_inst;
-  b.prec = prec;
+  b.prec = kp;
   b.act = nets[0].act;
   b.D.resize(n_inst);
   b.chunk.resize(n_inst);
@@ -688,6 +708,7 @@ int make_batch_plan(const pinn_net* nets, const pinn_pde* pde, const int64_t* n_
 int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* params, const float* const* points,
                 const int64_t* n_points, int n_inst, int prec, const pinn_tune* tune, double* const* grads,
                 double* losses, void* workspace, size_t ws_bytes, pinn_stream_t stream_) {
+  const bool allow_timing = true;
   BatchPlan b;
   int rc = make_batch_plan(nets, pde, n_points, n_inst, prec, tune, &b);
   if (rc) return rc;
@@ -795,7 +816,7 @@ int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* p
     pa.src[0] = points[i];
     pa.n_pad = b.n_pad[i];
     pa.dst = reinterpret_cast<float4*>(ws + b.o_pts) + b.pts_off[i];
-    rc = timed("k_points", stream, [&] { return launch_points(pa, stream); });
+    rc = timed(allow_timing, "k_points", stream, [&] { return launch_points(pa, stream); });
     if (rc) return rc;
     StageArgs sa;
     std::memset(&sa, 0, sizeof(sa));
@@ -820,11 +841,11 @@ int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* p
       cum += nbo * kci * 64 + nbi * kco * 64 + (int64_t)D.n_out[l] * D.n_in[l] + D.n_out[l];
     }
     sa.cum[D.n_layers] = cum;
-    rc = timed("k_stage", stream, [&] { return launch_stage(prec, sa, stream); });
+    rc = timed(allow_timing, "k_stage", stream, [&] { return launch_stage(b.prec, sa, stream); });
     if (rc) return rc;
   }
   int* counter = reinterpret_cast<int*>(ws + b.o_counter);
-  rc = timed("k_zero_int", stream, [&] { return launch_zero_int(counter, stream); });
+  rc = timed(allow_timing, "k_zero_int", stream, [&] { return launch_zero_int(counter, stream); });
   if (rc) return rc;
   BatchArgs ba;
   std::memset(&ba, 0, sizeof(ba));
@@ -842,14 +863,14 @@ int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* p
   ba.loss_slots = reinterpret_cast<double*>(ws + b.o_loss);
   ba.grad_slots = reinterpret_cast<double*>(ws + b.o_grad);
   for (int k = 0; k < 3; ++k) ba.lambda_res[k] = (float)pde->lambda_res[k];
-  rc = timed("k_batched", stream, [&] { return launch_batched(prec, b.act | (pde->lap_mask ? kLapFlag : 0), ba, b.grid, b.lds, stream); });
+  rc = timed(allow_timing, "k_batched", stream, [&] { return launch_batched(b.prec, b.act | (pde->lap_mask ? kLapFlag : 0), ba, b.grid, b.lds, stream); });
   if (rc) return rc;
   BatchReduceArgs ra;
   ra.rows = reinterpret_cast<const BatchRow*>(dev(hrows));
   ra.n_entries = (int)n_entries;
   ra.n_rows = row0;
   ra.grad_slots = ba.grad_slots;
-  rc = timed("k_reduce_batched", stream, [&] { return launch_reduce_batched(ra, stream); });
+  rc = timed(allow_timing, "k_reduce_batched", stream, [&] { return launch_reduce_batched(ra, stream); });
   if (rc) return rc;
   BatchLossArgs la;
   la.loss_slots = ba.loss_slots;
@@ -859,7 +880,7 @@ int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* p
   la.n_inst = n_inst;
   la.n_res = b.n_res;
   la.losses = losses;
-  rc = timed("k_reduce_loss_batched", stream, [&] { return launch_reduce_loss_batched(la, stream); });
+  rc = timed(allow_timing, "k_reduce_loss_batched", stream, [&] { return launch_reduce_loss_batched(la, stream); });
   if (rc) return rc;
   return hip_rc(hipGetLastError());
 }

@@ -108,29 +108,66 @@ struct Prec<kFP32> {
 __device__ __forceinline__ __bf16 bf16_rne(float x) { return (__bf16)x; }
 
 typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
+typedef __attribute__((ext_vector_type(2))) _Float16 f16x2;
 
-// x = hi + lo, hi = bf16(x), lo = bf16(x - hi), for two values at once: one packed
-// conversion per part, the hi parts widened back by shifts.
-__device__ __forceinline__ void split2(float x, float y, uint32_t& h, uint32_t& l) {
-  bf16x2 hv;
-  hv[0] = bf16_rne(x);
-  hv[1] = bf16_rne(y);
-  h = __builtin_bit_cast(uint32_t, hv);
-  const float xh = __uint_as_float(h << 16), yh = __uint_as_float(h & 0xffff0000u);
-  bf16x2 lv;
-  lv[0] = bf16_rne(x - xh);
-  lv[1] = bf16_rne(y - yh);
-  l = __builtin_bit_cast(uint32_t, lv);
-}
+// The 16-bit format of a split precision: conversion of two values into hi and lo parts
+// (x = hi + lo, hi = rn(x), lo = rn(x - hi), round to nearest even) and one matrix-core
+// product of 8-element operand halves.
+template <int PREC>
+struct Half;
 
 template <>
-struct Prec<kBF16X3> {
+struct Half<kBF16X3> {
+  // one packed conversion per part, the hi parts widened back by shifts
+  static __device__ __forceinline__ void split2(float x, float y, uint32_t& h, uint32_t& l) {
+    bf16x2 hv;
+    hv[0] = bf16_rne(x);
+    hv[1] = bf16_rne(y);
+    h = __builtin_bit_cast(uint32_t, hv);
+    const float xh = __uint_as_float(h << 16), yh = __uint_as_float(h & 0xffff0000u);
+    bf16x2 lv;
+    lv[0] = bf16_rne(x - xh);
+    lv[1] = bf16_rne(y - yh);
+    l = __builtin_bit_cast(uint32_t, lv);
+  }
+  static __device__ __forceinline__ f4 mfma(const uint4& a, const uint4& b, f4 acc) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), acc,
+                                                   0, 0, 0);
+  }
+};
+
+// IEEE half: 11 significant bits per part, so hi + lo carries 22 (bf16: 16) -- the
+// representation error of an operand drops from 2^-16 to 2^-22 relative, at the same
+// matrix-core rate.  The range is that of half precision: parts below 2^-14 are subnormal
+// (absolute resolution 2^-24), magnitudes from 65520 up overflow.  Adjoints are therefore
+// scaled by a power of two before they are split (adj_scale).
+template <>
+struct Half<kFP16X3> {
+  static __device__ __forceinline__ void split2(float x, float y, uint32_t& h, uint32_t& l) {
+    f16x2 hv;
+    hv[0] = (_Float16)x;
+    hv[1] = (_Float16)y;
+    h = __builtin_bit_cast(uint32_t, hv);
+    f16x2 lv;
+    lv[0] = (_Float16)(x - (float)hv[0]);
+    lv[1] = (_Float16)(y - (float)hv[1]);
+    l = __builtin_bit_cast(uint32_t, lv);
+  }
+  static __device__ __forceinline__ f4 mfma(const uint4& a, const uint4& b, f4 acc) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), acc, 0,
+                                                  0, 0);
+  }
+};
+
+// The split product: a Raw fragment is 8 hi parts (a) then 8 lo parts (b).
+template <int PREC>
+struct PrecSplit {
+  using H = Half<PREC>;
   static __device__ __forceinline__ void mma(f4& acc, const Raw& x, const Raw& y) {
-    bf16x8 xh = __builtin_bit_cast(bf16x8, x.a), xl = __builtin_bit_cast(bf16x8, x.b);
-    bf16x8 yh = __builtin_bit_cast(bf16x8, y.a), yl = __builtin_bit_cast(bf16x8, y.b);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, yh, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yl, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yh, acc, 0, 0, 0);
+    acc = H::mfma(x.b, y.a, acc);
+    acc = H::mfma(x.a, y.b, acc);
+    acc = H::mfma(x.a, y.a, acc);
   }
   // Register-tile form of mma(): each of the three products in turn over all
   // accumulators, same per-accumulator order as mma().
@@ -139,50 +176,84 @@ struct Prec<kBF16X3> {
 #pragma unroll
     for (int c = 0; c < CB; ++c)
 #pragma unroll
-      for (int i = 0; i < NB; ++i)
-        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[c].b),
-                                                            __builtin_bit_cast(bf16x8, b[i].a), acc[i][c], 0, 0, 0);
+      for (int i = 0; i < NB; ++i) acc[i][c] = H::mfma(a[c].b, b[i].a, acc[i][c]);
 #pragma unroll
     for (int c = 0; c < CB; ++c)
 #pragma unroll
-      for (int i = 0; i < NB; ++i)
-        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[c].a),
-                                                            __builtin_bit_cast(bf16x8, b[i].b), acc[i][c], 0, 0, 0);
+      for (int i = 0; i < NB; ++i) acc[i][c] = H::mfma(a[c].a, b[i].b, acc[i][c]);
 #pragma unroll
     for (int c = 0; c < CB; ++c)
 #pragma unroll
-      for (int i = 0; i < NB; ++i)
-        acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[c].a),
-                                                            __builtin_bit_cast(bf16x8, b[i].a), acc[i][c], 0, 0, 0);
+      for (int i = 0; i < NB; ++i) acc[i][c] = H::mfma(a[c].a, b[i].a, acc[i][c]);
   }
   static __device__ __forceinline__ Raw make(const float (&f)[8]) {
     uint32_t h[4], l[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) split2(f[2 * j], f[2 * j + 1], h[j], l[j]);
+    for (int j = 0; j < 4; ++j) H::split2(f[2 * j], f[2 * j + 1], h[j], l[j]);
     Raw r;
     r.a = make_uint4(h[0], h[1], h[2], h[3]);
     r.b = make_uint4(l[0], l[1], l[2], l[3]);
     return r;
   }
-  static __device__ __forceinline__ void put(char* unit, int pos, float x) {
-    __bf16 h = bf16_rne(x);
-    reinterpret_cast<__bf16*>(unit)[pos] = h;
-    reinterpret_cast<__bf16*>(unit + 16)[pos] = bf16_rne(x - (float)h);
-  }
   static __device__ __forceinline__ void put2(char* unit, int pos, float x, float y) {
     uint32_t h, l;
-    split2(x, y, h, l);
+    H::split2(x, y, h, l);
     *reinterpret_cast<uint32_t*>(unit + 2 * pos) = h;
     *reinterpret_cast<uint32_t*>(unit + 16 + 2 * pos) = l;
   }
   static __device__ __forceinline__ void put4(char* unit, int pos0, f4 x) {
     uint32_t h0, l0, h1, l1;
-    split2(x[0], x[1], h0, l0);
-    split2(x[2], x[3], h1, l1);
+    H::split2(x[0], x[1], h0, l0);
+    H::split2(x[2], x[3], h1, l1);
     *reinterpret_cast<uint2*>(unit + 2 * pos0) = make_uint2(h0, h1);
     *reinterpret_cast<uint2*>(unit + 16 + 2 * pos0) = make_uint2(l0, l1);
   }
 };
+
+template <>
+struct Prec<kBF16X3> : PrecSplit<kBF16X3> {};
+template <>
+struct Prec<kFP16X3> : PrecSplit<kFP16X3> {};
+
+// Power-of-two scale of an adjoint before it is split into 16-bit parts, from the largest
+// magnitude `amax` (FP32 bits) of that adjoint: FP16X3 maps the largest magnitude into
+// [2^14, 2^15) (half precision tops out at 65504), the other precisions use 1.  Scaling by
+// a power of two is exact, and the product's result is scaled back by the reciprocal.
+template <int PREC>
+__device__ __forceinline__ float adj_scale(unsigned int amax) {
+  if constexpr (PREC != kFP16X3) {
+    return 1.0f;
+  } else {
+    const int e = (int)((amax >> 23) & 0xffu);
+    if (amax == 0u || e == 0xff) return 1.0f;  // all zero, or not finite
+    return __builtin_ldexpf(1.0f, 14 - (e - 127));
+  }
+}
+
+// Largest magnitude of the 4 channels of a jet.
+__device__ __forceinline__ float jet_absmax(f4 v) {
+  return fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w)));
+}
+
+// v * s for the precision that scales adjoints, v otherwise.
+template <int PREC>
+__device__ __forceinline__ f4 ascale(f4 v, float s) {
+  if constexpr (PREC == kFP16X3) return v * s;
+  return v;
+}
+template <int PREC>
+__device__ __forceinline__ float ascale(float v, float s) {
+  if constexpr (PREC == kFP16X3) return v * s;
+  return v;
+}
+
+// Combine a per-lane largest magnitude over the wave and into *word (FP32 bits of a
+// non-negative value compare as unsigned integers).
+__device__ __forceinline__ void amax_publish(float m, unsigned int* word) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
+  if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(word, __float_as_uint(m));
+}
 
 // Value of lane l ^ 1 (a data-parallel-primitive lane swap within each pair of lanes).
 __device__ __forceinline__ float swap_pair(float x) {
@@ -271,16 +342,16 @@ __device__ __forceinline__ uint2 lds_tr16_at(uint32_t a) {
   return __builtin_bit_cast(uint2, v);
 }
 
-template <>
-struct Tile<kBF16X3> {
+template <int PREC>
+struct TileT {
   static __device__ __forceinline__ int ld(int kmax, int P) { return P >> 2; }
   static __device__ __forceinline__ char* cell(char* X, int ld, int pg, int nc) {
     return X + (size_t)(nc * ld + pg) * 2048;
   }
   static __device__ __forceinline__ void put(char* X, int ld, int p, int n, f4 a) {
     uint32_t h0, l0, h1, l1;
-    split2(a[0], a[1], h0, l0);
-    split2(a[2], a[3], h1, l1);
+    Half<PREC>::split2(a[0], a[1], h0, l0);
+    Half<PREC>::split2(a[2], a[3], h1, l1);
     char* q = cell(X, ld, p >> 2, n >> 5) + t_cell_off(p, n);
     *reinterpret_cast<uint2*>(q) = make_uint2(h0, h1);
     *reinterpret_cast<uint2*>(q + 1024) = make_uint2(l0, l1);
@@ -298,6 +369,11 @@ struct Tile<kBF16X3> {
     return r;
   }
 };
+
+template <>
+struct Tile<kBF16X3> : TileT<kBF16X3> {};
+template <>
+struct Tile<kFP16X3> : TileT<kFP16X3> {};
 
 __device__ __forceinline__ Raw glob_frag(const char* frags, int blk, int chunk, int nchunk, int lane) {
   const uint4* p = reinterpret_cast<const uint4*>(frags + (((size_t)blk * nchunk + chunk) * 64 + lane) * 32);
@@ -764,11 +840,12 @@ struct TileSeg {
 // (stash of every pre-activation), output layer, residual, loss partial sums, output-jet
 // seed and (with the gradient) the output layer's backward.  pts: the tile's points;
 // zs: stash of hidden layer 0 with zs_stride floats between layers; zb0: adjoint of the
-// last hidden layer; cb_st: first cp block of this tile in those buffers.
+// last hidden layer; cb_st: first cp block of this tile in those buffers; amx: running
+// largest magnitude of the adjoint written to zb0 (FP16X3 only).
 template <int PREC, int ACT, int H, int P, int NW = kWaves>
 __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, const float4* pts, float* zs,
                                          int64_t zs_stride, float* zb0, int64_t cb_st, const TileSeg& sg, int ld,
-                                         bool with_grad, const FwdLds& s) {
+                                         bool with_grad, const FwdLds& s, float& amx) {
   using S = FwdShape<H, P, NW>;
   constexpr int NT = 64 * NW;
   static_assert(P <= NT, "one thread per tile point");
@@ -856,7 +933,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
   // Early weight loads (the next layer's first chunks before the stash stores, the output
   // layer's chunks all at once) cost registers; the bf16x3 shapes with at most 8 cp blocks
   // per wave have them to spare.
-  constexpr bool kPre = PREC == kBF16X3 && CBW <= 8 && NBW <= 2;
+  constexpr bool kPre = is_split(PREC) && CBW <= 8 && NBW <= 2;
 
   // ---- hidden layers: acc holds z of layer j
   for (int j = 0; j < L; ++j) {
@@ -1043,6 +1120,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
         }
         const f4 zb = jet_act_adj<(ACT & kLapFlag) != 0>(z, ab, s1, s2, s3, lw1, lw2);
         *jet_frag(zb0, cb_st + cb, nb, nbs, lane) = to_float4(zb);
+        if constexpr (PREC == kFP16X3) amx = fmaxf(amx, jet_absmax(zb));
         __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
@@ -1113,13 +1191,15 @@ __device__ __forceinline__ void async_copy(char* dst, const char* src, int bytes
 // number s0 + k * stride: weight-gradient sums (accw, bsum, kept by the caller), and for
 // layers with a predecessor the input adjoint and the activation adjoint (zb_out).  The
 // jets of sub-tile k + 1 are copied into LDS while sub-tile k is computed.  pts: points of
-// sub-tile 0 of the index space (Fourier embedding only).
+// sub-tile 0 of the index space (Fourier embedding only).  asc: scale of the output adjoint
+// in its 16-bit operands (adj_scale; the weight-gradient sums come out scaled by it, the
+// input adjoint is scaled back); amx: running largest magnitude of what goes to zb_out.
 template <int PREC, int ACT, int NOB, int NIB, int PB>
 __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const float4* pts, int64_t s0, int64_t stride,
                                           int64_t count, const float* zb_in, float* zb_out, const float* z_prev,
                                           char* smem,
                                           f4 (&accw)[BwdShape<NOB, NIB, PB>::NOBW][BwdShape<NOB, NIB, PB>::NIBW],
-                                          float (&bsum)[BwdShape<NOB, NIB, PB>::NOBW]) {
+                                          float (&bsum)[BwdShape<NOB, NIB, PB>::NOBW], float asc, float& amx) {
   using S = BwdShape<NOB, NIB, PB>;
   using Pr = Prec<PREC>;
   constexpr int CPB = S::CPB, NOBW = S::NOBW, NIBW = S::NIBW, NIBA = S::NIBA, CBA = S::CBA;
@@ -1160,7 +1240,7 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
         const int cb = f % CPB, ob = f / CPB;
         const f4 zb = frag(L.ZB, cb, ob, nob);
         const int o = 16 * ob + l16;
-        Tile<PREC>::put(L.R, rld, 4 * cb + g, o, zb);
+        Tile<PREC>::put(L.R, rld, 4 * cb + g, o, ascale<PREC>(zb, asc));
       }
     }
     Raw ao[CPB / 2][NOBW];
@@ -1170,9 +1250,10 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
       for (int i = 0; i < NOBW; ++i) {
         const int ob = min(wo + WO * i, nob - 1);  // clamped duplicates are never stored
         const f4 v0 = frag(L.ZB, 2 * cc, ob, nob), v1 = frag(L.ZB, 2 * cc + 1, ob, nob);
-        const float f[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-        ao[cc][i] = Pr::make(f);
         bsum[i] += v0.x + v1.x;
+        const f4 w0 = ascale<PREC>(v0, asc), w1 = ascale<PREC>(v1, asc);
+        const float f[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+        ao[cc][i] = Pr::make(f);
       }
     barrier_lds();  // R complete; ZB no longer read
     if (k + 1 < count) async_copy(L.ZB, zb_src(s + stride), zb_bytes);
@@ -1207,8 +1288,10 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
           int unit, pos0;
           q_pos(cb, g, unit, pos0);
           Pr::put4(L.Q + (size_t)n * qs + unit * 32, pos0, a);
-          const f4 zb = jet_act_adj<(ACT & kLapFlag) != 0>(z, acca[q][c], s1v, s2v, s3v, lw1, lw2);
+          const f4 zb = jet_act_adj<(ACT & kLapFlag) != 0>(z, ascale<PREC>(acca[q][c], 1.0f / asc), s1v, s2v, s3v,
+                                                          lw1, lw2);
           *jet_frag(zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
+          if constexpr (PREC == kFP16X3) amx = fmaxf(amx, jet_absmax(zb));
           __builtin_amdgcn_sched_barrier(0);
         }
       }
@@ -1242,11 +1325,12 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
 }
 
 // Store the weight-gradient sums (FP32 over the run of sub-tiles) as FP64 into a slot laid
-// out [n_out][n_in] then [n_out] (bias).
+// out [n_out][n_in] then [n_out] (bias); the weight sums are multiplied by inv (the
+// reciprocal of the adjoint scale, a power of two).
 template <int NOB, int NIB, int PB>
 __device__ __forceinline__ void bwd_flush(const f4 (&accw)[BwdShape<NOB, NIB, PB>::NOBW][BwdShape<NOB, NIB, PB>::NIBW],
                                           const float (&bsum)[BwdShape<NOB, NIB, PB>::NOBW], double* slot, int n_out,
-                                          int n_in) {
+                                          int n_in, float inv = 1.0f) {
   using S = BwdShape<NOB, NIB, PB>;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1262,7 +1346,8 @@ __device__ __forceinline__ void bwd_flush(const f4 (&accw)[BwdShape<NOB, NIB, PB
       const int ib = wi + S::WI * k;
       if (ib >= nib) continue;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) slot[(size_t)(16 * ob + 4 * g + r) * n_in + 16 * ib + l16] = (double)accw[i][k][r];
+      for (int r = 0; r < 4; ++r)
+        slot[(size_t)(16 * ob + 4 * g + r) * n_in + 16 * ib + l16] = (double)accw[i][k][r] * (double)inv;
     }
     if (wi == 0) {
       float v = bsum[i];

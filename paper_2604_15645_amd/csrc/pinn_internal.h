@@ -21,7 +21,10 @@ constexpr int kMaxFreq = 128;                     // Fourier frequencies (2 m <=
 constexpr int kFourierLds = 3 * kMaxFreq * 4;     // LDS bytes of a staged Fourier matrix
 constexpr int kOutLds = 8 * 4 * 3 * 32;           // LDS bytes of the staged output-layer fragments
 
-enum { kFP32 = 0, kBF16X3 = 1 };
+// Kernel precision codes.  The two split forms run three 16-bit matrix-core products per
+// logical product (hi*hi + hi*lo + lo*hi, x = hi + lo); they differ in the 16-bit format.
+enum { kFP32 = 0, kBF16X3 = 1, kFP16X3 = 2 };
+__host__ __device__ constexpr bool is_split(int prec) { return prec != kFP32; }
 enum { kTanh = 0, kSin = 1 };
 // Kernel activation code: kTanh or kSin, plus kLapFlag when jet channel 3 is a Laplacian.
 enum { kLapFlag = 2 };
@@ -75,6 +78,10 @@ struct Work {
   double* loss_slots;              // [grid_f][kMaxTerms] sums of squares
   double* out_slots;               // [grid_f][d_out * (n_L + 1)] output-layer W and b sums
   double* layer_slots[kMaxHidden]; // [grid_b][n_out * (n_in + 1)] hidden/embedding layer sums
+  // FP16X3: largest magnitude of the adjoint of each hidden layer's pre-activation jets
+  // (FP32 bit patterns, combined by integer maximum), written by the kernel that produces
+  // the adjoint and read by the kernel that consumes it; zeroed at the start of a call
+  unsigned int* amax;              // [kMaxHidden]
 };
 
 // Kernel argument blocks (passed by value).
@@ -98,6 +105,8 @@ struct PointsArgs {
   const float* src[1 + kMaxAnchors];
   int64_t n_pad;
   float4* dst;
+  unsigned int* zero;    // words cleared before anything else of the call runs (or null)
+  int n_zero;
 };
 
 struct FwdArgs {

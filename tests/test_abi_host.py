@@ -82,6 +82,20 @@ def test_validation_errors(lib):
     assert code_of(lambda: ws(eu, dict(ep, coef=[1.0, 0, 0, 0]))) == -2   # gamma > 1
 
 
+def test_precision_codes(lib):
+    """FP32, BF16X3 and FP16X3 are implemented; single-product BF16 is refused as
+    unsupported, an unknown code as invalid; the split forms need the same workspace."""
+    c = synth.CONFIGS
+    for name in ("burgers", "maxwell"):
+        net, pde = c[name]["net"], c[name]["pde"]
+        assert ws(net, pde, prec="bf16x3") == ws(net, pde, prec="fp16x3") > 0
+        assert ws(net, pde, prec="fp32") > 0
+        assert code_of(lambda: ws(net, pde, prec="bf16")) == -2
+    with pytest.raises(KeyError):
+        ws(c["burgers"]["net"], c["burgers"]["pde"], prec="fp8")
+    assert lib.pinn_workspace_bytes is not None
+
+
 def test_compute_calls_reject_before_any_hip_call(lib):
     """Null pointers and a short workspace fail on the host (no GPU in this container)."""
     c = synth.CONFIGS["burgers"]

@@ -39,15 +39,18 @@ def to_dev(insts, dev):
     return params, pts
 
 
-# bf16x3 on the sweep networks: the split represents each operand to about 2^-18 relative,
-# so jets carry ~1e-5 error; residuals that cancel strongly (|r| much smaller than |u_t|,
-# |u u_x|) amplify it, and a NumPy emulation of the same products reaches 1.6e-4 on such
-# draws.  The 1e-4 gate holds on the four benchmark networks; here the measured bound is
-# asserted, and FP32 must meet its 1e-5 gate on every network.
-SWEEP_TOL = {"fp32": 1e-5, "bf16x3": 5e-4}
+# BF16X3 represents each operand to about 2^-16 (hi + lo hold 16 significant bits), so the
+# jets carry errors of a few 1e-5; where a network's residual is several times smaller than
+# the terms it is formed from (|r| << |u_t|, |u u_x|) that error is amplified by the ratio.
+# A NumPy emulation of the same products (no kernel involved) reaches 1.6e-4 on the
+# residual of one of these draws (a 4 x 128 network whose terms are 5.6 times its residual).
+# The split with IEEE half parts (FP16X3, 22 significant bits, the same three products at
+# the same matrix-core rate) meets the 1e-4 gate on every network; BF16X3 is held to the
+# bound its representation allows on this sample; FP32 to its 1e-5 gate.
+SWEEP_TOL = {"fp32": 1e-5, "fp16x3": 1e-4, "bf16x3": 5e-4}
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
 def test_batched_matches_oracle(oracle, dev, prec):
     import torch
     from paper_2604_15645_amd import binding
@@ -69,7 +72,7 @@ def test_batched_matches_oracle(oracle, dev, prec):
     assert not bad, bad
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
 def test_batched_matches_single_calls(dev, prec):
     import torch
     from paper_2604_15645_amd import binding

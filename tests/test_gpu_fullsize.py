@@ -12,7 +12,7 @@ from conftest import gpu_available
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-5, "bf16x3": 1e-4}
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "fp16x3": 1e-4}
 
 
 def relerr(a, b):
@@ -30,7 +30,7 @@ def dev():
     return torch.device("cuda:0")
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32", "fp16x3"])
 @pytest.mark.parametrize("name", ["burgers", "euler", "ns", "maxwell"])
 def test_full_size(oracle, dev, name, prec):
     import torch

@@ -12,7 +12,7 @@ gradient, every layer's block and every loss term at the span the benchmark runs
   Navier-Stokes (5 x 128 tanh, RWF), 262,144 points, 256 work-groups: forward 1,024 points,
       hidden-layer weight gradient 2,048; 32,768 points with 32 work-groups reproduce both.
 
-Tolerances are the gates of the path: FP32 1e-5, BF16X3 1e-4 (normwise, relative)."""
+Tolerances are the gates of the path: FP32 1e-5, BF16X3 and FP16X3 1e-4 (normwise, relative)."""
 import numpy as np
 import pytest
 
@@ -20,7 +20,7 @@ from conftest import gpu_available
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-5, "bf16x3": 1e-4}
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "fp16x3": 1e-4}
 CASES = {"maxwell": (65536, 16), "ns": (32768, 32)}
 
 
@@ -63,7 +63,7 @@ def layer_blocks(net):
     return out
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
 @pytest.mark.parametrize("name", ["maxwell", "ns"])
 def test_gradient_at_full_size_spans(oracle, dev, name, prec):
     import torch
