@@ -170,6 +170,23 @@ int pinn_residual_bwd(const pinn_net* net, const pinn_pde* pde, const float* par
                       const pinn_tune* tune, float* residual, double* loss, double* grad,
                       void* workspace, size_t ws_bytes, pinn_stream_t stream);
 
+/* The fused step without a caller workspace, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation).  Arguments and results as pinn_residual_bwd.  The workspace is the
+ * library's own static device array of PINN_NOALLOC_MAX_BYTES, one per GPU, held until
+ * the process ends; this call allocates nothing.  A problem whose pinn_workspace_bytes(...,
+ * with_grad = 1, ...) exceeds that size is refused with PINN_E_WORKSPACE before any HIP
+ * call.  Every call on one GPU uses that GPU's array and leaves its contents behind (each
+ * call clears what it needs cleared): calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  The per-kernel timing record is
+ * not kept for these calls (it would create events). */
+#define PINN_NOALLOC_MAX_BYTES (64u << 20)
+int pinn_residual_bwd_noalloc(const pinn_net* net, const pinn_pde* pde, const float* params,
+                              const float* fourier_B, const float* points, int64_t n_points,
+                              const pinn_anchor* anchors, int n_anchor, int prec, uint32_t flags,
+                              const pinn_tune* tune, float* residual, double* loss, double* grad,
+                              pinn_stream_t stream);
+
 /* Many independent networks in one persistent launch (the paper's benchmark sweeps ran
  * each network separately).  Instance i has its own descriptor nets[i] (host array), the
  * shared PDE `pde`, its own params[i], points[i] (n_points[i] x d_in, device) and grads[i]

@@ -55,7 +55,8 @@ _lib = None
 
 # Symbols the header declares (checked by the CPU tests).
 EXPORTS = ["pinn_param_count", "pinn_n_residuals", "pinn_workspace_bytes", "pinn_residual_fwd",
-           "pinn_residual_bwd", "pinn_batched_workspace_bytes", "pinn_batched_bwd",
+           "pinn_residual_bwd", "pinn_residual_bwd_noalloc", "pinn_batched_workspace_bytes",
+           "pinn_batched_bwd",
            "pinn_timing_enable", "pinn_timing_collect", "pinn_status_string"]
 
 
@@ -81,6 +82,8 @@ def lib():
         L.pinn_residual_fwd.argtypes = common + [vp, ctypes.c_size_t, vp]
         L.pinn_residual_bwd.restype = ctypes.c_int
         L.pinn_residual_bwd.argtypes = common + [vp, vp, ctypes.c_size_t, vp]
+        L.pinn_residual_bwd_noalloc.restype = ctypes.c_int
+        L.pinn_residual_bwd_noalloc.argtypes = common + [vp, vp]
         L.pinn_batched_workspace_bytes.restype = ctypes.c_int
         L.pinn_batched_workspace_bytes.argtypes = [P(PinnNet), P(PinnPde), P(ctypes.c_int64), ctypes.c_int,
                                                    ctypes.c_int, P(PinnTune), P(ctypes.c_size_t)]
@@ -285,6 +288,49 @@ def residual_step(net_spec, pde_spec, params, B, points, anchors=(), prec="bf16x
     if rc != 0:
         raise PinnError(where, rc)
     return {"loss": loss, "grad": g if grad else None, "residual": res if residual else None}
+
+
+NOALLOC_MAX_BYTES = 64 << 20   # PINN_NOALLOC_MAX_BYTES
+
+
+def residual_step_noalloc(net_spec, pde_spec, params, B, points, anchors=(), prec="bf16x3",
+                          tune=None, flags=0, out=None):
+    """One call of pinn_residual_bwd_noalloc: the fused step on the library's own static
+    device scratch (no workspace).  Arguments and results as residual_step(grad=True,
+    residual=True); result tensors come from `out` when given."""
+    _check_dev(params, "params")
+    _check_dev(points, "points")
+    if B is not None:
+        _check_dev(B, "fourier_B")
+    for a in anchors:
+        _check_dev(a["points"], "anchor points")
+        _check_dev(a["targets"], "anchor targets")
+    _check_shapes(net_spec, params, B, points, anchors)
+    dev = points.device
+    n, p = net_struct(net_spec), pde_struct(pde_spec)
+    arr = _anchor_array(anchors)
+    t = tune_struct(tune)
+    tref = ctypes.byref(t) if t is not None else None
+    npts = int(points.shape[0])
+    nres = n_residuals(pde_spec["pde"])
+    out = out or {}
+    loss = out.get("loss")
+    if loss is None:
+        loss = torch.empty(1 + nres + len(anchors), dtype=torch.float64, device=dev)
+    res = out.get("residual")
+    if res is None:
+        res = torch.empty((npts, nres), dtype=torch.float32, device=dev)
+    g = out.get("grad")
+    if g is None:
+        g = torch.empty(param_count(net_spec), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = lib().pinn_residual_bwd_noalloc(ctypes.byref(n), ctypes.byref(p), params.data_ptr(),
+                                         B.data_ptr() if B is not None else None, points.data_ptr(),
+                                         npts, arr, len(anchors), PRECS[prec], int(flags), tref,
+                                         res.data_ptr(), loss.data_ptr(), g.data_ptr(), stream)
+    if rc != 0:
+        raise PinnError("pinn_residual_bwd_noalloc", rc)
+    return {"loss": loss, "grad": g, "residual": res}
 
 
 def timing_enable(on=True):

@@ -18,7 +18,7 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
 ]
-SOURCES = ["k_forward.hip", "k_backward.hip", "k_batched.hip", "k_misc.hip", "pinn_api.cpp"]
+SOURCES = ["k_forward.hip", "k_backward.hip", "k_batched.hip", "k_misc.hip", "pinn_noalloc.hip", "pinn_api.cpp"]
 
 
 def hipcc():

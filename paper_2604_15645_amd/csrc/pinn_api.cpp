@@ -887,6 +887,18 @@ int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* p
 
 }  // namespace
 
+namespace pinn {
+// The fused step on a caller-provided workspace with event timing disabled (used by the
+// allocation-free entry point, whose workspace is the library's static device scratch).
+int run_bwd_untimed(const pinn_net* net, const pinn_pde* pde, const float* params, const float* B,
+                    const float* points, int64_t n_points, const pinn_anchor* anchors, int n_anchor, int prec,
+                    uint32_t flags, const pinn_tune* tune, float* residual, double* loss, double* grad,
+                    void* workspace, size_t ws_bytes, pinn_stream_t stream) {
+  return run(net, pde, params, B, points, n_points, anchors, n_anchor, prec, flags, tune, residual, loss, grad,
+             workspace, ws_bytes, stream, true, false);
+}
+}  // namespace pinn
+
 extern "C" {
 
 int64_t pinn_param_count(const pinn_net* net) {
