@@ -9,7 +9,8 @@ generator produces), so that nothing but data is shared with the HIP path:
 
   net = {"d_in", "d_out", "widths": [..], "act": "tanh"|"sin", "w0", "n_freq",
          "rwf", "has_bias"}
-  pde = {"pde": "burgers"|"euler1d"|"ns2d"|"maxwell", "lap_mask", "coef": [..4],
+  pde = {"pde": "burgers"|"euler1d"|"ns2d"|"maxwell"|"advection"|"allen_cahn", "lap_mask",
+         "coef": [..4],
          "lambda_res": [..3], "norm_N"}
 Arrays may be float32; they are promoted to float64 before the call.
 """
@@ -23,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pinn_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-PDE_IDS = {"burgers": 1, "euler1d": 2, "ns2d": 3, "maxwell": 4}
+PDE_IDS = {"burgers": 1, "euler1d": 2, "ns2d": 3, "maxwell": 4, "advection": 5, "allen_cahn": 6}
 ACTS = {"tanh": 0, "sin": 1}
 
 
@@ -130,7 +131,7 @@ def n_channels(net_spec, lap_mask):
 
 
 def n_residuals(pde_name):
-    return 1 if pde_name == "burgers" else 3
+    return 3 if pde_name in ("euler1d", "ns2d", "maxwell") else 1
 
 
 def param_count(net_spec):

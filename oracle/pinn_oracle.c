@@ -17,8 +17,9 @@
  *   residuals    -- Burgers (Sec. 4.3 equation, with a viscosity term nu*u_xx, nu = 0 gives
  *                   the printed inviscid form); 1D Euler in conservative form (Sec. 4.6);
  *                   steady incompressible Navier-Stokes (Sec. 4.4); 2D Maxwell, the
- *                   (E_z, H_x, H_y) system of Sec. 4.8.  Each residual is "left side minus
- *                   right side" of the printed equation.
+ *                   (E_z, H_x, H_y) system of Sec. 4.8; linear advection (Sec. 4.1,
+ *                   u_t + c u_x); Allen-Cahn (Sec. 4.2, u_t - D u_xx + k (u^3 - u)).  Each
+ *                   residual is "left side minus right side" of the printed equation.
  *   loss         -- Sec. 2.3 "Loss function": mean of squared residuals per constraint,
  *                   summed (one mean per residual component, weighted by lambda_c), plus
  *                   value-only supervision terms (initial / boundary data) each with its
@@ -48,7 +49,7 @@
 #define OR_BLOCK 64          /* points per fixed summation block */
 
 enum { OR_OK = 0, OR_E_INVALID = -1, OR_E_UNSUPPORTED = -2, OR_E_NOMEM = -3 };
-enum { OR_BURGERS = 1, OR_EULER1D = 2, OR_NS2D = 3, OR_MAXWELL = 4 };
+enum { OR_BURGERS = 1, OR_EULER1D = 2, OR_NS2D = 3, OR_MAXWELL = 4, OR_ADVECTION = 5, OR_ALLEN_CAHN = 6 };
 
 typedef struct {
   int32_t d_in, d_out, n_hidden;
@@ -63,7 +64,8 @@ typedef struct {
 typedef struct {
   int32_t pde_id;
   int32_t lap_mask;     /* bit k set: input k belongs to the Laplacian set */
-  double coef[4];       /* Burgers nu | Euler gamma | NS Re | Maxwell eps, mu */
+  double coef[4];       /* Burgers nu | Euler gamma | NS Re | Maxwell eps, mu | advection c |
+                           Allen-Cahn D, k */
   double lambda_res[3];
   double norm_N;        /* divisor of the residual mean; 0 means "number of points" */
 } or_pde;
@@ -121,7 +123,9 @@ static int n_channels(const or_net* net, int lap_mask) {
   return 1 + net->d_in + (lap_mask != 0 ? 1 : 0);
 }
 
-static int n_residuals(int pde_id) { return pde_id == OR_BURGERS ? 1 : 3; }
+static int n_residuals(int pde_id) {
+  return pde_id == OR_EULER1D || pde_id == OR_NS2D || pde_id == OR_MAXWELL ? 3 : 1;
+}
 
 static int check_net(const or_net* net, int lap_mask) {
   if (!net) return OR_E_INVALID;
@@ -368,6 +372,27 @@ static void residual_point(const or_pde* pde, int d_in, const double* y, int C, 
       }
       break;
     }
+    case OR_ADVECTION: { /* inputs (x, t): u_t + c u_x (Sec. 4.1) */
+      double c = pde->coef[0];
+      double ux = Y(0, 1), ut = Y(0, 2);
+      r[0] = ut + c * ux;
+      if (rbar) {
+        YB(0, 1) += rbar[0] * c;
+        YB(0, 2) += rbar[0];
+      }
+      break;
+    }
+    case OR_ALLEN_CAHN: { /* inputs (x, t): u_t - D u_xx + k u^3 - k u (Sec. 4.2) */
+      double D = pde->coef[0], k = pde->coef[1];
+      double u = Y(0, 0), ut = Y(0, 2), uxx = Y(0, LAP);
+      r[0] = ut - D * uxx + k * u * u * u - k * u;
+      if (rbar) {
+        YB(0, 0) += rbar[0] * (3.0 * k * u * u - k);
+        YB(0, 2) += rbar[0];
+        YB(0, LAP) += rbar[0] * (-D);
+      }
+      break;
+    }
     default:
       break;
   }
@@ -391,6 +416,12 @@ static int check_pde(const or_net* net, const or_pde* pde) {
     case OR_MAXWELL:
       if (net->d_in != 3 || net->d_out != 3 || pde->coef[0] == 0.0 || pde->coef[1] == 0.0)
         return OR_E_UNSUPPORTED;
+      return OR_OK;
+    case OR_ADVECTION:
+      if (net->d_in != 2 || net->d_out < 1) return OR_E_UNSUPPORTED;
+      return OR_OK;
+    case OR_ALLEN_CAHN:
+      if (net->d_in != 2 || net->d_out < 1 || pde->lap_mask != 1) return OR_E_UNSUPPORTED;
       return OR_OK;
     default:
       return OR_E_UNSUPPORTED;

@@ -23,9 +23,13 @@ PDES = {
     "euler1d": dict(pde="euler1d", lap_mask=0, coef=[1.4, 0, 0, 0]),
     "ns2d": dict(pde="ns2d", lap_mask=3, coef=[100.0, 0, 0, 0]),
     "maxwell": dict(pde="maxwell", lap_mask=0, coef=[1.0, 1.0, 0, 0]),
+    # Sec. 4.1 (c = 10 there) and Sec. 4.2 (D = 1e-4, k = 5 there); the pins use a larger D
+    # so that a dropped diffusion term cannot hide below the tolerance
+    "advection": dict(pde="advection", lap_mask=0, coef=[2.5, 0, 0, 0]),
+    "allen_cahn": dict(pde="allen_cahn", lap_mask=1, coef=[0.05, 5.0, 0, 0]),
 }
-D_IN = {"burgers": 2, "euler1d": 2, "ns2d": 2, "maxwell": 3}
-D_OUT = {"burgers": 1, "euler1d": 3, "ns2d": 3, "maxwell": 3}
+D_IN = {"burgers": 2, "euler1d": 2, "ns2d": 2, "maxwell": 3, "advection": 2, "allen_cahn": 2}
+D_OUT = {"burgers": 1, "euler1d": 3, "ns2d": 3, "maxwell": 3, "advection": 1, "allen_cahn": 1}
 
 
 def small_net(pde, widths=(6, 5), act="tanh", n_freq=0, rwf=False, has_bias=True, w0=1.0):
@@ -130,7 +134,8 @@ def test_jets_match_finite_differences(oracle, variant):
 
 @pytest.mark.parametrize("pde,variant", [("burgers", "rwf"), ("burgers", "rff_sin"),
                                          ("euler1d", "rff"), ("ns2d", "rwf"),
-                                         ("maxwell", "rff_sin"), ("ns2d", "nobias")])
+                                         ("maxwell", "rff_sin"), ("ns2d", "nobias"),
+                                         ("advection", "rff"), ("allen_cahn", "rwf")])
 def test_gradient_matches_central_differences(oracle, pde, variant):
     """Every parameter of a tiny network: central differences of the FP64 loss."""
     net = small_net(pde, widths=(5, 4), act="sin" if "sin" in variant else "tanh",
@@ -236,6 +241,14 @@ def torch_loss(net, pde, params_np, B, pts_np, anchors):
         q = [rho, rho * u, rho * E]
         fl = [rho * u, rho * u * u + p, u * (rho * E + p)]
         res = [d(q[i], 1) + d(fl[i], 0) for i in range(3)]
+    elif name == "advection":
+        c = pde["coef"][0]
+        u = y[:, 0]
+        res = [d(u, 1) + c * d(u, 0)]
+    elif name == "allen_cahn":
+        D, k = pde["coef"][0], pde["coef"][1]
+        u = y[:, 0]
+        res = [d(u, 1) - D * d(d(u, 0), 0) + k * u ** 3 - k * u]
     elif name == "ns2d":
         Re = pde["coef"][0]
         u, v, p = y[:, 0], y[:, 1], y[:, 2]
@@ -267,7 +280,8 @@ def torch_loss(net, pde, params_np, B, pts_np, anchors):
 @pytest.mark.parametrize("pde,variant", [("burgers", "plain"), ("burgers", "rff_rwf"),
                                          ("euler1d", "rff"), ("ns2d", "rwf"),
                                          ("ns2d", "sin"), ("maxwell", "rff_sin"),
-                                         ("maxwell", "plain")])
+                                         ("maxwell", "plain"), ("advection", "rff_sin"),
+                                         ("allen_cahn", "plain"), ("allen_cahn", "rwf")])
 def test_oracle_matches_torch_autograd(oracle, pde, variant):
     """The paper computes residuals and gradients with autograd (Sec. 2.3); the oracle's
     forward-mode jets and reverse sweep must give the same numbers.  The Euler residual
@@ -363,6 +377,41 @@ def test_burgers_manufactured(oracle):
     assert np.allclose(oracle.pde_residual(pde, 2, 1, j)[:, 0], exp, rtol=1e-13, atol=1e-14)
 
 
+def test_advection_manufactured(oracle):
+    """Sec. 4.1: a profile translated with speed c is an exact solution; a decaying one
+    leaves e^{-t} (c cos x - sin x)."""
+    x, t = sp.symbols("x t")
+    c = 2.5
+    pts = rng(17).uniform([0, 0], [2 * math.pi, 1], size=(6, 2))
+    pde = dict(pde="advection", lap_mask=0, coef=[c, 0, 0, 0])
+    j = analytic_jets([sp.sin(x - c * t)], (x, t), (), pts)
+    assert np.abs(oracle.pde_residual(pde, 2, 1, j)).max() < 1e-14
+    j = analytic_jets([sp.sin(x) * sp.exp(-t)], (x, t), (), pts)
+    xv, tv = pts[:, 0], pts[:, 1]
+    exp = np.exp(-tv) * (c * np.cos(xv) - np.sin(xv))
+    assert np.allclose(oracle.pde_residual(pde, 2, 1, j)[:, 0], exp, rtol=1e-13, atol=1e-14)
+
+
+def test_allen_cahn_manufactured(oracle):
+    """Sec. 4.2: the initial profile u = x^2 cos(pi x) (time-independent, so u_t = 0) and
+    a decaying sine, against the residual written out term by term."""
+    x, t = sp.symbols("x t")
+    D, k = 0.05, 5.0
+    pts = rng(18).uniform([-1, 0], [1, 1], size=(6, 2))
+    pde = dict(pde="allen_cahn", lap_mask=1, coef=[D, k, 0, 0])
+    xv, tv = pts[:, 0], pts[:, 1]
+    u0 = xv ** 2 * np.cos(np.pi * xv)
+    uxx = (2 * np.cos(np.pi * xv) - 4 * np.pi * xv * np.sin(np.pi * xv)
+           - np.pi ** 2 * xv ** 2 * np.cos(np.pi * xv))
+    j = analytic_jets([x ** 2 * sp.cos(sp.pi * x) + 0 * t], (x, t), (x,), pts)
+    assert np.allclose(oracle.pde_residual(pde, 2, 1, j)[:, 0], -D * uxx + k * (u0 ** 3 - u0),
+                       rtol=1e-13, atol=1e-14)
+    j = analytic_jets([sp.sin(sp.pi * x) * sp.exp(-t)], (x, t), (x,), pts)
+    u = np.sin(np.pi * xv) * np.exp(-tv)
+    exp = -u + D * np.pi ** 2 * u + k * (u ** 3 - u)
+    assert np.allclose(oracle.pde_residual(pde, 2, 1, j)[:, 0], exp, rtol=1e-13, atol=1e-14)
+
+
 def test_euler_manufactured(oracle):
     x, t = sp.symbols("x t")
     pts = rng(7).uniform([0, 0], [1, 0.2], size=(6, 2))
@@ -447,6 +496,16 @@ def exact_case(kind):
                    has_bias=True)
         params = np.concatenate([Wout.ravel(), [1.0, u0, 1.1]])
         return net, PDES["euler1d"], params, B, r.uniform(0, 1, size=(40, 2))
+    if kind == "advection_wave":
+        # u = 0.8 sin(x - c t) + b: one Fourier column (1, -c), sine coefficient 0.8
+        c = PDES["advection"]["coef"][0]
+        B = np.array([[1.0, 0.7], [-c, 2.0]])
+        Wout = np.zeros((1, 4))
+        Wout[0, 2] = 0.8
+        net = dict(d_in=2, d_out=1, widths=[], act="tanh", w0=1.0, n_freq=2, rwf=False,
+                   has_bias=True)
+        params = np.concatenate([Wout.ravel(), [0.25]])
+        return net, PDES["advection"], params, B, r.uniform([0, 0], [2 * math.pi, 1], size=(40, 2))
     if kind == "ns_couette":
         Wout = np.array([[0.0, 1.0], [0.0, 0.0], [0.0, 0.0]])
         net = dict(d_in=2, d_out=3, widths=[], act="tanh", w0=1.0, n_freq=0, rwf=False,
@@ -456,7 +515,7 @@ def exact_case(kind):
     raise KeyError(kind)
 
 
-@pytest.mark.parametrize("kind", ["maxwell_wave", "euler_entropy", "ns_couette"])
+@pytest.mark.parametrize("kind", ["maxwell_wave", "euler_entropy", "ns_couette", "advection_wave"])
 def test_exact_representable_networks(oracle, kind):
     net, pde, params, B, pts = exact_case(kind)
     res = oracle.loss_grad(net, pde, params, B, pts)
@@ -465,7 +524,7 @@ def test_exact_representable_networks(oracle, kind):
     assert np.abs(res["grad"]).max() < 1e-14
 
 
-@pytest.mark.parametrize("pde", ["burgers", "euler1d", "ns2d", "maxwell"])
+@pytest.mark.parametrize("pde", ["burgers", "euler1d", "ns2d", "maxwell", "advection"])
 def test_constant_output_network_has_zero_residual(oracle, pde):
     """With W_out = 0 the outputs are the output biases: every derivative vanishes."""
     net = small_net(pde, widths=(6, 6), n_freq=3, act="sin")
