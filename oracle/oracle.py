@@ -8,7 +8,7 @@ Network and PDE descriptions are plain dicts (the same dicts the seeded input
 generator produces), so that nothing but data is shared with the HIP path:
 
   net = {"d_in", "d_out", "widths": [..], "act": "tanh"|"sin", "w0", "n_freq",
-         "rwf", "has_bias"}
+         "rwf", "has_bias", "periodic_mask", "period_train_mask", "period": [..3]}
   pde = {"pde": "burgers"|"euler1d"|"ns2d"|"maxwell"|"advection"|"allen_cahn", "lap_mask",
          "coef": [..4],
          "lambda_res": [..3], "norm_N"}
@@ -33,7 +33,8 @@ class _Net(ctypes.Structure):
                 ("n_hidden", ctypes.c_int32), ("width", ctypes.c_int32 * 8),
                 ("act", ctypes.c_int32), ("w0", ctypes.c_double),
                 ("n_freq", ctypes.c_int32), ("rwf", ctypes.c_int32),
-                ("has_bias", ctypes.c_int32)]
+                ("has_bias", ctypes.c_int32), ("periodic_mask", ctypes.c_int32),
+                ("period_train_mask", ctypes.c_int32), ("period", ctypes.c_double * 3)]
 
 
 class _Pde(ctypes.Structure):
@@ -101,6 +102,11 @@ def _net(spec):
     n.n_freq = int(spec.get("n_freq", 0))
     n.rwf = int(bool(spec.get("rwf", False)))
     n.has_bias = int(bool(spec.get("has_bias", True)))
+    n.periodic_mask = int(spec.get("periodic_mask", 0))
+    n.period_train_mask = int(spec.get("period_train_mask", 0))
+    per = list(spec.get("period", [])) + [0.0] * 3
+    for k in range(3):
+        n.period[k] = float(per[k])
     return n
 
 

@@ -11,7 +11,10 @@
  *                   linear output layer; tanh activation (Sec. 2.2), sine activation
  *                   sin(w0 z) (App. A.5 "Periodic activation function").
  *   embedding    -- Sec. 2.6.1 "Random Fourier features": gamma(x) = [cos(xB), sin(xB)],
- *                   B fixed, cos block first (App. A.2).
+ *                   B fixed, cos block first (App. A.2); or Sec. 2.6.3 "strict periodic
+ *                   boundary conditions": each periodic input x_k becomes
+ *                   [cos(2 pi x_k / P_k), sin(2 pi x_k / P_k)], the other inputs pass
+ *                   through, and a period may be a trainable parameter (P_t in Sec. 2.6.3).
  *   factorisation-- Sec. 2.6.2 "Random weight factorization": W = diag(exp s) V for every
  *                   linear layer l = 1..L+1.
  *   residuals    -- Burgers (Sec. 4.3 equation, with a viscosity term nu*u_xx, nu = 0 gives
@@ -47,6 +50,7 @@
 #define OR_MAX_HIDDEN 8
 #define OR_MAX_CH 5          /* value + 3 first derivatives + Laplacian */
 #define OR_BLOCK 64          /* points per fixed summation block */
+static const double OR_PI = 3.14159265358979323846;
 
 enum { OR_OK = 0, OR_E_INVALID = -1, OR_E_UNSUPPORTED = -2, OR_E_NOMEM = -3 };
 enum { OR_BURGERS = 1, OR_EULER1D = 2, OR_NS2D = 3, OR_MAXWELL = 4, OR_ADVECTION = 5, OR_ALLEN_CAHN = 6 };
@@ -59,6 +63,9 @@ typedef struct {
   int32_t n_freq;   /* 0: identity embedding, else Fourier features with m = n_freq */
   int32_t rwf;      /* 1: every linear layer stored as (V, s), W = diag(exp s) V */
   int32_t has_bias;
+  int32_t periodic_mask;     /* bit k: input k enters as [cos, sin](2 pi x_k / P_k) */
+  int32_t period_train_mask; /* bit k: P_k is a trainable parameter (after the layers) */
+  double period[3];          /* P_k of the periodic inputs that are not trained */
 } or_net;
 
 typedef struct {
@@ -83,7 +90,19 @@ typedef struct {
 static int n_layers(const or_net* net) { return net->n_hidden + 1; }
 
 static int embed_width(const or_net* net) {
+  if (net->periodic_mask) {
+    int e = 0;
+    for (int k = 0; k < net->d_in; ++k) e += (net->periodic_mask >> k) & 1 ? 2 : 1;
+    return e;
+  }
   return net->n_freq > 0 ? 2 * net->n_freq : net->d_in;
+}
+
+/* Trainable periods: one parameter each, after every layer's parameters, in input order. */
+static int n_train_periods(const or_net* net) {
+  int n = 0;
+  for (int k = 0; k < net->d_in; ++k) n += (net->period_train_mask >> k) & 1;
+  return n;
 }
 
 static int layer_in(const or_net* net, int l) {
@@ -116,7 +135,17 @@ static int64_t layer_offsets(const or_net* net, int l, int64_t* off_w, int64_t* 
 }
 
 int64_t or_param_count(const or_net* net) {
-  return layer_offsets(net, n_layers(net) - 1, 0, 0, 0);
+  return layer_offsets(net, n_layers(net) - 1, 0, 0, 0) + n_train_periods(net);
+}
+
+/* Period of every input (0 for inputs that pass through). */
+static void input_periods(const or_net* net, const double* params, double* per) {
+  int64_t t = layer_offsets(net, n_layers(net) - 1, 0, 0, 0);
+  for (int k = 0; k < 3; ++k) per[k] = 0.0;
+  for (int k = 0; k < net->d_in; ++k) {
+    if (!((net->periodic_mask >> k) & 1)) continue;
+    per[k] = (net->period_train_mask >> k) & 1 ? params[t++] : net->period[k];
+  }
 }
 
 static int n_channels(const or_net* net, int lap_mask) {
@@ -136,6 +165,12 @@ static int check_net(const or_net* net, int lap_mask) {
   if (net->act != 0 && net->act != 1) return OR_E_INVALID;
   if (net->n_freq < 0 || net->n_freq > 4096) return OR_E_INVALID;
   if (lap_mask & ~((1 << net->d_in) - 1)) return OR_E_INVALID;
+  const int all = (1 << net->d_in) - 1;
+  if ((net->periodic_mask & ~all) || (net->period_train_mask & ~net->periodic_mask)) return OR_E_INVALID;
+  if (net->periodic_mask && net->n_freq > 0) return OR_E_UNSUPPORTED;
+  for (int k = 0; k < net->d_in; ++k)
+    if ((net->periodic_mask >> k) & 1 && !((net->period_train_mask >> k) & 1) && !(net->period[k] != 0.0))
+      return OR_E_INVALID;
   return OR_OK;
 }
 
@@ -198,11 +233,37 @@ static void act_derivs(const or_net* net, double z, double* s0, double* s1, doub
 /* Embedding jets of one point: A0[j*C + c].  Identity: value x_j, d/dx_k = [j == k],
  * Laplacian 0.  Fourier features (Sec. 2.6.1): v_j = sum_k x_k B[k][j];
  * feature j < m is cos(v_j), feature m + j is sin(v_j); their derivatives follow from
- * the chain rule. */
-static void embed_point(const or_net* net, int lap_mask, const double* B, const double* x,
-                        double* A0, int C) {
+ * the chain rule.  Periodic inputs (Sec. 2.6.3): per[k] is the period P_k. */
+static void embed_point(const or_net* net, int lap_mask, const double* B, const double* per,
+                        const double* x, double* A0, int C) {
   int d = net->d_in, e = embed_width(net);
   memset(A0, 0, sizeof(double) * (size_t)e * C);
+  if (net->periodic_mask) {
+    /* Sec. 2.6.3: omega = 2 pi / P_k; cos(omega x_k) and sin(omega x_k) depend on x_k
+     * alone, so their only derivative channel is k (and the Laplacian if k is in S). */
+    int f = 0;
+    for (int k = 0; k < d; ++k) {
+      if (!((net->periodic_mask >> k) & 1)) {
+        A0[f * C + 0] = x[k];
+        A0[f * C + 1 + k] = 1.0;
+        ++f;
+        continue;
+      }
+      double w = 2.0 * OR_PI / per[k], cv = cos(w * x[k]), sv = sin(w * x[k]);
+      double* ac = A0 + (size_t)f * C;
+      double* as = A0 + (size_t)(f + 1) * C;
+      ac[0] = cv;
+      as[0] = sv;
+      ac[1 + k] = -w * sv;
+      as[1 + k] = w * cv;
+      if (lap_mask & (1 << k)) {
+        ac[1 + d] = -w * w * cv;
+        as[1 + d] = -w * w * sv;
+      }
+      f += 2;
+    }
+    return;
+  }
   if (net->n_freq == 0) {
     for (int j = 0; j < d; ++j) {
       A0[j * C + 0] = x[j];
@@ -269,8 +330,9 @@ static void act_jets(const or_net* net, int lap_mask, int n, const double* z, do
 /* Forward pass of one point.  zbuf[l] holds the pre-activation jets of hidden layer l,
  * abuf[l] the activation jets feeding linear layer l (abuf[0] = embedding). */
 static void forward_point(const or_net* net, int lap_mask, const or_weights* ow, const double* B,
-                          const double* x, double** abuf, double** zbuf, double* y, int C) {
-  embed_point(net, lap_mask, B, x, abuf[0], C);
+                          const double* per, const double* x, double** abuf, double** zbuf, double* y,
+                          int C) {
+  embed_point(net, lap_mask, B, per, x, abuf[0], C);
   int L = net->n_hidden;
   for (int l = 0; l < L; ++l) {
     linear_jets(ow->w[l], ow->b[l], layer_out(net, l), layer_in(net, l), abuf[l], zbuf[l], C);
@@ -535,10 +597,41 @@ static int64_t eff_offset(const or_net* net, int l) {
   return off;
 }
 
-/* Reverse sweep of one point given the output-jet seed in s->yb (forward already done). */
-static void backward_point(const or_net* net, int lap_mask, const or_weights* ow, or_scratch* s,
-                           double* geff, int C) {
+/* d(loss)/dP_k of the trainable periods (Sec. 2.6.3) from the adjoint abar0 of the
+ * embedding jets: omega = 2 pi / P_k, d omega / dP_k = -omega / P_k, and each jet entry of
+ * the pair [cos, sin](omega x_k) differentiated in omega.  gper: one slot per trainable
+ * period, in input order. */
+static void period_grad(const or_net* net, int lap_mask, const double* per, const double* x,
+                        const double* abar0, int C, double* gper) {
+  int d = net->d_in, f = 0, t = 0;
+  for (int k = 0; k < d; ++k) {
+    if (!((net->periodic_mask >> k) & 1)) {
+      ++f;
+      continue;
+    }
+    if ((net->period_train_mask >> k) & 1) {
+      double w = 2.0 * OR_PI / per[k], xk = x[k];
+      double cv = cos(w * xk), sv = sin(w * xk);
+      const double* bc = abar0 + (size_t)f * C;
+      const double* bs = abar0 + (size_t)(f + 1) * C;
+      double dw = bc[0] * (-xk * sv) + bs[0] * (xk * cv);
+      dw += bc[1 + k] * (-sv - w * xk * cv) + bs[1 + k] * (cv - w * xk * sv);
+      if (lap_mask & (1 << k))
+        dw += bc[1 + d] * (-2.0 * w * cv + w * w * xk * sv) + bs[1 + d] * (-2.0 * w * sv - w * w * xk * cv);
+      gper[t] += dw * (-w / per[k]);
+      ++t;
+    }
+    f += 2;
+  }
+}
+
+/* Reverse sweep of one point given the output-jet seed in s->yb (forward already done).
+ * With trainable periods the adjoint of the embedding jets is formed as well, and the
+ * period gradient goes to geff[eff_offset(L + 1) + t]. */
+static void backward_point(const or_net* net, int lap_mask, const or_weights* ow, const double* per,
+                           const double* x, or_scratch* s, double* geff, int C) {
   int L = net->n_hidden;
+  const int ntp = n_train_periods(net);
   /* output layer */
   {
     int ni = layer_in(net, L), no = net->d_out;
@@ -551,8 +644,9 @@ static void backward_point(const or_net* net, int lap_mask, const or_weights* ow
     act_jets_adjoint(net, lap_mask, no, s->z[l], s->ab, s->zb, C);
     double* g = geff + eff_offset(net, l);
     linear_jets_adjoint(ow->w[l], no, ni, s->a[l], s->zb, g, g + (int64_t)no * ni,
-                        l > 0 ? s->ab : 0, C);
+                        l > 0 || ntp > 0 ? s->ab : 0, C);
   }
+  if (ntp > 0) period_grad(net, lap_mask, per, x, s->ab, C, geff + eff_offset(net, L + 1));
 }
 
 /* --------------------------------------------------------------- public API */
@@ -565,6 +659,8 @@ int or_forward_jets(const or_net* net, int lap_mask, const double* params, const
   if (n < 0 || (n > 0 && (!params || !pts || !jets))) return OR_E_INVALID;
   if (net->n_freq > 0 && !B) return OR_E_INVALID;
   int C = n_channels(net, lap_mask);
+  double per[3];
+  input_periods(net, params, per);
   or_weights ow;
   rc = build_weights(net, params, &ow);
   if (rc) { free_weights(net, &ow); return rc; }
@@ -578,7 +674,7 @@ int or_forward_jets(const or_net* net, int lap_mask, const double* params, const
     } else {
 #pragma omp for schedule(static)
       for (int64_t i = 0; i < n; ++i) {
-        forward_point(net, lap_mask, &ow, B, pts + i * net->d_in, s.a, s.z, s.y, C);
+        forward_point(net, lap_mask, &ow, B, per, pts + i * net->d_in, s.a, s.z, s.y, C);
         memcpy(jets + i * net->d_out * C, s.y, sizeof(double) * net->d_out * C);
       }
     }
@@ -632,7 +728,10 @@ int or_loss_grad(const or_net* net, const or_pde* pde, const double* params, con
   const int nr = n_residuals(pde->pde_id);
   const int d = net->d_in, dout = net->d_out;
   const double N = pde->norm_N > 0 ? pde->norm_N : (double)n;
-  const int64_t neff = eff_offset(net, net->n_hidden + 1);
+  const int ntp = n_train_periods(net);
+  const int64_t neff = eff_offset(net, net->n_hidden + 1) + ntp;
+  double per[3];
+  input_periods(net, params, per);
 
   or_weights ow;
   rc = build_weights(net, params, &ow);
@@ -686,7 +785,7 @@ int or_loss_grad(const or_net* net, const or_pde* pde, const double* params, con
         int64_t i1 = i0 + OR_BLOCK < seg_n[seg] ? i0 + OR_BLOCK : seg_n[seg];
         for (int64_t i = i0; i < i1; ++i) {
           const double* x = seg == 0 ? pts + i * d : anchors[seg - 1].points + i * d;
-          forward_point(net, lap, &ow, B, x, s.a, s.z, s.y, C);
+          forward_point(net, lap, &ow, B, per, x, s.a, s.z, s.y, C);
           memset(s.yb, 0, sizeof(s.yb));
           if (seg == 0) {
             double r[3], rb[3];
@@ -707,7 +806,7 @@ int or_loss_grad(const or_net* net, const or_pde* pde, const double* params, con
               s.yb[o * C + 0] = 2.0 * an->lambda * diff / Ns;
             }
           }
-          if (g) backward_point(net, lap, &ow, &s, g, C);
+          if (g) backward_point(net, lap, &ow, per, x, &s, g, C);
         }
       }
       free_scratch(net, &s);
@@ -748,6 +847,8 @@ int or_loss_grad(const or_net* net, const or_pde* pde, const double* params, con
           if (net->has_bias) grad[offb + i] = gb[i];
         }
       }
+      const int64_t np_layers = layer_offsets(net, n_layers(net) - 1, 0, 0, 0);
+      for (int t = 0; t < ntp; ++t) grad[np_layers + t] = geff[eff_offset(net, net->n_hidden + 1) + t];
     }
   }
   free(geff);

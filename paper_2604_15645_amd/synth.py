@@ -18,6 +18,10 @@ these synthetic sets stand in for its benchmark problems with their shapes):
            1,048,576 uniform points on [0,1]^3, eps = mu = 1.
   sweep    64 independent Burgers networks, widths {32,64,128,256}, depths 3..6,
            4k..128k points each.
+  advection  linear advection u_t + c u_x (Sec. 4.1, c = 10), MLP 2 -> 4x64 tanh -> 1,
+           16,384 uniform points on [0,2pi]x[0,1] plus 128 initial points (target sin x).
+  allen_cahn Allen-Cahn u_t - 1e-4 u_xx + 5 u^3 - 5 u (Sec. 4.2), MLP 2 -> 4x128 tanh -> 1,
+           16,384 uniform points on [-1,1]x[0,1] plus 128 initial points (target x^2 cos(pi x)).
 Weights are Xavier-normal (std = sqrt(2 / (fan_in + fan_out))), biases zero; with
 perturb=True biases (and factorisation scales) get random non-zero values so that
 parity tests exercise every parameter path.
@@ -53,12 +57,37 @@ CONFIGS = {
         pde=dict(pde="maxwell", lap_mask=0, coef=[1.0, 1.0, 0, 0], lambda_res=[1.0, 1.0, 1.0],
                  norm_N=0.0),
         box=[(0.0, 1.0), (0.0, 1.0), (0.0, 1.0)], n_points=1048576, rff_sigma=2.0, index=3),
+    "advection": dict(
+        net=dict(d_in=2, d_out=1, widths=[64, 64, 64, 64], act="tanh", w0=1.0, n_freq=0,
+                 rwf=False, has_bias=True),
+        pde=dict(pde="advection", lap_mask=0, coef=[10.0, 0, 0, 0], lambda_res=[1.0, 1.0, 1.0],
+                 norm_N=0.0),
+        box=[(0.0, 2.0 * math.pi), (0.0, 1.0)], n_points=16384, rff_sigma=0.0, index=5),
+    "allen_cahn": dict(
+        net=dict(d_in=2, d_out=1, widths=[128, 128, 128, 128], act="tanh", w0=1.0, n_freq=0,
+                 rwf=False, has_bias=True),
+        pde=dict(pde="allen_cahn", lap_mask=1, coef=[1e-4, 5.0, 0, 0], lambda_res=[1.0, 1.0, 1.0],
+                 norm_N=0.0),
+        box=[(-1.0, 1.0), (0.0, 1.0)], n_points=16384, rff_sigma=0.0, index=6),
 }
+
+
+def embed_width(net):
+    """Width of the network input: 2 m Fourier features, or each input once (twice when it
+    enters through the periodic [cos, sin] pair)."""
+    pm = int(net.get("periodic_mask", 0))
+    if pm:
+        return sum(2 if (pm >> k) & 1 else 1 for k in range(net["d_in"]))
+    return 2 * net["n_freq"] if net.get("n_freq", 0) else net["d_in"]
+
+
+def n_train_periods(net):
+    return bin(int(net.get("period_train_mask", 0))).count("1")
 
 
 def layer_dims(net):
     """(n_out, n_in) of every linear layer, input side first."""
-    e = 2 * net["n_freq"] if net.get("n_freq", 0) else net["d_in"]
+    e = embed_width(net)
     dims = []
     prev = e
     for w in net["widths"]:
@@ -72,11 +101,12 @@ def param_count(net):
     n = 0
     for no, ni in layer_dims(net):
         n += no * ni + (no if net.get("rwf") else 0) + (no if net.get("has_bias", True) else 0)
-    return n
+    return n + n_train_periods(net)
 
 
 def init_params(net, rng, perturb=False, rwf_mean=1.0, rwf_std=0.1):
-    """Flat FP32 parameters, per layer [W or V (row-major n_out x n_in)] [s] [b]."""
+    """Flat FP32 parameters, per layer [W or V (row-major n_out x n_in)] [s] [b], then the
+    trainable periods (initial value net["period"][k], in input order)."""
     out = []
     for no, ni in layer_dims(net):
         std = math.sqrt(2.0 / (ni + no))
@@ -85,6 +115,8 @@ def init_params(net, rng, perturb=False, rwf_mean=1.0, rwf_std=0.1):
             out.append(rng.normal(rwf_mean, rwf_std, size=no))
         if net.get("has_bias", True):
             out.append(rng.normal(0.0, 0.1, size=no) if perturb else np.zeros(no))
+    tm = int(net.get("period_train_mask", 0))
+    out.append(np.array([net["period"][k] for k in range(net["d_in"]) if (tm >> k) & 1], dtype=np.float64))
     return np.concatenate(out).astype(np.float32)
 
 
@@ -113,6 +145,16 @@ def burgers_anchors(rng, n_ic=128, n_bc=128):
             dict(points=bc_pts, targets=bc_tgt, out_mask=1, **{"lambda": 1.0})]
 
 
+def initial_anchors(rng, name, n=128):
+    """Initial data u(x, 0) of the advection (sin x) and Allen-Cahn (x^2 cos(pi x)) problems."""
+    lo, hi = CONFIGS[name]["box"][0]
+    x = rng.uniform(lo, hi, size=n)
+    pts = np.stack([x, np.zeros(n)], axis=1).astype(np.float32)
+    xd = pts[:, 0].astype(np.float64)
+    tgt = np.sin(xd) if name == "advection" else xd * xd * np.cos(np.pi * xd)
+    return [dict(points=pts, targets=tgt.astype(np.float32)[:, None], out_mask=1, **{"lambda": 1.0})]
+
+
 def make_case(name, n_points=None, seed=None, perturb=False, anchors=None):
     """One workload: dict(net, pde, params, B, points, anchors)."""
     cfg = CONFIGS[name]
@@ -126,8 +168,10 @@ def make_case(name, n_points=None, seed=None, perturb=False, anchors=None):
     n = cfg["n_points"] if n_points is None else n_points
     pts = uniform_points(rng, cfg["box"], n)
     if anchors is None:
-        anchors = name == "burgers"
-    anc = burgers_anchors(rng) if anchors else []
+        anchors = name in ("burgers", "advection", "allen_cahn")
+    anc = []
+    if anchors:
+        anc = burgers_anchors(rng) if name == "burgers" else initial_anchors(rng, name)
     return dict(name=name, net=net, pde=pde, params=params, B=B, points=pts, anchors=anc)
 
 

@@ -201,9 +201,28 @@ def torch_network(net, params, B):
             off += no
         layers.append((W, s, b))
     Bt = None if B is None else torch.as_tensor(B, dtype=torch.float64)
+    pm, tm = int(net.get("periodic_mask", 0)), int(net.get("period_train_mask", 0))
+    periods = []
+    t_off = off
+    for k in range(net["d_in"]):
+        if (tm >> k) & 1:
+            periods.append(params[t_off])
+            t_off += 1
+        else:
+            periods.append(net.get("period", [0, 0, 0])[k])
 
     def f(x):
         h = x
+        if pm:
+            # Sec. 2.6.3: w(x) = [cos(2 pi x_k / P_k), sin(2 pi x_k / P_k)] per periodic input
+            cols = []
+            for k in range(net["d_in"]):
+                if (pm >> k) & 1:
+                    a = 2 * math.pi / periods[k] * x[:, k:k + 1]
+                    cols += [torch.cos(a), torch.sin(a)]
+                else:
+                    cols.append(x[:, k:k + 1])
+            h = torch.cat(cols, -1)
         if Bt is not None:
             xm = x @ Bt
             h = torch.cat([torch.cos(xm), torch.sin(xm)], -1)
@@ -470,6 +489,90 @@ def test_maxwell_plane_wave(oracle):
     ph = kx * pts[:, 0] + ky * pts[:, 1] - w2 * pts[:, 2]
     assert np.allclose(r[:, 0], (w2 - (kx * kx + ky * ky) / w2) * np.sin(ph), atol=1e-14)
     assert np.abs(r[:, 1:]).max() < 1e-14
+
+
+# ------------------------------------------------ strict periodic embedding (Sec. 2.6.3)
+
+def periodic_net(pde, widths=(7, 6), act="tanh", train=True):
+    """Inputs (x, t): x periodic with P_x = 2 (fixed), t periodic with P_t trainable
+    (initial value 1.3), the form of the equation in Sec. 2.6.3."""
+    return dict(d_in=2, d_out=D_OUT[pde], widths=list(widths), act=act, w0=1.0, n_freq=0,
+                rwf=False, has_bias=True, periodic_mask=3, period_train_mask=2 if train else 0,
+                period=[2.0, 1.3, 0.0])
+
+
+def test_periodic_embedding_is_periodic(oracle):
+    """The defining property: the output and every derivative jet agree at x and x + P_x
+    and at t and t + P_t (also with P_t a trained value other than its initial one)."""
+    net = periodic_net("burgers")
+    r = rng(19)
+    params = synth.init_params(net, r, perturb=True).astype(np.float64)
+    params[-1] = 1.7                   # the trainable period, moved away from its start
+    pts = r.uniform([-1, 0], [1, 1], size=(12, 2))
+    j0 = oracle.forward_jets(net, 1, params, None, pts)
+    j1 = oracle.forward_jets(net, 1, params, None, pts + np.array([2.0, 0.0]))
+    j2 = oracle.forward_jets(net, 1, params, None, pts + np.array([0.0, 1.7]))
+    j3 = oracle.forward_jets(net, 1, params, None, pts + np.array([0.5, 0.0]))
+    scale = np.abs(j0).max()
+    assert np.abs(j1 - j0).max() < 1e-13 * scale
+    assert np.abs(j2 - j0).max() < 1e-13 * scale
+    assert np.abs(j3 - j0).max() > 1e-3 * scale  # not constant: a half period changes it
+
+
+def test_periodic_single_neuron_closed_form(oracle):
+    """u = c tanh(a1 cos(wx) + a2 sin(wx) + a3 t + b) + d with x periodic (w = 2 pi / P)
+    and t passed through (the form of the listing in App. A.4): jets from sympy."""
+    x, t = sp.symbols("x t")
+    P = 1.6
+    net = dict(d_in=2, d_out=1, widths=[1], act="tanh", w0=1.0, n_freq=0, rwf=False,
+               has_bias=True, periodic_mask=1, period_train_mask=0, period=[P, 0.0, 0.0])
+    a1, a2, a3, b, c, d = 0.7, -1.1, 0.4, 0.2, 1.3, -0.5
+    params = np.array([a1, a2, a3, b, c, d])
+    w = 2 * sp.pi / P
+    u = c * sp.tanh(a1 * sp.cos(w * x) + a2 * sp.sin(w * x) + a3 * t + b) + d
+    pts = rng(20).uniform([-1, 0], [1, 1], size=(5, 2))
+    exp = analytic_jets([u], (x, t), (x,), pts)
+    got = oracle.forward_jets(net, 1, params, None, pts)
+    assert np.allclose(got, exp, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("pde,act", [("burgers", "tanh"), ("advection", "sin"), ("allen_cahn", "tanh")])
+def test_periodic_embedding_matches_torch_autograd(oracle, pde, act):
+    """Loss, residuals and gradient, including dL/dP_t of the trainable period, against
+    autograd of the paper's map (Sec. 2.6.3) with P_t a leaf of the graph."""
+    net = periodic_net(pde, act=act)
+    r = rng(21)
+    params = synth.init_params(net, r, perturb=True).astype(np.float64)
+    pts = r.uniform([-1, 0], [1, 1], size=(29, 2))
+    anchors = [dict(points=r.uniform([-1, 0], [1, 0], size=(6, 2)), targets=r.normal(size=(6, 1)),
+                    out_mask=1, **{"lambda": 0.8})]
+    spec = dict(PDES[pde], lambda_res=[1.2, 1, 1])
+    got = oracle.loss_grad(net, spec, params, None, pts, anchors)
+    loss, res, grad = torch_loss(net, spec, params, None, pts, anchors)
+    assert relerr(got["loss"], loss) < 1e-12
+    assert relerr(got["residual"], res) < 1e-12
+    assert relerr(got["grad"], grad) < 1e-11
+    assert abs(got["grad"][-1] - grad[-1]) <= 1e-11 * max(1.0, abs(grad[-1]))
+    assert abs(grad[-1]) > 1e-6     # the period gradient is exercised, not trivially zero
+
+
+def test_periodic_gradient_matches_central_differences(oracle):
+    net = periodic_net("burgers", widths=(4, 3))
+    r = rng(22)
+    params = synth.init_params(net, r, perturb=True).astype(np.float64)
+    pts = r.uniform([-1, 0], [1, 1], size=(7, 2))
+    spec = PDES["burgers"]
+    g = oracle.loss_grad(net, spec, params, None, pts)["grad"]
+    fd = np.zeros_like(g)
+    for i in range(params.size):
+        h = 1e-6 * max(1.0, abs(params[i]))
+        pp = params.copy()
+        pp[i] += h
+        lp = oracle.loss_grad(net, spec, pp, None, pts, want_grad=False)["loss"][0]
+        pp[i] -= 2 * h
+        lm = oracle.loss_grad(net, spec, pp, None, pts, want_grad=False)["loss"][0]
+        fd[i] = (lp - lm) / (2 * h)
+    assert np.abs(fd - g).max() <= 1e-6 * max(1e-3, np.abs(g).max())
 
 
 # ----------------------------------------------------- exactly representable networks
