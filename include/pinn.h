@@ -11,7 +11,7 @@
  *   residual  per PDE, "left side minus right side" of the printed equation:
  *             Burgers (Sec. 4.3, with viscosity nu u_xx), 1D Euler in conservative form
  *             (Sec. 4.6), steady incompressible Navier-Stokes (Sec. 4.4), 2D Maxwell
- *             (Sec. 4.8).
+ *             (Sec. 4.8), linear advection (Sec. 4.1), Allen-Cahn (Sec. 4.2).
  *   loss      Sec. 2.3: L = sum_c lambda_c (1/N) sum_i r_c(x_i)^2
  *                         + sum_s lambda_s (1/N_s) sum_i sum_{o in mask_s} (y_o(x_i) - t_{o,i})^2
  *   gradient  dL/dtheta for every parameter theta (the quantity the optimiser of Sec. 2.3
@@ -25,10 +25,11 @@
  *   record declared at the end).  Calls are asynchronous on `stream` (a hipStream_t; NULL = the null stream);
  *   the return code reports argument errors (checked on the host, before any HIP call)
  *   and launch errors.  Calls sharing a workspace must not overlap.
- *   Points: n x d_in, row-major, FP32, inputs ordered (x,t) Burgers/Euler, (x,y) NS,
- *   (x,y,t) Maxwell.  Parameters: FP32, flat, per linear layer l = 0..n_hidden (input
+ *   Points: n x d_in, row-major, FP32, inputs ordered (x,t) Burgers/Euler/advection/
+ *   Allen-Cahn, (x,y) NS, (x,y,t) Maxwell.  Parameters: FP32, flat, per linear layer l = 0..n_hidden (input
  *   side first): [W_l or V_l (n_out x n_in, row-major)] [s_l (n_out) if rwf]
- *   [b_l (n_out) if has_bias].  Gradient: FP64 in the same layout.
+ *   [b_l (n_out) if has_bias], then the trainable periods of a periodic embedding.
+ *   Gradient: FP64 in the same layout.
  *   Device limits: d_in <= 3, d_out <= 3, 1 + d_in + (Laplacian needed) <= 4 derivative
  *   channels, hidden widths multiples of 32 and <= 256, n_freq a multiple of 16 with
  *   2*n_freq <= 256, n_hidden in 1..8.
@@ -58,7 +59,10 @@ typedef enum {
   PINN_PDE_BURGERS = 1,       /* in (x,t), out u:          u_t + u u_x - nu u_xx       */
   PINN_PDE_EULER1D = 2,       /* in (x,t), out (rho,u,p):  conservative 1D Euler       */
   PINN_PDE_NS2D_STEADY = 3,   /* in (x,y), out (u,v,p):    continuity + 2 momentum     */
-  PINN_PDE_MAXWELL_TE2D = 4   /* in (x,y,t), out (E_z,H_x,H_y)                          */
+  PINN_PDE_MAXWELL_TE2D = 4,  /* in (x,y,t), out (E_z,H_x,H_y)                          */
+  PINN_PDE_ADVECTION = 5,     /* in (x,t), out u:          u_t + c u_x (Sec. 4.1)      */
+  PINN_PDE_ALLEN_CAHN = 6     /* in (x,t), out u:          u_t - D u_xx + k (u^3 - u)
+                                 (Sec. 4.2; the paper's D = 1e-4, k = 5)              */
 } pinn_pde_id;
 
 typedef enum { PINN_ACT_TANH = 0, PINN_ACT_SIN = 1 } pinn_act;
@@ -100,6 +104,15 @@ typedef struct {
   int32_t n_freq;        /* 0: identity embedding; m > 0: Fourier features, B is d_in x m */
   int32_t rwf;           /* 1: every linear layer stored as (V, s), W = diag(exp s) V    */
   int32_t has_bias;      /* 1: every linear layer has a bias                             */
+  /* Strict periodic input embedding (Sec. 2.6.3; requires n_freq == 0): input k with bit k
+   * of periodic_mask enters the network as the pair [cos(2 pi x_k / P_k), sin(2 pi x_k / P_k)],
+   * the other inputs as themselves, in input order; the output is then periodic in x_k
+   * with period P_k, derivatives included.  P_k is period[k], or, with bit k of
+   * period_train_mask, a trainable parameter stored after every layer's parameters (one
+   * FP32 value per trained input, in input order) whose gradient is returned there.      */
+  int32_t periodic_mask;
+  int32_t period_train_mask; /* subset of periodic_mask                                   */
+  float period[3];
 } pinn_net;
 
 /* (host) PDE descriptor. */
@@ -107,7 +120,8 @@ typedef struct {
   int32_t pde_id;        /* pinn_pde_id                                                  */
   int32_t lap_mask;      /* bit k: input k belongs to the Laplacian set S (Burgers: x,
                             NS: x and y; Euler and Maxwell need none)                     */
-  double coef[4];        /* Burgers: nu | Euler: gamma | NS: Re | Maxwell: eps, mu       */
+  double coef[4];        /* Burgers: nu | Euler: gamma | NS: Re | Maxwell: eps, mu |
+                            advection: c | Allen-Cahn: D, k                               */
   double lambda_res[3];  /* weight of each residual component's mean square             */
   double norm_N;         /* divisor of the residual means; 0 = n_points of this call.
                             A caller that shards the points passes the global count.     */

@@ -9,7 +9,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpinn.so")
 
-PDE_IDS = {"burgers": 1, "euler1d": 2, "ns2d": 3, "maxwell": 4}
+PDE_IDS = {"burgers": 1, "euler1d": 2, "ns2d": 3, "maxwell": 4, "advection": 5, "allen_cahn": 6}
 ACTS = {"tanh": 0, "sin": 1}
 PRECS = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp16x3": 4}
 FLAG_CHECK_FINITE = 1
@@ -21,7 +21,9 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported configuration",
 class PinnNet(ctypes.Structure):
     _fields_ = [("d_in", ctypes.c_int32), ("d_out", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
                 ("width", ctypes.c_int32 * 8), ("act", ctypes.c_int32), ("w0", ctypes.c_float),
-                ("n_freq", ctypes.c_int32), ("rwf", ctypes.c_int32), ("has_bias", ctypes.c_int32)]
+                ("n_freq", ctypes.c_int32), ("rwf", ctypes.c_int32), ("has_bias", ctypes.c_int32),
+                ("periodic_mask", ctypes.c_int32), ("period_train_mask", ctypes.c_int32),
+                ("period", ctypes.c_float * 3)]
 
 
 class PinnPde(ctypes.Structure):
@@ -115,6 +117,11 @@ def net_struct(spec):
     n.n_freq = int(spec.get("n_freq", 0))
     n.rwf = int(bool(spec.get("rwf", False)))
     n.has_bias = int(bool(spec.get("has_bias", True)))
+    n.periodic_mask = int(spec.get("periodic_mask", 0))
+    n.period_train_mask = int(spec.get("period_train_mask", 0))
+    per = list(spec.get("period", [])) + [0.0] * 3
+    for k in range(3):
+        n.period[k] = float(per[k])
     return n
 
 

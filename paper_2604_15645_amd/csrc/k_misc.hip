@@ -22,6 +22,20 @@ __device__ __forceinline__ float eff_w(const StageArgs& a, int l, int o, int i) 
 template <int PREC>
 __global__ void k_stage(const StageArgs a) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < 3 && a.omega) {  // omega_k = 2 pi / P_k of the periodic inputs (Sec. 2.6.3)
+    const int k = (int)t;
+    float w = 0.0f;
+    if ((a.periodic_mask >> k) & 1) {
+      float P = a.period[k];
+      if ((a.period_train_mask >> k) & 1) {
+        int r = 0;
+        for (int j = 0; j < k; ++j) r += (a.period_train_mask >> j) & 1;
+        P = a.params[a.off_p + r];
+      }
+      w = 6.2831853071795865f / P;
+    }
+    a.omega[k] = w;
+  }
   if (t >= a.cum[a.n_layers]) return;
   int l = 0;
   while (t >= a.cum[l + 1]) ++l;
@@ -92,8 +106,61 @@ __global__ __launch_bounds__(kThreads, 1) void k_grad0(const Grad0Args A) {
   const int64_t per = (A.n_cb + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * per;
   const int64_t hi = lo + per < A.n_cb ? lo + per : A.n_cb;
+  if (A.periodic_mask) {
+    int ng = 0;
+    for (int k = 0; k < A.d_in; ++k) ng += 2 * ((A.period_train_mask >> k) & 1);
+    grad0p_range(A, lo, hi, A.slots + (size_t)blockIdx.x * A.n_out * (A.e + 1 + ng), reinterpret_cast<float*>(smem));
+    return;
+  }
   grad0_range(A.zb, A.pts, A.n_out, A.d_in, lo, hi, A.slots + (size_t)blockIdx.x * A.n_out * (A.d_in + 1),
               reinterpret_cast<float*>(smem));
+}
+
+// d(loss)/dP_k of every trained period (one work-group): the G sums of each output reduced
+// over the slots in slot order, weighted by the effective first-layer weights, summed over
+// the outputs in order, times d omega / dP = -omega / P = -omega^2 / (2 pi).
+__global__ void k_reduce_period(const PeriodReduceArgs A) {
+  __shared__ double part[256];
+  int ng = 0;
+  for (int k = 0; k < A.d_in; ++k) ng += 2 * ((A.period_train_mask >> k) & 1);
+  int f = 0, t = 0, j = 0;
+  for (int k = 0; k < A.d_in; ++k) {
+    if (!((A.periodic_mask >> k) & 1)) {
+      ++f;
+      continue;
+    }
+    if ((A.period_train_mask >> k) & 1) {
+      for (int o0 = 0; o0 < A.n_out; o0 += 256) {
+        const int o = o0 + (int)threadIdx.x;
+        double v = 0.0;
+        if (o < A.n_out) {
+          double g0 = 0.0, g1 = 0.0;
+          for (int sl = 0; sl < A.n_slots; ++sl) {
+            const double* G = A.slots + (size_t)sl * A.slot_stride + (size_t)A.n_out * (A.e + 1) + (size_t)o * ng;
+            g0 += G[j];
+            g1 += G[j + 1];
+          }
+          v = (double)A.w[(size_t)o * A.e + f] * g0 + (double)A.w[(size_t)o * A.e + f + 1] * g1;
+        }
+        __syncthreads();
+        part[threadIdx.x] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          double sum = o0 == 0 ? 0.0 : A.grad[A.off_p + t];
+          for (int i = 0; i < 256; ++i) sum += part[i];
+          A.grad[A.off_p + t] = sum;
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const double w = (double)A.omega[k];
+        A.grad[A.off_p + t] *= -w * w / 6.283185307179586;
+      }
+      ++t;
+      j += 2;
+    }
+    f += 2;
+  }
 }
 
 // ================================================================== reductions
@@ -290,6 +357,11 @@ int launch_reduce_batched(const BatchReduceArgs& a, hipStream_t s) {
 
 int launch_reduce_loss_batched(const BatchLossArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_loss_batched, dim3(a.n_inst), dim3(64), 0, s, a);
+  return launch_status(hipGetLastError());
+}
+
+int launch_reduce_period(const PeriodReduceArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_period, dim3(1), dim3(256), 0, s, a);
   return launch_status(hipGetLastError());
 }
 

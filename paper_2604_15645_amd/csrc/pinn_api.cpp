@@ -28,6 +28,8 @@ struct Dims {
   int n_in[kMaxLayers], n_out[kMaxLayers];
   int64_t off_w[kMaxLayers], off_s[kMaxLayers], off_b[kMaxLayers];
   int64_t n_params;
+  int64_t off_p;  // first trainable period (after every layer's parameters)
+  int n_tp;       // trainable periods
   int hmax;      // widest hidden layer
   int H;         // width bucket of the kernels: 32, 64, 128 or 256
 };
@@ -42,12 +44,22 @@ int check_net(const pinn_net* net, Dims* d) {
   if (!std::isfinite(net->w0)) return PINN_E_INVALID;
   for (int l = 0; l < net->n_hidden; ++l)
     if (net->width[l] < 1 || net->width[l] > 4096) return PINN_E_INVALID;
+  const int all = (1 << net->d_in) - 1;
+  if ((net->periodic_mask & ~all) || (net->period_train_mask & ~net->periodic_mask)) return PINN_E_INVALID;
+  for (int k = 0; k < net->d_in; ++k)
+    if ((net->periodic_mask >> k) & 1 && !((net->period_train_mask >> k) & 1) &&
+        !(std::isfinite(net->period[k]) && net->period[k] != 0.0f))
+      return PINN_E_INVALID;
   Dims& D = *d;
   D.L = net->n_hidden;
   D.n_layers = D.L + 1;
   D.d_in = net->d_in;
   D.d_out = net->d_out;
   D.e = net->n_freq > 0 ? 2 * net->n_freq : net->d_in;
+  if (net->periodic_mask) {
+    D.e = 0;
+    for (int k = 0; k < net->d_in; ++k) D.e += (net->periodic_mask >> k) & 1 ? 2 : 1;
+  }
   int64_t off = 0;
   D.hmax = 0;
   for (int l = 0; l < D.n_layers; ++l) {
@@ -61,7 +73,10 @@ int check_net(const pinn_net* net, Dims* d) {
     if (net->rwf) { D.off_s[l] = off; off += D.n_out[l]; }
     if (net->has_bias) { D.off_b[l] = off; off += D.n_out[l]; }
   }
-  D.n_params = off;
+  D.off_p = off;
+  D.n_tp = 0;
+  for (int k = 0; k < net->d_in; ++k) D.n_tp += (net->period_train_mask >> k) & 1;
+  D.n_params = off + D.n_tp;
   D.H = D.hmax <= 32 ? 32 : D.hmax <= 64 ? 64 : D.hmax <= 128 ? 128 : 256;
   return PINN_OK;
 }
@@ -72,6 +87,7 @@ int check_supported(const pinn_net* net, const Dims& D, int lap_mask) {
   for (int l = 0; l < D.L; ++l)
     if (D.n_out[l] % 32 != 0 || D.n_out[l] > 256) return PINN_E_UNSUPPORTED;
   if (net->n_freq > 0 && (net->n_freq % 16 != 0 || 2 * net->n_freq > 256)) return PINN_E_UNSUPPORTED;
+  if (net->periodic_mask && net->n_freq > 0) return PINN_E_UNSUPPORTED;  // one embedding at a time
   const int C = 1 + net->d_in + (lap_mask ? 1 : 0);
   if (C > 4) return PINN_E_UNSUPPORTED;
   if (lap_mask && net->d_in != 2) return PINN_E_UNSUPPORTED;
@@ -101,6 +117,12 @@ int check_pde(const pinn_net* net, const pinn_pde* pde) {
       if (net->d_in != 3 || net->d_out != 3 || pde->coef[0] == 0.0 || pde->coef[1] == 0.0)
         return PINN_E_UNSUPPORTED;
       return PINN_OK;
+    case PINN_PDE_ADVECTION:  // first derivatives only
+      if (net->d_in != 2 || pde->lap_mask != 0) return PINN_E_UNSUPPORTED;
+      return PINN_OK;
+    case PINN_PDE_ALLEN_CAHN:  // the Laplacian channel must be u_xx alone
+      if (net->d_in != 2 || pde->lap_mask != 1) return PINN_E_UNSUPPORTED;
+      return PINN_OK;
     default:
       return PINN_E_UNSUPPORTED;
   }
@@ -119,7 +141,9 @@ int kernel_prec(int prec, int* kp) {
 
 int n_res_of(int pde_id) {
   switch (pde_id) {
-    case PINN_PDE_BURGERS: return 1;
+    case PINN_PDE_BURGERS:
+    case PINN_PDE_ADVECTION:
+    case PINN_PDE_ALLEN_CAHN: return 1;
     case PINN_PDE_EULER1D:
     case PINN_PDE_NS2D_STEADY:
     case PINN_PDE_MAXWELL_TE2D: return 3;
@@ -181,7 +205,8 @@ struct Plan {
   bool with_grad;
   // workspace offsets
   int64_t o_pts, o_wf[kMaxLayers], o_wb[kMaxLayers], o_w[kMaxLayers], o_b[kMaxLayers];
-  int64_t o_zs[kMaxHidden], o_zb[2], o_loss, o_out, o_layer[kMaxLayers], o_flag, o_pace, o_amax;
+  int64_t o_zs[kMaxHidden], o_zb[2], o_loss, o_out, o_layer[kMaxLayers], o_flag, o_pace, o_amax, o_omega;
+  int ng0;                // period sums per first-layer output (2 per trained period)
   int64_t zs_stride;
   int64_t bytes;
 };
@@ -277,6 +302,8 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   p.o_loss = take((int64_t)p.grid_f * kMaxTerms * 8);
   p.o_flag = take(16);
   p.o_amax = take(kMaxHidden * 4);
+  p.o_omega = take(16);
+  p.ng0 = 2 * D.n_tp;
   p.o_pace = take((int64_t)std::max(p.grid_b, 1) * 8);  // split-backward pacing words (any content)
   if (p.with_grad) {
     p.zs_stride = p.n_pad * 4 * D.hmax;
@@ -286,7 +313,7 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
     p.o_out = take((int64_t)p.grid_f * D.d_out * (D.n_in[D.L] + 1) * 8);
     for (int l = 0; l < D.L; ++l) {
       int grid = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : p.grid_g0) : p.grid_b;
-      p.o_layer[l] = take((int64_t)grid * D.n_out[l] * (D.n_in[l] + 1) * 8);
+      p.o_layer[l] = take((int64_t)grid * D.n_out[l] * (D.n_in[l] + 1 + (l == 0 ? p.ng0 : 0)) * 8);
     }
   }
   p.bytes = o;
@@ -346,6 +373,8 @@ NetDev make_netdev(const pinn_net* net, const pinn_pde* pde, const Plan& p, char
   nd.d_out = D.d_out;
   nd.e = D.e;
   nd.n_freq = net->n_freq;
+  nd.periodic_mask = net->periodic_mask;
+  nd.omega = reinterpret_cast<const float*>(ws + p.o_omega);
   nd.lap_mask = pde->lap_mask;
   nd.lapch = pde->lap_mask ? 1 + D.d_in : -1;
   nd.w0 = net->w0;
@@ -419,6 +448,11 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     a.n_layers = D.n_layers;
     a.rwf = net->rwf;
     a.has_bias = net->has_bias;
+    a.periodic_mask = net->periodic_mask;
+    a.period_train_mask = net->period_train_mask;
+    for (int k = 0; k < 3; ++k) a.period[k] = net->period[k];
+    a.off_p = D.off_p;
+    a.omega = reinterpret_cast<float*>(ws + p.o_omega);
     a.params = params;
     int64_t cum = 0;
     for (int l = 0; l < D.n_layers; ++l) {
@@ -519,12 +553,18 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       if (rc) return rc;
     } else {
       Grad0Args a;
+      std::memset(&a, 0, sizeof(a));
       a.zb = wk.zb[cur];
       a.pts = wk.pts;
       a.n_out = D.n_out[0];
       a.d_in = D.d_in;
       a.n_cb = p.n_pad / 4;
       a.slots = wk.layer_slots[0];
+      a.periodic_mask = net->periodic_mask;
+      a.period_train_mask = net->period_train_mask;
+      a.lap_mask = pde->lap_mask;
+      a.e = D.e;
+      a.omega = reinterpret_cast<const float*>(ws + p.o_omega);
       rc = timed(allow_timing, "k_grad0", stream, [&] { return launch_grad0(a, p.grid_g0, stream); });
       if (rc) return rc;
     }
@@ -539,7 +579,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.off_s = D.off_s[l];
       a.off_b = D.off_b[l];
       a.grad = grad;
-      a.slot_stride = (int64_t)D.n_out[l] * (D.n_in[l] + 1);
+      a.slot_stride = (int64_t)D.n_out[l] * (D.n_in[l] + 1 + (l == 0 ? p.ng0 : 0));
       if (l == D.L) {
         a.slots = wk.out_slots;
         a.n_slots = p.grid_f;
@@ -548,6 +588,24 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
         a.n_slots = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : p.grid_g0) : (p.split ? p.grid_b / 2 : p.grid_b);
       }
       rc = timed(allow_timing, "k_reduce_layer", stream, [&] { return launch_reduce_layer(a, stream); });
+      if (rc) return rc;
+    }
+    if (D.n_tp > 0) {  // trained periods of the periodic embedding (after layer 0's sums)
+      PeriodReduceArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.slots = wk.layer_slots[0];
+      a.n_slots = p.grid_g0;
+      a.slot_stride = (int64_t)D.n_out[0] * (D.e + 1 + p.ng0);
+      a.n_out = D.n_out[0];
+      a.e = D.e;
+      a.periodic_mask = net->periodic_mask;
+      a.period_train_mask = net->period_train_mask;
+      a.d_in = D.d_in;
+      a.w = reinterpret_cast<const float*>(ws + p.o_w[0]);
+      a.omega = reinterpret_cast<const float*>(ws + p.o_omega);
+      a.grad = grad;
+      a.off_p = D.off_p;
+      rc = timed(allow_timing, "k_reduce_period", stream, [&] { return launch_reduce_period(a, stream); });
       if (rc) return rc;
     }
   }
@@ -608,7 +666,7 @@ int make_batch_plan(const pinn_net* nets, const pinn_pde* pde, const int64_t* n_
     if (rc) return rc;
     rc = check_supported(&nets[i], b.D[i], pde->lap_mask);
     if (rc) return rc;
-    if (nets[i].n_freq != 0 || nets[i].act != b.act || nets[i].d_in != nets[0].d_in ||
+    if (nets[i].n_freq != 0 || nets[i].periodic_mask != 0 || nets[i].act != b.act || nets[i].d_in != nets[0].d_in ||
         nets[i].d_out != nets[0].d_out)
       return PINN_E_UNSUPPORTED;
     if (n_points[i] <= 0) return PINN_E_INVALID;

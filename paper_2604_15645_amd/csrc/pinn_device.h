@@ -674,6 +674,24 @@ __device__ __forceinline__ void residual_point(const PdeDev& pde, int lapch, con
       yb[0][1] = -b2 * im;
       break;
     }
+    case kAdvection: {  // (x, t): u_t + c u_x
+      const float c = pde.coef[0];
+      r[0] = y[0][2] + c * y[0][1];
+      const float b = g[0] * r[0];
+      yb[0][1] = b * c;
+      yb[0][2] = b;
+      break;
+    }
+    case kAllenCahn: {  // (x, t): u_t - D u_xx + k u^3 - k u
+      const float D = pde.coef[0], k = pde.coef[1];
+      const float u = y[0][0], ut = y[0][2], uxx = y[0][3];
+      r[0] = ut - D * uxx + k * u * u * u - k * u;
+      const float b = g[0] * r[0];
+      yb[0][0] = b * k * (3.0f * u * u - 1.0f);
+      yb[0][2] = b;
+      yb[0][3] = -b * D;
+      break;
+    }
     default:
       break;
   }
@@ -729,6 +747,67 @@ __device__ __forceinline__ void rff_jets(const NetDev& net, const float* B, cons
 }
 
 __device__ __forceinline__ void wait_async() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Strict periodic embedding (Sec. 2.6.3): jets of the e features of one point, channels
+// value, d/dx_k in channel 1 + k, and in channel 3 the Laplacian over lap_mask when the PDE
+// has one (two inputs).  Input k of periodic_mask gives the pair cos(omega_k x_k),
+// sin(omega_k x_k), whose only derivative is in x_k; every other input passes through.
+// dw (optional): derivative of each feature's jet with respect to omega_k (pass-through
+// features: zero).
+__device__ __forceinline__ void periodic_jets(int d_in, int periodic_mask, int lap_mask, bool lap,
+                                              const float* omega, float4 x, f4 (&ej)[6], f4* dw) {
+  const float xs[3] = {x.x, x.y, x.z};
+  int f = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k >= d_in) break;
+    const int ch = 1 + k;
+    if (!((periodic_mask >> k) & 1)) {
+      f4 v = f4{0.f, 0.f, 0.f, 0.f};
+      v[0] = xs[k];
+      v[ch] = 1.0f;
+      ej[f] = v;
+      if (dw) dw[f] = f4{0.f, 0.f, 0.f, 0.f};
+      ++f;
+      continue;
+    }
+    const float w = omega[k], xk = xs[k];
+    float sv, cv;
+    sincos_fast(w * xk, sv, cv);
+    const bool inlap = lap && ((lap_mask >> k) & 1);
+    f4 c = f4{0.f, 0.f, 0.f, 0.f}, sn = f4{0.f, 0.f, 0.f, 0.f};
+    c[0] = cv;
+    sn[0] = sv;
+    c[ch] = -w * sv;
+    sn[ch] = w * cv;
+    if (inlap) {
+      c[3] = -w * w * cv;
+      sn[3] = -w * w * sv;
+    }
+    ej[f] = c;
+    ej[f + 1] = sn;
+    if (dw) {
+      f4 dc = f4{0.f, 0.f, 0.f, 0.f}, ds = f4{0.f, 0.f, 0.f, 0.f};
+      dc[0] = -xk * sv;
+      ds[0] = xk * cv;
+      dc[ch] = -sv - w * xk * cv;
+      ds[ch] = cv - w * xk * sv;
+      if (inlap) {
+        dc[3] = -2.0f * w * cv + w * w * xk * sv;
+        ds[3] = -2.0f * w * sv - w * w * xk * cv;
+      }
+      dw[f] = dc;
+      dw[f + 1] = ds;
+    }
+    f += 2;
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+    if (j >= f) {
+      ej[j] = f4{0.f, 0.f, 0.f, 0.f};
+      if (dw) dw[j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+}
 
 // Work-group barrier for LDS traffic: this wave's LDS operations complete (lgkmcnt 0), then
 // s_barrier.  Unlike __syncthreads it does not wait for the wave's outstanding vector-memory
@@ -868,7 +947,29 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
   f4 acc[NBW][CBW];
   // ---- layer 0
   const LayerDev& l0 = net.layer[0];
-  if (net.n_freq == 0) {
+  if (net.periodic_mask) {
+    // periodic embedding: z = W e(x) + b with the features' jets computed per point
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+      const int nb = wn + WN * i;
+      const bool ok = nb * 16 < l0.n_out;
+      const int n = ok ? 16 * nb + l16 : 0;
+      float w[6];
+#pragma unroll
+      for (int f = 0; f < 6; ++f) w[f] = ok && f < net.e ? l0.w[n * net.e + f] : 0.0f;
+      const float bn = ok ? l0.b[n] : 0.0f;
+#pragma unroll
+      for (int c = 0; c < CBW; ++c) {
+        const float4 x = s.PT[4 * (wc * CBW + c) + g];
+        f4 ej[6];
+        periodic_jets(net.d_in, net.periodic_mask, net.lap_mask, net.lapch >= 0, net.omega, x, ej, nullptr);
+        f4 z = f4{bn, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int f = 0; f < 6; ++f) z += w[f] * ej[f];
+        acc[i][c] = z;
+      }
+    }
+  } else if (net.n_freq == 0) {
     // identity embedding: z = W x + b on the value channel, d z / d x_k = W[:, k]
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
@@ -1409,6 +1510,85 @@ __device__ __forceinline__ void grad0_range(const float* zb, const float4* pts, 
       for (int k = 0; k < 4; ++k) t[k] += (double)red[(w * 256 + i) * 4 + k];
     for (int k = 0; k < d_in; ++k) slot[(size_t)i * d_in + k] = t[k];
     slot[(size_t)n_out * d_in + i] = t[3];
+  }
+}
+
+// First-layer weight gradient with the periodic embedding (Sec. 2.6.3): for every output o
+// W_bar[o][j] = sum_points sum_c zbar[o][c] e_j[c], b_bar[o] = sum zbar[o][0], and for the
+// features j of trained periods G[o][j] = sum zbar[o][c] d e_j[c] / d omega (the period
+// gradient follows from G and W in the reduction).  Four output blocks at a time; per
+// block the sums run over the cp blocks in order.  Slot: [n_out][e], [n_out], [n_out][ng].
+// red: LDS scratch of kWaves * 64 * 13 floats.
+__device__ __forceinline__ void grad0p_range(const Grad0Args& A, int64_t cb_lo, int64_t cb_hi, double* slot,
+                                             float* red) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nob = A.n_out / 16, e = A.e;
+  const bool lap = A.lap_mask != 0;
+  // features whose jets depend on a trained period (bit f; two per trained input)
+  int tmask = 0, ng = 0;
+  {
+    int f = 0;
+    for (int k = 0; k < A.d_in; ++k) {
+      if (!((A.periodic_mask >> k) & 1)) {
+        ++f;
+        continue;
+      }
+      if ((A.period_train_mask >> k) & 1) {
+        tmask |= 3 << f;
+        ng += 2;
+      }
+      f += 2;
+    }
+  }
+  // sums per output: sum[0 .. e) weights, sum[6] bias, sum[7 + f] period term of feature f
+  constexpr int kG = 4;  // output blocks per pass
+  for (int og = 0; og < nob; og += kG) {
+    float sum[kG][13];
+#pragma unroll
+    for (int q = 0; q < kG; ++q)
+#pragma unroll
+      for (int a = 0; a < 13; ++a) sum[q][a] = 0.f;
+    for (int64_t cb = cb_lo + wave; cb < cb_hi; cb += kWaves) {
+      f4 ej[6], dw[6];
+      periodic_jets(A.d_in, A.periodic_mask, A.lap_mask, lap, A.omega, A.pts[4 * cb + g], ej, dw);
+#pragma unroll
+      for (int q = 0; q < kG; ++q) {
+        const int ob = og + q;
+        if (ob >= nob) continue;
+        const f4 z = to_f4(*jet_frag(const_cast<float*>(A.zb), cb, ob, nob, lane));
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+          if (j < e) sum[q][j] += z.x * ej[j].x + z.y * ej[j].y + z.z * ej[j].z + z.w * ej[j].w;
+        sum[q][6] += z.x;
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+          if ((tmask >> f) & 1) sum[q][7 + f] += z.x * dw[f].x + z.y * dw[f].y + z.z * dw[f].z + z.w * dw[f].w;
+      }
+    }
+    __syncthreads();  // red free
+#pragma unroll
+    for (int q = 0; q < kG; ++q)
+#pragma unroll
+      for (int a = 0; a < 13; ++a) {
+        float v = sum[q][a];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (g == 0) red[((wave * kG + q) * 16 + l16) * 13 + a] = v;
+      }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kG * 16; i += kThreads) {
+      const int o = 16 * og + i;
+      if (o >= A.n_out) continue;
+      double t[13];
+      for (int a = 0; a < 13; ++a) t[a] = 0.0;
+      for (int w = 0; w < kWaves; ++w)
+        for (int a = 0; a < 13; ++a) t[a] += (double)red[(w * kG * 16 + i) * 13 + a];
+      for (int j = 0; j < e; ++j) slot[(size_t)o * e + j] = t[j];
+      slot[(size_t)A.n_out * e + o] = t[6];
+      for (int f = 0, j = 0; f < e; ++f)
+        if ((tmask >> f) & 1) slot[(size_t)A.n_out * (e + 1) + (size_t)o * ng + j++] = t[7 + f];
+    }
   }
 }
 

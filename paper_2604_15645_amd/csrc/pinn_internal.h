@@ -28,7 +28,7 @@ __host__ __device__ constexpr bool is_split(int prec) { return prec != kFP32; }
 enum { kTanh = 0, kSin = 1 };
 // Kernel activation code: kTanh or kSin, plus kLapFlag when jet channel 3 is a Laplacian.
 enum { kLapFlag = 2 };
-enum { kBurgers = 1, kEuler1D = 2, kNS2D = 3, kMaxwell = 4 };
+enum { kBurgers = 1, kEuler1D = 2, kNS2D = 3, kMaxwell = 4, kAdvection = 5, kAllenCahn = 6 };
 
 // One linear layer as the kernels see it (all pointers into the workspace).
 struct LayerDev {
@@ -44,8 +44,10 @@ struct LayerDev {
 struct NetDev {
   int L;               // hidden layers
   int d_in, d_out;
-  int e;               // embedding width (d_in or 2 * n_freq)
+  int e;               // embedding width (d_in, 2 * n_freq, or inputs with periodic ones twice)
   int n_freq;
+  int periodic_mask;   // inputs embedded as [cos, sin](omega_k x_k) (0: identity or Fourier)
+  const float* omega;  // omega_k = 2 pi / P_k of the periodic inputs (workspace, from k_stage)
   int lap_mask;        // inputs in the Laplacian set
   int lapch;           // channel of the Laplacian (-1 if none)
   float w0;
@@ -88,6 +90,10 @@ struct Work {
 struct StageArgs {
   int n_layers;
   int rwf, has_bias;
+  int periodic_mask, period_train_mask;
+  float period[3];
+  int64_t off_p;                // first trainable period in params
+  float* omega;                 // out: 2 pi / P_k per input (0 for inputs that pass through)
   const float* params;
   int64_t off_w[kMaxLayers], off_s[kMaxLayers], off_b[kMaxLayers];
   int n_in[kMaxLayers], n_out[kMaxLayers];
@@ -141,7 +147,26 @@ struct Grad0Args {
   const float4* pts;
   int n_out, d_in;
   int64_t n_cb;       // cp blocks of the padded point set
-  double* slots;      // [gridDim][n_out * (d_in + 1)]
+  double* slots;      // [gridDim][n_out * (e + 1) (+ n_out * 2 * trained periods)]
+  // periodic embedding (0: identity): the weight gradient runs over the e embedding
+  // features, and for every trained period the sums G[o][j] = sum zbar[o] . d e_j / d omega
+  // of its two features follow the bias sums
+  int periodic_mask, period_train_mask, lap_mask, e;
+  const float* omega;
+};
+
+// d(loss)/dP_k of the trained periods: (-omega_k / P_k) sum_o sum_j W[o][j] G[o][j], the G
+// sums reduced over the work-group slots in slot order.
+struct PeriodReduceArgs {
+  const double* slots;
+  int n_slots;
+  int64_t slot_stride;
+  int n_out, e;
+  int periodic_mask, period_train_mask, d_in;
+  const float* w;       // effective first-layer weights, n_out x e
+  const float* omega;
+  double* grad;         // the gradient, periods at off_p
+  int64_t off_p;
 };
 
 struct ReduceArgs {
@@ -244,6 +269,7 @@ int launch_forward(int prec, int act, int H, int P, const FwdArgs& a, int grid, 
 int launch_backward(int prec, int act, int H, bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s);
 int launch_grad0(const Grad0Args& a, int grid, hipStream_t s);
 int launch_reduce_layer(const ReduceArgs& a, hipStream_t s);
+int launch_reduce_period(const PeriodReduceArgs& a, hipStream_t s);
 int launch_reduce_loss(const LossArgs& a, hipStream_t s);
 int launch_batched(int prec, int act, const BatchArgs& a, int grid, size_t lds, hipStream_t s);
 int launch_reduce_batched(const BatchReduceArgs& a, hipStream_t s);

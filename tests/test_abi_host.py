@@ -80,6 +80,14 @@ def test_validation_errors(lib):
     assert code_of(lambda: ws(dict(mx, n_freq=20), mp)) == -2             # m multiple of 16
     eu, ep = c["euler"]["net"], c["euler"]["pde"]
     assert code_of(lambda: ws(eu, dict(ep, coef=[1.0, 0, 0, 0]))) == -2   # gamma > 1
+    an, ap = c["advection"]["net"], c["advection"]["pde"]
+    assert ws(an, ap) > 0
+    assert code_of(lambda: ws(an, dict(ap, lap_mask=1))) == -2            # first derivatives only
+    ac, acp = c["allen_cahn"]["net"], c["allen_cahn"]["pde"]
+    assert ws(ac, acp) > 0
+    assert code_of(lambda: ws(ac, dict(acp, lap_mask=0))) == -2           # needs u_xx
+    assert code_of(lambda: ws(mx, dict(mp, pde="advection"))) == -2       # inputs (x, t)
+    assert binding.n_residuals("advection") == binding.n_residuals("allen_cahn") == 1
 
 
 def test_precision_codes(lib):

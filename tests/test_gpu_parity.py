@@ -72,7 +72,8 @@ def check(got, ref, prec, what="", tol=None):
     assert not bad, (what, prec, bad)
 
 
-CASES = [("burgers", 1000), ("euler", 900), ("ns", 700), ("maxwell", 300)]
+CASES = [("burgers", 1000), ("euler", 900), ("ns", 700), ("maxwell", 300), ("advection", 800),
+         ("allen_cahn", 600)]
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -114,7 +115,7 @@ def test_tiny_and_ragged_point_counts(oracle, dev, n, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("name", ["burgers", "euler", "ns", "maxwell"])
+@pytest.mark.parametrize("name", ["burgers", "euler", "ns", "maxwell", "advection"])
 def test_constant_output_network_is_exact(dev, name, prec):
     """With the output weights zero the outputs are the (non-zero) output biases, every
     derivative vanishes, and so do the residual of every PDE, the loss and the whole
@@ -181,3 +182,35 @@ def test_repeat_is_bitwise_identical(dev):
     b = run_gpu(case, dev, "bf16x3")
     for k in ("loss", "grad", "residual"):
         assert np.array_equal(a[k], b[k]), k
+
+
+PERIODIC = {
+    # Sec. 2.6.3: x periodic with a fixed period, t periodic with a trainable one
+    "burgers": dict(periodic_mask=3, period_train_mask=2, period=[2.0, 1.3, 0.0]),
+    # the listing of App. A.4: x periodic (P = 2 pi), t passed through
+    "advection": dict(periodic_mask=1, period_train_mask=0, period=[2 * np.pi, 0.0, 0.0]),
+    "allen_cahn": dict(periodic_mask=3, period_train_mask=2, period=[2.0, 1.2, 0.0]),
+    # Maxwell in a periodic box (Sec. 4.8): x and y periodic, t with a trainable period
+    "maxwell": dict(periodic_mask=7, period_train_mask=4, period=[1.0, 1.0, 1.5]),
+}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", ["burgers", "advection", "allen_cahn", "maxwell"])
+def test_periodic_embedding(oracle, dev, name, prec):
+    """Strict periodic input embedding (Sec. 2.6.3) with fixed and trainable periods: every
+    residual, loss term and the whole gradient, the trained period's entry included."""
+    from paper_2604_15645_amd import synth
+    cfg = synth.CONFIGS[name]
+    net = dict(cfg["net"], n_freq=0, widths=[128, 128] if name == "maxwell" else [64, 64, 64],
+               **PERIODIC[name])
+    anchors = []
+    case = synth.make_custom(net, dict(cfg["pde"]), cfg["box"], 700, seed=91, anchors=anchors)
+    got = run_gpu(case, dev, prec)
+    ref = run_oracle(oracle, case)
+    check(got, ref, prec, "periodic-" + name)
+    ntp = bin(net["period_train_mask"]).count("1")
+    if ntp:
+        g, r = got["grad"][-ntp:], ref["grad"][-ntp:]
+        print("period gradient", g, r)
+        assert np.all(np.abs(g - r) <= TOL[prec] * np.abs(r) + 1e-12), (g, r)
