@@ -205,3 +205,28 @@ def loss_grad(net_spec, pde_spec, params, B, pts, anchors=(), want_grad=True,
     if rc != 0:
         raise ValueError("or_loss_grad failed: %d" % rc)
     return {"loss": loss, "residual": res, "grad": grad}
+
+
+def term_grads(net_spec, pde_spec, params, B, pts, anchors=()):
+    """Gradient of each loss term on its own (Sec. 2.6.4 balances the terms by the norms
+    of these): term 0 is the residual term (every residual component with its weight
+    lambda_c), term 1 + a the supervision set a (with its weight).  Each term involves
+    only its own points, so its gradient is the gradient of the loss evaluated on those
+    points alone.  Returns (loss terms as loss_grad does, list of gradients)."""
+    d_in = int(net_spec["d_in"])
+    full = loss_grad(net_spec, pde_spec, params, B, pts, anchors, want_residual=False)
+    grads = [loss_grad(net_spec, pde_spec, params, B, pts, (), want_residual=False)["grad"]]
+    for a in anchors:
+        grads.append(loss_grad(net_spec, pde_spec, params, B, np.zeros((0, d_in)), [a],
+                               want_residual=False)["grad"])
+    return full["loss"], grads
+
+
+def balance_update(grads, lam, alpha=0.9, eps=1e-9):
+    """Loss-balancing weights of Sec. 2.6.4: with n_t the 2-norm of term t's gradient,
+    lambda_hat_t = (sum_s n_s) / (n_t + eps) (eps guards a vanishing gradient, as the code
+    listing of the paper does), and the weights move by an exponential moving average,
+    lambda_t <- alpha lambda_t + (1 - alpha) lambda_hat_t.  Returns (lambda, lambda_hat)."""
+    norms = np.array([np.sqrt(np.sum(np.asarray(g, dtype=np.float64) ** 2)) for g in grads])
+    hat = norms.sum() / (norms + eps)
+    return alpha * np.asarray(lam, dtype=np.float64) + (1.0 - alpha) * hat, hat

@@ -690,3 +690,41 @@ def test_planted_mistake_is_caught(oracle):
     assert not np.allclose(wrong[:, 0], exp, rtol=1e-6)
     right = oracle.pde_residual(dict(pde="burgers", lap_mask=1, coef=[nu, 0, 0, 0]), 2, 1, j)
     assert np.allclose(right[:, 0], exp, rtol=1e-13)
+
+
+# -------------------------------------------------- loss balancing (Sec. 2.6.4)
+
+def test_term_gradients_add_up_and_match_differences(oracle):
+    """The per-term gradients sum to the gradient of the whole loss, and the supervision
+    term's gradient matches central differences of that term's loss alone."""
+    case = synth.make_case("burgers", n_points=60, seed=23, perturb=True)
+    case["anchors"] = [dict(a, points=a["points"][:10], targets=a["targets"][:10]) for a in case["anchors"]]
+    net, pde, p = case["net"], case["pde"], case["params"].astype(np.float64)
+    loss, grads = oracle.term_grads(net, pde, p, None, case["points"], case["anchors"])
+    full = oracle.loss_grad(net, pde, p, None, case["points"], case["anchors"])
+    assert len(grads) == 3
+    assert relerr(sum(grads), full["grad"]) < 1e-14
+    assert np.array_equal(loss, full["loss"])
+    a = case["anchors"][1]
+    for i in rng(24).choice(p.size, size=12, replace=False):
+        h = 1e-6 * max(1.0, abs(p[i]))
+        pp = p.copy()
+        pp[i] += h
+        lp = oracle.loss_grad(net, pde, pp, None, np.zeros((0, 2)), [a], want_grad=False)["loss"][0]
+        pp[i] -= 2 * h
+        lm = oracle.loss_grad(net, pde, pp, None, np.zeros((0, 2)), [a], want_grad=False)["loss"][0]
+        assert abs((lp - lm) / (2 * h) - grads[2][i]) <= 1e-7 * max(1.0, np.abs(grads[2]).max())
+
+
+def test_balance_update_worked_example(oracle):
+    """Gradient norms 1, 2, 3 give lambda_hat = 6, 3, 2 (the sum of the norms over each);
+    alpha = 0.9 moves the weights a tenth of the way there; rescaling every gradient by the
+    same factor leaves lambda_hat unchanged; alpha = 1 keeps the weights."""
+    g = [np.array([1.0, 0.0]), np.array([0.0, 2.0]), np.array([1.8, 2.4])]
+    lam, hat = oracle.balance_update(g, [1.0, 1.0, 1.0], alpha=0.9, eps=0.0)
+    assert np.allclose(hat, [6.0, 3.0, 2.0], rtol=1e-15)
+    assert np.allclose(lam, [1.5, 1.2, 1.1], rtol=1e-15)
+    _, hat2 = oracle.balance_update([7.5 * x for x in g], [1.0, 1.0, 1.0], eps=0.0)
+    assert np.allclose(hat2, hat, rtol=1e-14)
+    lam1, _ = oracle.balance_update(g, [0.3, 4.0, 2.0], alpha=1.0)
+    assert np.array_equal(lam1, [0.3, 4.0, 2.0])
