@@ -201,6 +201,34 @@ int pinn_residual_bwd_noalloc(const pinn_net* net, const pinn_pde* pde, const fl
                               const pinn_tune* tune, float* residual, double* loss, double* grad,
                               pinn_stream_t stream);
 
+/* Per-term gradients for loss balancing (Sec. 2.6.4).  Term 0 is the residual term (every
+ * residual component with its weight lambda_res[c], mean over the n_points residual points
+ * or pde->norm_N), term 1 + a the supervision set a (its weight and mean).  Each term
+ * involves only its own points, so the call runs the fused step over each term's points
+ * in turn (together the point work of one pinn_residual_bwd call):
+ *   loss   FP64 [1 + n_res + n_anchor], as pinn_residual_bwd (the total is the sum)
+ *   grads  FP64 [(1 + n_anchor) x pinn_param_count], term t's gradient at t * n_params;
+ *          their sum is pinn_residual_bwd's gradient
+ * n_points >= 1 and every set non-empty.  Workspace from pinn_term_grads_workspace_bytes. */
+int pinn_term_grads_workspace_bytes(const pinn_net* net, const pinn_pde* pde, int64_t n_points,
+                                    const pinn_anchor* anchors, int n_anchor, int prec,
+                                    const pinn_tune* tune, size_t* bytes);
+int pinn_term_grads(const pinn_net* net, const pinn_pde* pde, const float* params,
+                    const float* fourier_B, const float* points, int64_t n_points,
+                    const pinn_anchor* anchors, int n_anchor, int prec, uint32_t flags,
+                    const pinn_tune* tune, double* loss, double* grads, void* workspace,
+                    size_t ws_bytes, pinn_stream_t stream);
+
+/* Loss-balancing weights from per-term gradients (Sec. 2.6.4), on the device, without a
+ * host round trip.  With n_t = ||grads[t]||_2 (FP64, fixed summation order):
+ *   lambda_hat[t] = (n_0 + ... + n_{T-1}) / (n_t + eps)
+ *   lambda[t]    <- alpha * lambda[t] + (1 - alpha) * lambda_hat[t]     (paper: alpha 0.9)
+ * eps (>= 0) guards a vanishing gradient (the paper's code uses 1e-9).  grads: device FP64
+ * [n_terms x n_params]; lambda: device FP64 [n_terms], updated in place; lambda_hat:
+ * device FP64 [n_terms] or NULL.  1 <= n_terms <= 16, 0 <= alpha <= 1. */
+int pinn_balance_update(const double* grads, int n_terms, int64_t n_params, double* lambda,
+                        double* lambda_hat, double alpha, double eps, pinn_stream_t stream);
+
 /* Many independent networks in one persistent launch (the paper's benchmark sweeps ran
  * each network separately).  Instance i has its own descriptor nets[i] (host array), the
  * shared PDE `pde`, its own params[i], points[i] (n_points[i] x d_in, device) and grads[i]

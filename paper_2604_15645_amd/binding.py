@@ -58,7 +58,8 @@ _lib = None
 # Symbols the header declares (checked by the CPU tests).
 EXPORTS = ["pinn_param_count", "pinn_n_residuals", "pinn_workspace_bytes", "pinn_residual_fwd",
            "pinn_residual_bwd", "pinn_residual_bwd_noalloc", "pinn_batched_workspace_bytes",
-           "pinn_batched_bwd",
+           "pinn_batched_bwd", "pinn_term_grads_workspace_bytes", "pinn_term_grads",
+           "pinn_balance_update",
            "pinn_timing_enable", "pinn_timing_collect", "pinn_status_string"]
 
 
@@ -92,6 +93,14 @@ def lib():
         L.pinn_batched_bwd.restype = ctypes.c_int
         L.pinn_batched_bwd.argtypes = [P(PinnNet), P(PinnPde), P(vp), P(vp), P(ctypes.c_int64), ctypes.c_int,
                                        ctypes.c_int, P(PinnTune), P(vp), vp, vp, ctypes.c_size_t, vp]
+        L.pinn_term_grads_workspace_bytes.restype = ctypes.c_int
+        L.pinn_term_grads_workspace_bytes.argtypes = [P(PinnNet), P(PinnPde), ctypes.c_int64, P(PinnAnchor),
+                                                      ctypes.c_int, ctypes.c_int, P(PinnTune), P(ctypes.c_size_t)]
+        L.pinn_term_grads.restype = ctypes.c_int
+        L.pinn_term_grads.argtypes = common[:-2] + [vp, vp, vp, ctypes.c_size_t, vp]
+        L.pinn_balance_update.restype = ctypes.c_int
+        L.pinn_balance_update.argtypes = [vp, ctypes.c_int, ctypes.c_int64, vp, vp, ctypes.c_double,
+                                          ctypes.c_double, vp]
         L.pinn_timing_enable.restype = ctypes.c_int
         L.pinn_timing_enable.argtypes = [ctypes.c_int]
         L.pinn_timing_collect.restype = ctypes.c_int
@@ -338,6 +347,60 @@ def residual_step_noalloc(net_spec, pde_spec, params, B, points, anchors=(), pre
     if rc != 0:
         raise PinnError("pinn_residual_bwd_noalloc", rc)
     return {"loss": loss, "grad": g, "residual": res}
+
+
+def term_grads(net_spec, pde_spec, params, B, points, anchors=(), prec="bf16x3", tune=None,
+               flags=0, workspace=None):
+    """One call of pinn_term_grads: dict(loss = FP64 [1 + n_res + n_anchor],
+    grads = FP64 [1 + n_anchor, n_params]) -- the residual term's gradient, then each
+    supervision set's."""
+    _check_dev(params, "params")
+    _check_dev(points, "points")
+    if B is not None:
+        _check_dev(B, "fourier_B")
+    for a in anchors:
+        _check_dev(a["points"], "anchor points")
+        _check_dev(a["targets"], "anchor targets")
+    _check_shapes(net_spec, params, B, points, anchors)
+    dev = points.device
+    n, p = net_struct(net_spec), pde_struct(pde_spec)
+    arr = _anchor_array(anchors)
+    t = tune_struct(tune)
+    tref = ctypes.byref(t) if t is not None else None
+    npts = int(points.shape[0])
+    size = ctypes.c_size_t(0)
+    rc = lib().pinn_term_grads_workspace_bytes(ctypes.byref(n), ctypes.byref(p), npts, arr, len(anchors),
+                                               PRECS[prec], tref, ctypes.byref(size))
+    if rc != 0:
+        raise PinnError("pinn_term_grads_workspace_bytes", rc)
+    ws = (workspace or _ws(dev)).get(int(size.value))
+    nres = n_residuals(pde_spec["pde"])
+    loss = torch.empty(1 + nres + len(anchors), dtype=torch.float64, device=dev)
+    grads = torch.empty((1 + len(anchors), param_count(net_spec)), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = lib().pinn_term_grads(ctypes.byref(n), ctypes.byref(p), params.data_ptr(),
+                               B.data_ptr() if B is not None else None, points.data_ptr(), npts, arr,
+                               len(anchors), PRECS[prec], int(flags), tref, loss.data_ptr(), grads.data_ptr(),
+                               ws.data_ptr(), ws.numel(), stream)
+    if rc != 0:
+        raise PinnError("pinn_term_grads", rc)
+    return {"loss": loss, "grads": grads}
+
+
+def balance_update(grads, lam, alpha=0.9, eps=1e-9, want_hat=True):
+    """pinn_balance_update on device tensors: grads FP64 [T, n_params], lam FP64 [T]
+    (updated in place).  Returns lambda_hat (FP64 [T]) or None."""
+    _check_dev(grads, "grads", torch.float64)
+    _check_dev(lam, "lambda", torch.float64)
+    if grads.dim() != 2 or lam.numel() != grads.shape[0]:
+        raise ValueError("grads must be (T, n_params) and lambda (T,)")
+    hat = torch.empty_like(lam) if want_hat else None
+    stream = torch.cuda.current_stream(grads.device).cuda_stream
+    rc = lib().pinn_balance_update(grads.data_ptr(), int(grads.shape[0]), int(grads.shape[1]), lam.data_ptr(),
+                                   hat.data_ptr() if hat is not None else None, float(alpha), float(eps), stream)
+    if rc != 0:
+        raise PinnError("pinn_balance_update", rc)
+    return hat
 
 
 def timing_enable(on=True):

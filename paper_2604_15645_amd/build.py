@@ -18,7 +18,9 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
 ]
-SOURCES = ["k_forward.hip", "k_backward.hip", "k_batched.hip", "k_misc.hip", "pinn_noalloc.hip", "pinn_api.cpp"]
+SOURCES = ["k_forward_fp32.hip", "k_forward_bf16x3.hip", "k_forward_fp16x3.hip", "k_backward_fp32.hip",
+           "k_backward_bf16x3.hip", "k_backward_fp16x3.hip", "k_batched.hip", "k_misc.hip", "pinn_noalloc.hip",
+           "pinn_api.cpp"]
 
 
 def hipcc():
@@ -40,7 +42,7 @@ def _compile(src):
 def build(verbose=False):
     """Compile every source and link libpinn.so (always rebuilds)."""
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
+    with ThreadPoolExecutor(min(len(SOURCES), max(2, os.cpu_count() or 2))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs

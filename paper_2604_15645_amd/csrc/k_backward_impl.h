@@ -1,8 +1,9 @@
-// k_backward.hip -- one linear layer's backward: the generic, wide and split-role kernels
+// k_backward_impl.h -- one linear layer's backward: the generic, wide and split-role kernels
 // and their launcher.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#pragma once
 #include "pinn_device.h"
 
 namespace pinn {
@@ -572,6 +573,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
 
 
 // ================================================================== launcher
+// (instantiated per precision in k_backward_<precision>.hip, so that the three compile in
+// parallel)
 
 namespace {
 
@@ -666,10 +669,9 @@ int bwd_a(int act, int H, bool embed, const BwdArgs& a, int grid, size_t lds, hi
   }
 }
 
-int launch_backward(int prec, int act, int H, bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  if (prec == kFP32) return bwd_a<kFP32>(act, H, embed, a, grid, lds, s);
-  if (prec == kFP16X3) return bwd_a<kFP16X3>(act, H, embed, a, grid, lds, s);
-  return bwd_a<kBF16X3>(act, H, embed, a, grid, lds, s);
-}
+// Each precision is instantiated in its own translation unit.
+extern template int bwd_a<kFP32>(int act, int H, bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s);
+extern template int bwd_a<kBF16X3>(int act, int H, bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s);
+extern template int bwd_a<kFP16X3>(int act, int H, bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s);
 
 }  // namespace pinn

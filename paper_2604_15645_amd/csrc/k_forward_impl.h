@@ -1,8 +1,9 @@
-// k_forward.hip -- the fused forward kernel (embedding jets, hidden layers, output layer,
+// k_forward_impl.h -- the fused forward kernel (embedding jets, hidden layers, output layer,
 // residual, loss partial sums, adjoint seed, output-layer backward) and its launcher.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#pragma once
 #include "pinn_device.h"
 
 namespace pinn {
@@ -39,6 +40,8 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void k_forward(const FwdArgs A) {
 
 
 // ================================================================== launcher
+// (instantiated per precision in k_forward_<precision>.hip, so that the three compile in
+// parallel)
 
 namespace {
 
@@ -82,10 +85,9 @@ int fwd_a(int act, int H, int P, const FwdArgs& a, int grid, size_t lds, hipStre
   }
 }
 
-int launch_forward(int prec, int act, int H, int P, const FwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  if (prec == kFP32) return fwd_a<kFP32>(act, H, P, a, grid, lds, s);
-  if (prec == kFP16X3) return fwd_a<kFP16X3>(act, H, P, a, grid, lds, s);
-  return fwd_a<kBF16X3>(act, H, P, a, grid, lds, s);
-}
+// Each precision is instantiated in its own translation unit.
+extern template int fwd_a<kFP32>(int act, int H, int P, const FwdArgs& a, int grid, size_t lds, hipStream_t s);
+extern template int fwd_a<kBF16X3>(int act, int H, int P, const FwdArgs& a, int grid, size_t lds, hipStream_t s);
+extern template int fwd_a<kFP16X3>(int act, int H, int P, const FwdArgs& a, int grid, size_t lds, hipStream_t s);
 
 }  // namespace pinn

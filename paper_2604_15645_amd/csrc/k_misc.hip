@@ -360,6 +360,67 @@ int launch_reduce_loss_batched(const BatchLossArgs& a, hipStream_t s) {
   return launch_status(hipGetLastError());
 }
 
+// Loss terms of the per-term call: each term's own call wrote [total, residual
+// components, its supervision set]; the caller's array is [total, components, sets].
+__global__ void k_assemble_terms(const double* tmp, int n_terms, int n_res, double* loss) {
+  if (threadIdx.x != 0) return;
+  const int stride = 2 + n_res;
+  double total = 0.0;
+  for (int c = 0; c < n_res; ++c) {
+    loss[1 + c] = tmp[1 + c];
+    total += tmp[1 + c];
+  }
+  for (int t = 1; t < n_terms; ++t) {
+    const double v = tmp[(size_t)t * stride + 1 + n_res];
+    loss[1 + n_res + t - 1] = v;
+    total += v;
+  }
+  loss[0] = total;
+}
+
+// Loss-balancing weights (Sec. 2.6.4): n_t = ||grad_t||_2 (FP64, fixed summation order),
+// lambda_hat_t = sum_s n_s / (n_t + eps), lambda_t <- alpha lambda_t + (1 - alpha) lambda_hat_t.
+__global__ void k_balance(const double* grads, int n_terms, int64_t n_params, double* lambda, double* hat,
+                          double alpha, double eps) {
+  __shared__ double part[256];
+  __shared__ double norms[16];
+  for (int t = 0; t < n_terms; ++t) {
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < n_params; i += 256) {
+      const double g = grads[(size_t)t * n_params + i];
+      v += g * g;
+    }
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+      if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) norms[t] = sqrt(part[0]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int t = 0; t < n_terms; ++t) sum += norms[t];
+    for (int t = 0; t < n_terms; ++t) {
+      const double h = sum / (norms[t] + eps);
+      if (hat) hat[t] = h;
+      lambda[t] = alpha * lambda[t] + (1.0 - alpha) * h;
+    }
+  }
+}
+
+int launch_assemble_terms(const double* tmp, int n_terms, int n_res, double* loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_assemble_terms, dim3(1), dim3(64), 0, s, tmp, n_terms, n_res, loss);
+  return launch_status(hipGetLastError());
+}
+
+int launch_balance(const double* grads, int n_terms, int64_t n_params, double* lambda, double* hat, double alpha,
+                   double eps, hipStream_t s) {
+  hipLaunchKernelGGL(k_balance, dim3(1), dim3(256), 0, s, grads, n_terms, n_params, lambda, hat, alpha, eps);
+  return launch_status(hipGetLastError());
+}
+
 int launch_reduce_period(const PeriodReduceArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_period, dim3(1), dim3(256), 0, s, a);
   return launch_status(hipGetLastError());

@@ -993,6 +993,68 @@ int pinn_residual_bwd(const pinn_net* net, const pinn_pde* pde, const float* par
              grad, workspace, ws_bytes, stream, true);
 }
 
+int pinn_term_grads_workspace_bytes(const pinn_net* net, const pinn_pde* pde, int64_t n_points,
+                                    const pinn_anchor* anchors, int n_anchor, int prec, const pinn_tune* tune,
+                                    size_t* bytes) {
+  if (!bytes || !pde || n_points < 1 || n_anchor < 0 || n_anchor > kMaxAnchors || (n_anchor > 0 && !anchors))
+    return PINN_E_INVALID;
+  for (int a = 0; a < n_anchor; ++a)
+    if (anchors[a].n < 1) return PINN_E_INVALID;
+  Plan p;
+  int rc = make_plan(net, pde, n_points, nullptr, 0, prec, 1, tune, &p);
+  if (rc) return rc;
+  int64_t run_bytes = p.bytes;
+  for (int a = 0; a < n_anchor; ++a) {
+    rc = make_plan(net, pde, 0, &anchors[a], 1, prec, 1, tune, &p);
+    if (rc) return rc;
+    run_bytes = std::max(run_bytes, p.bytes);
+  }
+  const int64_t tmp = align_up((int64_t)(1 + n_anchor) * (2 + n_res_of(pde->pde_id)) * 8, kAlign);
+  *bytes = (size_t)(tmp + run_bytes);
+  return PINN_OK;
+}
+
+int pinn_term_grads(const pinn_net* net, const pinn_pde* pde, const float* params, const float* fourier_B,
+                    const float* points, int64_t n_points, const pinn_anchor* anchors, int n_anchor, int prec,
+                    uint32_t flags, const pinn_tune* tune, double* loss, double* grads, void* workspace,
+                    size_t ws_bytes, pinn_stream_t stream) {
+  size_t need = 0;
+  int rc = pinn_term_grads_workspace_bytes(net, pde, n_points, anchors, n_anchor, prec, tune, &need);
+  if (rc) return rc;
+  if (!loss || !grads || !workspace) return PINN_E_INVALID;
+  if (ws_bytes < need) return PINN_E_WORKSPACE;
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return PINN_E_INVALID;
+  const int nres = n_res_of(pde->pde_id);
+  const int64_t np = pinn_param_count(net);
+  const int64_t tmp_bytes = align_up((int64_t)(1 + n_anchor) * (2 + nres) * 8, kAlign);
+  double* tmp = static_cast<double*>(workspace);
+  void* run_ws = static_cast<char*>(workspace) + tmp_bytes;
+  const size_t run_bytes = ws_bytes - (size_t)tmp_bytes;
+  // each term over its own points: together the same point work as one fused call
+  rc = run(net, pde, params, fourier_B, points, n_points, nullptr, 0, prec, flags, tune, nullptr, tmp, grads, run_ws,
+           run_bytes, stream, true);
+  if (rc) return rc;
+  for (int a = 0; a < n_anchor; ++a) {
+    rc = run(net, pde, params, fourier_B, nullptr, 0, &anchors[a], 1, prec, flags & ~(uint32_t)PINN_FLAG_CHECK_FINITE,
+             tune, nullptr, tmp + (size_t)(1 + a) * (2 + nres), grads + (size_t)(1 + a) * np, run_ws, run_bytes,
+             stream, true);
+    if (rc) return rc;
+  }
+  rc = launch_assemble_terms(tmp, 1 + n_anchor, nres, loss, reinterpret_cast<hipStream_t>(stream));
+  if (rc) return rc;
+  return hip_rc(hipGetLastError());
+}
+
+int pinn_balance_update(const double* grads, int n_terms, int64_t n_params, double* lambda, double* lambda_hat,
+                        double alpha, double eps, pinn_stream_t stream) {
+  if (!grads || !lambda || n_terms < 1 || n_terms > 16 || n_params < 1) return PINN_E_INVALID;
+  if (!(alpha >= 0.0 && alpha <= 1.0) || !(eps >= 0.0) || !std::isfinite(eps)) return PINN_E_INVALID;
+  int rc = launch_balance(grads, n_terms, n_params, lambda, lambda_hat, alpha, eps,
+                          reinterpret_cast<hipStream_t>(stream));
+  if (rc) return rc;
+  return hip_rc(hipGetLastError());
+}
+
 int pinn_batched_workspace_bytes(const pinn_net* nets, const pinn_pde* pde, const int64_t* n_points, int n_inst,
                                  int prec, const pinn_tune* tune_table, size_t* bytes) {
   if (!bytes) return PINN_E_INVALID;

@@ -270,6 +270,9 @@ int launch_backward(int prec, int act, int H, bool embed, const BwdArgs& a, int 
 int launch_grad0(const Grad0Args& a, int grid, hipStream_t s);
 int launch_reduce_layer(const ReduceArgs& a, hipStream_t s);
 int launch_reduce_period(const PeriodReduceArgs& a, hipStream_t s);
+int launch_assemble_terms(const double* tmp, int n_terms, int n_res, double* loss, hipStream_t s);
+int launch_balance(const double* grads, int n_terms, int64_t n_params, double* lambda, double* hat, double alpha,
+                   double eps, hipStream_t s);
 int launch_reduce_loss(const LossArgs& a, hipStream_t s);
 int launch_batched(int prec, int act, const BatchArgs& a, int grid, size_t lds, hipStream_t s);
 int launch_reduce_batched(const BatchReduceArgs& a, hipStream_t s);

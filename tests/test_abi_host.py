@@ -90,6 +90,24 @@ def test_validation_errors(lib):
     assert binding.n_residuals("advection") == binding.n_residuals("allen_cahn") == 1
 
 
+def test_term_grads_validation(lib):
+    """Per-term gradients need at least one residual point and non-empty supervision sets;
+    the balance update rejects bad sizes and weights on the host."""
+    import ctypes
+    c = synth.CONFIGS["burgers"]
+    n, p = binding.net_struct(c["net"]), binding.pde_struct(c["pde"])
+    size = ctypes.c_size_t(0)
+    arr = binding._anchor_array(())
+    assert lib.pinn_term_grads_workspace_bytes(ctypes.byref(n), ctypes.byref(p), 100, arr, 0, 1, None,
+                                               ctypes.byref(size)) == 0
+    assert size.value >= binding.workspace_bytes(c["net"], c["pde"], 100, (), "bf16x3", True)
+    assert lib.pinn_term_grads_workspace_bytes(ctypes.byref(n), ctypes.byref(p), 0, arr, 0, 1, None,
+                                               ctypes.byref(size)) == -1
+    assert lib.pinn_balance_update(16, 0, 10, 16, None, 0.9, 1e-9, None) == -1
+    assert lib.pinn_balance_update(16, 3, 10, 16, None, 1.5, 1e-9, None) == -1
+    assert lib.pinn_balance_update(16, 3, 10, 16, None, 0.9, -1.0, None) == -1
+
+
 def test_precision_codes(lib):
     """FP32, BF16X3 and FP16X3 are implemented; single-product BF16 is refused as
     unsupported, an unknown code as invalid; the split forms need the same workspace."""

@@ -1,0 +1,74 @@
+"""Per-term gradients and the loss-balancing update (Sec. 2.6.4) on the GPU, against the
+FP64 oracle: every term's gradient to the precision gate, their sum against the fused
+step, and the device-side weight update against the oracle's."""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "fp16x3": 1e-4}
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    import torch
+    return torch.device("cuda:0")
+
+
+def to_dev(case, dev):
+    import torch
+    t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    anchors = [dict(a, points=t(a["points"]), targets=t(a["targets"])) for a in case["anchors"]]
+    return t(case["params"]), t(case["B"]), t(case["points"]), anchors
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("name", ["burgers", "allen_cahn"])
+def test_term_gradients_match_oracle(oracle, dev, name, prec):
+    import torch
+    from paper_2604_15645_amd import binding, synth
+    case = synth.make_case(name, n_points=1500, seed=71, perturb=True)
+    params, B, pts, anchors = to_dev(case, dev)
+    out = binding.term_grads(case["net"], case["pde"], params, B, pts, anchors, prec=prec)
+    torch.cuda.synchronize()
+    loss, grads = out["loss"].cpu().numpy(), out["grads"].cpu().numpy()
+    rloss, rgrads = oracle.term_grads(case["net"], case["pde"], case["params"], case["B"], case["points"],
+                                      case["anchors"])
+    assert grads.shape[0] == len(rgrads) == 1 + len(case["anchors"])
+    errs = {"loss%d" % k: abs(loss[k] - rloss[k]) / abs(rloss[k]) for k in range(len(rloss))}
+    for t, g in enumerate(rgrads):
+        errs["grad_term%d" % t] = relerr(grads[t], g)
+    print(name, prec, {k: "%.2e" % v for k, v in errs.items()})
+    assert all(v <= TOL[prec] for v in errs.values()), errs
+    # the terms add up to the fused step's gradient (same kernels, other point groupings)
+    full = binding.residual_step(case["net"], case["pde"], params, B, pts, anchors, prec=prec)
+    torch.cuda.synchronize()
+    assert relerr(grads.sum(0), full["grad"].cpu().numpy()) <= TOL[prec]
+    assert relerr(loss, full["loss"].cpu().numpy()) <= TOL[prec]
+
+
+def test_balance_update_matches_oracle(oracle, dev):
+    import torch
+    from paper_2604_15645_amd import binding
+    rng = np.random.Generator(np.random.PCG64(72))
+    g = np.stack([rng.normal(size=5000) * s for s in (1e-3, 0.7, 42.0)])
+    lam0 = np.array([1.0, 2.5, 0.2])
+    for alpha, eps in ((0.9, 1e-9), (0.0, 0.0), (1.0, 1e-9)):
+        gt = torch.from_numpy(g).to(dev)
+        lt = torch.from_numpy(lam0.copy()).to(dev)
+        hat = binding.balance_update(gt, lt, alpha=alpha, eps=eps)
+        torch.cuda.synchronize()
+        rl, rh = oracle.balance_update(list(g), lam0, alpha=alpha, eps=eps)
+        assert relerr(hat.cpu().numpy(), rh) < 1e-13
+        assert relerr(lt.cpu().numpy(), rl) < 1e-13
