@@ -230,3 +230,39 @@ def balance_update(grads, lam, alpha=0.9, eps=1e-9):
     norms = np.array([np.sqrt(np.sum(np.asarray(g, dtype=np.float64) ** 2)) for g in grads])
     hat = norms.sum() / (norms + eps)
     return alpha * np.asarray(lam, dtype=np.float64) + (1.0 - alpha) * hat, hat
+
+
+def causal_weights(bin_losses, eps):
+    """Temporal-causality weights of Sec. 2.6.8: w_1 = 1 and
+    w_i = exp(-eps * sum_{k < i} L^k) for the later time segments."""
+    L = np.asarray(bin_losses, dtype=np.float64)
+    return np.exp(-eps * np.concatenate([[0.0], np.cumsum(L)[:-1]]))
+
+
+def causal_loss_grad(net_spec, pde_spec, params, B, pts, bin_n, eps, anchors=()):
+    """The causality-weighted residual loss of Sec. 2.6.8 and its gradient.  The residual
+    points come in M consecutive time segments of bin_n[i] points; L^i is the residual loss
+    of segment i alone (every component with its weight, mean over the segment's points),
+    w_i the causality weights, and L_pde = (1/M) sum_i w_i L^i.  The weights are held fixed
+    in the gradient (the paper computes them from the losses and does not differentiate
+    them).  Supervision sets add their own terms as in loss_grad.
+    Returns dict(loss=[total, residual component 0.., set 0..], grad, bin_loss, w)."""
+    M = len(bin_n)
+    nres = n_residuals(pde_spec["pde"])
+    d_in = int(net_spec["d_in"])
+    starts = np.concatenate([[0], np.cumsum(bin_n)])
+    per = [loss_grad(net_spec, pde_spec, params, B, pts[starts[i]:starts[i + 1]], (), want_residual=False)
+           for i in range(M)]
+    Lbin = np.array([r["loss"][0] for r in per])
+    w = causal_weights(Lbin, eps)
+    loss = np.zeros(1 + nres + len(anchors))
+    grad = np.zeros(param_count(net_spec))
+    for i in range(M):
+        loss[1:1 + nres] += w[i] / M * per[i]["loss"][1:1 + nres]
+        grad += w[i] / M * per[i]["grad"]
+    for a_i, a in enumerate(anchors):
+        r = loss_grad(net_spec, pde_spec, params, B, np.zeros((0, d_in)), [a], want_residual=False)
+        loss[1 + nres + a_i] = r["loss"][1 + nres]
+        grad += r["grad"]
+    loss[0] = loss[1:].sum()
+    return {"loss": loss, "grad": grad, "bin_loss": Lbin, "w": w}

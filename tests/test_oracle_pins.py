@@ -728,3 +728,42 @@ def test_balance_update_worked_example(oracle):
     assert np.allclose(hat2, hat, rtol=1e-14)
     lam1, _ = oracle.balance_update(g, [0.3, 4.0, 2.0], alpha=1.0)
     assert np.array_equal(lam1, [0.3, 4.0, 2.0])
+
+
+# ------------------------------------------------- temporal causality (Sec. 2.6.8)
+
+def test_causal_weights_worked_example(oracle):
+    """w_1 = 1, w_i = exp(-eps sum_{k<i} L^k): bin losses 0.5, 1, 2 with eps = 2 give
+    1, e^-1, e^-3 (the last bin's own loss never enters its weight)."""
+    w = oracle.causal_weights([0.5, 1.0, 2.0, 7.0], 2.0)
+    assert np.allclose(w, [1.0, math.exp(-1.0), math.exp(-3.0), math.exp(-7.0)], rtol=1e-15)
+    assert np.array_equal(oracle.causal_weights([3.0, 4.0], 0.0), [1.0, 1.0])
+
+
+def test_causal_loss_special_cases(oracle):
+    """One segment is the plain loss; eps = 0 is the mean of the segment losses; the
+    gradient is the w-weighted mean of the segments' gradients (weights held fixed), which
+    central differences confirm with the weights frozen at their values."""
+    case = synth.make_case("burgers", n_points=90, seed=25, perturb=True)
+    net, pde, p = case["net"], case["pde"], case["params"].astype(np.float64)
+    pts = case["points"][np.argsort(case["points"][:, 1])]
+    plain = oracle.loss_grad(net, pde, p, None, pts)
+    one = oracle.causal_loss_grad(net, pde, p, None, pts, [90], 5.0)
+    assert relerr(one["loss"], plain["loss"]) < 1e-14 and relerr(one["grad"], plain["grad"]) < 1e-14
+    bins = [20, 30, 40]
+    flat = oracle.causal_loss_grad(net, pde, p, None, pts, bins, 0.0)
+    segs = [oracle.loss_grad(net, pde, p, None, pts[a:b])["loss"][0] for a, b in ((0, 20), (20, 50), (50, 90))]
+    assert abs(flat["loss"][0] - np.mean(segs)) < 1e-14 * abs(flat["loss"][0])
+    res = oracle.causal_loss_grad(net, pde, p, None, pts, bins, 3.0)
+    w = res["w"]
+    assert np.allclose(w, np.exp(-3.0 * np.array([0.0, segs[0], segs[0] + segs[1]])), rtol=1e-14)
+    edges = ((0, 20), (20, 50), (50, 90))
+    for i in rng(26).choice(p.size, size=10, replace=False):
+        h = 1e-6 * max(1.0, abs(p[i]))
+        f = []
+        for sgn in (1, -1):
+            pp = p.copy()
+            pp[i] += sgn * h
+            f.append(sum(w[k] / 3 * oracle.loss_grad(net, pde, pp, None, pts[a:b], want_grad=False)["loss"][0]
+                         for k, (a, b) in enumerate(edges)))
+        assert abs((f[0] - f[1]) / (2 * h) - res["grad"][i]) <= 1e-7 * max(1.0, np.abs(res["grad"]).max())
