@@ -219,6 +219,37 @@ int pinn_term_grads(const pinn_net* net, const pinn_pde* pde, const float* param
                     const pinn_tune* tune, double* loss, double* grads, void* workspace,
                     size_t ws_bytes, pinn_stream_t stream);
 
+/* Temporal causality (Sec. 2.6.8).  The residual points come sorted into M consecutive
+ * time segments (segment i holds bin_n[i] points, in order).  With L^i the residual loss of
+ * segment i alone (every component with its weight lambda_res[c], mean over the segment's
+ * points) the weights are w_1 = 1, w_i = exp(-eps * (L^1 + ... + L^{i-1})), and the residual
+ * term becomes (1/M) sum_i w_i L^i.  The weights are computed from the current losses and
+ * held fixed in the gradient (the paper does not differentiate them).                     */
+typedef struct {
+  int32_t n_bins;        /* M, 1..256                                                    */
+  const int64_t* bin_n;  /* (host) [M] points per segment, >= 1 each, summing to n_points */
+  double eps;            /* decay rate, >= 0                                             */
+} pinn_causal;
+
+/* The fused step with the causality-weighted residual term: a forward pass per segment for
+ * the L^i (device), the weights on the device, then the fused step per segment with weight
+ * w_i / M, and the supervision sets (unweighted, as pinn_residual_bwd), accumulated.
+ *   residual  FP32 n_points x n_res (unweighted residuals), or NULL
+ *   loss      FP64 [1 + n_res + n_anchor]: total, weighted residual components, sets
+ *   grad      FP64 [pinn_param_count]
+ *   bin_loss, bin_w  FP64 [M] each, the L^i and the w_i (device), or NULL
+ * pde->norm_N must be 0 (each segment is its own mean).  The call makes 2M + 1 launch
+ * sequences; workspace from pinn_causal_workspace_bytes.                                  */
+int pinn_causal_workspace_bytes(const pinn_net* net, const pinn_pde* pde, int64_t n_points,
+                                const pinn_causal* causal, const pinn_anchor* anchors,
+                                int n_anchor, int prec, const pinn_tune* tune, size_t* bytes);
+int pinn_causal_bwd(const pinn_net* net, const pinn_pde* pde, const float* params,
+                    const float* fourier_B, const float* points, int64_t n_points,
+                    const pinn_causal* causal, const pinn_anchor* anchors, int n_anchor, int prec,
+                    uint32_t flags, const pinn_tune* tune, float* residual, double* loss,
+                    double* grad, double* bin_loss, double* bin_w, void* workspace,
+                    size_t ws_bytes, pinn_stream_t stream);
+
 /* Loss-balancing weights from per-term gradients (Sec. 2.6.4), on the device, without a
  * host round trip.  With n_t = ||grads[t]||_2 (FP64, fixed summation order):
  *   lambda_hat[t] = (n_0 + ... + n_{T-1}) / (n_t + eps)

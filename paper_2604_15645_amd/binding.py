@@ -42,6 +42,10 @@ class PinnTune(ctypes.Structure):
                 ("n_slots", ctypes.c_int32), ("chunk_points", ctypes.c_int32)]
 
 
+class PinnCausal(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int32), ("bin_n", ctypes.POINTER(ctypes.c_int64)), ("eps", ctypes.c_double)]
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double)]
@@ -59,7 +63,7 @@ _lib = None
 EXPORTS = ["pinn_param_count", "pinn_n_residuals", "pinn_workspace_bytes", "pinn_residual_fwd",
            "pinn_residual_bwd", "pinn_residual_bwd_noalloc", "pinn_batched_workspace_bytes",
            "pinn_batched_bwd", "pinn_term_grads_workspace_bytes", "pinn_term_grads",
-           "pinn_balance_update",
+           "pinn_balance_update", "pinn_causal_workspace_bytes", "pinn_causal_bwd",
            "pinn_timing_enable", "pinn_timing_collect", "pinn_status_string"]
 
 
@@ -98,6 +102,14 @@ def lib():
                                                       ctypes.c_int, ctypes.c_int, P(PinnTune), P(ctypes.c_size_t)]
         L.pinn_term_grads.restype = ctypes.c_int
         L.pinn_term_grads.argtypes = common[:-2] + [vp, vp, vp, ctypes.c_size_t, vp]
+        L.pinn_causal_workspace_bytes.restype = ctypes.c_int
+        L.pinn_causal_workspace_bytes.argtypes = [P(PinnNet), P(PinnPde), ctypes.c_int64, P(PinnCausal),
+                                                  P(PinnAnchor), ctypes.c_int, ctypes.c_int, P(PinnTune),
+                                                  P(ctypes.c_size_t)]
+        L.pinn_causal_bwd.restype = ctypes.c_int
+        L.pinn_causal_bwd.argtypes = [P(PinnNet), P(PinnPde), vp, vp, vp, ctypes.c_int64, P(PinnCausal),
+                                      P(PinnAnchor), ctypes.c_int, ctypes.c_int, ctypes.c_uint32, P(PinnTune),
+                                      vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.pinn_balance_update.restype = ctypes.c_int
         L.pinn_balance_update.argtypes = [vp, ctypes.c_int, ctypes.c_int64, vp, vp, ctypes.c_double,
                                           ctypes.c_double, vp]
@@ -385,6 +397,48 @@ def term_grads(net_spec, pde_spec, params, B, points, anchors=(), prec="bf16x3",
     if rc != 0:
         raise PinnError("pinn_term_grads", rc)
     return {"loss": loss, "grads": grads}
+
+
+def causal_step(net_spec, pde_spec, params, B, points, bin_n, eps, anchors=(), prec="bf16x3", tune=None,
+                flags=0, workspace=None):
+    """One call of pinn_causal_bwd (Sec. 2.6.8): points sorted into len(bin_n) consecutive
+    time segments.  Returns dict(loss, grad, residual, bin_loss, w)."""
+    _check_dev(params, "params")
+    _check_dev(points, "points")
+    if B is not None:
+        _check_dev(B, "fourier_B")
+    for a in anchors:
+        _check_dev(a["points"], "anchor points")
+        _check_dev(a["targets"], "anchor targets")
+    _check_shapes(net_spec, params, B, points, anchors)
+    dev = points.device
+    n, p = net_struct(net_spec), pde_struct(pde_spec)
+    arr = _anchor_array(anchors)
+    t = tune_struct(tune)
+    tref = ctypes.byref(t) if t is not None else None
+    bins = (ctypes.c_int64 * len(bin_n))(*[int(b) for b in bin_n])
+    cz = PinnCausal(len(bin_n), ctypes.cast(bins, ctypes.POINTER(ctypes.c_int64)), float(eps))
+    npts = int(points.shape[0])
+    size = ctypes.c_size_t(0)
+    rc = lib().pinn_causal_workspace_bytes(ctypes.byref(n), ctypes.byref(p), npts, ctypes.byref(cz), arr,
+                                           len(anchors), PRECS[prec], tref, ctypes.byref(size))
+    if rc != 0:
+        raise PinnError("pinn_causal_workspace_bytes", rc)
+    ws = (workspace or _ws(dev)).get(int(size.value))
+    nres = n_residuals(pde_spec["pde"])
+    loss = torch.empty(1 + nres + len(anchors), dtype=torch.float64, device=dev)
+    grad = torch.empty(param_count(net_spec), dtype=torch.float64, device=dev)
+    res = torch.empty((npts, nres), dtype=torch.float32, device=dev)
+    bl = torch.empty(len(bin_n), dtype=torch.float64, device=dev)
+    bw = torch.empty(len(bin_n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = lib().pinn_causal_bwd(ctypes.byref(n), ctypes.byref(p), params.data_ptr(),
+                               B.data_ptr() if B is not None else None, points.data_ptr(), npts, ctypes.byref(cz),
+                               arr, len(anchors), PRECS[prec], int(flags), tref, res.data_ptr(), loss.data_ptr(),
+                               grad.data_ptr(), bl.data_ptr(), bw.data_ptr(), ws.data_ptr(), ws.numel(), stream)
+    if rc != 0:
+        raise PinnError("pinn_causal_bwd", rc)
+    return {"loss": loss, "grad": grad, "residual": res, "bin_loss": bl, "w": bw}
 
 
 def balance_update(grads, lam, alpha=0.9, eps=1e-9, want_hat=True):

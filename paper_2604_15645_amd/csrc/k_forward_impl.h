@@ -15,6 +15,11 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void k_forward(const FwdArgs A) {
   const int ld = Tile<PREC>::ld(A.kmax, P);
   fwd_begin<H, P, NW>(s, A.net);
   float amx = 0.0f;
+  PdeDev pde = A.pde;
+  if (A.wscale) {  // a device-side weight of the residual term (causality segments)
+    const float w = *A.wscale;
+    for (int c = 0; c < 3; ++c) pde.seed_scale[c] *= w;
+  }
   for (int64_t tile = blockIdx.x; tile < A.n_tiles; tile += gridDim.x) {
     const int64_t p0 = tile * P;
     const int sid = seg_of(A.seg, p0);
@@ -27,7 +32,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void k_forward(const FwdArgs A) {
     sg.out_mask = sid == 0 ? 0 : A.seg.out_mask[sid - 1];
     sg.lam = sid == 0 ? 0.0f : A.seg.lam_anchor[sid - 1];
     sg.residual = (sid == 0 && A.residual) ? A.residual + (p0 - A.seg.start[0]) * A.pde.n_res : nullptr;
-    fwd_tile<PREC, ACT, H, P, NW>(A.net, A.pde, A.work.pts + p0, A.work.zs0, A.work.zs_stride, A.work.zb[0],
+    fwd_tile<PREC, ACT, H, P, NW>(A.net, pde, A.work.pts + p0, A.work.zs0, A.work.zs_stride, A.work.zb[0],
                                   tile * (P / 4), sg, ld, A.with_grad != 0, s, amx);
   }
   if constexpr (PREC == kFP16X3)

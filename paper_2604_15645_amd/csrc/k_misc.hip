@@ -121,6 +121,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_grad0(const Grad0Args A) {
 // the outputs in order, times d omega / dP = -omega / P = -omega^2 / (2 pi).
 __global__ void k_reduce_period(const PeriodReduceArgs A) {
   __shared__ double part[256];
+  double part0 = 0.0;  // running sum over the output blocks (thread 0)
   int ng = 0;
   for (int k = 0; k < A.d_in; ++k) ng += 2 * ((A.period_train_mask >> k) & 1);
   int f = 0, t = 0, j = 0;
@@ -146,15 +147,15 @@ __global__ void k_reduce_period(const PeriodReduceArgs A) {
         part[threadIdx.x] = v;
         __syncthreads();
         if (threadIdx.x == 0) {
-          double sum = o0 == 0 ? 0.0 : A.grad[A.off_p + t];
+          double sum = o0 == 0 ? 0.0 : part0;
           for (int i = 0; i < 256; ++i) sum += part[i];
-          A.grad[A.off_p + t] = sum;
+          part0 = sum;
         }
       }
       __syncthreads();
       if (threadIdx.x == 0) {
         const double w = (double)A.omega[k];
-        A.grad[A.off_p + t] *= -w * w / 6.283185307179586;
+        A.grad[A.off_p + t] = part0 * (-w * w / 6.283185307179586) + (A.accumulate ? A.grad[A.off_p + t] : 0.0);
       }
       ++t;
       j += 2;
@@ -204,10 +205,10 @@ __device__ __forceinline__ void reduce_row(const ReduceArgs& A, int o) {
       for (int q = 0; q < kRedGroups; ++q) s += part[q * NC + col0];
       if (col < A.n_in) {
         const double v = (double)A.params[A.off_w + (int64_t)o * A.n_in + col];
-        A.grad[A.off_w + (int64_t)o * A.n_in + col] = es * s;
+        A.grad[A.off_w + (int64_t)o * A.n_in + col] = es * s + (A.accumulate ? A.grad[A.off_w + (int64_t)o * A.n_in + col] : 0.0);
         ssum += s * es * v;
       } else if (A.has_bias) {
-        A.grad[A.off_b + o] = s;
+        A.grad[A.off_b + o] = s + (A.accumulate ? A.grad[A.off_b + o] : 0.0);
       }
     }
     __syncthreads();
@@ -219,7 +220,7 @@ __device__ __forceinline__ void reduce_row(const ReduceArgs& A, int o) {
       if (tid < st) red[tid] += red[tid + st];
       __syncthreads();
     }
-    if (tid == 0) A.grad[A.off_s + o] = red[0];
+    if (tid == 0) A.grad[A.off_s + o] = red[0] + (A.accumulate ? A.grad[A.off_s + o] : 0.0);
   }
 }
 
@@ -249,6 +250,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_batched(const BatchReduc
   a.off_s = e.off_s;
   a.off_b = e.off_b;
   a.grad = e.grad;
+  a.accumulate = 0;
   reduce_row(a, (int)(r - e.row0));
 }
 
@@ -294,13 +296,14 @@ __global__ __launch_bounds__(256) void k_reduce_loss(const LossArgs A) {
     __syncthreads();
   }
   if (tid == 0) {
+    const double ws = A.wscale ? (double)*A.wscale : 1.0;
     double total = 0.0;
     for (int k = 0; k < nt; ++k) {
-      const double t = red[k][0] * (k < A.n_res ? A.w_res[k] : A.w_anchor[k - A.n_res]);
-      A.loss[1 + k] = t;
+      const double t = red[k][0] * (k < A.n_res ? A.w_res[k] * ws : A.w_anchor[k - A.n_res]);
+      A.loss[1 + k] = t + (A.accumulate ? A.loss[1 + k] : 0.0);
       total += t;
     }
-    A.loss[0] = total;
+    A.loss[0] = total + (A.accumulate ? A.loss[0] : 0.0);
   }
 }
 
@@ -408,6 +411,29 @@ __global__ void k_balance(const double* grads, int n_terms, int64_t n_params, do
       lambda[t] = alpha * lambda[t] + (1.0 - alpha) * h;
     }
   }
+}
+
+// Causality weights (Sec. 2.6.8) from the segments' residual losses L^i (bin_loss[i * stride],
+// the totals of per-segment forward calls): w_0 = 1, w_i = exp(-eps sum_{k<i} L^k); the
+// segments' weights in the loss are w_i / M (wbin, FP32, read by the fused calls).
+__global__ void k_causal_weights(const double* bin_loss, int stride, int n_bins, double eps, float* wbin,
+                                 double* bin_loss_out, double* w_out) {
+  if (threadIdx.x != 0) return;
+  double cum = 0.0;
+  for (int i = 0; i < n_bins; ++i) {
+    const double L = bin_loss[(size_t)i * stride];
+    const double w = exp(-eps * cum);
+    wbin[i] = (float)(w / (double)n_bins);
+    if (bin_loss_out) bin_loss_out[i] = L;
+    if (w_out) w_out[i] = w;
+    cum += L;
+  }
+}
+
+int launch_causal_weights(const double* bin_loss, int stride, int n_bins, double eps, float* wbin, double* bin_loss_out,
+                          double* w_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_causal_weights, dim3(1), dim3(64), 0, s, bin_loss, stride, n_bins, eps, wbin, bin_loss_out, w_out);
+  return launch_status(hipGetLastError());
 }
 
 int launch_assemble_terms(const double* tmp, int n_terms, int n_res, double* loss, hipStream_t s) {

@@ -398,7 +398,8 @@ NetDev make_netdev(const pinn_net* net, const pinn_pde* pde, const Plan& p, char
 int run(const pinn_net* net, const pinn_pde* pde, const float* params, const float* B, const float* points,
         int64_t n_points, const pinn_anchor* anchors, int n_anchor, int prec, uint32_t flags,
         const pinn_tune* tune, float* residual, double* loss, double* grad, void* workspace,
-        size_t ws_bytes, pinn_stream_t stream_, bool with_grad, bool allow_timing = true) {
+        size_t ws_bytes, pinn_stream_t stream_, bool with_grad, bool allow_timing = true,
+        const float* wscale = nullptr, bool accumulate = false) {
   Plan p;
   int rc = make_plan(net, pde, n_points, anchors, n_anchor, prec, with_grad, tune, &p);
   if (rc) return rc;
@@ -514,6 +515,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     a.kmax = p.kmax;
     a.with_grad = p.with_grad;
     a.residual = residual;
+    a.wscale = wscale;
     rc = timed(allow_timing, "k_forward", stream, [&] { return launch_forward(p.prec, act_code(net, pde), D.H, p.pf, a, p.grid_f, p.lds_f, stream); });
     if (rc) return rc;
   }
@@ -570,6 +572,8 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     }
     for (int l = 0; l < D.n_layers; ++l) {
       ReduceArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.accumulate = accumulate;
       a.n_out = D.n_out[l];
       a.n_in = D.n_in[l];
       a.rwf = net->rwf;
@@ -605,6 +609,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.omega = reinterpret_cast<const float*>(ws + p.o_omega);
       a.grad = grad;
       a.off_p = D.off_p;
+      a.accumulate = accumulate;
       rc = timed(allow_timing, "k_reduce_period", stream, [&] { return launch_reduce_period(a, stream); });
       if (rc) return rc;
     }
@@ -620,6 +625,8 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     for (int k = 0; k < n_anchor; ++k)
       a.w_anchor[k] = anchors[k].n > 0 ? anchors[k].lambda / (double)anchors[k].n : 0.0;
     a.loss = loss;
+    a.wscale = wscale;
+    a.accumulate = accumulate;
     rc = timed(allow_timing, "k_reduce_loss", stream, [&] { return launch_reduce_loss(a, stream); });
     if (rc) return rc;
   }
@@ -1042,6 +1049,88 @@ int pinn_term_grads(const pinn_net* net, const pinn_pde* pde, const float* param
   }
   rc = launch_assemble_terms(tmp, 1 + n_anchor, nres, loss, reinterpret_cast<hipStream_t>(stream));
   if (rc) return rc;
+  return hip_rc(hipGetLastError());
+}
+
+int pinn_causal_workspace_bytes(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const pinn_causal* causal,
+                                const pinn_anchor* anchors, int n_anchor, int prec, const pinn_tune* tune,
+                                size_t* bytes) {
+  if (!bytes || !pde || !causal || !causal->bin_n || causal->n_bins < 1 || causal->n_bins > 256) return PINN_E_INVALID;
+  if (!(causal->eps >= 0.0) || !std::isfinite(causal->eps)) return PINN_E_INVALID;
+  if (pde->norm_N != 0.0) return PINN_E_INVALID;  // every segment is its own mean
+  int64_t tot = 0;
+  for (int i = 0; i < causal->n_bins; ++i) {
+    if (causal->bin_n[i] < 1) return PINN_E_INVALID;
+    tot += causal->bin_n[i];
+  }
+  if (tot != n_points) return PINN_E_INVALID;
+  int64_t run_bytes = 0;
+  Plan p;
+  for (int i = 0; i < causal->n_bins; ++i) {
+    int rc = make_plan(net, pde, causal->bin_n[i], nullptr, 0, prec, 1, tune, &p);
+    if (rc) return rc;
+    run_bytes = std::max(run_bytes, p.bytes);
+  }
+  if (n_anchor > 0) {
+    int rc = make_plan(net, pde, 0, anchors, n_anchor, prec, 1, tune, &p);
+    if (rc) return rc;
+    run_bytes = std::max(run_bytes, p.bytes);
+  }
+  const int64_t tmp = align_up((int64_t)causal->n_bins * (1 + n_res_of(pde->pde_id)) * 8 + causal->n_bins * 4, kAlign);
+  *bytes = (size_t)(tmp + run_bytes);
+  return PINN_OK;
+}
+
+int pinn_causal_bwd(const pinn_net* net, const pinn_pde* pde, const float* params, const float* fourier_B,
+                    const float* points, int64_t n_points, const pinn_causal* causal, const pinn_anchor* anchors,
+                    int n_anchor, int prec, uint32_t flags, const pinn_tune* tune, float* residual, double* loss,
+                    double* grad, double* bin_loss, double* bin_w, void* workspace, size_t ws_bytes,
+                    pinn_stream_t stream) {
+  size_t need = 0;
+  int rc = pinn_causal_workspace_bytes(net, pde, n_points, causal, anchors, n_anchor, prec, tune, &need);
+  if (rc) return rc;
+  if (!loss || !grad || !workspace || !points) return PINN_E_INVALID;
+  if (ws_bytes < need) return PINN_E_WORKSPACE;
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return PINN_E_INVALID;
+  const int M = causal->n_bins, nres = n_res_of(pde->pde_id), d = net->d_in;
+  const int stride = 1 + nres;
+  double* tl = static_cast<double*>(workspace);                       // [M][1 + n_res] segment losses
+  float* wbin = reinterpret_cast<float*>(tl + (size_t)M * stride);     // [M] w_i / M
+  const int64_t tmp = align_up((int64_t)M * stride * 8 + M * 4, kAlign);
+  void* run_ws = static_cast<char*>(workspace) + tmp;
+  const size_t run_bytes = ws_bytes - (size_t)tmp;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // pass 1: each time segment's residual loss L^i (forward only)
+  int64_t off = 0;
+  for (int i = 0; i < M; ++i) {
+    rc = run(net, pde, params, fourier_B, points + off * d, causal->bin_n[i], nullptr, 0, prec,
+             i == 0 ? flags : flags & ~(uint32_t)PINN_FLAG_CHECK_FINITE, tune, nullptr, tl + (size_t)i * stride,
+             nullptr, run_ws, run_bytes, stream, false);
+    if (rc) return rc;
+    off += causal->bin_n[i];
+  }
+  // the weights (Sec. 2.6.8), on the device
+  rc = launch_causal_weights(tl, stride, M, causal->eps, wbin, bin_loss, bin_w, s);
+  if (rc) return rc;
+  // pass 2: the fused step per segment with its weight w_i / M (held fixed), and the
+  // supervision sets, the gradients and loss terms accumulated
+  bool acc = false;
+  if (n_anchor > 0) {
+    rc = run(net, pde, params, fourier_B, nullptr, 0, anchors, n_anchor, prec, flags & ~(uint32_t)PINN_FLAG_CHECK_FINITE,
+             tune, nullptr, loss, grad, run_ws, run_bytes, stream, true);
+    if (rc) return rc;
+    acc = true;
+  }
+  off = 0;
+  for (int i = 0; i < M; ++i) {
+    pinn_pde pi = *pde;
+    rc = run(net, &pi, params, fourier_B, points + off * d, causal->bin_n[i], nullptr, 0, prec,
+             flags & ~(uint32_t)PINN_FLAG_CHECK_FINITE, tune, residual ? residual + off * nres : nullptr, loss, grad,
+             run_ws, run_bytes, stream, true, true, wbin + i, acc);
+    if (rc) return rc;
+    acc = true;
+    off += causal->bin_n[i];
+  }
   return hip_rc(hipGetLastError());
 }
 

@@ -124,6 +124,7 @@ struct FwdArgs {
   int kmax;          // widest GEMM input (R-layout row width, elements)
   int with_grad;
   float* residual;   // caller's n x n_res or null
+  const float* wscale;  // device weight multiplying the residual seed (or null)
 };
 
 struct BwdArgs {
@@ -167,6 +168,7 @@ struct PeriodReduceArgs {
   const float* omega;
   double* grad;         // the gradient, periods at off_p
   int64_t off_p;
+  int accumulate;
 };
 
 struct ReduceArgs {
@@ -178,6 +180,7 @@ struct ReduceArgs {
   const float* params;
   int64_t off_w, off_s, off_b;
   double* grad;
+  int accumulate;         // add to grad instead of overwriting it
 };
 
 struct LossArgs {
@@ -187,6 +190,8 @@ struct LossArgs {
   double w_res[3];        // lambda_c / N
   double w_anchor[kMaxAnchors];  // lambda_s / N_s
   double* loss;
+  const float* wscale;    // device weight of the residual terms (or null)
+  int accumulate;         // add to loss instead of overwriting it
 };
 
 // Many independent networks in one persistent launch.
@@ -271,6 +276,8 @@ int launch_grad0(const Grad0Args& a, int grid, hipStream_t s);
 int launch_reduce_layer(const ReduceArgs& a, hipStream_t s);
 int launch_reduce_period(const PeriodReduceArgs& a, hipStream_t s);
 int launch_assemble_terms(const double* tmp, int n_terms, int n_res, double* loss, hipStream_t s);
+int launch_causal_weights(const double* bin_loss, int stride, int n_bins, double eps, float* wbin, double* bin_loss_out,
+                          double* w_out, hipStream_t s);
 int launch_balance(const double* grads, int n_terms, int64_t n_params, double* lambda, double* hat, double alpha,
                    double eps, hipStream_t s);
 int launch_reduce_loss(const LossArgs& a, hipStream_t s);

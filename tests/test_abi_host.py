@@ -108,6 +108,26 @@ def test_term_grads_validation(lib):
     assert lib.pinn_balance_update(16, 3, 10, 16, None, 0.9, -1.0, None) == -1
 
 
+def test_causal_validation(lib):
+    """The causality call checks the segment sizes against the point count before any HIP
+    call."""
+    import ctypes
+    c = synth.CONFIGS["burgers"]
+    n, p = binding.net_struct(c["net"]), binding.pde_struct(c["pde"])
+    arr = binding._anchor_array(())
+    size = ctypes.c_size_t(0)
+
+    def ws_of(bins, npts, eps=1.0):
+        b = (ctypes.c_int64 * len(bins))(*bins)
+        cz = binding.PinnCausal(len(bins), ctypes.cast(b, ctypes.POINTER(ctypes.c_int64)), eps)
+        return lib.pinn_causal_workspace_bytes(ctypes.byref(n), ctypes.byref(p), npts, ctypes.byref(cz), arr, 0, 1,
+                                               None, ctypes.byref(size))
+    assert ws_of([100, 50], 150) == 0 and size.value > 0
+    assert ws_of([100, 50], 151) == -1        # segments must cover the points
+    assert ws_of([100, 0], 100) == -1         # no empty segment
+    assert ws_of([100, 50], 150, eps=-1.0) == -1
+
+
 def test_precision_codes(lib):
     """FP32, BF16X3 and FP16X3 are implemented; single-product BF16 is refused as
     unsupported, an unknown code as invalid; the split forms need the same workspace."""

@@ -72,3 +72,32 @@ def test_balance_update_matches_oracle(oracle, dev):
         rl, rh = oracle.balance_update(list(g), lam0, alpha=alpha, eps=eps)
         assert relerr(hat.cpu().numpy(), rh) < 1e-13
         assert relerr(lt.cpu().numpy(), rl) < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("name", ["burgers", "maxwell"])
+def test_causal_loss_matches_oracle(oracle, dev, name, prec):
+    """Temporal causality (Sec. 2.6.8): points sorted by time into segments of uneven size;
+    segment losses, weights, the weighted loss terms and the gradient against the oracle."""
+    import torch
+    from paper_2604_15645_amd import binding, synth
+    n = 1800 if name == "burgers" else 700
+    case = synth.make_case(name, n_points=n, seed=73, perturb=True)
+    tcol = case["net"]["d_in"] - 1
+    pts = case["points"][np.argsort(case["points"][:, tcol], kind="stable")]
+    case["points"] = np.ascontiguousarray(pts)
+    bin_n = [n // 5, n // 3, n - n // 5 - n // 3 - n // 7, n // 7]
+    eps = 50.0 if name == "burgers" else 1.5   # a tenth of the weight or more gone by the end
+    params, B, dpts, anchors = to_dev(case, dev)
+    out = binding.causal_step(case["net"], case["pde"], params, B, dpts, bin_n, eps, anchors, prec=prec)
+    torch.cuda.synchronize()
+    ref = oracle.causal_loss_grad(case["net"], case["pde"], case["params"], case["B"], case["points"], bin_n,
+                                  eps, case["anchors"])
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    errs = {"grad": relerr(got["grad"], ref["grad"]), "bin_loss": relerr(got["bin_loss"], ref["bin_loss"]),
+            "w": relerr(got["w"], ref["w"])}
+    for k in range(len(ref["loss"])):
+        errs["loss%d" % k] = abs(got["loss"][k] - ref["loss"][k]) / abs(ref["loss"][k])
+    print(name, prec, {k: "%.2e" % v for k, v in errs.items()}, "w", ref["w"])
+    assert all(v <= TOL[prec] for v in errs.values()), errs
+    assert ref["w"][-1] < 0.9   # the weights are not all one
