@@ -32,7 +32,8 @@
  *   Gradient: FP64 in the same layout.
  *   Device limits: d_in <= 3, d_out <= 3, 1 + d_in + (Laplacian needed) <= 4 derivative
  *   channels, hidden widths multiples of 32 and <= 256, n_freq a multiple of 16 with
- *   2*n_freq <= 256, n_hidden in 1..8.
+ *   2*n_freq <= 256, n_hidden in 1..8 (PINN_PREC_FP64: any width <= 256, any n_freq,
+ *   n_hidden in 0..8).
  */
 #ifndef PINN_H
 #define PINN_H
@@ -78,7 +79,11 @@ typedef enum {
   PINN_PREC_BF16 = 2,   /* one BF16 product per product (8 significant bits): not
                            implemented -- the derivative jets of a residual need more;
                            returns PINN_E_UNSUPPORTED                                   */
-  PINN_PREC_FP64 = 3,   /* reserved                                                     */
+  PINN_PREC_FP64 = 3,   /* double precision throughout on the vector ALU, one thread per
+                           point: a checking mode (finite differences at small steps,
+                           parity with an FP64 reference to rounding), not a fast path.
+                           Also takes any hidden width <= 256 and n_hidden = 0 (a linear
+                           read-out of the embedding).  Not available to the batched call. */
   PINN_PREC_FP16X3 = 4  /* as BF16X3 with IEEE half parts, hi = fp16(a), lo = fp16(a - hi),
                            FP16 matrix cores (the same rate as BF16): 22 significant bits,
                            operands represented to about 2^-22.  Half precision has a

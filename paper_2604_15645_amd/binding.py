@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libpinn.so")
 
 PDE_IDS = {"burgers": 1, "euler1d": 2, "ns2d": 3, "maxwell": 4, "advection": 5, "allen_cahn": 6}
 ACTS = {"tanh": 0, "sin": 1}
-PRECS = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp16x3": 4}
+PRECS = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp64": 3, "fp16x3": 4}
 FLAG_CHECK_FINITE = 1
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported configuration",

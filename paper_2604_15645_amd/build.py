@@ -19,7 +19,7 @@ HIP_FLAGS = [
     "-I" + os.path.join(ROOT, "include"),
 ]
 SOURCES = ["k_forward_fp32.hip", "k_forward_bf16x3.hip", "k_forward_fp16x3.hip", "k_backward_fp32.hip",
-           "k_backward_bf16x3.hip", "k_backward_fp16x3.hip", "k_batched.hip", "k_misc.hip", "pinn_noalloc.hip",
+           "k_backward_bf16x3.hip", "k_backward_fp16x3.hip", "k_batched.hip", "k_misc.hip", "k_fp64.hip", "pinn_noalloc.hip",
            "pinn_api.cpp"]
 
 

@@ -141,7 +141,9 @@ __global__ void k_reduce_period(const PeriodReduceArgs A) {
             g0 += G[j];
             g1 += G[j + 1];
           }
-          v = (double)A.w[(size_t)o * A.e + f] * g0 + (double)A.w[(size_t)o * A.e + f + 1] * g1;
+          const double wa = A.w64 ? A.w64[(size_t)o * A.e + f] : (double)A.w[(size_t)o * A.e + f];
+          const double wb = A.w64 ? A.w64[(size_t)o * A.e + f + 1] : (double)A.w[(size_t)o * A.e + f + 1];
+          v = wa * g0 + wb * g1;
         }
         __syncthreads();
         part[threadIdx.x] = v;
@@ -154,7 +156,7 @@ __global__ void k_reduce_period(const PeriodReduceArgs A) {
       }
       __syncthreads();
       if (threadIdx.x == 0) {
-        const double w = (double)A.omega[k];
+        const double w = A.omega64 ? A.omega64[k] : (double)A.omega[k];
         A.grad[A.off_p + t] = part0 * (-w * w / 6.283185307179586) + (A.accumulate ? A.grad[A.off_p + t] : 0.0);
       }
       ++t;
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(256) void k_reduce_loss(const LossArgs A) {
     __syncthreads();
   }
   if (tid == 0) {
-    const double ws = A.wscale ? (double)*A.wscale : 1.0;
+    const double ws = A.wscale ? *A.wscale : 1.0;
     double total = 0.0;
     for (int k = 0; k < nt; ++k) {
       const double t = red[k][0] * (k < A.n_res ? A.w_res[k] * ws : A.w_anchor[k - A.n_res]);
@@ -415,22 +417,22 @@ __global__ void k_balance(const double* grads, int n_terms, int64_t n_params, do
 
 // Causality weights (Sec. 2.6.8) from the segments' residual losses L^i (bin_loss[i * stride],
 // the totals of per-segment forward calls): w_0 = 1, w_i = exp(-eps sum_{k<i} L^k); the
-// segments' weights in the loss are w_i / M (wbin, FP32, read by the fused calls).
-__global__ void k_causal_weights(const double* bin_loss, int stride, int n_bins, double eps, float* wbin,
+// segments' weights in the loss are w_i / M (wbin, read by the fused calls).
+__global__ void k_causal_weights(const double* bin_loss, int stride, int n_bins, double eps, double* wbin,
                                  double* bin_loss_out, double* w_out) {
   if (threadIdx.x != 0) return;
   double cum = 0.0;
   for (int i = 0; i < n_bins; ++i) {
     const double L = bin_loss[(size_t)i * stride];
     const double w = exp(-eps * cum);
-    wbin[i] = (float)(w / (double)n_bins);
+    wbin[i] = w / (double)n_bins;
     if (bin_loss_out) bin_loss_out[i] = L;
     if (w_out) w_out[i] = w;
     cum += L;
   }
 }
 
-int launch_causal_weights(const double* bin_loss, int stride, int n_bins, double eps, float* wbin, double* bin_loss_out,
+int launch_causal_weights(const double* bin_loss, int stride, int n_bins, double eps, double* wbin, double* bin_loss_out,
                           double* w_out, hipStream_t s) {
   hipLaunchKernelGGL(k_causal_weights, dim3(1), dim3(64), 0, s, bin_loss, stride, n_bins, eps, wbin, bin_loss_out, w_out);
   return launch_status(hipGetLastError());

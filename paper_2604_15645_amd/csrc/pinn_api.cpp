@@ -135,6 +135,7 @@ int kernel_prec(int prec, int* kp) {
     case PINN_PREC_BF16X3: *kp = kBF16X3; return PINN_OK;
     case PINN_PREC_FP16X3: *kp = kFP16X3; return PINN_OK;
     case PINN_PREC_BF16: return PINN_E_UNSUPPORTED;  // single-product BF16: see pinn.h
+    case PINN_PREC_FP64: return PINN_E_UNSUPPORTED;  // its own kernels (run_fp64); not batched
     default: return PINN_E_INVALID;
   }
 }
@@ -395,11 +396,284 @@ NetDev make_netdev(const pinn_net* net, const pinn_pde* pde, const Plan& p, char
   return nd;
 }
 
+// ---------------------------------------------------------------- FP64 precision
+
+// What the FP64 kernels take: any width, n_hidden 0..8 (a linear read-out of the
+// embedding), the same channel rules as the other precisions.
+struct Plan64 {
+  Dims D;
+  int n_res, n_seg, ng;
+  int64_t seg_start[1 + kMaxAnchors], seg_n[1 + kMaxAnchors];
+  int64_t n_pad;
+  int blocks;
+  bool with_grad;
+  int64_t o_pts, o_w[kMaxLayers], o_b[kMaxLayers], o_omega, o_a[kMaxLayers], o_z[kMaxHidden], o_zb[kMaxHidden],
+      o_ab[2], o_yb, o_dw, o_loss, o_slot[kMaxLayers];
+  int64_t bytes;
+};
+
+int make_plan64(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const pinn_anchor* anchors, int n_anchor,
+                int with_grad, Plan64* P) {
+  Plan64& p = *P;
+  std::memset(&p, 0, sizeof(p));
+  int rc = check_net(net, &p.D);
+  if (rc) return rc;
+  rc = check_pde(net, pde);
+  if (rc) return rc;
+  if (n_points < 0 || n_anchor < 0 || n_anchor > kMaxAnchors) return PINN_E_INVALID;
+  if (n_anchor > 0 && !anchors) return PINN_E_INVALID;
+  int64_t tot = n_points;
+  for (int a = 0; a < n_anchor; ++a) {
+    if (anchors[a].n < 0 || !std::isfinite(anchors[a].lambda) || anchors[a].lambda < 0) return PINN_E_INVALID;
+    if (anchors[a].out_mask <= 0 || anchors[a].out_mask >= (1 << net->d_out)) return PINN_E_INVALID;
+    tot += anchors[a].n;
+  }
+  if (tot == 0) return PINN_E_INVALID;
+  const Dims& D = p.D;
+  for (int l = 0; l < D.L; ++l)
+    if (D.n_out[l] > 256) return PINN_E_UNSUPPORTED;
+  if (1 + net->d_in + (pde->lap_mask ? 1 : 0) > 4) return PINN_E_UNSUPPORTED;
+  if (pde->lap_mask && net->d_in != 2) return PINN_E_UNSUPPORTED;
+  if (net->periodic_mask && net->n_freq > 0) return PINN_E_UNSUPPORTED;
+  if (net->n_freq > 4096) return PINN_E_UNSUPPORTED;
+  p.n_res = n_res_of(pde->pde_id);
+  p.n_seg = 1 + n_anchor;
+  p.ng = 2 * D.n_tp;
+  p.with_grad = with_grad != 0;
+  int64_t cur = 0;
+  for (int s = 0; s < p.n_seg; ++s) {
+    p.seg_start[s] = cur;
+    p.seg_n[s] = s == 0 ? n_points : anchors[s - 1].n;
+    cur += align_up(std::max<int64_t>(p.seg_n[s], 1), kSegAlign);
+  }
+  p.n_pad = cur;
+  p.blocks = (int)((p.n_pad + 255) / 256);
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) { int64_t r = o; o = align_up(o + bytes, kAlign); return r; };
+  const int64_t col = p.n_pad * 4 * 8;  // one jet row over all points
+  p.o_pts = take(p.n_pad * 16);
+  for (int l = 0; l < D.n_layers; ++l) {
+    p.o_w[l] = take((int64_t)D.n_out[l] * D.n_in[l] * 8);
+    p.o_b[l] = take((int64_t)D.n_out[l] * 8);
+  }
+  p.o_omega = take(32);
+  for (int l = 0; l < D.n_layers; ++l) p.o_a[l] = take(col * D.n_in[l]);
+  int wmax = D.e;
+  for (int l = 0; l < D.L; ++l) {
+    p.o_z[l] = take(col * D.n_out[l]);
+    wmax = std::max(wmax, D.n_out[l]);
+  }
+  p.o_yb = take(col * D.d_out);
+  p.o_dw = take(col * std::max(p.ng, 1));
+  p.o_loss = take((int64_t)p.blocks * kMaxTerms * 8);
+  if (p.with_grad) {
+    for (int l = 0; l < D.L; ++l) p.o_zb[l] = take(col * D.n_out[l]);
+    p.o_ab[0] = take(col * wmax);
+    p.o_ab[1] = take(col * wmax);
+    for (int l = 0; l < D.n_layers; ++l)
+      p.o_slot[l] = take((int64_t)D.n_out[l] * (D.n_in[l] + 1 + (l == 0 ? p.ng : 0)) * 8);
+  }
+  p.bytes = o;
+  return PINN_OK;
+}
+
+int run_fp64(const pinn_net* net, const pinn_pde* pde, const float* params, const float* B, const float* points,
+             int64_t n_points, const pinn_anchor* anchors, int n_anchor, uint32_t flags, float* residual,
+             double* loss, double* grad, void* workspace, size_t ws_bytes, hipStream_t stream, bool with_grad,
+             const double* wscale, bool accumulate) {
+  Plan64 p;
+  int rc = make_plan64(net, pde, n_points, anchors, n_anchor, with_grad, &p);
+  if (rc) return rc;
+  if (!params || !loss || !workspace || (n_points > 0 && !points)) return PINN_E_INVALID;
+  if (with_grad && !grad) return PINN_E_INVALID;
+  if (net->n_freq > 0 && !B) return PINN_E_INVALID;
+  for (int a = 0; a < n_anchor; ++a)
+    if (anchors[a].n > 0 && (!anchors[a].points || !anchors[a].targets)) return PINN_E_INVALID;
+  if ((int64_t)ws_bytes < p.bytes) return PINN_E_WORKSPACE;
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return PINN_E_INVALID;
+  char* ws = static_cast<char*>(workspace);
+  const Dims& D = p.D;
+  if (flags & PINN_FLAG_CHECK_FINITE) {
+    int* flag = reinterpret_cast<int*>(ws + p.o_loss);  // scratch before the loss slots are written
+    rc = launch_check_finite(params, D.n_params, flag, stream);
+    if (rc) return rc;
+    int h = 0;
+    if (hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess) return PINN_E_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return PINN_E_HIP;
+    if (h) return PINN_E_NONFINITE;
+  }
+  {
+    PointsArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.d_in = D.d_in;
+    a.n_seg = p.n_seg;
+    for (int s = 0; s < p.n_seg; ++s) {
+      a.start[s] = p.seg_start[s];
+      a.n[s] = p.seg_n[s];
+      a.src[s] = s == 0 ? points : anchors[s - 1].points;
+    }
+    a.n_pad = p.n_pad;
+    a.dst = reinterpret_cast<float4*>(ws + p.o_pts);
+    rc = launch_points(a, stream);
+    if (rc) return rc;
+  }
+  F64StageArgs st;
+  std::memset(&st, 0, sizeof(st));
+  st.n_layers = D.n_layers;
+  st.rwf = net->rwf;
+  st.has_bias = net->has_bias;
+  st.periodic_mask = net->periodic_mask;
+  st.period_train_mask = net->period_train_mask;
+  for (int k = 0; k < 3; ++k) st.period[k] = net->period[k];
+  st.off_p = D.off_p;
+  st.params = params;
+  st.omega = reinterpret_cast<double*>(ws + p.o_omega);
+  F64Args a;
+  std::memset(&a, 0, sizeof(a));
+  a.n_pad = p.n_pad;
+  a.L = D.L;
+  a.d_in = D.d_in;
+  a.d_out = D.d_out;
+  a.e = D.e;
+  a.n_freq = net->n_freq;
+  a.act = net->act;
+  a.periodic_mask = net->periodic_mask;
+  a.period_train_mask = net->period_train_mask;
+  a.lap_mask = pde->lap_mask;
+  a.lapch = pde->lap_mask ? 1 + D.d_in : -1;
+  a.ng = p.ng;
+  a.w0 = (double)net->w0;
+  for (int l = 0; l < D.n_layers; ++l) {
+    st.off_w[l] = D.off_w[l];
+    st.off_s[l] = D.off_s[l];
+    st.off_b[l] = D.off_b[l];
+    st.n_in[l] = a.n_in[l] = D.n_in[l];
+    st.n_out[l] = a.n_out[l] = D.n_out[l];
+    st.w[l] = reinterpret_cast<double*>(ws + p.o_w[l]);
+    st.b[l] = reinterpret_cast<double*>(ws + p.o_b[l]);
+    a.w[l] = st.w[l];
+    a.b[l] = st.b[l];
+    a.a[l] = reinterpret_cast<double*>(ws + p.o_a[l]);
+  }
+  for (int l = 0; l < D.L; ++l) {
+    a.z[l] = reinterpret_cast<double*>(ws + p.o_z[l]);
+    if (p.with_grad) a.zb[l] = reinterpret_cast<double*>(ws + p.o_zb[l]);
+  }
+  if (p.with_grad) {
+    a.ab[0] = reinterpret_cast<double*>(ws + p.o_ab[0]);
+    a.ab[1] = reinterpret_cast<double*>(ws + p.o_ab[1]);
+  }
+  a.yb = reinterpret_cast<double*>(ws + p.o_yb);
+  a.dw = reinterpret_cast<double*>(ws + p.o_dw);
+  a.omega = st.omega;
+  a.B = B;
+  a.pts = reinterpret_cast<const float4*>(ws + p.o_pts);
+  a.pde_id = pde->pde_id;
+  a.n_res = p.n_res;
+  for (int k = 0; k < 4; ++k) a.coef[k] = pde->coef[k];
+  const double N = pde->norm_N > 0 ? pde->norm_N : (double)n_points;
+  for (int k = 0; k < 3; ++k) a.seed[k] = N > 0 ? 2.0 * pde->lambda_res[k] / N : 0.0;
+  for (int k = 0; k < n_anchor; ++k)
+    a.lam_anchor[k] = anchors[k].n > 0 ? 2.0 * anchors[k].lambda / (double)anchors[k].n : 0.0;
+  a.wscale = wscale;
+  a.seg.n_seg = p.n_seg;
+  for (int s = 0; s < p.n_seg; ++s) {
+    a.seg.start[s] = p.seg_start[s];
+    a.seg.n[s] = p.seg_n[s];
+  }
+  for (int k = 0; k < n_anchor; ++k) {
+    a.seg.targets[k] = anchors[k].targets;
+    a.seg.out_mask[k] = anchors[k].out_mask;
+  }
+  a.residual = residual;
+  a.loss_slots = reinterpret_cast<double*>(ws + p.o_loss);
+  double* slots[kMaxLayers] = {};
+  for (int l = 0; l < D.n_layers; ++l) slots[l] = p.with_grad ? reinterpret_cast<double*>(ws + p.o_slot[l]) : nullptr;
+  rc = launch_fp64(st, a, p.with_grad ? slots : nullptr, stream);
+  if (rc) return rc;
+  if (p.with_grad) {
+    for (int l = 0; l < D.n_layers; ++l) {
+      ReduceArgs r;
+      std::memset(&r, 0, sizeof(r));
+      r.slots = slots[l];
+      r.n_slots = 1;
+      r.slot_stride = (int64_t)D.n_out[l] * (D.n_in[l] + 1 + (l == 0 ? p.ng : 0));
+      r.n_out = D.n_out[l];
+      r.n_in = D.n_in[l];
+      r.rwf = net->rwf;
+      r.has_bias = net->has_bias;
+      r.params = params;
+      r.off_w = D.off_w[l];
+      r.off_s = D.off_s[l];
+      r.off_b = D.off_b[l];
+      r.grad = grad;
+      r.accumulate = accumulate;
+      rc = launch_reduce_layer(r, stream);
+      if (rc) return rc;
+    }
+    if (D.n_tp > 0) {
+      PeriodReduceArgs r;
+      std::memset(&r, 0, sizeof(r));
+      r.slots = slots[0];
+      r.n_slots = 1;
+      r.slot_stride = (int64_t)D.n_out[0] * (D.e + 1 + p.ng);
+      r.n_out = D.n_out[0];
+      r.e = D.e;
+      r.periodic_mask = net->periodic_mask;
+      r.period_train_mask = net->period_train_mask;
+      r.d_in = D.d_in;
+      r.w64 = a.w[0];
+      r.omega64 = a.omega;
+      r.grad = grad;
+      r.off_p = D.off_p;
+      r.accumulate = accumulate;
+      rc = launch_reduce_period(r, stream);
+      if (rc) return rc;
+    }
+  }
+  {
+    LossArgs l;
+    std::memset(&l, 0, sizeof(l));
+    l.slots = a.loss_slots;
+    l.n_slots = p.blocks;
+    l.n_res = p.n_res;
+    l.n_anchor = n_anchor;
+    for (int k = 0; k < 3; ++k) l.w_res[k] = N > 0 ? pde->lambda_res[k] / N : 0.0;
+    for (int k = 0; k < n_anchor; ++k) l.w_anchor[k] = anchors[k].n > 0 ? anchors[k].lambda / (double)anchors[k].n : 0.0;
+    l.loss = loss;
+    l.wscale = wscale;
+    l.accumulate = accumulate;
+    rc = launch_reduce_loss(l, stream);
+    if (rc) return rc;
+  }
+  return hip_rc(hipGetLastError());
+}
+
+// Workspace bytes of either kind of plan.
+int plan_bytes(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const pinn_anchor* anchors, int n_anchor,
+               int prec, int with_grad, const pinn_tune* tune, int64_t* bytes) {
+  if (prec == PINN_PREC_FP64) {
+    Plan64 p;
+    int rc = make_plan64(net, pde, n_points, anchors, n_anchor, with_grad, &p);
+    if (rc) return rc;
+    *bytes = p.bytes;
+    return PINN_OK;
+  }
+  Plan p;
+  int rc = make_plan(net, pde, n_points, anchors, n_anchor, prec, with_grad, tune, &p);
+  if (rc) return rc;
+  *bytes = p.bytes;
+  return PINN_OK;
+}
+
 int run(const pinn_net* net, const pinn_pde* pde, const float* params, const float* B, const float* points,
         int64_t n_points, const pinn_anchor* anchors, int n_anchor, int prec, uint32_t flags,
         const pinn_tune* tune, float* residual, double* loss, double* grad, void* workspace,
         size_t ws_bytes, pinn_stream_t stream_, bool with_grad, bool allow_timing = true,
-        const float* wscale = nullptr, bool accumulate = false) {
+        const double* wscale = nullptr, bool accumulate = false) {
+  if (prec == PINN_PREC_FP64)
+    return run_fp64(net, pde, params, B, points, n_points, anchors, n_anchor, flags, residual, loss, grad, workspace,
+                    ws_bytes, reinterpret_cast<hipStream_t>(stream_), with_grad, wscale, accumulate);
   Plan p;
   int rc = make_plan(net, pde, n_points, anchors, n_anchor, prec, with_grad, tune, &p);
   if (rc) return rc;
@@ -977,10 +1251,10 @@ int pinn_n_residuals(int pde_id) { return n_res_of(pde_id); }
 int pinn_workspace_bytes(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const pinn_anchor* anchors,
                          int n_anchor, int prec, int with_grad, const pinn_tune* tune, size_t* bytes) {
   if (!bytes) return PINN_E_INVALID;
-  Plan p;
-  int rc = make_plan(net, pde, n_points, anchors, n_anchor, prec, with_grad, tune, &p);
+  int64_t b = 0;
+  int rc = plan_bytes(net, pde, n_points, anchors, n_anchor, prec, with_grad, tune, &b);
   if (rc) return rc;
-  *bytes = (size_t)p.bytes;
+  *bytes = (size_t)b;
   return PINN_OK;
 }
 
@@ -1007,14 +1281,13 @@ int pinn_term_grads_workspace_bytes(const pinn_net* net, const pinn_pde* pde, in
     return PINN_E_INVALID;
   for (int a = 0; a < n_anchor; ++a)
     if (anchors[a].n < 1) return PINN_E_INVALID;
-  Plan p;
-  int rc = make_plan(net, pde, n_points, nullptr, 0, prec, 1, tune, &p);
+  int64_t run_bytes = 0, b = 0;
+  int rc = plan_bytes(net, pde, n_points, nullptr, 0, prec, 1, tune, &run_bytes);
   if (rc) return rc;
-  int64_t run_bytes = p.bytes;
   for (int a = 0; a < n_anchor; ++a) {
-    rc = make_plan(net, pde, 0, &anchors[a], 1, prec, 1, tune, &p);
+    rc = plan_bytes(net, pde, 0, &anchors[a], 1, prec, 1, tune, &b);
     if (rc) return rc;
-    run_bytes = std::max(run_bytes, p.bytes);
+    run_bytes = std::max(run_bytes, b);
   }
   const int64_t tmp = align_up((int64_t)(1 + n_anchor) * (2 + n_res_of(pde->pde_id)) * 8, kAlign);
   *bytes = (size_t)(tmp + run_bytes);
@@ -1064,19 +1337,18 @@ int pinn_causal_workspace_bytes(const pinn_net* net, const pinn_pde* pde, int64_
     tot += causal->bin_n[i];
   }
   if (tot != n_points) return PINN_E_INVALID;
-  int64_t run_bytes = 0;
-  Plan p;
+  int64_t run_bytes = 0, b = 0;
   for (int i = 0; i < causal->n_bins; ++i) {
-    int rc = make_plan(net, pde, causal->bin_n[i], nullptr, 0, prec, 1, tune, &p);
+    int rc = plan_bytes(net, pde, causal->bin_n[i], nullptr, 0, prec, 1, tune, &b);
     if (rc) return rc;
-    run_bytes = std::max(run_bytes, p.bytes);
+    run_bytes = std::max(run_bytes, b);
   }
   if (n_anchor > 0) {
-    int rc = make_plan(net, pde, 0, anchors, n_anchor, prec, 1, tune, &p);
+    int rc = plan_bytes(net, pde, 0, anchors, n_anchor, prec, 1, tune, &b);
     if (rc) return rc;
-    run_bytes = std::max(run_bytes, p.bytes);
+    run_bytes = std::max(run_bytes, b);
   }
-  const int64_t tmp = align_up((int64_t)causal->n_bins * (1 + n_res_of(pde->pde_id)) * 8 + causal->n_bins * 4, kAlign);
+  const int64_t tmp = align_up((int64_t)causal->n_bins * (1 + n_res_of(pde->pde_id)) * 8 + causal->n_bins * 8, kAlign);
   *bytes = (size_t)(tmp + run_bytes);
   return PINN_OK;
 }
@@ -1095,8 +1367,8 @@ int pinn_causal_bwd(const pinn_net* net, const pinn_pde* pde, const float* param
   const int M = causal->n_bins, nres = n_res_of(pde->pde_id), d = net->d_in;
   const int stride = 1 + nres;
   double* tl = static_cast<double*>(workspace);                       // [M][1 + n_res] segment losses
-  float* wbin = reinterpret_cast<float*>(tl + (size_t)M * stride);     // [M] w_i / M
-  const int64_t tmp = align_up((int64_t)M * stride * 8 + M * 4, kAlign);
+  double* wbin = tl + (size_t)M * stride;                               // [M] w_i / M
+  const int64_t tmp = align_up((int64_t)M * stride * 8 + M * 8, kAlign);
   void* run_ws = static_cast<char*>(workspace) + tmp;
   const size_t run_bytes = ws_bytes - (size_t)tmp;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);

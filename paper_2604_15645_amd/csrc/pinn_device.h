@@ -592,20 +592,20 @@ __device__ __forceinline__ f4 jet_act_adj(f4 z, f4 ab, float s1, float s2, float
 
 // Output jets y[o][c] (c: 0 value, 1.. derivatives, lapch Laplacian) -> residuals r and,
 // with the seed scale g_c = 2 lambda_c / N, the output-jet adjoint yb[o][c].
-__device__ __forceinline__ void residual_point(const PdeDev& pde, int lapch, const float (&y)[3][4],
-                                               float (&r)[3], float (&yb)[3][4]) {
+template <typename T, typename C>
+__device__ __forceinline__ void residual_point_t(int pde_id, const C* coef, const C* g, const T (&y)[3][4], T (&r)[3],
+                                                 T (&yb)[3][4]) {
 #pragma unroll
   for (int o = 0; o < 3; ++o)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) yb[o][c] = 0.0f;
-  r[0] = r[1] = r[2] = 0.0f;
-  const float* g = pde.seed_scale;
-  switch (pde.pde_id) {
+    for (int c = 0; c < 4; ++c) yb[o][c] = T(0);
+  r[0] = r[1] = r[2] = T(0);
+  switch (pde_id) {
     case kBurgers: {  // (x, t): u_t + u u_x - nu u_xx
-      const float nu = pde.coef[0];
-      const float u = y[0][0], ux = y[0][1], ut = y[0][2], uxx = y[0][3];
+      const T nu = (T)coef[0];
+      const T u = y[0][0], ux = y[0][1], ut = y[0][2], uxx = y[0][3];
       r[0] = ut + u * ux - nu * uxx;
-      const float b = g[0] * r[0];
+      const T b = (T)g[0] * r[0];
       yb[0][0] = b * ux;
       yb[0][1] = b * u;
       yb[0][2] = b;
@@ -613,37 +613,37 @@ __device__ __forceinline__ void residual_point(const PdeDev& pde, int lapch, con
       break;
     }
     case kEuler1D: {  // (x, t) -> (rho, u, p), conservative form expanded by the product rule
-      const float k = 1.0f / (pde.coef[0] - 1.0f);
-      const float rho = y[0][0], rx = y[0][1], rt = y[0][2];
-      const float u = y[1][0], ux = y[1][1], ut = y[1][2];
-      const float p = y[2][0], px = y[2][1], pt = y[2][2];
-      const float uu = u * u;
+      const T k = T(1) / ((T)coef[0] - T(1));
+      const T rho = y[0][0], rx = y[0][1], rt = y[0][2];
+      const T u = y[1][0], ux = y[1][1], ut = y[1][2];
+      const T p = y[2][0], px = y[2][1], pt = y[2][2];
+      const T uu = u * u;
       r[0] = rt + u * rx + rho * ux;
-      r[1] = u * rt + rho * ut + uu * rx + 2.0f * rho * u * ux + px;
-      r[2] = k * pt + 0.5f * uu * rt + rho * u * ut + (k + 1.0f) * (u * px + p * ux) +
-             0.5f * uu * u * rx + 1.5f * rho * uu * ux;
-      const float b0 = g[0] * r[0], b1 = g[1] * r[1], b2 = g[2] * r[2];
-      yb[0][0] = b0 * ux + b1 * (ut + 2.0f * u * ux) + b2 * (u * ut + 1.5f * uu * ux);
-      yb[0][1] = b0 * u + b1 * uu + b2 * 0.5f * uu * u;
-      yb[0][2] = b0 + b1 * u + b2 * 0.5f * uu;
-      yb[1][0] = b0 * rx + b1 * (rt + 2.0f * u * rx + 2.0f * rho * ux) +
-                 b2 * (u * rt + rho * ut + (k + 1.0f) * px + 1.5f * uu * rx + 3.0f * rho * u * ux);
-      yb[1][1] = b0 * rho + b1 * 2.0f * rho * u + b2 * ((k + 1.0f) * p + 1.5f * rho * uu);
+      r[1] = u * rt + rho * ut + uu * rx + T(2) * rho * u * ux + px;
+      r[2] = k * pt + T(0.5) * uu * rt + rho * u * ut + (k + T(1)) * (u * px + p * ux) +
+             T(0.5) * uu * u * rx + T(1.5) * rho * uu * ux;
+      const T b0 = (T)g[0] * r[0], b1 = (T)g[1] * r[1], b2 = (T)g[2] * r[2];
+      yb[0][0] = b0 * ux + b1 * (ut + T(2) * u * ux) + b2 * (u * ut + T(1.5) * uu * ux);
+      yb[0][1] = b0 * u + b1 * uu + b2 * T(0.5) * uu * u;
+      yb[0][2] = b0 + b1 * u + b2 * T(0.5) * uu;
+      yb[1][0] = b0 * rx + b1 * (rt + T(2) * u * rx + T(2) * rho * ux) +
+                 b2 * (u * rt + rho * ut + (k + T(1)) * px + T(1.5) * uu * rx + T(3) * rho * u * ux);
+      yb[1][1] = b0 * rho + b1 * T(2) * rho * u + b2 * ((k + T(1)) * p + T(1.5) * rho * uu);
       yb[1][2] = b1 * rho + b2 * rho * u;
-      yb[2][0] = b2 * (k + 1.0f) * ux;
-      yb[2][1] = b1 + b2 * (k + 1.0f) * u;
+      yb[2][0] = b2 * (k + T(1)) * ux;
+      yb[2][1] = b1 + b2 * (k + T(1)) * u;
       yb[2][2] = b2 * k;
       break;
     }
     case kNS2D: {  // (x, y) -> (u, v, p), steady incompressible, 1/Re viscosity
-      const float iRe = 1.0f / pde.coef[0];
-      const float u = y[0][0], ux = y[0][1], uy = y[0][2], lu = y[0][3];
-      const float v = y[1][0], vx = y[1][1], vy = y[1][2], lv = y[1][3];
-      const float px = y[2][1], py = y[2][2];
+      const T iRe = T(1) / (T)coef[0];
+      const T u = y[0][0], ux = y[0][1], uy = y[0][2], lu = y[0][3];
+      const T v = y[1][0], vx = y[1][1], vy = y[1][2], lv = y[1][3];
+      const T px = y[2][1], py = y[2][2];
       r[0] = ux + vy;
       r[1] = u * ux + v * uy + px - iRe * lu;
       r[2] = u * vx + v * vy + py - iRe * lv;
-      const float b0 = g[0] * r[0], b1 = g[1] * r[1], b2 = g[2] * r[2];
+      const T b0 = (T)g[0] * r[0], b1 = (T)g[1] * r[1], b2 = (T)g[2] * r[2];
       yb[0][0] = b1 * ux + b2 * vx;
       yb[0][1] = b0 + b1 * u;
       yb[0][2] = b1 * v;
@@ -657,14 +657,14 @@ __device__ __forceinline__ void residual_point(const PdeDev& pde, int lapch, con
       break;
     }
     case kMaxwell: {  // (x, y, t) -> (E_z, H_x, H_y)
-      const float ie = 1.0f / pde.coef[0], im = 1.0f / pde.coef[1];
-      const float ezx = y[0][1], ezy = y[0][2], ezt = y[0][3];
-      const float hxy = y[1][2], hxt = y[1][3];
-      const float hyx = y[2][1], hyt = y[2][3];
+      const T ie = T(1) / (T)coef[0], im = T(1) / (T)coef[1];
+      const T ezx = y[0][1], ezy = y[0][2], ezt = y[0][3];
+      const T hxy = y[1][2], hxt = y[1][3];
+      const T hyx = y[2][1], hyt = y[2][3];
       r[0] = ezt - ie * (hyx - hxy);
       r[1] = hxt + im * ezy;
       r[2] = hyt - im * ezx;
-      const float b0 = g[0] * r[0], b1 = g[1] * r[1], b2 = g[2] * r[2];
+      const T b0 = (T)g[0] * r[0], b1 = (T)g[1] * r[1], b2 = (T)g[2] * r[2];
       yb[0][3] = b0;
       yb[2][1] = -b0 * ie;
       yb[1][2] = b0 * ie;
@@ -675,19 +675,19 @@ __device__ __forceinline__ void residual_point(const PdeDev& pde, int lapch, con
       break;
     }
     case kAdvection: {  // (x, t): u_t + c u_x
-      const float c = pde.coef[0];
+      const T c = (T)coef[0];
       r[0] = y[0][2] + c * y[0][1];
-      const float b = g[0] * r[0];
+      const T b = (T)g[0] * r[0];
       yb[0][1] = b * c;
       yb[0][2] = b;
       break;
     }
     case kAllenCahn: {  // (x, t): u_t - D u_xx + k u^3 - k u
-      const float D = pde.coef[0], k = pde.coef[1];
-      const float u = y[0][0], ut = y[0][2], uxx = y[0][3];
+      const T D = (T)coef[0], k = (T)coef[1];
+      const T u = y[0][0], ut = y[0][2], uxx = y[0][3];
       r[0] = ut - D * uxx + k * u * u * u - k * u;
-      const float b = g[0] * r[0];
-      yb[0][0] = b * k * (3.0f * u * u - 1.0f);
+      const T b = (T)g[0] * r[0];
+      yb[0][0] = b * k * (T(3) * u * u - T(1));
       yb[0][2] = b;
       yb[0][3] = -b * D;
       break;
@@ -695,6 +695,11 @@ __device__ __forceinline__ void residual_point(const PdeDev& pde, int lapch, con
     default:
       break;
   }
+}
+
+__device__ __forceinline__ void residual_point(const PdeDev& pde, int lapch, const float (&y)[3][4], float (&r)[3],
+                                               float (&yb)[3][4]) {
+  residual_point_t<float, float>(pde.pde_id, pde.coef, pde.seed_scale, y, r, yb);
   (void)lapch;
 }
 

@@ -124,7 +124,7 @@ struct FwdArgs {
   int kmax;          // widest GEMM input (R-layout row width, elements)
   int with_grad;
   float* residual;   // caller's n x n_res or null
-  const float* wscale;  // device weight multiplying the residual seed (or null)
+  const double* wscale;  // device weight multiplying the residual seed (or null)
 };
 
 struct BwdArgs {
@@ -169,6 +169,8 @@ struct PeriodReduceArgs {
   double* grad;         // the gradient, periods at off_p
   int64_t off_p;
   int accumulate;
+  const double* w64;    // FP64 precision: double weights and omega instead of w / omega
+  const double* omega64;
 };
 
 struct ReduceArgs {
@@ -190,7 +192,7 @@ struct LossArgs {
   double w_res[3];        // lambda_c / N
   double w_anchor[kMaxAnchors];  // lambda_s / N_s
   double* loss;
-  const float* wscale;    // device weight of the residual terms (or null)
+  const double* wscale;   // device weight of the residual terms (or null)
   int accumulate;         // add to loss instead of overwriting it
 };
 
@@ -254,6 +256,50 @@ struct BatchLossArgs {
   double* losses;            // [n_inst][1 + n_res]
 };
 
+// The FP64 precision (k_fp64.hip): one thread per point, double precision throughout.
+struct F64StageArgs {
+  int n_layers, rwf, has_bias;
+  int periodic_mask, period_train_mask;
+  float period[3];
+  int64_t off_p;
+  const float* params;
+  int64_t off_w[kMaxLayers], off_s[kMaxLayers], off_b[kMaxLayers];
+  int n_in[kMaxLayers], n_out[kMaxLayers];
+  double* w[kMaxLayers];
+  double* b[kMaxLayers];
+  double* omega;                 // [3]
+};
+
+struct F64Args {
+  int64_t n_pad;
+  int L, d_in, d_out, e, n_freq, act;
+  int periodic_mask, period_train_mask, lap_mask, lapch;
+  int ng;                        // omega rows of the first layer (2 per trained period)
+  double w0;
+  int n_in[kMaxLayers], n_out[kMaxLayers];
+  const double* w[kMaxLayers];
+  const double* b[kMaxLayers];
+  double* a[kMaxLayers];         // jets feeding linear layer l (a[0]: embedding)
+  double* z[kMaxHidden];         // pre-activation jets of hidden layer l
+  double* zb[kMaxHidden];        // their adjoints
+  double* ab[2];                 // activation adjoints, alternating
+  double* yb;                    // output-jet seed
+  double* dw;                    // omega-derivatives of the trained periods' features
+  const double* omega;
+  const float* B;                // Fourier matrix (caller's)
+  const float4* pts;
+  int pde_id, n_res;
+  double coef[4];
+  double seed[3];                // 2 lambda_c / N
+  double lam_anchor[kMaxAnchors];  // 2 lambda_s / N_s
+  const double* wscale;          // device weight of the residual seed (or null)
+  SegDev seg;
+  float* residual;
+  double* loss_slots;            // [blocks][kMaxTerms]
+};
+
+int launch_fp64(const F64StageArgs& s, const F64Args& a, double* const* slots, hipStream_t st);
+
 // Sub-tile points of the wide bf16x3 layer backward (input width a multiple of 128).
 constexpr int wide_pb(int H) { return H >= 256 ? 16 : 32; }
 
@@ -276,7 +322,7 @@ int launch_grad0(const Grad0Args& a, int grid, hipStream_t s);
 int launch_reduce_layer(const ReduceArgs& a, hipStream_t s);
 int launch_reduce_period(const PeriodReduceArgs& a, hipStream_t s);
 int launch_assemble_terms(const double* tmp, int n_terms, int n_res, double* loss, hipStream_t s);
-int launch_causal_weights(const double* bin_loss, int stride, int n_bins, double eps, float* wbin, double* bin_loss_out,
+int launch_causal_weights(const double* bin_loss, int stride, int n_bins, double eps, double* wbin, double* bin_loss_out,
                           double* w_out, hipStream_t s);
 int launch_balance(const double* grads, int n_terms, int64_t n_params, double* lambda, double* hat, double alpha,
                    double eps, hipStream_t s);

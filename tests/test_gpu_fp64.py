@@ -1,0 +1,174 @@
+"""The FP64 precision (double throughout, one thread per point) against the FP64 oracle:
+parity at rounding level on every PDE and network feature, the exactly representable
+networks with no hidden layer, and directional finite differences with steps that are
+exact in the FP32 parameters."""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    import torch
+    return torch.device("cuda:0")
+
+
+def to_dev(case, dev):
+    import torch
+    t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    anchors = [dict(a, points=t(a["points"]), targets=t(a["targets"])) for a in case["anchors"]]
+    return t(case["params"]), t(case["B"]), t(case["points"]), anchors
+
+
+def run64(case, dev, grad=True):
+    import torch
+    from paper_2604_15645_amd import binding
+    params, B, pts, anchors = to_dev(case, dev)
+    out = binding.residual_step(case["net"], case["pde"], params, B, pts, anchors, prec="fp64", grad=grad)
+    torch.cuda.synchronize()
+    return {k: (None if v is None else v.cpu().numpy()) for k, v in out.items()}
+
+
+def variants():
+    from paper_2604_15645_amd import synth
+    out = []
+    for name, n in (("burgers", 500), ("euler", 300), ("ns", 300), ("maxwell", 120), ("advection", 400),
+                    ("allen_cahn", 400)):
+        out.append((name, synth.make_case(name, n_points=n, seed=81, perturb=True)))
+    cfg = synth.CONFIGS["burgers"]
+    net = dict(cfg["net"], widths=[24, 40], periodic_mask=3, period_train_mask=2, period=[2.0, 1.3, 0.0])
+    out.append(("burgers-periodic", synth.make_custom(net, dict(cfg["pde"]), cfg["box"], 300, seed=82)))
+    # w0 is FP32 in the descriptor: take a value FP32 holds exactly, as the oracle uses it as given
+    net = dict(d_in=2, d_out=3, widths=[48, 20, 36], act="sin", w0=1.3125, n_freq=0, rwf=True, has_bias=False)
+    pde = dict(pde="ns2d", lap_mask=3, coef=[40.0, 0, 0, 0], lambda_res=[1.0, 0.5, 2.0])
+    out.append(("uneven-rwf-nobias", synth.make_custom(net, pde, [(0, 1), (0, 1)], 250, seed=83)))
+    return out
+
+
+@pytest.mark.parametrize("k", range(8))
+def test_fp64_parity(oracle, dev, k):
+    name, case = variants()[k]
+    got = run64(case, dev)
+    ref = oracle.loss_grad(case["net"], case["pde"], case["params"], case["B"], case["points"], case["anchors"])
+    errs = {"residual": relerr(got["residual"], ref["residual"].astype(np.float32)),
+            "loss": float(np.max(np.abs(got["loss"] - ref["loss"]) / np.abs(ref["loss"]))),
+            "grad": relerr(got["grad"], ref["grad"])}
+    print(name, {k: "%.2e" % v for k, v in errs.items()})
+    # the residual output is FP32 (rounded from the FP64 value)
+    assert errs["residual"] <= 1e-7 and errs["loss"] <= TOL64 and errs["grad"] <= TOL64, (name, errs)
+
+
+def exact_networks():
+    """Networks whose output solves the PDE exactly (no hidden layer: a linear read-out of
+    the embedding): residual, loss and gradient vanish."""
+    from paper_2604_15645_amd import synth
+    rng = np.random.Generator(np.random.PCG64(84))
+    cases = []
+    kx, ky = 2.0, -1.5
+    w = math.hypot(kx, ky)
+    B = np.array([[kx, 0.4], [ky, 1.1], [-w, -0.3]], dtype=np.float32)
+    Wout = np.zeros((3, 4), dtype=np.float32)
+    Wout[0, 0], Wout[1, 0], Wout[2, 0] = 1.0, ky / w, -kx / w
+    net = dict(d_in=3, d_out=3, widths=[], act="tanh", w0=1.0, n_freq=2, rwf=False, has_bias=True)
+    cases.append(("maxwell plane wave", net, synth.CONFIGS["maxwell"]["pde"],
+                  np.concatenate([Wout.ravel(), rng.normal(size=3).astype(np.float32)]), B,
+                  rng.uniform(0, 1, size=(200, 3)).astype(np.float32)))
+    u0 = 0.5
+    B = np.array([[math.pi], [-math.pi * u0]], dtype=np.float32)
+    Wout = np.zeros((3, 2), dtype=np.float32)
+    Wout[0, 1] = 0.25
+    net = dict(d_in=2, d_out=3, widths=[], act="tanh", w0=1.0, n_freq=1, rwf=False, has_bias=True)
+    cases.append(("euler entropy wave", net, synth.CONFIGS["euler"]["pde"],
+                  np.concatenate([Wout.ravel(), np.array([1.0, u0, 1.1], dtype=np.float32)]), B,
+                  rng.uniform(0, 1, size=(200, 2)).astype(np.float32)))
+    net = dict(d_in=2, d_out=3, widths=[], act="tanh", w0=1.0, n_freq=0, rwf=False, has_bias=True)
+    Wout = np.array([[0.0, 1.0], [0.0, 0.0], [0.0, 0.0]], dtype=np.float32)
+    cases.append(("couette", net, synth.CONFIGS["ns"]["pde"],
+                  np.concatenate([Wout.ravel(), np.array([0.0, 0.0, 0.3], dtype=np.float32)]), None,
+                  rng.uniform(0, 1, size=(200, 2)).astype(np.float32)))
+    return cases
+
+
+@pytest.mark.parametrize("k", range(3))
+def test_fp64_exact_networks(dev, k):
+    import torch
+    from paper_2604_15645_amd import binding
+    name, net, pde, params, B, pts = exact_networks()[k]
+    t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    out = binding.residual_step(net, pde, t(params), t(B), t(pts), (), prec="fp64")
+    torch.cuda.synchronize()
+    res, loss, grad = (out[k].cpu().numpy() for k in ("residual", "loss", "grad"))
+    print(name, "max |r| %.2e  loss %.2e  max |grad| %.2e" % (np.abs(res).max(), loss[0], np.abs(grad).max()))
+    # FP32 inputs (B, weights) make the representation exact only to FP32 rounding of the
+    # wave's parameters, so the residual is at that level, not zero
+    assert np.abs(res).max() < 1e-5 and loss[0] < 1e-10 and np.abs(grad).max() < 1e-5
+
+
+@pytest.mark.parametrize("name", ["ns", "maxwell"])
+def test_fp64_directional_differences(dev, name):
+    """The loss along a direction v whose steps are exact in FP32 (p +- h v is exactly
+    representable): Richardson-extrapolated central differences against g . v."""
+    import torch
+    from paper_2604_15645_amd import binding, synth
+    case = synth.make_case(name, n_points=200, seed=85, perturb=True)
+    p = case["params"].astype(np.float32)
+    rng = np.random.Generator(np.random.PCG64(86))
+    h = 2.0 ** -14
+    v = rng.choice([-1.0, 1.0], size=p.size) * (rng.uniform(size=p.size) < 0.3)
+    for hh in (h, h / 2):  # keep the coordinates where both step sizes are exact
+        for sgn in (1, -1):
+            q = (p.astype(np.float64) + sgn * hh * v).astype(np.float32)
+            v = np.where(q.astype(np.float64) - p.astype(np.float64) == sgn * hh * v, v, 0.0)
+    assert np.count_nonzero(v) > 100
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    B = None if case["B"] is None else t(case["B"])
+    pts = t(case["points"])
+
+    def L(pp):
+        out = binding.residual_step(case["net"], case["pde"], t(pp.astype(np.float32)), B, pts, (), prec="fp64",
+                                    grad=False, residual=False)
+        torch.cuda.synchronize()
+        return out["loss"].cpu().numpy()[0]
+    out = binding.residual_step(case["net"], case["pde"], t(p), B, pts, (), prec="fp64", residual=False)
+    torch.cuda.synchronize()
+    gv = float(out["grad"].cpu().numpy() @ v)
+    d = lambda hh: (L(p + hh * v) - L(p - hh * v)) / (2 * hh)
+    fd = (4 * d(h / 2) - d(h)) / 3
+    print(name, "g.v %.12e  fd %.12e  rel %.2e" % (gv, fd, abs(fd - gv) / abs(gv)))
+    assert abs(fd - gv) <= 1e-8 * abs(gv)
+
+
+def test_fp64_term_and_causal_calls(oracle, dev):
+    """The per-term and causality calls run on the FP64 kernels too."""
+    import torch
+    from paper_2604_15645_amd import binding, synth
+    case = synth.make_case("burgers", n_points=400, seed=87, perturb=True)
+    case["points"] = np.ascontiguousarray(case["points"][np.argsort(case["points"][:, 1], kind="stable")])
+    params, B, pts, anchors = to_dev(case, dev)
+    tg = binding.term_grads(case["net"], case["pde"], params, B, pts, anchors, prec="fp64")
+    cz = binding.causal_step(case["net"], case["pde"], params, B, pts, [100, 150, 150], 30.0, anchors, prec="fp64")
+    torch.cuda.synchronize()
+    _, rg = oracle.term_grads(case["net"], case["pde"], case["params"], None, case["points"], case["anchors"])
+    rc = oracle.causal_loss_grad(case["net"], case["pde"], case["params"], None, case["points"], [100, 150, 150],
+                                 30.0, case["anchors"])
+    errs = {"term%d" % t_: relerr(tg["grads"][t_].cpu().numpy(), g) for t_, g in enumerate(rg)}
+    errs["causal_grad"] = relerr(cz["grad"].cpu().numpy(), rc["grad"])
+    errs["causal_loss"] = relerr(cz["loss"].cpu().numpy(), rc["loss"])
+    print({k: "%.2e" % v for k, v in errs.items()})
+    assert all(v <= TOL64 for v in errs.values()), errs
