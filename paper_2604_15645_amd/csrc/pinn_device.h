@@ -753,65 +753,69 @@ __device__ __forceinline__ void rff_jets(const NetDev& net, const float* B, cons
 
 __device__ __forceinline__ void wait_async() { __builtin_amdgcn_s_waitcnt(0); }
 
-// Strict periodic embedding (Sec. 2.6.3): jets of the e features of one point, channels
+// Strict periodic embedding (Sec. 2.6.3): jets of the features of one point, channels
 // value, d/dx_k in channel 1 + k, and in channel 3 the Laplacian over lap_mask when the PDE
 // has one (two inputs).  Input k of periodic_mask gives the pair cos(omega_k x_k),
 // sin(omega_k x_k), whose only derivative is in x_k; every other input passes through.
-// dw (optional): derivative of each feature's jet with respect to omega_k (pass-through
-// features: zero).
+// The jets sit in fixed slots so that every index is a compile-time constant (no private
+// array in scratch memory): slots 2k and 2k + 1 belong to input k (cos and sin, or the input
+// itself and an empty slot).  dw (optional): derivative of each slot's jet with respect to
+// omega_k (zero for pass-through inputs).
 __device__ __forceinline__ void periodic_jets(int d_in, int periodic_mask, int lap_mask, bool lap,
                                               const float* omega, float4 x, f4 (&ej)[6], f4* dw) {
   const float xs[3] = {x.x, x.y, x.z};
-  int f = 0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    if (k >= d_in) break;
     const int ch = 1 + k;
-    if (!((periodic_mask >> k) & 1)) {
-      f4 v = f4{0.f, 0.f, 0.f, 0.f};
-      v[0] = xs[k];
-      v[ch] = 1.0f;
-      ej[f] = v;
-      if (dw) dw[f] = f4{0.f, 0.f, 0.f, 0.f};
-      ++f;
-      continue;
-    }
-    const float w = omega[k], xk = xs[k];
-    float sv, cv;
-    sincos_fast(w * xk, sv, cv);
-    const bool inlap = lap && ((lap_mask >> k) & 1);
     f4 c = f4{0.f, 0.f, 0.f, 0.f}, sn = f4{0.f, 0.f, 0.f, 0.f};
-    c[0] = cv;
-    sn[0] = sv;
-    c[ch] = -w * sv;
-    sn[ch] = w * cv;
-    if (inlap) {
-      c[3] = -w * w * cv;
-      sn[3] = -w * w * sv;
-    }
-    ej[f] = c;
-    ej[f + 1] = sn;
-    if (dw) {
-      f4 dc = f4{0.f, 0.f, 0.f, 0.f}, ds = f4{0.f, 0.f, 0.f, 0.f};
-      dc[0] = -xk * sv;
-      ds[0] = xk * cv;
-      dc[ch] = -sv - w * xk * cv;
-      ds[ch] = cv - w * xk * sv;
-      if (inlap) {
-        dc[3] = -2.0f * w * cv + w * w * xk * sv;
-        ds[3] = -2.0f * w * sv - w * w * xk * cv;
+    f4 dc = f4{0.f, 0.f, 0.f, 0.f}, ds = f4{0.f, 0.f, 0.f, 0.f};
+    if (k < d_in) {
+      if (!((periodic_mask >> k) & 1)) {
+        c[0] = xs[k];
+        c[ch] = 1.0f;
+      } else {
+        const float w = omega[k], xk = xs[k];
+        float sv, cv;
+        sincos_fast(w * xk, sv, cv);
+        const bool inlap = lap && ((lap_mask >> k) & 1);
+        c[0] = cv;
+        sn[0] = sv;
+        c[ch] = -w * sv;
+        sn[ch] = w * cv;
+        if (inlap) {
+          c[3] = -w * w * cv;
+          sn[3] = -w * w * sv;
+        }
+        if (dw) {
+          dc[0] = -xk * sv;
+          ds[0] = xk * cv;
+          dc[ch] = -sv - w * xk * cv;
+          ds[ch] = cv - w * xk * sv;
+          if (inlap) {
+            dc[3] = -2.0f * w * cv + w * w * xk * sv;
+            ds[3] = -2.0f * w * sv - w * w * xk * cv;
+          }
+        }
       }
-      dw[f] = dc;
-      dw[f + 1] = ds;
     }
-    f += 2;
+    ej[2 * k] = c;
+    ej[2 * k + 1] = sn;
+    if (dw) {
+      dw[2 * k] = dc;
+      dw[2 * k + 1] = ds;
+    }
   }
-#pragma unroll
-  for (int j = 0; j < 6; ++j)
-    if (j >= f) {
-      ej[j] = f4{0.f, 0.f, 0.f, 0.f};
-      if (dw) dw[j] = f4{0.f, 0.f, 0.f, 0.f};
-    }
+}
+
+// Feature index (column of the first layer's weights) of a periodic_jets slot, or -1 for an
+// empty slot.  Wave-uniform.
+__device__ __forceinline__ int periodic_feature(int d_in, int periodic_mask, int slot) {
+  const int k = slot >> 1;
+  if (k >= d_in) return -1;
+  int base = 0;
+  for (int j = 0; j < k; ++j) base += (periodic_mask >> j) & 1 ? 2 : 1;
+  if (slot & 1) return (periodic_mask >> k) & 1 ? base + 1 : -1;
+  return base;
 }
 
 // Work-group barrier for LDS traffic: this wave's LDS operations complete (lgkmcnt 0), then
@@ -952,29 +956,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
   f4 acc[NBW][CBW];
   // ---- layer 0
   const LayerDev& l0 = net.layer[0];
-  if (net.periodic_mask) {
-    // periodic embedding: z = W e(x) + b with the features' jets computed per point
-#pragma unroll
-    for (int i = 0; i < NBW; ++i) {
-      const int nb = wn + WN * i;
-      const bool ok = nb * 16 < l0.n_out;
-      const int n = ok ? 16 * nb + l16 : 0;
-      float w[6];
-#pragma unroll
-      for (int f = 0; f < 6; ++f) w[f] = ok && f < net.e ? l0.w[n * net.e + f] : 0.0f;
-      const float bn = ok ? l0.b[n] : 0.0f;
-#pragma unroll
-      for (int c = 0; c < CBW; ++c) {
-        const float4 x = s.PT[4 * (wc * CBW + c) + g];
-        f4 ej[6];
-        periodic_jets(net.d_in, net.periodic_mask, net.lap_mask, net.lapch >= 0, net.omega, x, ej, nullptr);
-        f4 z = f4{bn, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int f = 0; f < 6; ++f) z += w[f] * ej[f];
-        acc[i][c] = z;
-      }
-    }
-  } else if (net.n_freq == 0) {
+  if (net.n_freq == 0 && !net.periodic_mask) {
     // identity embedding: z = W x + b on the value channel, d z / d x_k = W[:, k]
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
@@ -999,18 +981,39 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       }
     }
   } else {
-    // Fourier-feature jets into the R layout, then z = W gamma + b
-    // blocks of 4 points x 16 frequencies per wave: lane (g, l16) takes point 4 pb + g,
-    // frequency 16 jb + l16, the write pattern of an accumulator block
-    const int m = net.n_freq;
-    const int nj = m >> 4;
-    for (int b = wave; b < (P / 4) * nj; b += NW) {
-      const int pb = b / nj, jb = b - (b / nj) * nj;
-      const int p = 4 * pb + g, j = 16 * jb + l16;
-      f4 cj, sj;
-      rff_jets(net, s.BF, s.PT[p], j, cj, sj);
-      Tile<PREC>::put(X, ld, p, j, cj);
-      Tile<PREC>::put(X, ld, p, m + j, sj);
+    if (net.periodic_mask) {
+      // periodic embedding (Sec. 2.6.3): the e <= 6 feature jets of each point into the
+      // tile, the rest of the first 32-wide reduction chunk cleared (its weights are zero,
+      // but the tile holds the previous layer's jets), then z = W e + b as for Fourier
+      // features; lane (g, l16) takes point 4 pb + g and column l16 or 16 + l16
+      for (int pb = wave; pb < P / 4; pb += NW) {
+        const int p = 4 * pb + g;
+        f4 ej[6];
+        periodic_jets(net.d_in, net.periodic_mask, net.lap_mask, net.lapch >= 0, net.omega, s.PT[p], ej, nullptr);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int col = 16 * h + l16;
+          f4 v = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int q = 0; q < 6; ++q)
+            if (periodic_feature(net.d_in, net.periodic_mask, q) == col) v = ej[q];
+          Tile<PREC>::put(X, ld, p, col, v);
+        }
+      }
+    } else {
+      // Fourier-feature jets into the tile, then z = W gamma + b
+      // blocks of 4 points x 16 frequencies per wave: lane (g, l16) takes point 4 pb + g,
+      // frequency 16 jb + l16, the write pattern of an accumulator block
+      const int m = net.n_freq;
+      const int nj = m >> 4;
+      for (int b = wave; b < (P / 4) * nj; b += NW) {
+        const int pb = b / nj, jb = b - (b / nj) * nj;
+        const int p = 4 * pb + g, j = 16 * jb + l16;
+        f4 cj, sj;
+        rff_jets(net, s.BF, s.PT[p], j, cj, sj);
+        Tile<PREC>::put(X, ld, p, j, cj);
+        Tile<PREC>::put(X, ld, p, m + j, sj);
+      }
     }
     barrier_lds();
 #pragma unroll
@@ -1530,23 +1533,15 @@ __device__ __forceinline__ void grad0p_range(const Grad0Args& A, int64_t cb_lo, 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nob = A.n_out / 16, e = A.e;
   const bool lap = A.lap_mask != 0;
-  // features whose jets depend on a trained period (bit f; two per trained input)
+  // slots of trained periods (bits 2k and 2k + 1 for a trained input k)
   int tmask = 0, ng = 0;
-  {
-    int f = 0;
-    for (int k = 0; k < A.d_in; ++k) {
-      if (!((A.periodic_mask >> k) & 1)) {
-        ++f;
-        continue;
-      }
-      if ((A.period_train_mask >> k) & 1) {
-        tmask |= 3 << f;
-        ng += 2;
-      }
-      f += 2;
+  for (int k = 0; k < A.d_in; ++k)
+    if ((A.period_train_mask >> k) & 1) {
+      tmask |= 3 << (2 * k);
+      ng += 2;
     }
-  }
-  // sums per output: sum[0 .. e) weights, sum[6] bias, sum[7 + f] period term of feature f
+  // sums per output, by slot of periodic_jets: sum[q] weights, sum[6] bias, sum[7 + q] the
+  // period terms of trained slots
   constexpr int kG = 4;  // output blocks per pass
   for (int og = 0; og < nob; og += kG) {
     float sum[kG][13];
@@ -1563,8 +1558,7 @@ __device__ __forceinline__ void grad0p_range(const Grad0Args& A, int64_t cb_lo, 
         if (ob >= nob) continue;
         const f4 z = to_f4(*jet_frag(const_cast<float*>(A.zb), cb, ob, nob, lane));
 #pragma unroll
-        for (int j = 0; j < 6; ++j)
-          if (j < e) sum[q][j] += z.x * ej[j].x + z.y * ej[j].y + z.z * ej[j].z + z.w * ej[j].w;
+        for (int j = 0; j < 6; ++j) sum[q][j] += z.x * ej[j].x + z.y * ej[j].y + z.z * ej[j].z + z.w * ej[j].w;
         sum[q][6] += z.x;
 #pragma unroll
         for (int f = 0; f < 6; ++f)
@@ -1589,10 +1583,12 @@ __device__ __forceinline__ void grad0p_range(const Grad0Args& A, int64_t cb_lo, 
       for (int a = 0; a < 13; ++a) t[a] = 0.0;
       for (int w = 0; w < kWaves; ++w)
         for (int a = 0; a < 13; ++a) t[a] += (double)red[(w * kG * 16 + i) * 13 + a];
-      for (int j = 0; j < e; ++j) slot[(size_t)o * e + j] = t[j];
+      for (int q = 0, j = 0; q < 6; ++q) {
+        const int f = periodic_feature(A.d_in, A.periodic_mask, q);
+        if (f >= 0) slot[(size_t)o * e + f] = t[q];
+        if ((tmask >> q) & 1) slot[(size_t)A.n_out * (e + 1) + (size_t)o * ng + j++] = t[7 + q];
+      }
       slot[(size_t)A.n_out * e + o] = t[6];
-      for (int f = 0, j = 0; f < e; ++f)
-        if ((tmask >> f) & 1) slot[(size_t)A.n_out * (e + 1) + (size_t)o * ng + j++] = t[7 + f];
     }
   }
 }
