@@ -9,9 +9,8 @@ generator produces), so that nothing but data is shared with the HIP path:
 
   net = {"d_in", "d_out", "widths": [..], "act": "tanh"|"sin", "w0", "n_freq",
          "rwf", "has_bias", "periodic_mask", "period_train_mask", "period": [..3]}
-  pde = {"pde": "burgers"|"euler1d"|"ns2d"|"maxwell"|"advection"|"allen_cahn", "lap_mask",
-         "coef": [..4],
-         "lambda_res": [..3], "norm_N"}
+  pde = {"pde": "burgers"|"euler1d"|"ns2d"|"maxwell"|"advection"|"allen_cahn"|"euler2d",
+         "lap_mask", "coef": [..4], "lambda_res": [..4], "norm_N"}
 Arrays may be float32; they are promoted to float64 before the call.
 """
 import ctypes
@@ -24,7 +23,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pinn_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-PDE_IDS = {"burgers": 1, "euler1d": 2, "ns2d": 3, "maxwell": 4, "advection": 5, "allen_cahn": 6}
+PDE_IDS = {"burgers": 1, "euler1d": 2, "ns2d": 3, "maxwell": 4, "advection": 5, "allen_cahn": 6,
+           "euler2d": 7}
+MAX_RES = 4
 ACTS = {"tanh": 0, "sin": 1}
 
 
@@ -39,7 +40,7 @@ class _Net(ctypes.Structure):
 
 class _Pde(ctypes.Structure):
     _fields_ = [("pde_id", ctypes.c_int32), ("lap_mask", ctypes.c_int32),
-                ("coef", ctypes.c_double * 4), ("lambda_res", ctypes.c_double * 3),
+                ("coef", ctypes.c_double * 4), ("lambda_res", ctypes.c_double * MAX_RES),
                 ("norm_N", ctypes.c_double)]
 
 
@@ -117,8 +118,8 @@ def _pde(spec):
     coef = list(spec.get("coef", [])) + [0.0] * 4
     for i in range(4):
         p.coef[i] = float(coef[i])
-    lam = list(spec.get("lambda_res", [1.0, 1.0, 1.0])) + [1.0] * 3
-    for i in range(3):
+    lam = list(spec.get("lambda_res", [])) + [1.0] * MAX_RES
+    for i in range(MAX_RES):
         p.lambda_res[i] = float(lam[i])
     p.norm_N = float(spec.get("norm_N", 0.0))
     return p
@@ -137,7 +138,7 @@ def n_channels(net_spec, lap_mask):
 
 
 def n_residuals(pde_name):
-    return 3 if pde_name in ("euler1d", "ns2d", "maxwell") else 1
+    return int(lib().or_n_residuals(PDE_IDS[pde_name]))
 
 
 def param_count(net_spec):

@@ -21,7 +21,8 @@
  *                   the printed inviscid form); 1D Euler in conservative form (Sec. 4.6);
  *                   steady incompressible Navier-Stokes (Sec. 4.4); 2D Maxwell, the
  *                   (E_z, H_x, H_y) system of Sec. 4.8; linear advection (Sec. 4.1,
- *                   u_t + c u_x); Allen-Cahn (Sec. 4.2, u_t - D u_xx + k (u^3 - u)).  Each
+ *                   u_t + c u_x); Allen-Cahn (Sec. 4.2, u_t - D u_xx + k (u^3 - u)); 2D Euler
+ *                   in conservative form, outputs (rho, u, v, p) (Sec. 4.7).  Each
  *                   residual is "left side minus right side" of the printed equation.
  *   loss         -- Sec. 2.3 "Loss function": mean of squared residuals per constraint,
  *                   summed (one mean per residual component, weighted by lambda_c), plus
@@ -53,7 +54,9 @@
 static const double OR_PI = 3.14159265358979323846;
 
 enum { OR_OK = 0, OR_E_INVALID = -1, OR_E_UNSUPPORTED = -2, OR_E_NOMEM = -3 };
-enum { OR_BURGERS = 1, OR_EULER1D = 2, OR_NS2D = 3, OR_MAXWELL = 4, OR_ADVECTION = 5, OR_ALLEN_CAHN = 6 };
+#define OR_MAX_OUT 4         /* outputs (rho, u, v, p) of the 2D Euler system */
+enum { OR_BURGERS = 1, OR_EULER1D = 2, OR_NS2D = 3, OR_MAXWELL = 4, OR_ADVECTION = 5, OR_ALLEN_CAHN = 6,
+       OR_EULER2D = 7 };
 
 typedef struct {
   int32_t d_in, d_out, n_hidden;
@@ -72,8 +75,8 @@ typedef struct {
   int32_t pde_id;
   int32_t lap_mask;     /* bit k set: input k belongs to the Laplacian set */
   double coef[4];       /* Burgers nu | Euler gamma | NS Re | Maxwell eps, mu | advection c |
-                           Allen-Cahn D, k */
-  double lambda_res[3];
+                           Allen-Cahn D, k | 2D Euler gamma */
+  double lambda_res[OR_MAX_OUT];
   double norm_N;        /* divisor of the residual mean; 0 means "number of points" */
 } or_pde;
 
@@ -153,12 +156,13 @@ static int n_channels(const or_net* net, int lap_mask) {
 }
 
 static int n_residuals(int pde_id) {
+  if (pde_id == OR_EULER2D) return 4;
   return pde_id == OR_EULER1D || pde_id == OR_NS2D || pde_id == OR_MAXWELL ? 3 : 1;
 }
 
 static int check_net(const or_net* net, int lap_mask) {
   if (!net) return OR_E_INVALID;
-  if (net->d_in < 1 || net->d_in > 3 || net->d_out < 1 || net->d_out > 3) return OR_E_INVALID;
+  if (net->d_in < 1 || net->d_in > 3 || net->d_out < 1 || net->d_out > OR_MAX_OUT) return OR_E_INVALID;
   if (net->n_hidden < 0 || net->n_hidden > OR_MAX_HIDDEN) return OR_E_INVALID;
   for (int l = 0; l < net->n_hidden; ++l)
     if (net->width[l] < 1 || net->width[l] > 4096) return OR_E_INVALID;
@@ -455,6 +459,71 @@ static void residual_point(const or_pde* pde, int d_in, const double* y, int C, 
       }
       break;
     }
+    case OR_EULER2D: { /* inputs (x, y, t), outputs (rho, u, v, p); conservative form (Sec. 4.7) */
+      /* With q = u^2 + v^2 and g = 1 / (gamma - 1): rho E = g p + rho q / 2 and
+       * rho E + p = H = (g + 1) p + rho q / 2.  Every conservative derivative is expanded
+       * by the product rule into the output jets. */
+      double g = 1.0 / (pde->coef[0] - 1.0);
+      double rho = Y(0, 0), rx = Y(0, 1), ry = Y(0, 2), rt = Y(0, 3);
+      double u = Y(1, 0), ux = Y(1, 1), uy = Y(1, 2), ut = Y(1, 3);
+      double v = Y(2, 0), vx = Y(2, 1), vy = Y(2, 2), vt = Y(2, 3);
+      double p = Y(3, 0), px = Y(3, 1), py = Y(3, 2), pt = Y(3, 3);
+      double q = u * u + v * v;
+      double H = (g + 1.0) * p + 0.5 * rho * q;
+      double Hx = (g + 1.0) * px + 0.5 * q * rx + rho * (u * ux + v * vx);  /* d/dx of H */
+      double Hy = (g + 1.0) * py + 0.5 * q * ry + rho * (u * uy + v * vy);  /* d/dy of H */
+      double Et = g * pt + 0.5 * q * rt + rho * (u * ut + v * vt);        /* d/dt of rho E */
+      /* d/dt(rho) + d/dx(rho u) + d/dy(rho v) */
+      r[0] = rt + (u * rx + rho * ux) + (v * ry + rho * vy);
+      /* d/dt(rho u) + d/dx(rho u^2 + p) + d/dy(rho u v) */
+      r[1] = (u * rt + rho * ut) + (u * u * rx + 2.0 * rho * u * ux + px) + (u * v * ry + rho * v * uy + rho * u * vy);
+      /* d/dt(rho v) + d/dx(rho u v) + d/dy(rho v^2 + p) */
+      r[2] = (v * rt + rho * vt) + (u * v * rx + rho * v * ux + rho * u * vx) + (v * v * ry + 2.0 * rho * v * vy + py);
+      /* d/dt(rho E) + d/dx(u H) + d/dy(v H) */
+      r[3] = Et + (ux * H + u * Hx) + (vy * H + v * Hy);
+      if (rbar) {
+        double b0 = rbar[0], b1 = rbar[1], b2 = rbar[2], b3 = rbar[3];
+        /* adjoints of rho, u, v, p and their derivatives, then of the intermediates */
+        double a_r = 0, a_rx = 0, a_ry = 0, a_rt = 0, a_u = 0, a_ux = 0, a_uy = 0, a_ut = 0;
+        double a_v = 0, a_vx = 0, a_vy = 0, a_vt = 0, a_p = 0, a_px = 0, a_py = 0, a_pt = 0;
+        /* r[0] */
+        a_rt += b0; a_u += b0 * rx; a_rx += b0 * u; a_r += b0 * (ux + vy); a_ux += b0 * rho;
+        a_v += b0 * ry; a_ry += b0 * v; a_vy += b0 * rho;
+        /* r[1] */
+        a_u += b1 * (rt + 2.0 * u * rx + 2.0 * rho * ux + v * ry + rho * vy);
+        a_r += b1 * (ut + 2.0 * u * ux + v * uy + u * vy);
+        a_v += b1 * (u * ry + rho * uy);
+        a_rt += b1 * u; a_ut += b1 * rho; a_rx += b1 * u * u; a_ux += b1 * 2.0 * rho * u; a_px += b1;
+        a_ry += b1 * u * v; a_uy += b1 * rho * v; a_vy += b1 * rho * u;
+        /* r[2] */
+        a_v += b2 * (rt + u * rx + rho * ux + 2.0 * v * ry + 2.0 * rho * vy);
+        a_r += b2 * (vt + v * ux + u * vx + 2.0 * v * vy);
+        a_u += b2 * (v * rx + rho * vx);
+        a_rt += b2 * v; a_vt += b2 * rho; a_rx += b2 * u * v; a_ux += b2 * rho * v; a_vx += b2 * rho * u;
+        a_ry += b2 * v * v; a_vy += b2 * 2.0 * rho * v; a_py += b2;
+        /* r[3] = Et + ux H + u Hx + vy H + v Hy */
+        double a_Et = b3, a_H = b3 * (ux + vy), a_Hx = b3 * u, a_Hy = b3 * v, a_q = 0.0;
+        a_ux += b3 * H; a_vy += b3 * H; a_u += b3 * Hx; a_v += b3 * Hy;
+        /* Et */
+        a_pt += g * a_Et; a_q += 0.5 * rt * a_Et; a_rt += 0.5 * q * a_Et; a_r += (u * ut + v * vt) * a_Et;
+        a_u += rho * ut * a_Et; a_ut += rho * u * a_Et; a_v += rho * vt * a_Et; a_vt += rho * v * a_Et;
+        /* Hx */
+        a_px += (g + 1.0) * a_Hx; a_q += 0.5 * rx * a_Hx; a_rx += 0.5 * q * a_Hx; a_r += (u * ux + v * vx) * a_Hx;
+        a_u += rho * ux * a_Hx; a_ux += rho * u * a_Hx; a_v += rho * vx * a_Hx; a_vx += rho * v * a_Hx;
+        /* Hy */
+        a_py += (g + 1.0) * a_Hy; a_q += 0.5 * ry * a_Hy; a_ry += 0.5 * q * a_Hy; a_r += (u * uy + v * vy) * a_Hy;
+        a_u += rho * uy * a_Hy; a_uy += rho * u * a_Hy; a_v += rho * vy * a_Hy; a_vy += rho * v * a_Hy;
+        /* H */
+        a_p += (g + 1.0) * a_H; a_r += 0.5 * q * a_H; a_q += 0.5 * rho * a_H;
+        /* q */
+        a_u += 2.0 * u * a_q; a_v += 2.0 * v * a_q;
+        YB(0, 0) += a_r; YB(0, 1) += a_rx; YB(0, 2) += a_ry; YB(0, 3) += a_rt;
+        YB(1, 0) += a_u; YB(1, 1) += a_ux; YB(1, 2) += a_uy; YB(1, 3) += a_ut;
+        YB(2, 0) += a_v; YB(2, 1) += a_vx; YB(2, 2) += a_vy; YB(2, 3) += a_vt;
+        YB(3, 0) += a_p; YB(3, 1) += a_px; YB(3, 2) += a_py; YB(3, 3) += a_pt;
+      }
+      break;
+    }
     default:
       break;
   }
@@ -484,6 +553,9 @@ static int check_pde(const or_net* net, const or_pde* pde) {
       return OR_OK;
     case OR_ALLEN_CAHN:
       if (net->d_in != 2 || net->d_out < 1 || pde->lap_mask != 1) return OR_E_UNSUPPORTED;
+      return OR_OK;
+    case OR_EULER2D:
+      if (net->d_in != 3 || net->d_out != 4 || pde->lap_mask != 0 || !(pde->coef[0] > 1.0)) return OR_E_UNSUPPORTED;
       return OR_OK;
     default:
       return OR_E_UNSUPPORTED;
@@ -557,14 +629,14 @@ typedef struct {
   double* z[OR_MAX_HIDDEN];
   double* ab;   /* adjoint of activation jets, max width */
   double* zb;   /* adjoint of pre-activation jets, max width */
-  double y[3 * OR_MAX_CH];
-  double yb[3 * OR_MAX_CH];
+  double y[OR_MAX_OUT * OR_MAX_CH];
+  double yb[OR_MAX_OUT * OR_MAX_CH];
 } or_scratch;
 
 static int max_width(const or_net* net) {
   int w = embed_width(net);
   for (int l = 0; l < net->n_hidden; ++l) w = net->width[l] > w ? net->width[l] : w;
-  return w > 3 ? w : 3;
+  return w > OR_MAX_OUT ? w : OR_MAX_OUT;
 }
 
 static int alloc_scratch(const or_net* net, int C, or_scratch* s) {
@@ -749,7 +821,7 @@ int or_loss_grad(const or_net* net, const or_pde* pde, const double* params, con
     nblocks += seg_blocks[s];
   }
   int nterm = 1 + nr + n_anchor;
-  double term[1 + 3 + 8];
+  double term[1 + OR_MAX_OUT + 8];
   memset(term, 0, sizeof(term));
   double* geff = grad ? (double*)calloc((size_t)neff, sizeof(double)) : 0;
 
@@ -788,7 +860,7 @@ int or_loss_grad(const or_net* net, const or_pde* pde, const double* params, con
           forward_point(net, lap, &ow, B, per, x, s.a, s.z, s.y, C);
           memset(s.yb, 0, sizeof(s.yb));
           if (seg == 0) {
-            double r[3], rb[3];
+            double r[OR_MAX_OUT], rb[OR_MAX_OUT];
             residual_point(pde, d, s.y, C, r, 0, 0);
             for (int c = 0; c < nr; ++c) {
               t[1 + c] += pde->lambda_res[c] * r[c] * r[c] / N;

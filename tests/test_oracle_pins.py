@@ -27,9 +27,15 @@ PDES = {
     # so that a dropped diffusion term cannot hide below the tolerance
     "advection": dict(pde="advection", lap_mask=0, coef=[2.5, 0, 0, 0]),
     "allen_cahn": dict(pde="allen_cahn", lap_mask=1, coef=[0.05, 5.0, 0, 0]),
+    "euler2d": dict(pde="euler2d", lap_mask=0, coef=[1.4, 0, 0, 0]),
 }
-D_IN = {"burgers": 2, "euler1d": 2, "ns2d": 2, "maxwell": 3, "advection": 2, "allen_cahn": 2}
-D_OUT = {"burgers": 1, "euler1d": 3, "ns2d": 3, "maxwell": 3, "advection": 1, "allen_cahn": 1}
+D_IN = {"burgers": 2, "euler1d": 2, "ns2d": 2, "maxwell": 3, "advection": 2, "allen_cahn": 2,
+        "euler2d": 3}
+D_OUT = {"burgers": 1, "euler1d": 3, "ns2d": 3, "maxwell": 3, "advection": 1, "allen_cahn": 1,
+         "euler2d": 4}
+# output biases added to perturbed Euler networks so that density and pressure stay away
+# from zero (rho, u, [v,] p)
+EULER_SHIFT = {"euler1d": [2.0, 0.3, 1.5], "euler2d": [2.0, 0.3, -0.2, 1.5]}
 
 
 def small_net(pde, widths=(6, 5), act="tanh", n_freq=0, rwf=False, has_bias=True, w0=1.0):
@@ -260,6 +266,15 @@ def torch_loss(net, pde, params_np, B, pts_np, anchors):
         q = [rho, rho * u, rho * E]
         fl = [rho * u, rho * u * u + p, u * (rho * E + p)]
         res = [d(q[i], 1) + d(fl[i], 0) for i in range(3)]
+    elif name == "euler2d":
+        # conservative form of Sec. 4.7: inputs (x, y, t), outputs (rho, u, v, p)
+        gam = pde["coef"][0]
+        rho, u, v, p = y[:, 0], y[:, 1], y[:, 2], y[:, 3]
+        E = p / ((gam - 1.0) * rho) + 0.5 * (u * u + v * v)
+        q = [rho, rho * u, rho * v, rho * E]
+        fx = [rho * u, rho * u * u + p, rho * u * v, u * (rho * E + p)]
+        fy = [rho * v, rho * u * v, rho * v * v + p, v * (rho * E + p)]
+        res = [d(q[i], 2) + d(fx[i], 0) + d(fy[i], 1) for i in range(4)]
     elif name == "advection":
         c = pde["coef"][0]
         u = y[:, 0]
@@ -300,7 +315,8 @@ def torch_loss(net, pde, params_np, B, pts_np, anchors):
                                          ("euler1d", "rff"), ("ns2d", "rwf"),
                                          ("ns2d", "sin"), ("maxwell", "rff_sin"),
                                          ("maxwell", "plain"), ("advection", "rff_sin"),
-                                         ("allen_cahn", "plain"), ("allen_cahn", "rwf")])
+                                         ("allen_cahn", "plain"), ("allen_cahn", "rwf"),
+                                         ("euler2d", "rff"), ("euler2d", "rwf")])
 def test_oracle_matches_torch_autograd(oracle, pde, variant):
     """The paper computes residuals and gradients with autograd (Sec. 2.3); the oracle's
     forward-mode jets and reverse sweep must give the same numbers.  The Euler residual
@@ -311,15 +327,15 @@ def test_oracle_matches_torch_autograd(oracle, pde, variant):
     params = synth.init_params(net, r, perturb=True).astype(np.float64)
     B = r.normal(0, 1.5, size=(net["d_in"], net["n_freq"])) if net["n_freq"] else None
     pts = r.uniform(0.05, 0.95, size=(33, net["d_in"]))
-    if pde == "euler1d":
+    if pde in EULER_SHIFT:
         # keep density and pressure away from zero: shift the output biases
         L = synth.layer_dims(net)[-1][0]
-        params[-L:] += np.array([2.0, 0.3, 1.5])
+        params[-L:] += np.array(EULER_SHIFT[pde])
     anchors = []
     if pde == "burgers":
         anchors = [dict(points=r.uniform(-1, 1, size=(5, 2)),
                         targets=r.normal(size=(5, 1)), out_mask=1, **{"lambda": 0.9})]
-    spec = dict(PDES[pde], lambda_res=[1.0, 0.7, 1.3])
+    spec = dict(PDES[pde], lambda_res=[1.0, 0.7, 1.3, 0.8])
     got = oracle.loss_grad(net, spec, params, B, pts, anchors)
     loss, res, grad = torch_loss(net, spec, params, B, pts, anchors)
     assert relerr(got["loss"], loss) < 1e-12
@@ -327,9 +343,10 @@ def test_oracle_matches_torch_autograd(oracle, pde, variant):
     assert relerr(got["grad"], grad) < 1e-11
 
 
-@pytest.mark.parametrize("pde,masks", [("ns2d", (5, 6)), ("euler1d", (2, 7)), ("maxwell", (4, 3))])
+@pytest.mark.parametrize("pde,masks", [("ns2d", (5, 6)), ("euler1d", (2, 7)), ("maxwell", (4, 3)),
+                                       ("euler2d", (15, 10))])
 def test_multi_output_supervision_matches_torch_autograd(oracle, pde, masks):
-    """Value supervision on networks with three outputs (Sec. 2.3: one mean square per
+    """Value supervision on networks with several outputs (Sec. 2.3: one mean square per
     supervised quantity): every out_mask bit, not only output 0, against the autograd
     formulation, and the gradient against central differences of the oracle's loss."""
     net = small_net(pde, widths=(7, 6), act="tanh", n_freq=3 if pde != "ns2d" else 0, w0=1.0)
@@ -337,12 +354,13 @@ def test_multi_output_supervision_matches_torch_autograd(oracle, pde, masks):
     params = synth.init_params(net, r, perturb=True).astype(np.float64)
     B = r.normal(0, 1.2, size=(net["d_in"], net["n_freq"])) if net["n_freq"] else None
     pts = r.uniform(0.05, 0.95, size=(19, net["d_in"]))
-    if pde == "euler1d":
-        params[-3:] += np.array([2.0, 0.3, 1.5])
+    if pde in EULER_SHIFT:
+        params[-D_OUT[pde]:] += np.array(EULER_SHIFT[pde])
     anchors = [dict(points=r.uniform(0.0, 1.0, size=(6 + k, net["d_in"])),
-                    targets=r.normal(size=(6 + k, 3)), out_mask=m, **{"lambda": 0.6 + 0.5 * k})
+                    targets=r.normal(size=(6 + k, D_OUT[pde])), out_mask=m,
+                    **{"lambda": 0.6 + 0.5 * k})
                for k, m in enumerate(masks)]
-    spec = dict(PDES[pde], lambda_res=[1.0, 0.7, 1.3])
+    spec = dict(PDES[pde], lambda_res=[1.0, 0.7, 1.3, 0.8])
     got = oracle.loss_grad(net, spec, params, B, pts, anchors)
     loss, res, grad = torch_loss(net, spec, params, B, pts, anchors)
     assert relerr(got["loss"], loss) < 1e-12
@@ -350,8 +368,9 @@ def test_multi_output_supervision_matches_torch_autograd(oracle, pde, masks):
     # each supervision term differs from the term with only output 0 supervised
     only0 = [dict(a, out_mask=1) for a in anchors]
     base = oracle.loss_grad(net, spec, params, B, pts, only0)
+    first = 1 + oracle.n_residuals(pde)
     for k in range(len(anchors)):
-        assert abs(got["loss"][4 + k] - base["loss"][4 + k]) > 1e-6 * abs(got["loss"][4 + k])
+        assert abs(got["loss"][first + k] - base["loss"][first + k]) > 1e-6 * abs(got["loss"][first + k])
     # central differences of the oracle's own loss along random directions
     for j in range(3):
         v = r.normal(size=params.size)
@@ -456,6 +475,44 @@ def test_euler_manufactured(oracle):
         assert np.allclose(got[i], exp, rtol=1e-12, atol=1e-13)
 
 
+def test_euler2d_manufactured(oracle):
+    """Sec. 4.7: a density wave carried by a uniform flow at constant pressure is an exact
+    solution; a general smooth state against the conservative form differentiated
+    symbolically (fluxes in x and y, total energy with both velocity components)."""
+    x, y, t = sp.symbols("x y t")
+    pts = rng(27).uniform([0, 0, 0], [1, 1, 0.25], size=(6, 3))
+    pde = dict(pde="euler2d", lap_mask=0, coef=[1.4, 0, 0, 0])
+    u0, v0, p0 = 0.75, -0.5, 1.0
+    rho = 1 + sp.Rational(1, 4) * sp.sin(2 * sp.pi * (x - u0 * t)) * sp.cos(2 * sp.pi * (y - v0 * t))
+    j = analytic_jets([rho, sp.Float(u0) + 0 * x, sp.Float(v0) + 0 * x, sp.Float(p0) + 0 * x],
+                      (x, y, t), (), pts)
+    assert np.abs(oracle.pde_residual(pde, 3, 4, j)).max() < 1e-13
+    rho = 1.5 + 0.3 * sp.sin(2 * x - y + t)
+    u = 0.4 * sp.cos(x + 2 * y - 3 * t)
+    v = -0.2 + 0.3 * sp.sin(x * y + t)
+    p = 1.0 + 0.2 * x * x - 0.1 * y + 0.1 * t
+    g = 1.4
+    rE = p / (g - 1) + rho * (u * u + v * v) / 2
+    q = [rho, rho * u, rho * v, rE]
+    fx = [rho * u, rho * u * u + p, rho * u * v, u * (rE + p)]
+    fy = [rho * v, rho * u * v, rho * v * v + p, v * (rE + p)]
+    j = analytic_jets([rho, u, v, p], (x, y, t), (), pts)
+    got = oracle.pde_residual(pde, 3, 4, j)
+    for i, pt in enumerate(pts):
+        sub = {x: pt[0], y: pt[1], t: pt[2]}
+        exp = [float((sp.diff(q[k], t) + sp.diff(fx[k], x) + sp.diff(fy[k], y)).subs(sub))
+               for k in range(4)]
+        assert np.allclose(got[i], exp, rtol=1e-12, atol=1e-13)
+    # each component reacts to its own flux: the 1D Euler system is the y-independent case
+    j1 = analytic_jets([rho.subs(y, 0), u.subs(y, 0), p.subs(y, 0)], (x, t), (), pts[:, [0, 2]])
+    j2 = analytic_jets([rho.subs(y, 0), u.subs(y, 0), sp.Float(0) + 0 * x, p.subs(y, 0)], (x, y, t), (),
+                       pts)
+    r1 = oracle.pde_residual(dict(pde, pde="euler1d"), 2, 3, j1)
+    r2 = oracle.pde_residual(pde, 3, 4, j2)
+    assert np.allclose(r2[:, [0, 1, 3]], r1, rtol=1e-12, atol=1e-13)
+    assert np.abs(r2[:, 2]).max() < 1e-13
+
+
 def test_navier_stokes_kovasznay(oracle):
     """Kovasznay flow solves the steady incompressible equations exactly."""
     x, y = sp.symbols("x y")
@@ -556,6 +613,26 @@ def test_periodic_embedding_matches_torch_autograd(oracle, pde, act):
     assert abs(grad[-1]) > 1e-6     # the period gradient is exercised, not trivially zero
 
 
+def test_euler2d_periodic_matches_torch_autograd(oracle):
+    """The 2D Riemann set-up of Sec. 4.7: x and y enter through the periodic pair (P = 1,
+    the unit square), t through itself, four outputs; loss, residuals and gradient against
+    autograd of the conservative fluxes, with supervision of all four initial fields."""
+    net = dict(d_in=3, d_out=4, widths=[8, 7], act="tanh", w0=1.0, n_freq=0, rwf=True,
+               has_bias=True, periodic_mask=3, period_train_mask=0, period=[1.0, 1.0, 0.0])
+    r = rng(26)
+    params = synth.init_params(net, r, perturb=True).astype(np.float64)
+    params[-4:] += np.array(EULER_SHIFT["euler2d"])
+    pts = r.uniform([0, 0, 0], [1, 1, 0.25], size=(27, 3))
+    anchors = [dict(points=np.c_[r.uniform(0, 1, size=(7, 2)), np.zeros(7)],
+                    targets=r.normal(size=(7, 4)), out_mask=15, **{"lambda": 0.7})]
+    spec = dict(PDES["euler2d"], lambda_res=[1.1, 0.9, 1.3, 0.6])
+    got = oracle.loss_grad(net, spec, params, None, pts, anchors)
+    loss, res, grad = torch_loss(net, spec, params, None, pts, anchors)
+    assert relerr(got["loss"], loss) < 1e-12
+    assert relerr(got["residual"], res) < 1e-12
+    assert relerr(got["grad"], grad) < 1e-11
+
+
 def test_periodic_gradient_matches_central_differences(oracle):
     net = periodic_net("burgers", widths=(4, 3))
     r = rng(22)
@@ -599,6 +676,16 @@ def exact_case(kind):
                    has_bias=True)
         params = np.concatenate([Wout.ravel(), [1.0, u0, 1.1]])
         return net, PDES["euler1d"], params, B, r.uniform(0, 1, size=(40, 2))
+    if kind == "euler2d_entropy":
+        # rho = 1.2 + 0.3 sin(2 pi (x - u0 t) + 2 pi (y - v0 t)), (u, v, p) = (u0, v0, p0)
+        u0, v0 = 0.75, -0.5
+        B = np.array([[2 * math.pi], [2 * math.pi], [-2 * math.pi * (u0 + v0)]])
+        Wout = np.zeros((4, 2))
+        Wout[0, 1] = 0.3
+        net = dict(d_in=3, d_out=4, widths=[], act="tanh", w0=1.0, n_freq=1, rwf=False,
+                   has_bias=True)
+        params = np.concatenate([Wout.ravel(), [1.2, u0, v0, 1.0]])
+        return net, PDES["euler2d"], params, B, r.uniform(0, 1, size=(40, 3))
     if kind == "advection_wave":
         # u = 0.8 sin(x - c t) + b: one Fourier column (1, -c), sine coefficient 0.8
         c = PDES["advection"]["coef"][0]
@@ -618,7 +705,8 @@ def exact_case(kind):
     raise KeyError(kind)
 
 
-@pytest.mark.parametrize("kind", ["maxwell_wave", "euler_entropy", "ns_couette", "advection_wave"])
+@pytest.mark.parametrize("kind", ["maxwell_wave", "euler_entropy", "ns_couette", "advection_wave",
+                                  "euler2d_entropy"])
 def test_exact_representable_networks(oracle, kind):
     net, pde, params, B, pts = exact_case(kind)
     res = oracle.loss_grad(net, pde, params, B, pts)
@@ -627,7 +715,7 @@ def test_exact_representable_networks(oracle, kind):
     assert np.abs(res["grad"]).max() < 1e-14
 
 
-@pytest.mark.parametrize("pde", ["burgers", "euler1d", "ns2d", "maxwell", "advection"])
+@pytest.mark.parametrize("pde", ["burgers", "euler1d", "ns2d", "maxwell", "advection", "euler2d"])
 def test_constant_output_network_has_zero_residual(oracle, pde):
     """With W_out = 0 the outputs are the output biases: every derivative vanishes."""
     net = small_net(pde, widths=(6, 6), n_freq=3, act="sin")
