@@ -26,11 +26,11 @@
  *   the return code reports argument errors (checked on the host, before any HIP call)
  *   and launch errors.  Calls sharing a workspace must not overlap.
  *   Points: n x d_in, row-major, FP32, inputs ordered (x,t) Burgers/Euler/advection/
- *   Allen-Cahn, (x,y) NS, (x,y,t) Maxwell.  Parameters: FP32, flat, per linear layer l = 0..n_hidden (input
+ *   Allen-Cahn, (x,y) NS, (x,y,t) Maxwell and 2D Euler.  Parameters: FP32, flat, per linear layer l = 0..n_hidden (input
  *   side first): [W_l or V_l (n_out x n_in, row-major)] [s_l (n_out) if rwf]
  *   [b_l (n_out) if has_bias], then the trainable periods of a periodic embedding.
  *   Gradient: FP64 in the same layout.
- *   Device limits: d_in <= 3, d_out <= 3, 1 + d_in + (Laplacian needed) <= 4 derivative
+ *   Device limits: d_in <= 3, d_out <= 4, 1 + d_in + (Laplacian needed) <= 4 derivative
  *   channels, hidden widths multiples of 32 and <= 256, n_freq a multiple of 16 with
  *   2*n_freq <= 256, n_hidden in 1..8 (PINN_PREC_FP64: any width <= 256, any n_freq,
  *   n_hidden in 0..8).
@@ -62,8 +62,10 @@ typedef enum {
   PINN_PDE_NS2D_STEADY = 3,   /* in (x,y), out (u,v,p):    continuity + 2 momentum     */
   PINN_PDE_MAXWELL_TE2D = 4,  /* in (x,y,t), out (E_z,H_x,H_y)                          */
   PINN_PDE_ADVECTION = 5,     /* in (x,t), out u:          u_t + c u_x (Sec. 4.1)      */
-  PINN_PDE_ALLEN_CAHN = 6     /* in (x,t), out u:          u_t - D u_xx + k (u^3 - u)
+  PINN_PDE_ALLEN_CAHN = 6,    /* in (x,t), out u:          u_t - D u_xx + k (u^3 - u)
                                  (Sec. 4.2; the paper's D = 1e-4, k = 5)              */
+  PINN_PDE_EULER2D = 7        /* in (x,y,t), out (rho,u,v,p): conservative 2D Euler,
+                                 mass, two momentum and energy residuals (Sec. 4.7)   */
 } pinn_pde_id;
 
 typedef enum { PINN_ACT_TANH = 0, PINN_ACT_SIN = 1 } pinn_act;
@@ -101,7 +103,7 @@ typedef enum {
 
 /* (host) Network descriptor. */
 typedef struct {
-  int32_t d_in, d_out;   /* 1..3 each                                                    */
+  int32_t d_in, d_out;   /* d_in 1..3, d_out 1..4                                        */
   int32_t n_hidden;      /* hidden layers L                                              */
   int32_t width[8];      /* hidden widths                                                */
   int32_t act;           /* pinn_act                                                     */
@@ -126,8 +128,8 @@ typedef struct {
   int32_t lap_mask;      /* bit k: input k belongs to the Laplacian set S (Burgers: x,
                             NS: x and y; Euler and Maxwell need none)                     */
   double coef[4];        /* Burgers: nu | Euler: gamma | NS: Re | Maxwell: eps, mu |
-                            advection: c | Allen-Cahn: D, k                               */
-  double lambda_res[3];  /* weight of each residual component's mean square             */
+                            advection: c | Allen-Cahn: D, k | 2D Euler: gamma             */
+  double lambda_res[4];  /* weight of each residual component's mean square             */
   double norm_N;         /* divisor of the residual means; 0 = n_points of this call.
                             A caller that shards the points passes the global count.     */
 } pinn_pde;

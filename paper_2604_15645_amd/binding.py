@@ -9,7 +9,9 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpinn.so")
 
-PDE_IDS = {"burgers": 1, "euler1d": 2, "ns2d": 3, "maxwell": 4, "advection": 5, "allen_cahn": 6}
+PDE_IDS = {"burgers": 1, "euler1d": 2, "ns2d": 3, "maxwell": 4, "advection": 5, "allen_cahn": 6,
+           "euler2d": 7}
+MAX_RES = 4  # residual components (and outputs) a PDE descriptor can carry
 ACTS = {"tanh": 0, "sin": 1}
 PRECS = {"fp32": 0, "bf16x3": 1, "bf16": 2, "fp64": 3, "fp16x3": 4}
 FLAG_CHECK_FINITE = 1
@@ -28,7 +30,7 @@ class PinnNet(ctypes.Structure):
 
 class PinnPde(ctypes.Structure):
     _fields_ = [("pde_id", ctypes.c_int32), ("lap_mask", ctypes.c_int32),
-                ("coef", ctypes.c_double * 4), ("lambda_res", ctypes.c_double * 3),
+                ("coef", ctypes.c_double * 4), ("lambda_res", ctypes.c_double * MAX_RES),
                 ("norm_N", ctypes.c_double)]
 
 
@@ -153,8 +155,8 @@ def pde_struct(spec):
     coef = list(spec.get("coef", [])) + [0.0] * 4
     for i in range(4):
         p.coef[i] = float(coef[i])
-    lam = list(spec.get("lambda_res", [1.0, 1.0, 1.0])) + [1.0] * 3
-    for i in range(3):
+    lam = list(spec.get("lambda_res", [])) + [1.0] * MAX_RES
+    for i in range(MAX_RES):
         p.lambda_res[i] = float(lam[i])
     p.norm_N = float(spec.get("norm_N", 0.0))
     return p

@@ -40,7 +40,7 @@ __device__ __forceinline__ void run_item(const BatchArgs& A, const BatchInst& in
   double* loss_slot = A.loss_slots + (size_t)item * kMaxTerms;
   double* gslot = A.grad_slots + it.slot_off;
   PdeDev pde = A.pde;
-  for (int c = 0; c < 3; ++c) pde.seed_scale[c] = 2.0f * A.lambda_res[c] / (float)in.n;
+  for (int c = 0; c < kMaxOut; ++c) pde.seed_scale[c] = 2.0f * A.lambda_res[c] / (float)in.n;
   // forward over the item's tiles; amx: largest magnitude of the adjoint the forward writes
   // (FP16X3 scales each layer's adjoint by the item's own largest magnitude)
   float amx = 0.0f;
@@ -122,8 +122,8 @@ size_t batched_lds(int kmax, int H) {
   const int PB = 2048 / H;
   const int WN = H / 16 < kWaves ? H / 16 : kWaves;
   const int WC = kWaves / WN;
-  size_t f = (size_t)4 * PF * r_stride(kmax) + (size_t)PF * 16 + (size_t)PF * 12 * 4 * 2 + kWaves * 8 * 4 +
-             kMaxTerms * 8 + (size_t)WC * 3 * H * 8 + 3 * 8 + kFourierLds + kOutLds + 16;
+  size_t f = (size_t)4 * PF * r_stride(kmax) + (size_t)PF * 16 + (size_t)PF * kMaxOut * 4 * 4 * 2 + kWaves * 8 * 4 +
+             kMaxTerms * 8 + (size_t)WC * kMaxOut * H * 8 + kMaxOut * 8 + kFourierLds + kOutLds + 16;
   size_t b = bwd_lds_bytes(PB, H, H, true);
   size_t g = (size_t)kWaves * 256 * 4 * sizeof(float);
   size_t m = f > b ? f : b;

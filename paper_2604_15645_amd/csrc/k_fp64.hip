@@ -158,8 +158,8 @@ __global__ __launch_bounds__(256) void k64_forward(const F64Args A) {
       }
     }
     // output layer (linear)
-    double y[3][4], yb[3][4];
-    for (int o = 0; o < 3; ++o)
+    double y[kMaxOut][4], yb[kMaxOut][4];
+    for (int o = 0; o < kMaxOut; ++o)
       for (int c = 0; c < 4; ++c) y[o][c] = yb[o][c] = 0.0;
     const int L = A.L, ni = A.n_in[L];
     for (int o = 0; o < A.d_out; ++o) {
@@ -175,9 +175,9 @@ __global__ __launch_bounds__(256) void k64_forward(const F64Args A) {
     const int64_t i = p - A.seg.start[sid];
     if (i < A.seg.n[sid]) {
       if (sid == 0) {
-        double r[3], seed[3];
+        double r[kMaxOut], seed[kMaxOut];
         const double ws = A.wscale ? *A.wscale : 1.0;
-        for (int c = 0; c < 3; ++c) seed[c] = A.seed[c] * ws;
+        for (int c = 0; c < kMaxOut; ++c) seed[c] = A.seed[c] * ws;
         residual_point_t<double>(A.pde_id, A.coef, seed, y, r, yb);
         for (int c = 0; c < A.n_res; ++c) {
           part[c] = r[c] * r[c];

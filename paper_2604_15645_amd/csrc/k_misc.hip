@@ -260,13 +260,13 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_batched(const BatchReduc
 // thread per term (an instance has at most a few hundred items).
 __global__ void k_reduce_loss_batched(const BatchLossArgs A) {
   const int i = blockIdx.x;
-  __shared__ double term[3];
+  __shared__ double term[kMaxOut];
   const int k = threadIdx.x;
   if (k < A.n_res) {
     double t = 0.0;
     const double* p = A.loss_slots + (size_t)A.item0[i] * kMaxTerms + k;
     for (int s = 0; s < A.n_items[i]; ++s) t += p[(size_t)s * kMaxTerms];
-    t *= A.w_res[i * 3 + k];
+    t *= A.w_res[i * kMaxOut + k];
     A.losses[(size_t)i * (1 + A.n_res) + 1 + k] = t;
     term[k] = t;
   }

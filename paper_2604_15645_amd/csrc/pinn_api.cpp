@@ -36,7 +36,7 @@ struct Dims {
 
 int check_net(const pinn_net* net, Dims* d) {
   if (!net) return PINN_E_INVALID;
-  if (net->d_in < 1 || net->d_in > 3 || net->d_out < 1 || net->d_out > 3) return PINN_E_INVALID;
+  if (net->d_in < 1 || net->d_in > 3 || net->d_out < 1 || net->d_out > kMaxOut) return PINN_E_INVALID;
   if (net->n_hidden < 0 || net->n_hidden > kMaxHidden) return PINN_E_INVALID;
   if (net->act != PINN_ACT_TANH && net->act != PINN_ACT_SIN) return PINN_E_INVALID;
   if (net->n_freq < 0 || net->n_freq > 4096) return PINN_E_INVALID;
@@ -97,7 +97,7 @@ int check_supported(const pinn_net* net, const Dims& D, int lap_mask) {
 int check_pde(const pinn_net* net, const pinn_pde* pde) {
   if (!pde) return PINN_E_INVALID;
   if (pde->lap_mask < 0 || (pde->lap_mask & ~((1 << net->d_in) - 1))) return PINN_E_INVALID;
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < kMaxOut; ++k)
     if (!std::isfinite(pde->lambda_res[k]) || pde->lambda_res[k] < 0) return PINN_E_INVALID;
   if (!std::isfinite(pde->norm_N) || pde->norm_N < 0) return PINN_E_INVALID;
   for (int k = 0; k < 4; ++k)
@@ -122,6 +122,10 @@ int check_pde(const pinn_net* net, const pinn_pde* pde) {
       return PINN_OK;
     case PINN_PDE_ALLEN_CAHN:  // the Laplacian channel must be u_xx alone
       if (net->d_in != 2 || pde->lap_mask != 1) return PINN_E_UNSUPPORTED;
+      return PINN_OK;
+    case PINN_PDE_EULER2D:  // first derivatives in x, y, t
+      if (net->d_in != 3 || net->d_out != 4 || pde->lap_mask != 0 || !(pde->coef[0] > 1.0))
+        return PINN_E_UNSUPPORTED;
       return PINN_OK;
     default:
       return PINN_E_UNSUPPORTED;
@@ -148,6 +152,7 @@ int n_res_of(int pde_id) {
     case PINN_PDE_EULER1D:
     case PINN_PDE_NS2D_STEADY:
     case PINN_PDE_MAXWELL_TE2D: return 3;
+    case PINN_PDE_EULER2D: return 4;
     default: return -1;
   }
 }
@@ -173,10 +178,10 @@ size_t fwd_lds(int P, int kmax, int H) {
   const int WC = NW / WN;
   size_t b = (size_t)4 * P * (kmax * 4 + 16) * (fwd_double_x(P) ? 2 : 1);  // X (one or two)
   b += (size_t)P * 16;                           // PT
-  b += (size_t)P * 12 * 4 * 2;                   // YJ, YB
+  b += (size_t)P * kMaxOut * 4 * 4 * 2;          // YJ, YB
   b += NW * 8 * 4;                               // RED
   b += kMaxTerms * 8;                            // LOSS
-  b += (size_t)WC * 3 * H * 8 + 3 * 8;           // WL, BL
+  b += (size_t)WC * kMaxOut * H * 8 + kMaxOut * 8;  // WL, BL
   b += kFourierLds;                              // BF
   b += kOutLds + 16;                             // OW (16-byte aligned)
   return b;
@@ -572,7 +577,7 @@ int run_fp64(const pinn_net* net, const pinn_pde* pde, const float* params, cons
   a.n_res = p.n_res;
   for (int k = 0; k < 4; ++k) a.coef[k] = pde->coef[k];
   const double N = pde->norm_N > 0 ? pde->norm_N : (double)n_points;
-  for (int k = 0; k < 3; ++k) a.seed[k] = N > 0 ? 2.0 * pde->lambda_res[k] / N : 0.0;
+  for (int k = 0; k < kMaxOut; ++k) a.seed[k] = N > 0 ? 2.0 * pde->lambda_res[k] / N : 0.0;
   for (int k = 0; k < n_anchor; ++k)
     a.lam_anchor[k] = anchors[k].n > 0 ? 2.0 * anchors[k].lambda / (double)anchors[k].n : 0.0;
   a.wscale = wscale;
@@ -638,7 +643,7 @@ int run_fp64(const pinn_net* net, const pinn_pde* pde, const float* params, cons
     l.n_slots = p.blocks;
     l.n_res = p.n_res;
     l.n_anchor = n_anchor;
-    for (int k = 0; k < 3; ++k) l.w_res[k] = N > 0 ? pde->lambda_res[k] / N : 0.0;
+    for (int k = 0; k < kMaxOut; ++k) l.w_res[k] = N > 0 ? pde->lambda_res[k] / N : 0.0;
     for (int k = 0; k < n_anchor; ++k) l.w_anchor[k] = anchors[k].n > 0 ? anchors[k].lambda / (double)anchors[k].n : 0.0;
     l.loss = loss;
     l.wscale = wscale;
@@ -773,7 +778,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     a.pde.pde_id = pde->pde_id;
     a.pde.n_res = p.n_res;
     for (int k = 0; k < 4; ++k) a.pde.coef[k] = (float)pde->coef[k];
-    for (int k = 0; k < 3; ++k) a.pde.seed_scale[k] = N > 0 ? (float)(2.0 * pde->lambda_res[k] / N) : 0.0f;
+    for (int k = 0; k < kMaxOut; ++k) a.pde.seed_scale[k] = N > 0 ? (float)(2.0 * pde->lambda_res[k] / N) : 0.0f;
     a.seg.n_seg = p.n_seg;
     for (int s = 0; s < p.n_seg; ++s) {
       a.seg.start[s] = p.seg_start[s];
@@ -895,7 +900,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     a.n_slots = p.grid_f;
     a.n_res = p.n_res;
     a.n_anchor = n_anchor;
-    for (int k = 0; k < 3; ++k) a.w_res[k] = N > 0 ? pde->lambda_res[k] / N : 0.0;
+    for (int k = 0; k < kMaxOut; ++k) a.w_res[k] = N > 0 ? pde->lambda_res[k] / N : 0.0;
     for (int k = 0; k < n_anchor; ++k)
       a.w_anchor[k] = anchors[k].n > 0 ? anchors[k].lambda / (double)anchors[k].n : 0.0;
     a.loss = loss;
@@ -1034,7 +1039,7 @@ int make_batch_plan(const pinn_net* nets, const pinn_pde* pde, const int64_t* n_
   for (int i = 0; i < n_inst; ++i) n_rows_entries += b.D[i].n_layers;
   b.tables_bytes = (int64_t)sizeof(BatchInst) * n_inst + (int64_t)sizeof(BatchItem) * b.n_items +
                    (int64_t)sizeof(int64_t) * b.n_items + (int64_t)sizeof(BatchRow) * n_rows_entries +
-                   (int64_t)n_inst * (sizeof(int64_t) + sizeof(int) + 3 * sizeof(double)) + 64 * 8;
+                   (int64_t)n_inst * (sizeof(int64_t) + sizeof(int) + kMaxOut * sizeof(double)) + 64 * 8;
   b.o_tables = take(b.tables_bytes);
   b.o_counter = take(16);
   b.o_loss = take((int64_t)b.n_items * kMaxTerms * 8);
@@ -1135,7 +1140,7 @@ int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* p
     }
     hitem0[i] = b.item0[i];
     hnitems[i] = (int)b.n_items_of[i];
-    for (int k = 0; k < 3; ++k) hw[i * 3 + k] = pde->lambda_res[k] / (double)n_points[i];
+    for (int k = 0; k < kMaxOut; ++k) hw[i * kMaxOut + k] = pde->lambda_res[k] / (double)n_points[i];
   }
   for (int q = 0; q < b.n_items; ++q) {
     hitems[q] = b.items[q];
@@ -1201,7 +1206,7 @@ int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* p
   ba.scratch_per_wg = b.scratch_per_wg;
   ba.loss_slots = reinterpret_cast<double*>(ws + b.o_loss);
   ba.grad_slots = reinterpret_cast<double*>(ws + b.o_grad);
-  for (int k = 0; k < 3; ++k) ba.lambda_res[k] = (float)pde->lambda_res[k];
+  for (int k = 0; k < kMaxOut; ++k) ba.lambda_res[k] = (float)pde->lambda_res[k];
   rc = timed(allow_timing, "k_batched", stream, [&] { return launch_batched(b.prec, b.act | (pde->lap_mask ? kLapFlag : 0), ba, b.grid, b.lds, stream); });
   if (rc) return rc;
   BatchReduceArgs ra;

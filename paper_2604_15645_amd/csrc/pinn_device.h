@@ -593,13 +593,14 @@ __device__ __forceinline__ f4 jet_act_adj(f4 z, f4 ab, float s1, float s2, float
 // Output jets y[o][c] (c: 0 value, 1.. derivatives, lapch Laplacian) -> residuals r and,
 // with the seed scale g_c = 2 lambda_c / N, the output-jet adjoint yb[o][c].
 template <typename T, typename C>
-__device__ __forceinline__ void residual_point_t(int pde_id, const C* coef, const C* g, const T (&y)[3][4], T (&r)[3],
-                                                 T (&yb)[3][4]) {
+__device__ __forceinline__ void residual_point_t(int pde_id, const C* coef, const C* g, const T (&y)[kMaxOut][4],
+                                                 T (&r)[kMaxOut], T (&yb)[kMaxOut][4]) {
 #pragma unroll
-  for (int o = 0; o < 3; ++o)
+  for (int o = 0; o < kMaxOut; ++o) {
+    r[o] = T(0);
 #pragma unroll
     for (int c = 0; c < 4; ++c) yb[o][c] = T(0);
-  r[0] = r[1] = r[2] = T(0);
+  }
   switch (pde_id) {
     case kBurgers: {  // (x, t): u_t + u u_x - nu u_xx
       const T nu = (T)coef[0];
@@ -692,13 +693,60 @@ __device__ __forceinline__ void residual_point_t(int pde_id, const C* coef, cons
       yb[0][3] = -b * D;
       break;
     }
+    case kEuler2D: {  // (x, y, t) -> (rho, u, v, p), conservative form expanded by the product rule
+      // e = rho E = k p + rho q / 2 with q = u^2 + v^2 and k = 1 / (gamma - 1); the energy
+      // flux is (u, v) h with h = e + p, whose derivatives hx, hy enter the last equation
+      const T k = T(1) / ((T)coef[0] - T(1));
+      const T rho = y[0][0], rx = y[0][1], ry = y[0][2], rt = y[0][3];
+      const T u = y[1][0], ux = y[1][1], uy = y[1][2], ut = y[1][3];
+      const T v = y[2][0], vx = y[2][1], vy = y[2][2], vt = y[2][3];
+      const T p = y[3][0], px = y[3][1], py = y[3][2], pt = y[3][3];
+      const T k1 = k + T(1), q = u * u + v * v, hq = T(0.5) * q;
+      const T h = k1 * p + rho * hq;
+      const T hx = k1 * px + hq * rx + rho * (u * ux + v * vx);
+      const T hy = k1 * py + hq * ry + rho * (u * uy + v * vy);
+      const T et = k * pt + hq * rt + rho * (u * ut + v * vt);
+      // material derivative of rho and the divergence of (u, v)
+      const T dr = rt + u * rx + v * ry, dv = ux + vy;
+      const T du = ut + u * ux + v * uy, dvv = vt + u * vx + v * vy;
+      r[0] = dr + rho * dv;
+      r[1] = u * r[0] + rho * du + px;
+      r[2] = v * r[0] + rho * dvv + py;
+      r[3] = et + dv * h + u * hx + v * hy;
+      const T b0 = (T)g[0] * r[0], b1 = (T)g[1] * r[1], b2 = (T)g[2] * r[2], b3 = (T)g[3] * r[3];
+      // r1 and r2 reach the jets through r0 as well: its total weight c0
+      const T c0 = b0 + b1 * u + b2 * v;
+      // adjoints of the energy intermediates
+      const T a_h = b3 * dv, a_hx = b3 * u, a_hy = b3 * v;
+      const T a_q = T(0.5) * (b3 * rt + a_hx * rx + a_hy * ry + a_h * rho);
+      yb[0][0] = c0 * dv + b1 * du + b2 * dvv + b3 * (u * ut + v * vt) + a_hx * (u * ux + v * vx) +
+                 a_hy * (u * uy + v * vy) + a_h * hq;
+      yb[0][1] = c0 * u + a_hx * hq;
+      yb[0][2] = c0 * v + a_hy * hq;
+      yb[0][3] = c0 + b3 * hq;
+      yb[1][0] = c0 * rx + b1 * (r[0] + rho * ux) + b2 * rho * vx + b3 * (rho * ut + hx) + a_hx * rho * ux +
+                 a_hy * rho * uy + T(2) * u * a_q;
+      yb[1][1] = c0 * rho + b1 * rho * u + b3 * h + a_hx * rho * u;
+      yb[1][2] = b1 * rho * v + a_hy * rho * u;
+      yb[1][3] = b1 * rho + b3 * rho * u;
+      yb[2][0] = c0 * ry + b1 * rho * uy + b2 * (r[0] + rho * vy) + b3 * (rho * vt + hy) + a_hx * rho * vx +
+                 a_hy * rho * vy + T(2) * v * a_q;
+      yb[2][1] = b2 * rho * u + a_hx * rho * v;
+      yb[2][2] = c0 * rho + b2 * rho * v + b3 * h + a_hy * rho * v;
+      yb[2][3] = b2 * rho + b3 * rho * v;
+      yb[3][0] = a_h * k1;
+      yb[3][1] = b1 + a_hx * k1;
+      yb[3][2] = b2 + a_hy * k1;
+      yb[3][3] = b3 * k;
+      break;
+    }
     default:
       break;
   }
 }
 
-__device__ __forceinline__ void residual_point(const PdeDev& pde, int lapch, const float (&y)[3][4], float (&r)[3],
-                                               float (&yb)[3][4]) {
+__device__ __forceinline__ void residual_point(const PdeDev& pde, int lapch, const float (&y)[kMaxOut][4],
+                                               float (&r)[kMaxOut], float (&yb)[kMaxOut][4]) {
   residual_point_t<float, float>(pde.pde_id, pde.coef, pde.seed_scale, y, r, yb);
   (void)lapch;
 }
@@ -848,15 +896,15 @@ struct FwdLds {
   char* X;       // layer-input tile (4P rows)
   char* X2;      // second layer-input tile (16-point tiles), else X
   float4* PT;    // tile points
-  float* YJ;     // [P][3][4] output jets
-  float* YB;     // [P][3][4] output-jet adjoints
+  float* YJ;     // [P][kMaxOut][4] output jets
+  float* YB;     // [P][kMaxOut][4] output-jet adjoints
   float* RED;    // [waves][8] wave partial sums (loss terms, then output-bias adjoints)
   double* LOSS;  // [kMaxTerms] sums of squares (FP64, per work item)
-  double* WL;    // [WC][3][H] output-layer weight-gradient sums
-  double* BL;    // [3] output-layer bias-gradient sums
+  double* WL;    // [WC][kMaxOut][H] output-layer weight-gradient sums
+  double* BL;    // [kMaxOut] output-layer bias-gradient sums
   float* BF;     // Fourier matrix, d_in x n_freq (staged once per launch)
   char* OW;      // output-layer weight fragments of the lanes that carry an output:
-                 // [chunk < 8][g < 4][output < 3][32 B] (staged once per launch)
+                 // [chunk < 8][g < 4][output < kMaxOut][32 B] (staged once per launch)
 };
 
 template <int H, int P, int NW = kWaves>
@@ -866,12 +914,12 @@ __device__ __forceinline__ FwdLds fwd_carve(char* smem, int rs) {
   s.X2 = fwd_double_x(P) ? smem + (size_t)4 * P * rs : smem;
   s.PT = reinterpret_cast<float4*>(smem + (size_t)4 * P * rs * (fwd_double_x(P) ? 2 : 1));
   s.YJ = reinterpret_cast<float*>(s.PT + P);
-  s.YB = s.YJ + P * 12;
-  s.RED = s.YB + P * 12;
+  s.YB = s.YJ + P * 4 * kMaxOut;
+  s.RED = s.YB + P * 4 * kMaxOut;
   s.LOSS = reinterpret_cast<double*>(s.RED + NW * 8);
   s.WL = s.LOSS + kMaxTerms;
-  s.BL = s.WL + FwdShape<H, P, NW>::WC * 3 * H;
-  s.BF = reinterpret_cast<float*>(s.BL + 3);
+  s.BL = s.WL + FwdShape<H, P, NW>::WC * kMaxOut * H;
+  s.BF = reinterpret_cast<float*>(s.BL + kMaxOut);
   s.OW = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(s.BF + 3 * kMaxFreq) + 15) & ~(uintptr_t)15);
   return s;
 }
@@ -881,12 +929,12 @@ template <int H, int P, int NW = kWaves>
 __device__ __forceinline__ void fwd_begin(const FwdLds& s, const NetDev& net) {
   constexpr int NT = 64 * NW;
   for (int i = threadIdx.x; i < kMaxTerms; i += NT) s.LOSS[i] = 0.0;
-  for (int i = threadIdx.x; i < FwdShape<H, P, NW>::WC * 3 * H + 3; i += NT) s.WL[i] = 0.0;
+  for (int i = threadIdx.x; i < FwdShape<H, P, NW>::WC * kMaxOut * H + kMaxOut; i += NT) s.WL[i] = 0.0;
   for (int i = threadIdx.x; i < net.d_in * net.n_freq; i += NT) s.BF[i] = net.B[i];
   // output layer: of each 16-lane group only lanes 0 .. d_out - 1 carry a column
   const LayerDev& lo = net.layer[net.L];
   for (int i = threadIdx.x; i < kOutLds / 4; i += NT) {
-    const int w = i & 7, r = i >> 3, o = r % 3, g = (r / 3) & 3, kc = r / 12;
+    const int w = i & 7, r = i >> 3, o = r % kMaxOut, g = (r / kMaxOut) & 3, kc = r / (4 * kMaxOut);
     uint32_t v = 0;
     if (kc < lo.kci && o < net.d_out)
       v = reinterpret_cast<const uint32_t*>(lo.wf + ((size_t)kc * 64 + 16 * g + o) * 32)[w];
@@ -906,7 +954,7 @@ __device__ __forceinline__ void fwd_end(const FwdLds& s, double* loss_slot, doub
     for (int i = threadIdx.x; i < dout * nL; i += NT) {
       const int o = i / nL, n = i - o * nL;
       double t = 0.0;
-      for (int c = 0; c < FwdShape<H, P, NW>::WC; ++c) t += s.WL[(c * 3 + o) * H + n];
+      for (int c = 0; c < FwdShape<H, P, NW>::WC; ++c) t += s.WL[(c * kMaxOut + o) * H + n];
       out_slot[i] = t;
     }
     for (int o = threadIdx.x; o < dout; o += NT) out_slot[dout * nL + o] = s.BL[o];
@@ -1107,7 +1155,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
     }
   }
 
-  // ---- output layer (d_out <= 3 columns of one 16-wide block): waves over cp blocks, the
+  // ---- output layer (d_out <= kMaxOut columns of one 16-wide block): waves over cp blocks, the
   // weight fragments from their staged copy in LDS (zero on the lanes without an output)
   const char* XL = ((L - 1) & 1) ? X : s.X2;  // the last hidden layer's activations
   const float obias = l16 < dout ? lout.b[l16] : 0.0f;
@@ -1118,30 +1166,30 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       Raw bw;
       bw.a = make_uint4(0, 0, 0, 0);
       bw.b = bw.a;
-      if (l16 < 3) bw = *reinterpret_cast<const Raw*>(s.OW + ((kc * 4 + g) * 3 + l16) * 32);
+      if (l16 < kMaxOut) bw = *reinterpret_cast<const Raw*>(s.OW + ((kc * 4 + g) * kMaxOut + l16) * 32);
       Pr::mma(y, a, bw);
     }
     if (l16 < dout) {
       y.x += obias;
-      float* dst = s.YJ + ((4 * cb + g) * 3 + l16) * 4;
+      float* dst = s.YJ + ((4 * cb + g) * kMaxOut + l16) * 4;
       *reinterpret_cast<float4*>(dst) = to_float4(y);
     }
   }
   barrier_lds();
 
   // ---- residual (or supervision misfit), loss partial sums and the output-jet seed
-  float part[3] = {0.f, 0.f, 0.f};
-  float ybv[3] = {0.f, 0.f, 0.f};  // value-channel output adjoints: the output bias gradient
+  float part[kMaxOut] = {};
+  float ybv[kMaxOut] = {};  // value-channel output adjoints: the output bias gradient
   if (tid < P) {
     const int p = tid;
-    float y[3][4], yb[3][4];
+    float y[kMaxOut][4], yb[kMaxOut][4];
 #pragma unroll
-    for (int o = 0; o < 3; ++o)
+    for (int o = 0; o < kMaxOut; ++o)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) y[o][c] = o < dout ? s.YJ[(p * 3 + o) * 4 + c] : 0.0f;
+      for (int c = 0; c < 4; ++c) y[o][c] = o < dout ? s.YJ[(p * kMaxOut + o) * 4 + c] : 0.0f;
     const bool valid = p < sg.nvalid;
     if (sg.kind == 0) {
-      float r[3];
+      float r[kMaxOut];
       residual_point(pde, net.lapch, y, r, yb);
       if (valid) {
         for (int c = 0; c < pde.n_res; ++c) part[c] = r[c] * r[c];
@@ -1150,7 +1198,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       }
     } else {
 #pragma unroll
-      for (int o = 0; o < 3; ++o)
+      for (int o = 0; o < kMaxOut; ++o)
 #pragma unroll
         for (int c = 0; c < 4; ++c) yb[o][c] = 0.0f;
       if (valid) {
@@ -1164,18 +1212,19 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
     }
     if (!valid) {
 #pragma unroll
-      for (int o = 0; o < 3; ++o)
+      for (int o = 0; o < kMaxOut; ++o)
 #pragma unroll
         for (int c = 0; c < 4; ++c) yb[o][c] = 0.0f;
     }
 #pragma unroll
-    for (int o = 0; o < 3; ++o) {
-      *reinterpret_cast<float4*>(s.YB + (p * 3 + o) * 4) = make_float4(yb[o][0], yb[o][1], yb[o][2], yb[o][3]);
+    for (int o = 0; o < kMaxOut; ++o) {
+      *reinterpret_cast<float4*>(s.YB + (p * kMaxOut + o) * 4) = make_float4(yb[o][0], yb[o][1], yb[o][2], yb[o][3]);
       ybv[o] = yb[o][0];
     }
   }
+  static_assert(kMaxOut <= 4, "RED holds 4 loss terms and 4 output-bias sums per wave");
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < kMaxOut; ++k) {
     const float v = wave_sum(part[k]);
     const float u = wave_sum(ybv[k]);
     if (lane == 0) {
@@ -1207,9 +1256,9 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
       const int nb = wn + WN * i;
       if (nb >= nbs) continue;
       const int n = 16 * nb + l16;
-      float wo[3], wsum[3] = {0.f, 0.f, 0.f};
+      float wo[kMaxOut], wsum[kMaxOut] = {};
 #pragma unroll
-      for (int o = 0; o < 3; ++o) wo[o] = o < dout ? lout.w[o * nL + n] : 0.0f;
+      for (int o = 0; o < kMaxOut; ++o) wo[o] = o < dout ? lout.w[o * nL + n] : 0.0f;
       // pre-activation jets of the last hidden layer: still in the accumulators when the
       // tile is small, else read back from the stash (fewer live registers)
 #pragma unroll(kLive ? CBW : 1)
@@ -1222,8 +1271,9 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
         const f4 a = jet_act<(ACT & kLapFlag) != 0>(z, s0, s1, s2, lw1, lw2);
         f4 ab = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int o = 0; o < 3; ++o) {
-          const f4 yb = to_f4(*reinterpret_cast<const float4*>(s.YB + (p * 3 + o) * 4));
+        for (int o = 0; o < kMaxOut; ++o) {
+          if (o >= 3 && o >= dout) continue;  // a fourth output only where there is one
+          const f4 yb = to_f4(*reinterpret_cast<const float4*>(s.YB + (p * kMaxOut + o) * 4));
           ab += yb * wo[o];
           wsum[o] += yb.x * a.x + yb.y * a.y + yb.z * a.z + yb.w * a.w;
         }
@@ -1233,11 +1283,11 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
         __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
-      for (int o = 0; o < 3; ++o) {
+      for (int o = 0; o < kMaxOut; ++o) {
         float v = wsum[o];
         v += __shfl_xor(v, 16, 64);
         v += __shfl_xor(v, 32, 64);
-        if (g == 0 && o < dout) s.WL[(wc * 3 + o) * H + n] += (double)v;
+        if (g == 0 && o < dout) s.WL[(wc * kMaxOut + o) * H + n] += (double)v;
       }
     }
   }

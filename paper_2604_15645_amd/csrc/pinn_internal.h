@@ -11,7 +11,8 @@ namespace pinn {
 constexpr int kMaxHidden = 8;
 constexpr int kMaxLayers = kMaxHidden + 1;
 constexpr int kMaxAnchors = 8;
-constexpr int kMaxTerms = 3 + kMaxAnchors;
+constexpr int kMaxOut = 4;      // network outputs and residual components (2D Euler: 4)
+constexpr int kMaxTerms = kMaxOut + kMaxAnchors;
 constexpr int kSegAlign = 128;  // every point segment starts at a multiple of this
 constexpr int kWaves = 8;
 constexpr int kRedThreads = 1024;  // reduction blocks: kRedGroups slot groups x 256 columns
@@ -19,7 +20,7 @@ constexpr int kRedGroups = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kMaxFreq = 128;                     // Fourier frequencies (2 m <= 256)
 constexpr int kFourierLds = 3 * kMaxFreq * 4;     // LDS bytes of a staged Fourier matrix
-constexpr int kOutLds = 8 * 4 * 3 * 32;           // LDS bytes of the staged output-layer fragments
+constexpr int kOutLds = 8 * 4 * kMaxOut * 32;     // LDS bytes of the staged output-layer fragments
 
 // Kernel precision codes.  The two split forms run three 16-bit matrix-core products per
 // logical product (hi*hi + hi*lo + lo*hi, x = hi + lo); they differ in the 16-bit format.
@@ -28,7 +29,7 @@ __host__ __device__ constexpr bool is_split(int prec) { return prec != kFP32; }
 enum { kTanh = 0, kSin = 1 };
 // Kernel activation code: kTanh or kSin, plus kLapFlag when jet channel 3 is a Laplacian.
 enum { kLapFlag = 2 };
-enum { kBurgers = 1, kEuler1D = 2, kNS2D = 3, kMaxwell = 4, kAdvection = 5, kAllenCahn = 6 };
+enum { kBurgers = 1, kEuler1D = 2, kNS2D = 3, kMaxwell = 4, kAdvection = 5, kAllenCahn = 6, kEuler2D = 7 };
 
 // One linear layer as the kernels see it (all pointers into the workspace).
 struct LayerDev {
@@ -67,7 +68,7 @@ struct SegDev {
 struct PdeDev {
   int pde_id, n_res;
   float coef[4];
-  float seed_scale[3];             // 2 lambda_c / N
+  float seed_scale[kMaxOut];       // 2 lambda_c / N
 };
 
 // Workspace pieces used by the kernels.
@@ -189,7 +190,7 @@ struct LossArgs {
   const double* slots;
   int n_slots;
   int n_res, n_anchor;
-  double w_res[3];        // lambda_c / N
+  double w_res[kMaxOut];  // lambda_c / N
   double w_anchor[kMaxAnchors];  // lambda_s / N_s
   double* loss;
   const double* wscale;   // device weight of the residual terms (or null)
@@ -226,7 +227,7 @@ struct BatchArgs {
   int64_t scratch_per_wg;    // floats
   double* loss_slots;        // [n_items][kMaxTerms]
   double* grad_slots;
-  float lambda_res[3];       // residual weights; the seed scale is 2 lambda / n per instance
+  float lambda_res[kMaxOut]; // residual weights; the seed scale is 2 lambda / n per instance
 };
 
 struct BatchRow {            // one (instance, layer): rows [row0, row0 + n_out) of the grid
@@ -251,7 +252,7 @@ struct BatchLossArgs {
   const double* loss_slots;
   const int64_t* item0;      // first item of each instance
   const int* n_items;
-  const double* w_res;       // [n_inst][3] lambda_c / N_i
+  const double* w_res;       // [n_inst][kMaxOut] lambda_c / N_i
   int n_inst, n_res;
   double* losses;            // [n_inst][1 + n_res]
 };
@@ -290,7 +291,7 @@ struct F64Args {
   const float4* pts;
   int pde_id, n_res;
   double coef[4];
-  double seed[3];                // 2 lambda_c / N
+  double seed[kMaxOut];          // 2 lambda_c / N
   double lam_anchor[kMaxAnchors];  // 2 lambda_s / N_s
   const double* wscale;          // device weight of the residual seed (or null)
   SegDev seg;

@@ -22,6 +22,12 @@ these synthetic sets stand in for its benchmark problems with their shapes):
            16,384 uniform points on [0,2pi]x[0,1] plus 128 initial points (target sin x).
   allen_cahn Allen-Cahn u_t - 1e-4 u_xx + 5 u^3 - 5 u (Sec. 4.2), MLP 2 -> 4x128 tanh -> 1,
            16,384 uniform points on [-1,1]x[0,1] plus 128 initial points (target x^2 cos(pi x)).
+  euler2d  2D Euler in conservative form (Sec. 4.7, the four-quadrant Riemann problem of its
+           configuration 6, gamma = 1.4), x and y through the strict periodic pair with
+           P = 1 (Sec. 2.6.3), weight factorisation, MLP 5 -> 4x128 tanh -> 4 (the paper
+           prints no width or depth for it), 262,144 = 64^3 uniform points on
+           [0,1]^2 x [0,0.3] plus 256 initial points carrying the four quadrant states
+           (rho, u, v, p) as targets of all four outputs.
 Weights are Xavier-normal (std = sqrt(2 / (fan_in + fan_out))), biases zero; with
 perturb=True biases (and factorisation scales) get random non-zero values so that
 parity tests exercise every parameter path.
@@ -69,7 +75,18 @@ CONFIGS = {
         pde=dict(pde="allen_cahn", lap_mask=1, coef=[1e-4, 5.0, 0, 0], lambda_res=[1.0, 1.0, 1.0],
                  norm_N=0.0),
         box=[(-1.0, 1.0), (0.0, 1.0)], n_points=16384, rff_sigma=0.0, index=6),
+    "euler2d": dict(
+        net=dict(d_in=3, d_out=4, widths=[128, 128, 128, 128], act="tanh", w0=1.0, n_freq=0,
+                 rwf=True, has_bias=True, periodic_mask=3, period_train_mask=0,
+                 period=[1.0, 1.0, 0.0]),
+        pde=dict(pde="euler2d", lap_mask=0, coef=[1.4, 0, 0, 0],
+                 lambda_res=[1.0, 1.0, 1.0, 1.0], norm_N=0.0),
+        box=[(0.0, 1.0), (0.0, 1.0), (0.0, 0.3)], n_points=262144, rff_sigma=0.0, index=7),
 }
+
+# Sec. 4.7, configuration 6: (rho, u, v, p) in the quadrants x > 0.5 / y > 0.5 and so on
+RIEMANN6 = {(1, 1): (1.0, 0.75, -0.5, 1.0), (0, 1): (2.0, 0.75, 0.5, 1.0),
+            (0, 0): (1.0, -0.75, 0.5, 1.0), (1, 0): (3.0, -0.75, -0.5, 1.0)}
 
 
 def embed_width(net):
@@ -155,6 +172,14 @@ def initial_anchors(rng, name, n=128):
     return [dict(points=pts, targets=tgt.astype(np.float32)[:, None], out_mask=1, **{"lambda": 1.0})]
 
 
+def riemann_anchors(rng, n=256):
+    """Initial data of the four-quadrant problem at t = 0, every output supervised."""
+    xy = rng.uniform(0.0, 1.0, size=(n, 2))
+    pts = np.c_[xy, np.zeros(n)].astype(np.float32)
+    tgt = np.array([RIEMANN6[(int(a > 0.5), int(b > 0.5))] for a, b in pts[:, :2]], dtype=np.float32)
+    return [dict(points=pts, targets=tgt, out_mask=15, **{"lambda": 1.0})]
+
+
 def make_case(name, n_points=None, seed=None, perturb=False, anchors=None):
     """One workload: dict(net, pde, params, B, points, anchors)."""
     cfg = CONFIGS[name]
@@ -168,10 +193,15 @@ def make_case(name, n_points=None, seed=None, perturb=False, anchors=None):
     n = cfg["n_points"] if n_points is None else n_points
     pts = uniform_points(rng, cfg["box"], n)
     if anchors is None:
-        anchors = name in ("burgers", "advection", "allen_cahn")
+        anchors = name in ("burgers", "advection", "allen_cahn", "euler2d")
     anc = []
     if anchors:
-        anc = burgers_anchors(rng) if name == "burgers" else initial_anchors(rng, name)
+        if name == "burgers":
+            anc = burgers_anchors(rng)
+        elif name == "euler2d":
+            anc = riemann_anchors(rng)
+        else:
+            anc = initial_anchors(rng, name)
     return dict(name=name, net=net, pde=pde, params=params, B=B, points=pts, anchors=anc)
 
 

@@ -88,6 +88,14 @@ def test_validation_errors(lib):
     assert code_of(lambda: ws(ac, dict(acp, lap_mask=0))) == -2           # needs u_xx
     assert code_of(lambda: ws(mx, dict(mp, pde="advection"))) == -2       # inputs (x, t)
     assert binding.n_residuals("advection") == binding.n_residuals("allen_cahn") == 1
+    e2, e2p = c["euler2d"]["net"], c["euler2d"]["pde"]
+    assert ws(e2, e2p) > 0
+    assert binding.n_residuals("euler2d") == 4
+    assert code_of(lambda: ws(e2, dict(e2p, lap_mask=1))) == -2           # first derivatives only
+    assert code_of(lambda: ws(dict(e2, d_out=3), e2p)) == -2              # (rho, u, v, p)
+    assert code_of(lambda: ws(mx, dict(mp, pde="euler2d"))) == -2         # four outputs
+    assert code_of(lambda: ws(dict(e2, d_out=5), e2p)) == -1              # at most four outputs
+    assert code_of(lambda: ws(e2, dict(e2p, lambda_res=[1, 1, 1, -1]))) == -1
 
 
 def test_term_grads_validation(lib):

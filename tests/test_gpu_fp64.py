@@ -49,7 +49,7 @@ def variants():
     from paper_2604_15645_amd import synth
     out = []
     for name, n in (("burgers", 500), ("euler", 300), ("ns", 300), ("maxwell", 120), ("advection", 400),
-                    ("allen_cahn", 400)):
+                    ("allen_cahn", 400), ("euler2d", 200)):
         out.append((name, synth.make_case(name, n_points=n, seed=81, perturb=True)))
     cfg = synth.CONFIGS["burgers"]
     net = dict(cfg["net"], widths=[24, 40], periodic_mask=3, period_train_mask=2, period=[2.0, 1.3, 0.0])
@@ -61,7 +61,7 @@ def variants():
     return out
 
 
-@pytest.mark.parametrize("k", range(8))
+@pytest.mark.parametrize("k", range(9))
 def test_fp64_parity(oracle, dev, k):
     name, case = variants()[k]
     got = run64(case, dev)
@@ -97,6 +97,17 @@ def exact_networks():
     cases.append(("euler entropy wave", net, synth.CONFIGS["euler"]["pde"],
                   np.concatenate([Wout.ravel(), np.array([1.0, u0, 1.1], dtype=np.float32)]), B,
                   rng.uniform(0, 1, size=(200, 2)).astype(np.float32)))
+    # 2D Euler (Sec. 4.7): a density wave carried by the uniform flow (u0, v0) at constant
+    # pressure; with u0 - v0 = 1.25 and the frequencies 2 pi, 2 pi, -pi / 2 the transport
+    # identity holds exactly in the FP32 values (0.25 fl(2 pi) = fl(pi / 2))
+    u0, v0 = 0.75, -0.5
+    B = np.array([[2 * math.pi], [2 * math.pi], [-2 * math.pi * (u0 + v0)]], dtype=np.float32)
+    Wout = np.zeros((4, 2), dtype=np.float32)
+    Wout[0, 1] = 0.3
+    net = dict(d_in=3, d_out=4, widths=[], act="tanh", w0=1.0, n_freq=1, rwf=False, has_bias=True)
+    cases.append(("euler2d density wave", net, synth.CONFIGS["euler2d"]["pde"],
+                  np.concatenate([Wout.ravel(), np.array([1.2, u0, v0, 1.0], dtype=np.float32)]), B,
+                  rng.uniform(0, 1, size=(200, 3)).astype(np.float32)))
     net = dict(d_in=2, d_out=3, widths=[], act="tanh", w0=1.0, n_freq=0, rwf=False, has_bias=True)
     Wout = np.array([[0.0, 1.0], [0.0, 0.0], [0.0, 0.0]], dtype=np.float32)
     cases.append(("couette", net, synth.CONFIGS["ns"]["pde"],
@@ -105,7 +116,7 @@ def exact_networks():
     return cases
 
 
-@pytest.mark.parametrize("k", range(3))
+@pytest.mark.parametrize("k", range(4))
 def test_fp64_exact_networks(dev, k):
     import torch
     from paper_2604_15645_amd import binding

@@ -31,7 +31,7 @@ def dev():
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp32", "fp16x3"])
-@pytest.mark.parametrize("name", ["burgers", "euler", "ns", "maxwell"])
+@pytest.mark.parametrize("name", ["burgers", "euler", "ns", "maxwell", "euler2d"])
 def test_full_size(oracle, dev, name, prec):
     import torch
     from paper_2604_15645_amd import binding, synth

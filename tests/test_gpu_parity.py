@@ -73,7 +73,7 @@ def check(got, ref, prec, what="", tol=None):
 
 
 CASES = [("burgers", 1000), ("euler", 900), ("ns", 700), ("maxwell", 300), ("advection", 800),
-         ("allen_cahn", 600)]
+         ("allen_cahn", 600), ("euler2d", 800)]
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -115,7 +115,7 @@ def test_tiny_and_ragged_point_counts(oracle, dev, n, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("name", ["burgers", "euler", "ns", "maxwell", "advection"])
+@pytest.mark.parametrize("name", ["burgers", "euler", "ns", "maxwell", "advection", "euler2d"])
 def test_constant_output_network_is_exact(dev, name, prec):
     """With the output weights zero the outputs are the (non-zero) output biases, every
     derivative vanishes, and so do the residual of every PDE, the loss and the whole
@@ -126,7 +126,7 @@ def test_constant_output_network_is_exact(dev, name, prec):
     tail = no * ni + (no if case["net"].get("rwf") else 0) + no
     p = case["params"].copy()
     p[len(p) - tail:len(p) - tail + no * ni] = 0.0
-    p[len(p) - no:] = np.array([1.5, 0.4, 2.0], dtype=np.float32)[:no]   # rho, p > 0 for Euler
+    p[len(p) - no:] = np.array([1.5, 0.4, 2.0, 1.1], dtype=np.float32)[:no]   # rho, p > 0 for Euler
     case["params"] = p
     got = run_gpu(case, dev, prec)
     assert np.all(got["residual"] == 0.0), name
@@ -135,15 +135,16 @@ def test_constant_output_network_is_exact(dev, name, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("name,masks", [("ns", (5, 6)), ("euler", (2, 7)), ("maxwell", (4, 3))])
+@pytest.mark.parametrize("name,masks", [("ns", (5, 6)), ("euler", (2, 7)), ("maxwell", (4, 3)),
+                                        ("euler2d", (15, 10))])
 def test_multi_output_supervision(oracle, dev, name, masks, prec):
     """Value supervision of outputs other than output 0 (every out_mask bit)."""
     from paper_2604_15645_amd import synth
     case = synth.make_case(name, n_points=400, seed=61, perturb=True)
     rng = np.random.Generator(np.random.PCG64(62))
-    d_in = case["net"]["d_in"]
+    d_in, d_out = case["net"]["d_in"], case["net"]["d_out"]
     case["anchors"] = [dict(points=rng.uniform(0, 1, size=(90 + 41 * k, d_in)).astype(np.float32),
-                            targets=rng.normal(size=(90 + 41 * k, 3)).astype(np.float32),
+                            targets=rng.normal(size=(90 + 41 * k, d_out)).astype(np.float32),
                             out_mask=m, **{"lambda": 0.5 + k})
                        for k, m in enumerate(masks)]
     check(run_gpu(case, dev, prec), run_oracle(oracle, case), prec, "%s-mask" % name)
