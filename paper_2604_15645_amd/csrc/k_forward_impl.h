@@ -18,7 +18,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void k_forward(const FwdArgs A) {
   PdeDev pde = A.pde;
   if (A.wscale) {  // a device-side weight of the residual term (causality segments)
     const float w = (float)*A.wscale;
-    for (int c = 0; c < 3; ++c) pde.seed_scale[c] *= w;
+    for (int c = 0; c < kMaxOut; ++c) pde.seed_scale[c] *= w;
   }
   for (int64_t tile = blockIdx.x; tile < A.n_tiles; tile += gridDim.x) {
     const int64_t p0 = tile * P;

@@ -34,7 +34,7 @@ def to_dev(case, dev):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
-@pytest.mark.parametrize("name", ["burgers", "allen_cahn"])
+@pytest.mark.parametrize("name", ["burgers", "allen_cahn", "euler2d"])
 def test_term_gradients_match_oracle(oracle, dev, name, prec):
     import torch
     from paper_2604_15645_amd import binding, synth
@@ -75,7 +75,7 @@ def test_balance_update_matches_oracle(oracle, dev):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
-@pytest.mark.parametrize("name", ["burgers", "maxwell"])
+@pytest.mark.parametrize("name", ["burgers", "maxwell", "euler2d"])
 def test_causal_loss_matches_oracle(oracle, dev, name, prec):
     """Temporal causality (Sec. 2.6.8): points sorted by time into segments of uneven size;
     segment losses, weights, the weighted loss terms and the gradient against the oracle."""
@@ -87,7 +87,9 @@ def test_causal_loss_matches_oracle(oracle, dev, name, prec):
     pts = case["points"][np.argsort(case["points"][:, tcol], kind="stable")]
     case["points"] = np.ascontiguousarray(pts)
     bin_n = [n // 5, n // 3, n - n // 5 - n // 3 - n // 7, n // 7]
-    eps = 50.0 if name == "burgers" else 1.5   # a tenth of the weight or more gone by the end
+    # a tenth of the weight or more gone by the end (the random 2D Euler network's segment
+    # losses are of order 1e7)
+    eps = {"burgers": 50.0, "maxwell": 1.5, "euler2d": 3e-8}[name]
     params, B, dpts, anchors = to_dev(case, dev)
     out = binding.causal_step(case["net"], case["pde"], params, B, dpts, bin_n, eps, anchors, prec=prec)
     torch.cuda.synchronize()

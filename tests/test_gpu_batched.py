@@ -103,3 +103,28 @@ def test_batched_is_deterministic(dev):
     assert torch.equal(la, b["losses"])
     for x, y in zip(ga, b["grads"]):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16x3"])
+def test_batched_four_output_networks(oracle, dev, prec):
+    """Networks with four outputs and four residual components (2D Euler, Sec. 4.7) in one
+    launch: identity embedding of (x, y, t), widths and depths differing per network."""
+    import torch
+    from paper_2604_15645_amd import binding, synth
+    cfg = synth.CONFIGS["euler2d"]
+    insts = []
+    for i, (widths, n) in enumerate((([64, 64], 900), ([128, 128, 128], 1300), ([32, 32, 32, 32], 500))):
+        net = dict(cfg["net"], widths=widths, periodic_mask=0, rwf=False)
+        insts.append(synth.make_custom(net, dict(cfg["pde"]), cfg["box"], n, seed=130 + i))
+    params, pts = to_dev(insts, dev)
+    out = binding.batched_step([c["net"] for c in insts], insts[0]["pde"], params, pts, prec=prec,
+                               tune_table=[dict(chunk_points=256) for _ in insts])
+    torch.cuda.synchronize()
+    losses = out["losses"].cpu().numpy()
+    for i, c in enumerate(insts):
+        ref = oracle.loss_grad(c["net"], c["pde"], c["params"], None, c["points"], want_residual=False)
+        el = np.abs(losses[i] - ref["loss"]).max() / np.abs(ref["loss"]).max()
+        eg = relerr(out["grads"][i].cpu().numpy(), ref["grad"])
+        print(prec, i, "loss %.2e grad %.2e" % (el, eg))
+        assert losses[i].shape == (5,)
+        assert el <= SWEEP_TOL[prec] and eg <= SWEEP_TOL[prec], (i, el, eg)
