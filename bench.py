@@ -10,8 +10,15 @@ single-GPU configuration of the benchmark set.  The BF16X3 path is the reported 
 the same three-product split with IEEE half parts (FP16X3, same matrix-core rate, 22
 instead of 16 significant bits per operand) and the plain FP32 matrix-core path are timed
 beside it.  The other configurations (Burgers,
-1D Euler, Navier-Stokes, and the 64-network Burgers sweep in one persistent launch) are
-timed in the same run and reported as extra keys of the same JSON line.
+1D Euler, Navier-Stokes, 2D Euler, and the 64-network Burgers sweep in one persistent
+launch) are timed in the same run and reported as extra keys of the same JSON line.
+
+Launch shapes: unless --no-autotune or an explicit shape is given, every configuration and
+precision is timed with the shape the autotuner picks on this device before the timed
+region (forward tile, split-backward sub-tile and work-group count for one network; work
+item sizes and work-group count for the batched sweep); the chosen shape, the time of the
+library's default shape and the number of candidates are reported beside each result, and
+parity is measured at the chosen shape.
 
 Roofline: the contractions are dense matrix products, so the bound is the matrix-core
 rate.  For bf16x3 every logical product is three BF16 products, so the achieved rate is
@@ -159,6 +166,21 @@ def time_steps(case, params, B, pts, anchors, prec, steps, warmup, tune=None, pe
     return ms, kernels, out
 
 
+def tune_shape(case, params, B, pts, anchors, prec, cache):
+    """The autotuner's launch shape for one network and precision, timed on this device
+    (every candidate shape, median of three calls); returns (tune, record)."""
+    from paper_2604_15645_amd import autotune
+    tune, ms, table = autotune.tune_single(case["net"], case["pde"], params, B, pts, anchors, prec=prec,
+                                           cache=cache, force=True)
+    default = [r["ms"] for r in table if not any(r["tune"].values())]
+    return tune, {"tune": tune, "ms": ms, "default_shape_ms": default[0] if default else None,
+                  "candidates": len(table)}
+
+
+def is_default(tune):
+    return tune is None or not any(tune.values())
+
+
 def relerr(a, b):
     import numpy as np
     a = np.asarray(a, dtype=np.float64).ravel()
@@ -175,9 +197,10 @@ def parity(out, ref):
             "grad": relerr(out["grad"].cpu().numpy(), ref["grad"])}
 
 
-def bench_config(name, dev, steps, warmup, sample, fp32=True):
-    """One single-network configuration at full size: both precisions, matrix-core
-    fractions of the whole step, and parity on a prefix of the points (oracle)."""
+def bench_config(name, dev, steps, warmup, sample, fp32=True, cache=None):
+    """One single-network configuration at full size: every precision with its autotuned
+    launch shape (when a tune cache is given), matrix-core fractions of the whole step, and
+    parity on a prefix of the points (oracle) at that shape."""
     import torch
     from oracle import oracle
     from paper_2604_15645_amd import binding, synth
@@ -191,20 +214,24 @@ def bench_config(name, dev, steps, warmup, sample, fp32=True):
     m = min(sample, n)
     ref = oracle.loss_grad(net, pde, case["params"], case["B"], case["points"][:m], case["anchors"])
     for prec in precs:
-        ms, _, _ = time_steps(case, params, B, pts, anchors, prec, steps, warmup, per_kernel=False)
-        o = binding.residual_step(net, pde, params, B, pts[:m].contiguous(), anchors, prec=prec)
+        tune, trec = tune_shape(case, params, B, pts, anchors, prec, cache) if cache else (None, None)
+        ms, _, _ = time_steps(case, params, B, pts, anchors, prec, steps, warmup, tune=tune, per_kernel=False)
+        o = binding.residual_step(net, pde, params, B, pts[:m].contiguous(), anchors, prec=prec, tune=tune)
         torch.cuda.synchronize()
         rec[prec] = {"ms_per_step": ms, "points_per_s": n / (ms / 1e3),
                      "mfma_frac": N_PROD[prec] * step_flops / (ms / 1e3) / PEAK[PEAK_OF[prec]],
                      "parity": dict(parity(o, ref), tol=TOL[prec], sample_points=m)}
+        if trec:
+            rec[prec]["autotune"] = trec
     if fp32:
         rec["speedup_bf16x3_vs_fp32"] = rec["fp32"]["ms_per_step"] / rec["bf16x3"]["ms_per_step"]
     return rec
 
 
-def bench_sweep(dev, steps, warmup):
+def bench_sweep(dev, steps, warmup, cache=None):
     """The 64 Burgers networks of uneven width, depth and point count in one persistent
-    launch (pinn_batched_bwd), against the same networks as 64 separate calls."""
+    launch (pinn_batched_bwd, work-item sizes and grid from the autotuner when a tune cache
+    is given), against the same networks as 64 separate calls."""
     import numpy as np
     import torch
     from oracle import oracle
@@ -227,8 +254,15 @@ def bench_sweep(dev, steps, warmup):
     refs = {i: oracle.loss_grad(insts[i]["net"], pde, insts[i]["params"], None, insts[i]["points"],
                                 want_residual=False) for i in sorted(pick.values())}
     for prec in ("bf16x3", "fp16x3", "fp32"):
+        table, trec = None, None
+        if cache:
+            from paper_2604_15645_amd import autotune
+            table, tms, log = autotune.tune_batched(nets, pde, params, pts, prec=prec, cache=cache, force=True)
+            best = min(log, key=lambda r: r["ms"])
+            trec = {"chunk_points": {str(k): v for k, v in best["chunks"].items()}, "grid": best["grid"],
+                    "ms": tms, "default_shape_ms": log[0]["ms"], "candidates": len(log)}
         ws = binding.Workspace(dev)
-        run = lambda: binding.batched_step(nets, pde, params, pts, prec=prec, workspace=ws)
+        run = lambda: binding.batched_step(nets, pde, params, pts, prec=prec, workspace=ws, tune_table=table)
         out = run()
         for _ in range(max(0, warmup - 1)):
             run()
@@ -264,6 +298,8 @@ def bench_sweep(dev, steps, warmup):
                      "separate_calls_ms": ms1, "speedup_vs_separate_calls": ms1 / ms,
                      "parity": dict(worst, tol=TOL[prec],
                                     instances=[int(i) for i in sorted(refs)])}
+        if trec:
+            rec[prec]["autotune"] = trec
         del ws, ws1
     return rec
 
@@ -282,6 +318,10 @@ def main():
                     help="skip the other configurations and the batched sweep")
     ap.add_argument("--tile-points", type=int, default=0, help="forward tile points (0 = the library's)")
     ap.add_argument("--grid", type=int, default=0, help="work-group cap (0 = the library's)")
+    ap.add_argument("--bwd-points", type=int, default=0,
+                    help="split-backward sub-tile points (0 = the library's)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the library's default launch shapes instead of the autotuner's")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -312,17 +352,34 @@ def main():
     n_total = n_points + sum(len(a["points"]) for a in case["anchors"])
     print("bench: %s, %d points" % (name, n_points), file=sys.stderr, flush=True)
 
-    tune = {"tile_points": args.tile_points, "grid": args.grid} if args.tile_points or args.grid else None
+    fixed = {"tile_points": args.tile_points, "grid": args.grid, "bwd_points": args.bwd_points}
+    explicit = any(fixed.values())
+    cache = None
+    if not explicit and not args.no_autotune:
+        import tempfile
+        from paper_2604_15645_amd import autotune
+        # a fresh cache per run: every shape is timed on this device, with this library
+        cache = autotune.TuneCache(os.path.join(tempfile.mkdtemp(prefix="pinn_tune_"), "tune.json"))
+    tunes, trecs = {}, {}
+    for prec in ("bf16x3", "fp16x3") + (() if args.no_fp32 else ("fp32",)):
+        if cache:
+            tunes[prec], trecs[prec] = tune_shape(case, params, B, pts, anchors, prec, cache)
+        else:
+            tunes[prec] = fixed if explicit else None
+    tune = tunes["bf16x3"]
+    print("bench: shapes %s" % json.dumps(tunes), file=sys.stderr, flush=True)
     ms16, k16, out16 = time_steps(case, params, B, pts, anchors, "bf16x3", args.steps, args.warmup, tune)
-    ms_h, k_h, _ = time_steps(case, params, B, pts, anchors, "fp16x3", args.steps, args.warmup, tune)
+    ms_h, k_h, _ = time_steps(case, params, B, pts, anchors, "fp16x3", args.steps, args.warmup, tunes["fp16x3"])
     fp16x3 = {"value": n_points / (ms_h / 1e3), "ms_per_step": ms_h,
-              "kernels_ms": {k: v[1] / v[0] for k, v in k_h.items()}}
+              "kernels_ms": {k: v[1] / v[0] for k, v in k_h.items()},
+              **({"autotune": trecs["fp16x3"]} if "fp16x3" in trecs else {})}
     fp32 = None
     if not args.no_fp32:
         ms32, k32, _ = time_steps(case, params, B, pts, anchors, "fp32",
-                                  max(2, args.steps // 4), min(args.warmup, 2))
+                                  max(2, args.steps // 4), min(args.warmup, 2), tunes["fp32"])
         fp32 = {"value": n_points / (ms32 / 1e3), "ms_per_step": ms32,
-                "kernels_ms": {k: v[1] / v[0] for k, v in k32.items()}}
+                "kernels_ms": {k: v[1] / v[0] for k, v in k32.items()},
+                **({"autotune": trecs["fp32"]} if "fp32" in trecs else {})}
     print("bench: timed", file=sys.stderr, flush=True)
 
     # matrix-core roofline of the dominant kernel (largest summed time per step), from the
@@ -337,7 +394,8 @@ def main():
     roof = None
     if alg:
         mfma = n_prod * alg / (avg_ms / 1e3)
-        is_full = n_points == synth.CONFIGS[name]["n_points"] and tune is None
+        # the committed counters were taken at the library's default shape
+        is_full = n_points == synth.CONFIGS[name]["n_points"] and is_default(tune)
         roof = {"kernel": dom, "bound": "mfma", "achieved": mfma / 1e12, "peak": PEAK["bf16"] / 1e12,
                 "unit": "TFLOP/s", "frac": mfma / PEAK["bf16"],
                 "traffic": measured_traffic(name, dom) if is_full else None,
@@ -364,13 +422,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %s" % (name, describe(net, pde, n_points)),
                    "points": n_points, "params": synth.param_count(net), "parallelism": "none",
-                   **({"tune": tune} if tune else {})},
+                   "tune": tune or {}},
         "step_alg_tflop": step_flops / 1e12,
         "step_mfma_frac": n_prod * step_flops / (ms16 / 1e3) / PEAK["bf16"],
         "kernels_ms": {k: v[1] / v[0] for k, v in k16.items()},
         "kernel_launches_per_step": {k: v[0] / args.steps for k, v in k16.items()},
         "roofline": roof,
     }
+    if "bf16x3" in trecs:
+        result["autotune"] = trecs["bf16x3"]
     fp16x3["step_mfma_frac"] = n_prod * step_flops / (fp16x3["ms_per_step"] / 1e3) / PEAK["bf16"]
     result["fp16x3"] = fp16x3
     if fp32:
@@ -402,7 +462,7 @@ def main():
         par = {}
         ptsm = pts[:m].contiguous()
         for prec in ("bf16x3", "fp16x3", "fp32"):
-            o = binding.residual_step(net, pde, params, B, ptsm, anchors, prec=prec)
+            o = binding.residual_step(net, pde, params, B, ptsm, anchors, prec=prec, tune=tunes.get(prec))
             torch.cuda.synchronize()
             par[prec] = dict(parity(o, ref), tol=TOL[prec])
         full = out16["residual"].cpu().numpy()[:m]
@@ -410,22 +470,25 @@ def main():
         result["parity_vs_oracle"] = par
         print("bench: cpu baseline and parity done", file=sys.stderr, flush=True)
 
-    if not args.no_others and not args.points and tune is None:
+    if not args.no_others and not args.points and not explicit:
         others = {}
-        for other in ("burgers", "euler", "ns", "maxwell"):
+        for other in ("burgers", "euler", "ns", "maxwell", "euler2d"):
             if other == name:
                 continue
             others[other] = bench_config(other, dev, args.steps, args.warmup, 8192,
-                                         fp32=not args.no_fp32)
+                                         fp32=not args.no_fp32, cache=cache)
             print("bench: %s done" % other, file=sys.stderr, flush=True)
         result["configs"] = others
-        result["sweep"] = bench_sweep(dev, max(3, args.steps // 2), args.warmup)
+        result["sweep"] = bench_sweep(dev, max(3, args.steps // 2), args.warmup, cache=cache)
         print("bench: sweep done", file=sys.stderr, flush=True)
     print(json.dumps(result))
 
 
 def describe(net, pde, n):
     emb = "RFF m=%d" % net["n_freq"] if net.get("n_freq") else "identity"
+    if net.get("periodic_mask"):
+        emb = "periodic " + ",".join("xyt"[k] if net["d_in"] == 3 else "xt"[k]
+                                     for k in range(net["d_in"]) if (net["periodic_mask"] >> k) & 1)
     return "%s, %s, %dx%d %s -> %d%s, %d points" % (
         pde["pde"], emb, len(net["widths"]), max(net["widths"]), net["act"], net["d_out"],
         ", RWF" if net.get("rwf") else "", n)

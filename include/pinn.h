@@ -145,10 +145,13 @@ typedef struct {
 
 /* (host) Optional launch shape; NULL selects the built-in plan.  Fields <= 0 = default. */
 typedef struct {
-  int32_t tile_points;   /* forward tile points: 16 or the width's default (32 for width
-                            256, 64 for 64..128, 128 for 32)                              */
+  int32_t tile_points;   /* forward tile points: the width's default (32 for width 256,
+                            64 for 64..128, 128 for 32), half of it when that is at least
+                            32, or 16                                                     */
   int32_t grid;          /* work-groups of the persistent launches (default 256)          */
-  int32_t n_slots;       /* reserved, 0                                                   */
+  int32_t bwd_points;    /* sub-tile points of the split-role hidden-layer backward
+                            (uniform hidden width 128 or 256, split precisions): the
+                            default (32 at width 128, 16 at 256) or half of it            */
   int32_t chunk_points;  /* batched call: points per work item, a multiple of 128
                             (default 1024 for width 256, 2048 for 128, 4096 below)       */
 } pinn_tune;

@@ -2,8 +2,10 @@
 
 The tunable launch parameters are those of `pinn_tune` in include/pinn.h:
 
-* single network (`pinn_residual_bwd`): the forward tile size (`tile_points`, the default
-  for the hidden width or 16 points) and the work-group count (`grid`);
+* single network (`pinn_residual_bwd`): the forward tile size (`tile_points`: the default
+  for the hidden width, half of it, or 16 points), the sub-tile of the split-role
+  hidden-layer backward (`bwd_points`: the default or half of it) and the work-group count
+  (`grid`); every combination the library builds for the network is timed;
 * many networks in one persistent launch (`pinn_batched_bwd`): the points per work item
   (`chunk_points`) for each hidden-width class, and the work-group count.
 
@@ -23,7 +25,6 @@ import statistics
 
 from . import binding
 
-FWD_TILES = (0, 16)                     # 0 = the library's default for the width
 GRIDS = (0, 128)                        # 0 = the library's default (one per compute unit)
 CHUNKS = (512, 1024, 2048, 4096, 8192)  # batched work-item sizes (multiples of 128)
 DEFAULT_CHUNK = {32: 4096, 64: 4096, 128: 2048, 256: 1024}   # the library's defaults
@@ -67,6 +68,21 @@ def width_class(net_spec):
         if w <= h:
             return h
     raise ValueError("hidden width above 256")
+
+
+FWD_DEFAULT = {32: 128, 64: 64, 128: 64, 256: 32}   # the library's forward tile per width
+SPLIT_DEFAULT = {128: 32, 256: 16}                   # split-role backward sub-tile per width
+
+
+def fwd_tiles(h):
+    """Forward tile candidates of a width class: the default (0), half of it, 16 points."""
+    half = FWD_DEFAULT[h] // 2
+    return (0,) + ((half,) if half >= 32 else ()) + (16,)
+
+
+def bwd_tiles(h):
+    """Split-backward sub-tile candidates: the default (0) and half of it."""
+    return (0,) + ((SPLIT_DEFAULT[h] // 2,) if h in SPLIT_DEFAULT else ())
 
 
 def signature(net_spec, pde_spec, n_points, prec):
@@ -127,17 +143,23 @@ def tune_single(net_spec, pde_spec, params, B, points, anchors=(), prec="bf16x3"
     if hit and not force:
         return hit["tune"], hit["ms"], hit.get("table", [])
     ws = binding.Workspace(dev)
+    # one untimed call first, so that no candidate pays for first-use costs (workspace
+    # growth, code-object loading)
+    binding.residual_step(net_spec, pde_spec, params, B, points, anchors, prec=prec, residual=False,
+                          workspace=ws)
     table = []
-    for tp in FWD_TILES:
-        for grid in GRIDS:
-            tune = {"tile_points": tp, "grid": grid}
-            try:
-                ms = _time(lambda: binding.residual_step(net_spec, pde_spec, params, B, points, anchors,
-                                                         prec=prec, residual=False, tune=tune,
-                                                         workspace=ws), reps)
-            except binding.PinnError:
-                continue          # shape the library does not build for this network
-            table.append({"tune": tune, "ms": ms})
+    h = width_class(net_spec)
+    for tp in fwd_tiles(h):
+        for bp in bwd_tiles(h):
+            for grid in GRIDS:
+                tune = {"tile_points": tp, "bwd_points": bp, "grid": grid}
+                try:
+                    ms = _time(lambda: binding.residual_step(net_spec, pde_spec, params, B, points, anchors,
+                                                             prec=prec, residual=False, tune=tune,
+                                                             workspace=ws), reps)
+                except binding.PinnError:
+                    continue          # shape the library does not build for this network
+                table.append({"tune": tune, "ms": ms})
     best = min(table, key=lambda r: r["ms"])
     cache.put(key, sig, {"tune": best["tune"], "ms": best["ms"], "table": table})
     return best["tune"], best["ms"], table
@@ -166,6 +188,7 @@ def tune_batched(net_specs, pde_spec, params, points, prec="bf16x3", reps=2, cac
         return _time(lambda: binding.batched_step(net_specs, pde_spec, params, points, prec=prec,
                                                   tune_table=tt, workspace=ws), reps)
 
+    run(best_chunks, best_grid)          # untimed: first-use costs
     best_ms = run(best_chunks, best_grid)
     log.append({"chunks": dict(best_chunks), "grid": best_grid, "ms": best_ms})
     for h in classes:

@@ -41,7 +41,7 @@ class PinnAnchor(ctypes.Structure):
 
 class PinnTune(ctypes.Structure):
     _fields_ = [("tile_points", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("n_slots", ctypes.c_int32), ("chunk_points", ctypes.c_int32)]
+                ("bwd_points", ctypes.c_int32), ("chunk_points", ctypes.c_int32)]
 
 
 class PinnCausal(ctypes.Structure):
@@ -168,7 +168,7 @@ def tune_struct(tune):
     t = PinnTune()
     t.tile_points = int(tune.get("tile_points", 0))
     t.grid = int(tune.get("grid", 0))
-    t.n_slots = int(tune.get("n_slots", 0))
+    t.bwd_points = int(tune.get("bwd_points", 0))
     t.chunk_points = int(tune.get("chunk_points", 0))
     return t
 

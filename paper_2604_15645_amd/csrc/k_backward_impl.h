@@ -604,7 +604,10 @@ int split_k(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
 
 template <int PREC, int ACT, int H>
 int bwd_split(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  if constexpr (H >= 128) return split_k<PREC, ACT, H / 16, H / 16, wide_pb(H), false>(a, grid, lds, s);
+  if constexpr (H >= 128) {
+    if (a.pb == wide_pb(H)) return split_k<PREC, ACT, H / 16, H / 16, wide_pb(H), false>(a, grid, lds, s);
+    if (a.pb == wide_pb(H) / 2) return split_k<PREC, ACT, H / 16, H / 16, wide_pb(H) / 2, false>(a, grid, lds, s);
+  }
   return -2;
 }
 

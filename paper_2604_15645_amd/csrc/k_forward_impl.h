@@ -60,8 +60,10 @@ int fwd(const FwdArgs& a, int grid, size_t lds, hipStream_t s) {
 
 template <int PREC, int ACT, int H>
 int fwd_p(int P, const FwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  constexpr int PD = H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128;
+  constexpr int PD = fwd_default_p(H), PH = fwd_half_p(H);
   if (P == PD) return fwd<PREC, ACT, H, PD>(a, grid, lds, s);
+  if constexpr (PH > 0)
+    if (P == PH) return fwd<PREC, ACT, H, PH>(a, grid, lds, s);
   if (P == 16) return fwd<PREC, ACT, H, 16>(a, grid, lds, s);
   return -2;
 }

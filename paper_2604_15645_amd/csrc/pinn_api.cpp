@@ -167,7 +167,7 @@ unsigned long long next_launch_id() {
   return n.fetch_add(1, std::memory_order_relaxed);
 }
 
-int default_fwd_p(int H) { return H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128; }
+int default_fwd_p(int H) { return fwd_default_p(H); }
 int default_bwd_p(int H) { return 2048 / H; }
 int embed_bwd_p(int H) { return H == 256 ? 8 : 16; }
 constexpr size_t kLdsBudget = 160 * 1024;
@@ -258,7 +258,7 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   p.pf = default_fwd_p(D.H);
   if (tune && tune->tile_points > 0) {
     int t = tune->tile_points;
-    if (t != 16 && t != p.pf) return PINN_E_UNSUPPORTED;
+    if (t != 16 && t != p.pf && t != fwd_half_p(D.H)) return PINN_E_UNSUPPORTED;
     p.pf = t;
   }
   if (fwd_lds(p.pf, p.kmax, D.H) > kLdsBudget) p.pf = 16;
@@ -274,6 +274,10 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   p.split = wide;
   for (int j = 1; j < D.L; ++j) p.split = p.split && D.n_in[j] == D.H && D.n_out[j] == D.H;
   p.pb = wide ? wide_pb(D.H) : default_bwd_p(D.H);
+  if (tune && tune->bwd_points > 0) {  // the split-role kernel's sub-tile: default or half
+    if (!p.split || (tune->bwd_points != p.pb && tune->bwd_points != p.pb / 2)) return PINN_E_UNSUPPORTED;
+    p.pb = tune->bwd_points;
+  }
   p.pb0 = wide0 ? wide_pb(D.H) : embed_bwd_p(D.H);
   p.lds_f = fwd_lds(p.pf, p.kmax, D.H);
   p.lds_b = wide ? (size_t)2 * p.pb * D.H * 16 : bwd_lds(p.pb, D.H, D.H, true);
@@ -812,6 +816,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.z_prev = wk.zs0 + (j - 1) * wk.zs_stride;
       a.slots = wk.layer_slots[j];
       a.wide = p.split ? 2 : p.wide;
+      a.pb = p.pb;
       a.pace = reinterpret_cast<unsigned long long*>(ws + p.o_pace);
       a.launch = next_launch_id();
       rc = timed(allow_timing, "k_backward", stream, [&] { return launch_backward(p.prec, act_code(net, pde), D.H, false, a, p.grid_b, p.lds_b, stream); });

@@ -138,6 +138,7 @@ struct BwdArgs {
   const float* z_prev;  // stash of the previous hidden layer (null for layer 0)
   double* slots;        // [gridDim][n_out * (n_in + 1)]
   int wide;             // use the wide bf16x3 kernel (input width a multiple of 128)
+  int pb;               // sub-tile points of the split-role kernel (wide_pb(H) or half)
   // split roles: progress of each weight-gradient work-group, (launch << 20) + sub-tile
   // index, read by its input-adjoint partner to stay at most one sub-tile ahead
   unsigned long long* pace;
@@ -303,6 +304,9 @@ int launch_fp64(const F64StageArgs& s, const F64Args& a, double* const* slots, h
 
 // Sub-tile points of the wide bf16x3 layer backward (input width a multiple of 128).
 constexpr int wide_pb(int H) { return H >= 256 ? 16 : 32; }
+// Forward tile points: the width's default, and the alternatives a caller may choose.
+constexpr int fwd_default_p(int H) { return H == 256 ? 32 : H == 128 ? 64 : H == 64 ? 64 : 128; }
+constexpr int fwd_half_p(int H) { return fwd_default_p(H) / 2 >= 32 ? fwd_default_p(H) / 2 : 0; }
 
 // Waves per work-group of the forward kernel for hidden width H and tile points P.
 constexpr int fwd_waves(int H, int P) { return kWaves; }

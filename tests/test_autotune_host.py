@@ -49,3 +49,32 @@ def test_default_chunks_match_library_defaults():
     assert autotune.DEFAULT_CHUNK == {32: 4096, 64: 4096, 128: 2048, 256: 1024}
     for c in autotune.CHUNKS:
         assert c % 128 == 0
+
+
+def test_candidate_shapes_are_the_library_shapes():
+    """Every forward-tile and split-backward candidate the tuner times is a shape the
+    library plans for that width (checked by the host-side workspace query), and shapes
+    outside the lists are refused."""
+    from paper_2604_15645_amd import binding
+    for name, h in (("burgers", 32), ("euler", 64), ("ns", 128), ("maxwell", 256)):
+        net, pde = synth.CONFIGS[name]["net"], synth.CONFIGS[name]["pde"]
+        for tp in autotune.fwd_tiles(h):
+            for bp in autotune.bwd_tiles(h):
+                tune = {"tile_points": tp, "bwd_points": bp}
+                assert binding.workspace_bytes(net, pde, 5000, (), "bf16x3", True, tune) > 0, (name, tune)
+        for bad in ({"tile_points": 48}, {"tile_points": 8}, {"bwd_points": 4}):
+            try:
+                binding.workspace_bytes(net, pde, 5000, (), "bf16x3", True, bad)
+                raise AssertionError((name, bad))
+            except binding.PinnError as e:
+                assert e.code == -2
+    # the split-role sub-tile is a split-precision, uniform-width choice
+    net, pde = synth.CONFIGS["ns"]["net"], synth.CONFIGS["ns"]["pde"]
+    for prec in ("fp32",):
+        try:
+            binding.workspace_bytes(net, pde, 5000, (), prec, True, {"bwd_points": 16})
+            raise AssertionError(prec)
+        except binding.PinnError as e:
+            assert e.code == -2
+    assert autotune.fwd_tiles(256) == (0, 16) and autotune.fwd_tiles(32) == (0, 64, 16)
+    assert autotune.bwd_tiles(64) == (0,) and autotune.bwd_tiles(256) == (0, 8)

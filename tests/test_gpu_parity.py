@@ -96,6 +96,24 @@ def test_parity_small_forward_tiles(oracle, dev, name, n, prec, grid):
     check(got, run_oracle(oracle, case), prec, "%s-p16-g%d" % (name, grid))
 
 
+# the other launch shapes the autotuner chooses among: half the default forward tile
+# (widths 32 to 128) and half the split-role backward's sub-tile (uniform widths 128, 256)
+SHAPES = [("burgers", 1000, {"tile_points": 64}), ("euler", 900, {"tile_points": 32}),
+          ("ns", 700, {"tile_points": 32}), ("ns", 700, {"bwd_points": 16}),
+          ("ns", 700, {"tile_points": 32, "bwd_points": 16, "grid": 24}),
+          ("maxwell", 300, {"bwd_points": 8}), ("maxwell", 300, {"bwd_points": 8, "grid": 16})]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name,n,tune", SHAPES)
+def test_parity_tuned_shapes(oracle, dev, name, n, tune, prec):
+    from paper_2604_15645_amd import synth
+    if prec == "fp32" and "bwd_points" in tune:
+        pytest.skip("the split-role backward runs in the split precisions only")
+    case = synth.make_case(name, n_points=n + 53, seed=3000 + n, perturb=True)
+    check(run_gpu(case, dev, prec, tune=tune), run_oracle(oracle, case), prec, "%s-%s" % (name, tune))
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_forward_only_matches(oracle, dev, prec):
     from paper_2604_15645_amd import synth
