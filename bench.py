@@ -364,8 +364,11 @@ def main():
     for prec in ("bf16x3", "fp16x3") + (() if args.no_fp32 else ("fp32",)):
         if cache:
             tunes[prec], trecs[prec] = tune_shape(case, params, B, pts, anchors, prec, cache)
+        elif explicit:
+            # the split-role sub-tile exists in the split precisions only
+            tunes[prec] = dict(fixed, bwd_points=0) if prec == "fp32" else fixed
         else:
-            tunes[prec] = fixed if explicit else None
+            tunes[prec] = None
     tune = tunes["bf16x3"]
     print("bench: shapes %s" % json.dumps(tunes), file=sys.stderr, flush=True)
     ms16, k16, out16 = time_steps(case, params, B, pts, anchors, "bf16x3", args.steps, args.warmup, tune)

@@ -22,6 +22,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pinn_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+CLANG = "/opt/rocm/llvm/bin/clang"
 
 PDE_IDS = {"burgers": 1, "euler1d": 2, "ns2d": 3, "maxwell": 4, "advection": 5, "allen_cahn": 6,
            "euler2d": 7}
@@ -50,6 +51,16 @@ class _Anchor(ctypes.Structure):
                 ("lambda_", ctypes.c_double)]
 
 
+def build_sanitized(out_dir):
+    """The oracle with AddressSanitizer and UndefinedBehaviorSanitizer (clang, no OpenMP),
+    for running the CPU tests under the sanitizers; returns the library path."""
+    out = os.path.join(out_dir, "liboracle_asan.so")
+    subprocess.check_call([CLANG, "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", "-fPIC", "-shared", "-std=c99", "-o", out,
+                           SRC, "-lm"])
+    return out
+
+
 def build(force=False):
     """Compile the oracle with gcc (plain -O2, IEEE semantics, OpenMP)."""
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
@@ -67,8 +78,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(LIB)
+        path = os.environ.get("PINN_ORACLE_LIB")   # a prebuilt variant (the sanitizer build)
+        if not path:
+            path = build()
+        L = ctypes.CDLL(path)
         L.or_param_count.restype = ctypes.c_int64
         L.or_param_count.argtypes = [ctypes.POINTER(_Net)]
         L.or_forward_jets.restype = ctypes.c_int

@@ -7,7 +7,8 @@ import os
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpinn.so")
+# PINN_LIB names another build of the same library (the host-sanitizer build of build.py)
+LIB_PATH = os.environ.get("PINN_LIB") or os.path.join(HERE, "libpinn.so")
 
 PDE_IDS = {"burgers": 1, "euler1d": 2, "ns2d": 3, "maxwell": 4, "advection": 5, "allen_cahn": 6,
            "euler2d": 7}

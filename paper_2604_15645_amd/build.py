@@ -55,6 +55,40 @@ def build(verbose=False):
     return LIB
 
 
+def asan_runtime():
+    """The AddressSanitizer runtime of the ROCm clang (preloaded to run sanitized builds
+    from an uninstrumented Python), or None."""
+    import glob
+    root = os.environ.get("ROCM_PATH", "/opt/rocm")
+    c = sorted(glob.glob(os.path.join(root, "llvm", "lib", "clang", "*", "lib", "linux",
+                                      "libclang_rt.asan-x86_64.so")))
+    return c[-1] if c else None
+
+
+def build_host_asan():
+    """libpinn with its host code (argument checks, planning, workspace layout, launch
+    set-up) built with AddressSanitizer and UndefinedBehaviorSanitizer; the kernels are the
+    objects of the last build().  Written to _build/libpinn_asan.so, which is returned."""
+    os.makedirs(BUILD, exist_ok=True)
+    obj = os.path.join(BUILD, "pinn_api_asan.o")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+    cmd = [hipcc()] + HIP_FLAGS + ["-g"] + san + ["-c", os.path.join(CSRC, "pinn_api.cpp"), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("compile failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
+    objs = [os.path.join(BUILD, s + ".o") for s in SOURCES if s != "pinn_api.cpp"]
+    missing = [o for o in objs if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError("build() first: missing %s" % missing)
+    out = os.path.join(BUILD, "libpinn_asan.so")
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC"] + san[:4] + ["-o", out] + objs + [obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
