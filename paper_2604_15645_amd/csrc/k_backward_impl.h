@@ -275,94 +275,6 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_wide(const BwdArgs A) 
 // one into registers before they are needed; vector-memory counters complete in issue
 // order, and the loop waits only for what it needs (role 0 leaves its adjoint stores
 // outstanding across the wait).
-template <int NOB, int NIB, int PB>
-struct SplitShape {
-  static constexpr int CPB = PB / 4;
-  static constexpr int NIBW = NIB / 8;   // input blocks per wave
-  static constexpr int NOBC = (NOB + 7) / 8;  // output blocks converted per wave
-  static constexpr int KC = NOB / 2;     // reduction chunks of the input adjoint (n_out / 32)
-  static constexpr int NSTORE = NIBW * CPB;  // adjoint stores per lane and sub-tile
-  static_assert(NIB % 8 == 0 && CPB % 2 == 0, "split backward shape");
-};
-
-// s_waitcnt with only the vector-memory count bounded (gfx9 encoding: vmcnt in bits 3:0
-// and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima).
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
-}
-
-// Input-adjoint product of the split backward's first role, with the copy of the next
-// sub-tile's adjoint into STG started first.  STG and R are distinct LDS regions; the
-// restrict qualifiers let the compiler's wait insertion see that the tile reads do not
-// depend on the copy.
-template <int PREC, int NIBW, int CPB, int KC>
-__device__ __forceinline__ void split_adjoint_product(f4 (&acca)[NIBW][CPB], char* __restrict__ STG,
-                                                      const char* __restrict__ R, int rld,
-                                                      const Raw (&wreg)[NIBW][KC], const char* next, int bytes,
-                                                      int lane) {
-  if (next) async_copy(STG, next, bytes);
-#pragma unroll
-  for (int q = 0; q < NIBW; ++q)
-#pragma unroll
-    for (int cb = 0; cb < CPB; ++cb) acca[q][cb] = f4{0.f, 0.f, 0.f, 0.f};
-  // the A fragment of cp block cb for chunk kc + 1 is read as soon as the products of chunk
-  // kc that use it have issued; per accumulator the order of Prec::mma is kept
-  Raw a[CPB];
-#pragma unroll
-  for (int cb = 0; cb < CPB; ++cb) a[cb] = Tile<PREC>::load(R, rld, cb, 0, lane);
-#pragma unroll
-  for (int kc = 0; kc < KC; ++kc) {
-#pragma unroll
-    for (int cb = 0; cb < CPB; ++cb) {
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q) acca[q][cb] = Half<PREC>::mfma(a[cb].b, wreg[q][kc].a, acca[q][cb]);
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q) acca[q][cb] = Half<PREC>::mfma(a[cb].a, wreg[q][kc].b, acca[q][cb]);
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q) acca[q][cb] = Half<PREC>::mfma(a[cb].a, wreg[q][kc].a, acca[q][cb]);
-      if (kc + 1 < KC) a[cb] = Tile<PREC>::load(R, rld, cb, kc + 1, lane);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-  // work that waits on vector memory (the pre-activations) stays after the product, so the
-  // copy started above runs under it
-  __builtin_amdgcn_sched_barrier(0);
-}
-
-// Weight-gradient product of the split backward's second role (A operands from the ZT
-// tile, B operands in registers), with the copy of the next sub-tile's adjoint into STG
-// started first; the restrict qualifiers tell the compiler's wait insertion that the ZT
-// reads do not depend on the copy.
-template <int PREC, int NOB, int NIBW, int CPB>
-__device__ __forceinline__ void split_weight_grad_product(f4 (&accw)[NOB][NIBW], const Raw (&aop)[NIBW][CPB / 2],
-                                                          char* __restrict__ STG, const char* __restrict__ ZT,
-                                                          const char* next, int bytes, int lane) {
-  if (next) async_copy(STG, next, bytes);
-  // A operands (one 2 KiB unit per output block) read D blocks ahead of their products, from a
-  // ring of D register sets; per accumulator the order of Prec::mma is kept
-  constexpr int D = NOB < 3 ? NOB : 3;
-#pragma unroll
-  for (int cc = 0; cc < CPB / 2; ++cc) {
-    Raw u[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) u[d] = lds_unit(ZT, d * (CPB / 2) + cc, lane, 64 * 32);
-#pragma unroll
-    for (int ob = 0; ob < NOB; ++ob) {
-      const Raw ao = u[ob % D];
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q) accw[ob][q] = Half<PREC>::mfma(ao.b, aop[q][cc].a, accw[ob][q]);
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q) accw[ob][q] = Half<PREC>::mfma(ao.a, aop[q][cc].b, accw[ob][q]);
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q) accw[ob][q] = Half<PREC>::mfma(ao.a, aop[q][cc].a, accw[ob][q]);
-      if (ob + D < NOB) u[ob % D] = lds_unit(ZT, (ob + D) * (CPB / 2) + cc, lane, 64 * 32);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-}
-
 constexpr int kPaceSpin = 512;  // polls of a pacing wait before it goes on regardless
 
 template <int PREC, int ACT, int NOB, int NIB, int PB, bool EMB>
