@@ -1385,6 +1385,20 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
   };
 
   if (count <= 0) return;
+  // input-adjoint weight fragments: at widths up to 128 (at most 4 per lane) loaded once
+  // for the whole range and kept in registers, wider layers stream them per sub-tile
+  constexpr int KCM = NOB / 2 > 0 ? NOB / 2 : 1;
+  constexpr bool kResW = NIBA * KCM <= 4;
+  Raw wres[NIBA][kResW ? KCM : 1];
+  if constexpr (kResW) {
+    if (has_prev) {
+#pragma unroll
+      for (int q = 0; q < NIBA; ++q)
+#pragma unroll
+        for (int kc = 0; kc < KCM; ++kc)
+          if (kc < ly.kco) wres[q][kc] = glob_frag(ly.wb, min(wa + WA * q, nib - 1), kc, ly.kco, lane);
+    }
+  }
   __syncthreads();  // the previous user of the LDS is done
   async_copy(L.ZB, zb_src(s0), zb_bytes);
   if (has_prev) async_copy(L.ZP, zp_src(s0), zp_bytes);
@@ -1424,11 +1438,22 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
       for (int q = 0; q < NIBA; ++q)
 #pragma unroll
         for (int c = 0; c < CBA; ++c) acca[q][c] = f4{0.f, 0.f, 0.f, 0.f};
-      {
+      if constexpr (kResW) {
+#pragma unroll
+        for (int kc = 0; kc < KCM; ++kc) {
+          if (kc >= ly.kco) break;
+          Raw a[CBA], b[NIBA];
+#pragma unroll
+          for (int c = 0; c < CBA; ++c) a[c] = Tile<PREC>::load(L.R, rld, wca * CBA + c, kc, lane);
+#pragma unroll
+          for (int q = 0; q < NIBA; ++q) b[q] = wres[q][kc];
+          Pr::template mma_tile<NIBA, CBA>(acca, a, b);
+        }
+      } else {
         int blk[NIBA];
 #pragma unroll
         for (int q = 0; q < NIBA; ++q) blk[q] = min(wa + WA * q, nib - 1);
-        gemm_tile<PREC, NIBA, CBA>(acca, L.R, rld, wca * CBA, ly.wb, ly.kco, blk, lane);
+        gemm_tile<PREC, NIBA, CBA, 8, true>(acca, L.R, rld, wca * CBA, ly.wb, ly.kco, blk, lane);
       }
       // (3) one pass over the layer input's pre-activations: recomputed activation jets
       // into Q (operand of the weight gradient) and the activation adjoint
