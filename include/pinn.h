@@ -270,8 +270,10 @@ int pinn_causal_bwd(const pinn_net* net, const pinn_pde* pde, const float* param
 int pinn_balance_update(const double* grads, int n_terms, int64_t n_params, double* lambda,
                         double* lambda_hat, double alpha, double eps, pinn_stream_t stream);
 
-/* Many independent networks in one persistent launch (the paper's benchmark sweeps ran
- * each network separately).  Instance i has its own descriptor nets[i] (host array), the
+/* Many independent networks in one persistent launch: the hyperparameter searches and
+ * repeated random initialisations whose cost Sec. 1.2 counts against PINNs, and the
+ * per-method comparisons of Sec. 4, where each network trains as a run of its own.
+ * Instance i has its own descriptor nets[i] (host array), the
  * shared PDE `pde`, its own params[i], points[i] (n_points[i] x d_in, device) and grads[i]
  * (device, FP64, parameter layout); losses (device, FP64) receives n_inst x (1 + n_res)
  * values (total, then per residual component; no supervision sets).  Every instance has an
