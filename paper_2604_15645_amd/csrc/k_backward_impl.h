@@ -378,7 +378,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
           float s0v, s1v, s2v, s3v;
           act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
           const f4 zb = jet_act_adj<kLap>(z, ascale<PREC>(acca[q][cb], 1.0f / asc), s1v, s2v, s3v, lw1, lw2);
-          *jet_frag(A.zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
+          // streamed past the caches: the next launch reads it, long after this one
+          __builtin_nontemporal_store(zb, reinterpret_cast<f4*>(jet_frag(A.zb_out, cb0 + cb, ib, nib, lane)));
           if constexpr (PREC == kFP16X3) amx = fmaxf(amx, jet_absmax(zb));
         }
       }

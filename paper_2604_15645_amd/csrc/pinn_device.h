@@ -402,6 +402,9 @@ __device__ __forceinline__ float4* jet_frag(float* buf, int64_t cb, int nb, int 
 // hardware drops, instead of behind a branch.  The number of vector-memory operations a wave
 // has issued then does not depend on the condition, so later waits for loads issued before
 // these stores can leave the stores in flight.
+// Cache-policy operand of the buffer intrinsics for a non-temporal (streaming) access.
+constexpr int kNonTemporal = 2;
+
 struct FragStore {
   __amdgpu_buffer_rsrc_t r;
   int nbs;
@@ -417,7 +420,9 @@ struct FragStore {
     int okv = ok;
     asm volatile("" : "+v"(okv));
     const unsigned off = okv ? (unsigned)(((cb * nbs + nb) * 64 + lane) * 16) : 0x80000000u;
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, v), r, off, 0, 0);
+    // non-temporal: the backward reads the stash long after, so it should not displace
+    // what this kernel re-reads from cache (the weight fragments)
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, v), r, off, 0, kNonTemporal);
   }
 };
 
@@ -1278,7 +1283,7 @@ __device__ __forceinline__ void fwd_tile(const NetDev& net, const PdeDev& pde, c
           wsum[o] += yb.x * a.x + yb.y * a.y + yb.z * a.z + yb.w * a.w;
         }
         const f4 zb = jet_act_adj<(ACT & kLapFlag) != 0>(z, ab, s1, s2, s3, lw1, lw2);
-        *jet_frag(zb0, cb_st + cb, nb, nbs, lane) = to_float4(zb);
+        __builtin_nontemporal_store(zb, reinterpret_cast<f4*>(jet_frag(zb0, cb_st + cb, nb, nbs, lane)));
         if constexpr (PREC == kFP16X3) amx = fmaxf(amx, jet_absmax(zb));
         __builtin_amdgcn_sched_barrier(0);
       }
