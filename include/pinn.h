@@ -159,7 +159,7 @@ typedef struct {
 /* Number of FP32 parameters of the network (layout above).  < 0 on a bad descriptor. */
 int64_t pinn_param_count(const pinn_net* net);
 
-/* Number of residual components of a PDE (1 or 3); < 0 if unknown. */
+/* Number of residual components of a PDE (1, 3 or 4); < 0 if unknown. */
 int pinn_n_residuals(int pde_id);
 
 /* Workspace bytes needed by pinn_residual_fwd / _bwd for this problem and plan.
