@@ -131,7 +131,7 @@ def test_fp64_exact_networks(dev, k):
     assert np.abs(res).max() < 1e-5 and loss[0] < 1e-10 and np.abs(grad).max() < 1e-5
 
 
-@pytest.mark.parametrize("name", ["ns", "maxwell"])
+@pytest.mark.parametrize("name", ["ns", "maxwell", "euler2d"])
 def test_fp64_directional_differences(dev, name):
     """The loss along a direction v whose steps are exact in FP32 (p +- h v is exactly
     representable): Richardson-extrapolated central differences against g . v."""
