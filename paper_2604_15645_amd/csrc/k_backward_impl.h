@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_wide(const BwdArgs A) 
 // outstanding across the wait).
 constexpr int kPaceSpin = 512;  // polls of a pacing wait before it goes on regardless
 
-template <int PREC, int ACT, int NOB, int NIB, int PB, bool EMB>
+template <int PREC, int ACT, int NOB, int NIB, int PB, bool EMB, bool FUSE0 = false>
 __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A) {
   using S = SplitShape<NOB, NIB, PB>;
   using Pr = Prec<PREC>;
@@ -343,11 +343,17 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
     wait_vm<0>();  // resident from here on: no wait for them inside the loop
     bool held = false;  // the partner had not reached the previous sub-tile when last read
     float amx = 0.0f;
+    // FUSE0: the first layer's sums per owned input block: W_bar[n][k] (k < d_in), b_bar[n]
+    float g0s[FUSE0 ? NIBW : 1][4];
+    if constexpr (FUSE0) {
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q) g0s[q][0] = g0s[q][1] = g0s[q][2] = g0s[q][3] = 0.0f;
+    }
     for (int64_t k = 0; k < count; ++k) {
       const int64_t s = rb + k * G;
       const int64_t cb0 = s * CPB;
-      if (k == 0)
-        wait_vm<0>();
+      if (k == 0 || FUSE0)
+        wait_vm<0>();  // (FUSE0 stores nothing: the last operations issued are the copy's)
       else
         wait_vm<S::NSTORE>();  // the staged adjoint; the previous sub-tile's stores may run on
       if (held && threadIdx.x == 0) {
@@ -363,6 +369,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
       barrier_lds();
       convert(nullptr);
       load_zp(s);  // after the staged reads: waiting for these must not wait for the next copy
+      float4 xp[FUSE0 ? CPB : 1];  // FUSE0: the sub-tile's points, loaded under the product
+      if constexpr (FUSE0) {
+#pragma unroll
+        for (int cb = 0; cb < CPB; ++cb) xp[cb] = A.work.pts[(cb0 + cb) * 4 + g];
+      }
       unsigned long long seen = ~0ull;
       if (A.pace) seen = __hip_atomic_load(&A.pace[rb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       barrier_lds();  // R complete; STG free
@@ -378,8 +389,18 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
           float s0v, s1v, s2v, s3v;
           act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
           const f4 zb = jet_act_adj<kLap>(z, ascale<PREC>(acca[q][cb], 1.0f / asc), s1v, s2v, s3v, lw1, lw2);
-          // streamed past the caches: the next launch reads it, long after this one
-          __builtin_nontemporal_store(zb, reinterpret_cast<f4*>(jet_frag(A.zb_out, cb0 + cb, ib, nib, lane)));
+          if constexpr (FUSE0) {
+            // identity embedding: the jets of input k are (x_k, e_k, 0), so the point
+            // contributes zbar.value x_k + zbar.d_k to W_bar[n][k] and zbar.value to b_bar[n]
+            const float4 x = xp[cb];
+            g0s[q][0] += zb.x * x.x + zb.y;
+            g0s[q][1] += zb.x * x.y + zb.z;
+            g0s[q][2] += zb.x * x.z + zb.w;  // (input 2 only when d_in = 3; dropped otherwise)
+            g0s[q][3] += zb.x;
+          } else {
+            // streamed past the caches: the next launch reads it, long after this one
+            __builtin_nontemporal_store(zb, reinterpret_cast<f4*>(jet_frag(A.zb_out, cb0 + cb, ib, nib, lane)));
+          }
           if constexpr (PREC == kFP16X3) amx = fmaxf(amx, jet_absmax(zb));
         }
       }
@@ -387,6 +408,26 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
       held = A.pace && seen < (A.launch << 20) + (unsigned long long)k;
     }
     if constexpr (PREC == kFP16X3) amax_publish(amx, &A.work.amax[A.layer - 1]);
+    if constexpr (FUSE0) {
+      // slot rb: [n_in][d_in] weight sums, then [n_in] bias sums (the first layer's layout)
+      const int d = A.net.d_in;
+      double* slot = A.g0_slots + (size_t)rb * n_in * (d + 1);
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q) {
+        const int n = 16 * (wave + 8 * q) + l16;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          float v = g0s[q][k];
+          v += __shfl_xor(v, 16, 64);
+          v += __shfl_xor(v, 32, 64);
+          g0s[q][k] = v;
+        }
+        if (g == 0) {
+          for (int k = 0; k < d; ++k) slot[(size_t)n * d + k] = (double)g0s[q][k];
+          slot[(size_t)n_in * d + n] = (double)g0s[q][3];
+        }
+      }
+    }
   } else {
     // ---- weight and bias gradient
     f4 accw[NOB][NIBW];
@@ -507,9 +548,9 @@ int bwd_wide(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
   return launch_status(hipGetLastError());
 }
 
-template <int PREC, int ACT, int NOB, int NIB, int PB, bool EMB>
+template <int PREC, int ACT, int NOB, int NIB, int PB, bool EMB, bool FUSE0 = false>
 int split_k(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
-  auto k = k_backward_split<PREC, ACT, NOB, NIB, PB, EMB>;
+  auto k = k_backward_split<PREC, ACT, NOB, NIB, PB, EMB, FUSE0>;
   if (set_lds(k, lds)) return -5;
   hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, a);
   return launch_status(hipGetLastError());
@@ -518,6 +559,12 @@ int split_k(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
 template <int PREC, int ACT, int H>
 int bwd_split(const BwdArgs& a, int grid, size_t lds, hipStream_t s) {
   if constexpr (H >= 128) {
+    if (a.g0_slots) {
+      if (a.pb == wide_pb(H)) return split_k<PREC, ACT, H / 16, H / 16, wide_pb(H), false, true>(a, grid, lds, s);
+      if (a.pb == wide_pb(H) / 2)
+        return split_k<PREC, ACT, H / 16, H / 16, wide_pb(H) / 2, false, true>(a, grid, lds, s);
+      return -2;
+    }
     if (a.pb == wide_pb(H)) return split_k<PREC, ACT, H / 16, H / 16, wide_pb(H), false>(a, grid, lds, s);
     if (a.pb == wide_pb(H) / 2) return split_k<PREC, ACT, H / 16, H / 16, wide_pb(H) / 2, false>(a, grid, lds, s);
   }

@@ -205,6 +205,7 @@ struct Plan {
   int pb0;
   bool wide, wide0;       // wide bf16x3 backward for the hidden layers / the embedding layer
   bool split;             // split-role bf16x3 backward for the hidden layers
+  bool fuse0;             // identity first layer: its gradient summed by layer 1's split backward
   int64_t n_tiles, n_sub, n_sub0;
   int grid_f, grid_b, grid_b0, grid_g0;
   size_t lds_f, lds_b, lds_b0;
@@ -297,6 +298,7 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   }
   p.grid_b0 = (int)std::min<int64_t>(p.n_sub0, cap);
   p.grid_g0 = (int)std::min<int64_t>(std::max<int64_t>(1, p.n_pad / 4 / 64), kGridCap);
+  p.fuse0 = p.with_grad && p.split && D.L >= 2 && net->n_freq == 0 && !net->periodic_mask;
   // workspace layout
   int64_t o = 0;
   auto take = [&](int64_t bytes) { int64_t r = o; o = align_up(o + bytes, kAlign); return r; };
@@ -322,7 +324,7 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
     p.o_zb[1] = take(p.n_pad * 4 * D.hmax * 4);
     p.o_out = take((int64_t)p.grid_f * D.d_out * (D.n_in[D.L] + 1) * 8);
     for (int l = 0; l < D.L; ++l) {
-      int grid = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : p.grid_g0) : p.grid_b;
+      int grid = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : (p.fuse0 ? p.grid_b / 2 : p.grid_g0)) : p.grid_b;
       p.o_layer[l] = take((int64_t)grid * D.n_out[l] * (D.n_in[l] + 1 + (l == 0 ? p.ng0 : 0)) * 8);
     }
   }
@@ -817,6 +819,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.slots = wk.layer_slots[j];
       a.wide = p.split ? 2 : p.wide;
       a.pb = p.pb;
+      if (j == 1 && p.fuse0) a.g0_slots = wk.layer_slots[0];
       a.pace = reinterpret_cast<unsigned long long*>(ws + p.o_pace);
       a.launch = next_launch_id();
       rc = timed(allow_timing, "k_backward", stream, [&] { return launch_backward(p.prec, act_code(net, pde), D.H, false, a, p.grid_b, p.lds_b, stream); });
@@ -837,7 +840,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       a.wide = p.wide0 ? (D.n_out[0] == D.H && D.H >= 64 ? 3 : 1) : 0;
       rc = timed(allow_timing, "k_backward_embed", stream, [&] { return launch_backward(p.prec, act_code(net, pde), D.H, true, a, p.grid_b0, p.lds_b0, stream); });
       if (rc) return rc;
-    } else {
+    } else if (!p.fuse0) {
       Grad0Args a;
       std::memset(&a, 0, sizeof(a));
       a.zb = wk.zb[cur];
@@ -873,7 +876,8 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
         a.n_slots = p.grid_f;
       } else {
         a.slots = wk.layer_slots[l];
-        a.n_slots = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : p.grid_g0) : (p.split ? p.grid_b / 2 : p.grid_b);
+        a.n_slots = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : (p.fuse0 ? p.grid_b / 2 : p.grid_g0))
+                           : (p.split ? p.grid_b / 2 : p.grid_b);
       }
       rc = timed(allow_timing, "k_reduce_layer", stream, [&] { return launch_reduce_layer(a, stream); });
       if (rc) return rc;

@@ -139,6 +139,10 @@ struct BwdArgs {
   double* slots;        // [gridDim][n_out * (n_in + 1)]
   int wide;             // use the wide bf16x3 kernel (input width a multiple of 128)
   int pb;               // sub-tile points of the split-role kernel (wide_pb(H) or half)
+  // layer 1 over an identity embedding (split-role kernel): the input-adjoint role sums the
+  // first layer's weight and bias gradient from the adjoint it computes, into these slots
+  // ([grid / 2][n_in * (d_in + 1)]), instead of writing that adjoint to zb_out
+  double* g0_slots;
   // split roles: progress of each weight-gradient work-group, (launch << 20) + sub-tile
   // index, read by its input-adjoint partner to stay at most one sub-tile ahead
   unsigned long long* pace;
