@@ -233,3 +233,17 @@ def test_periodic_embedding(oracle, dev, name, prec):
         g, r = got["grad"][-ntp:], ref["grad"][-ntp:]
         print("period gradient", g, r)
         assert np.all(np.abs(g - r) <= TOL[prec] * np.abs(r) + 1e-12), (g, r)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name,widths", [("maxwell", [128, 128, 128]), ("ns", [256, 256]), ("advection", [128, 128])])
+def test_identity_first_layer_summed_by_layer_one(oracle, dev, name, widths, prec):
+    """Identity first layer with uniform hidden widths of 128 or 256: in the split
+    precisions layer 1's backward sums the first layer's gradient itself (three inputs for
+    Maxwell, two with the Laplacian channel for Navier-Stokes, two without for advection)."""
+    from paper_2604_15645_amd import synth
+    cfg = synth.CONFIGS[name]
+    net = dict(cfg["net"], n_freq=0, widths=widths)
+    case = synth.make_custom(net, dict(cfg["pde"]), cfg["box"], 611, seed=95)
+    got = run_gpu(case, dev, prec)
+    check(got, run_oracle(oracle, case), prec, "fused-first-layer-" + name)
