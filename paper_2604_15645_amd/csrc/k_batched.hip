@@ -35,10 +35,13 @@ __device__ __forceinline__ float wg_max(float m, float* red) {
 // pre-activations read a second time.  The same loops as the two roles of the split-role
 // kernel, one after the other in one work-group: the weights are read once per item and
 // layer instead of once per sub-tile.  Sums go to the item's slot [n_out][n_in], [n_out].
+// With g0_slot (layer 1 over an identity embedding, points pts) the input adjoint is not
+// written: the first layer's weight and bias sums are formed from it in pass 1 and go to
+// g0_slot [n_in][d_in], [n_in].
 template <int PREC, int ACT, int H>
 __device__ __noinline__ void item_layer_two_pass(const NetDev& net, int j, int64_t n_sub, const float* zb_in,
                                                     float* zb_out, const float* z_prev, char* smem, double* slot,
-                                                    float asc, float& amx) {
+                                                    float asc, float& amx, const float4* pts, double* g0_slot) {
   constexpr int PB = wide_pb(H), NOB = H / 16;
   using S = SplitShape<NOB, NOB, PB>;
   using Pr = Prec<PREC>;
@@ -65,11 +68,19 @@ __device__ __noinline__ void item_layer_two_pass(const NetDev& net, int j, int64
       for (int cb = 0; cb < CPB; ++cb)
         zp[q][cb] = to_f4(*jet_frag(const_cast<float*>(z_prev), s * CPB + cb, wave + 8 * q, nib, lane));
   };
-  if (n_sub <= 0) return;
+  if (n_sub <= 0) {
+    if (g0_slot)
+      for (int i = threadIdx.x; i < H * (net.d_in + 1); i += kThreads) g0_slot[i] = 0.0;
+    return;
+  }
   __syncthreads();  // the previous user of the LDS is done
 
   // ---- pass 1: input adjoint and activation adjoint
   {
+    float g0s[NIBW][4];
+#pragma unroll
+    for (int q = 0; q < NIBW; ++q) g0s[q][0] = g0s[q][1] = g0s[q][2] = g0s[q][3] = 0.0f;
+    float4 xp[CPB];
     async_copy(STG, zb_src(0), zb_bytes);
     Raw wreg[NIBW][KC];
 #pragma unroll
@@ -79,7 +90,7 @@ __device__ __noinline__ void item_layer_two_pass(const NetDev& net, int j, int64
     wait_vm<0>();
     for (int64_t s = 0; s < n_sub; ++s) {
       const int64_t cb0 = s * CPB;
-      if (s == 0)
+      if (s == 0 || g0_slot)
         wait_vm<0>();
       else
         wait_vm<S::NSTORE>();  // the staged adjoint; the previous sub-tile's stores may run on
@@ -95,6 +106,9 @@ __device__ __noinline__ void item_layer_two_pass(const NetDev& net, int j, int64
         }
       }
       load_zp(s);
+      if (g0_slot)
+#pragma unroll
+        for (int cb = 0; cb < CPB; ++cb) xp[cb] = pts[(cb0 + cb) * 4 + g];
       barrier_lds();  // R complete; STG free
       f4 acca[NIBW][CPB];
       split_adjoint_product<PREC, NIBW, CPB, KC>(acca, STG, R, rld, wreg, s + 1 < n_sub ? zb_src(s + 1) : nullptr,
@@ -108,8 +122,34 @@ __device__ __noinline__ void item_layer_two_pass(const NetDev& net, int j, int64
           float s0v, s1v, s2v, s3v;
           act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
           const f4 zb = jet_act_adj<kLap>(z, ascale<PREC>(acca[q][cb], 1.0f / asc), s1v, s2v, s3v, lw1, lw2);
-          *jet_frag(zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
+          if (g0_slot) {
+            // the identity input's jets are (x_k, e_k, 0)
+            g0s[q][0] += zb.x * xp[cb].x + zb.y;
+            g0s[q][1] += zb.x * xp[cb].y + zb.z;
+            g0s[q][2] += zb.x * xp[cb].z + zb.w;
+            g0s[q][3] += zb.x;
+          } else {
+            *jet_frag(zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
+          }
           if constexpr (PREC == kFP16X3) amx = fmaxf(amx, jet_absmax(zb));
+        }
+      }
+    }
+    if (g0_slot) {
+      // every neuron block belongs to one wave: sums over its four lane groups only
+      const int d = net.d_in;
+#pragma unroll
+      for (int q = 0; q < NIBW; ++q) {
+        const int n = 16 * (wave + 8 * q) + l16;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          float v = g0s[q][k];
+          v += __shfl_xor(v, 16, 64);
+          v += __shfl_xor(v, 32, 64);
+          if (g == 0) {
+            if (k < d) g0_slot[(size_t)n * d + k] = (double)v;
+            if (k == 3) g0_slot[(size_t)H * d + n] = (double)v;
+          }
         }
       }
     }
@@ -243,7 +283,8 @@ __device__ __forceinline__ void run_item(const BatchArgs& A, const BatchInst& in
         if constexpr (PREC == kFP16X3) asc = adj_scale<PREC>(__float_as_uint(wg_max(amx, red)));
         amx = 0.0f;
         item_layer_two_pass<PREC, ACT, H>(net, j, npts / wide_pb(H), zb[cur], zb[cur ^ 1],
-                                          zs + (j - 1) * in.zs_stride, smem, gslot + in.eff_off[j], asc, amx);
+                                          zs + (j - 1) * in.zs_stride, smem, gslot + in.eff_off[j], asc, amx, pts,
+                                          j == 1 ? gslot + in.eff_off[0] : nullptr);
         cur ^= 1;
         continue;
       }
@@ -261,14 +302,16 @@ __device__ __forceinline__ void run_item(const BatchArgs& A, const BatchInst& in
     if constexpr (PREC == kFP16X3) asc = adj_scale<PREC>(__float_as_uint(wg_max(amx, red)));
     amx = 0.0f;
     bwd_range<PREC, ACT, H / 16, H / 16, PB>(net, j, pts, 0, 1, npts / PB, zb[cur], zb[cur ^ 1],
-                                             zs + (j - 1) * in.zs_stride, smem, accw, bsum, asc, amx);
+                                             zs + (j - 1) * in.zs_stride, smem, accw, bsum, asc, amx,
+                                             j == 1 ? gslot + in.eff_off[0] : nullptr);
     bwd_flush<H / 16, H / 16, PB>(accw, bsum, gslot + in.eff_off[j], net.layer[j].n_out, net.layer[j].n_in,
                                   1.0f / asc);
     cur ^= 1;
   }
-  // first layer (identity embedding)
-  grad0_range(zb[cur], pts, net.layer[0].n_out, net.d_in, 0, npts / 4, gslot + in.eff_off[0],
-              reinterpret_cast<float*>(smem));
+  // first layer (identity embedding): summed by layer 1's backward when there is one
+  if (net.L == 1)
+    grad0_range(zb[cur], pts, net.layer[0].n_out, net.d_in, 0, npts / 4, gslot + in.eff_off[0],
+                reinterpret_cast<float*>(smem));
   __syncthreads();
 }
 

@@ -1363,10 +1363,17 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
                                           int64_t count, const float* zb_in, float* zb_out, const float* z_prev,
                                           char* smem,
                                           f4 (&accw)[BwdShape<NOB, NIB, PB>::NOBW][BwdShape<NOB, NIB, PB>::NIBW],
-                                          float (&bsum)[BwdShape<NOB, NIB, PB>::NOBW], float asc, float& amx) {
+                                          float (&bsum)[BwdShape<NOB, NIB, PB>::NOBW], float asc, float& amx,
+                                          double* g0_slot = nullptr) {
   using S = BwdShape<NOB, NIB, PB>;
   using Pr = Prec<PREC>;
   constexpr int CPB = S::CPB, NOBW = S::NOBW, NIBW = S::NIBW, NIBA = S::NIBA, CBA = S::CBA;
+  // g0_slot (layer 1 over an identity embedding): the first layer's weight and bias sums
+  // are formed here from the input adjoint, which is then not written (slot layout
+  // [n_in][d_in] then [n_in])
+  float g0s[NIBA][4];
+#pragma unroll
+  for (int q = 0; q < NIBA; ++q) g0s[q][0] = g0s[q][1] = g0s[q][2] = g0s[q][3] = 0.0f;
   constexpr int WO = S::WO, WA = S::WA;
   const LayerDev& ly = net.layer[layer];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -1389,7 +1396,11 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
     return to_f4(*reinterpret_cast<const float4*>(base + ((size_t)(cb * nbs + nb) * 64 + lane) * 16));
   };
 
-  if (count <= 0) return;
+  if (count <= 0) {
+    if (g0_slot)
+      for (int i = tid; i < n_in * (net.d_in + 1); i += kThreads) g0_slot[i] = 0.0;
+    return;
+  }
   // input-adjoint weight fragments: at widths up to 128 (at most 4 per lane) loaded once
   // for the whole range and kept in registers, wider layers stream them per sub-tile
   constexpr int KCM = NOB / 2 > 0 ? NOB / 2 : 1;
@@ -1479,7 +1490,16 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
           Pr::put4(L.Q + (size_t)n * qs + unit * 32, pos0, a);
           const f4 zb = jet_act_adj<(ACT & kLapFlag) != 0>(z, ascale<PREC>(acca[q][c], 1.0f / asc), s1v, s2v, s3v,
                                                           lw1, lw2);
-          *jet_frag(zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
+          if (g0_slot) {
+            // the identity input's jets are (x_k, e_k, 0)
+            const float4 x = pts[(cb0 + cb) * 4 + g];
+            g0s[q][0] += zb.x * x.x + zb.y;
+            g0s[q][1] += zb.x * x.y + zb.z;
+            g0s[q][2] += zb.x * x.z + zb.w;
+            g0s[q][3] += zb.x;
+          } else {
+            *jet_frag(zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
+          }
           if constexpr (PREC == kFP16X3) amx = fmaxf(amx, jet_absmax(zb));
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -1510,6 +1530,31 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
 #pragma unroll
         for (int i = 0; i < NOBW; ++i) Pr::mma(accw[i][q], ao[cc][i], bq);
       }
+  }
+  if (g0_slot) {
+    // over the lanes of a neuron, then over the waves that share it (fixed order)
+    float* red = reinterpret_cast<float*>(smem);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NIBA; ++q) {
+      const int ib = wa + WA * q;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        float v = g0s[q][k];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (g == 0 && ib < nib) red[((size_t)wca * n_in + 16 * ib + l16) * 4 + k] = v;
+      }
+    }
+    __syncthreads();
+    const int d = net.d_in;
+    for (int i = tid; i < n_in; i += kThreads) {
+      double t[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int w = 0; w < kWaves / WA; ++w)
+        for (int k = 0; k < 4; ++k) t[k] += (double)red[((size_t)w * n_in + i) * 4 + k];
+      for (int k = 0; k < d; ++k) g0_slot[(size_t)i * d + k] = t[k];
+      g0_slot[(size_t)n_in * d + i] = t[3];
+    }
   }
 }
 

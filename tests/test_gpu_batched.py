@@ -128,3 +128,33 @@ def test_batched_four_output_networks(oracle, dev, prec):
         print(prec, i, "loss %.2e grad %.2e" % (el, eg))
         assert losses[i].shape == (5,)
         assert el <= SWEEP_TOL[prec] and eg <= SWEEP_TOL[prec], (i, el, eg)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
+def test_batched_first_layer_gradient(oracle, dev, prec):
+    """The first layer's gradient over the identity embedding: summed by layer 1's backward
+    in networks of two or more hidden layers (the two-pass loop at width 256 under bf16x3,
+    the one-pass loop otherwise), by its own pass in networks of one hidden layer."""
+    import torch
+    from paper_2604_15645_amd import binding, synth
+    cfg = synth.CONFIGS["burgers"]
+    insts = []
+    for i, (widths, n) in enumerate((([256], 700), ([256, 256, 256], 1100), ([128, 128], 900), ([64], 500),
+                                     ([32, 32, 32], 300))):
+        net = dict(cfg["net"], widths=widths)
+        insts.append(synth.make_custom(net, dict(cfg["pde"]), cfg["box"], n, seed=140 + i, perturb=True))
+    params, pts = to_dev(insts, dev)
+    out = binding.batched_step([c["net"] for c in insts], insts[0]["pde"], params, pts, prec=prec,
+                               tune_table=[dict(chunk_points=256) for _ in insts])
+    torch.cuda.synchronize()
+    losses = out["losses"].cpu().numpy()
+    for i, c in enumerate(insts):
+        ref = oracle.loss_grad(c["net"], c["pde"], c["params"], None, c["points"], want_residual=False)
+        el = np.abs(losses[i] - ref["loss"]).max() / np.abs(ref["loss"]).max()
+        got = out["grads"][i].cpu().numpy()
+        eg = relerr(got, ref["grad"])
+        # the first layer's weights and bias lead the parameter vector
+        n0 = c["net"]["widths"][0] * (c["net"]["d_in"] + 1)
+        e0 = relerr(got[:n0], ref["grad"][:n0])
+        print(prec, i, c["net"]["widths"], "loss %.2e grad %.2e first layer %.2e" % (el, eg, e0))
+        assert el <= SWEEP_TOL[prec] and eg <= SWEEP_TOL[prec] and e0 <= SWEEP_TOL[prec], (i, el, eg, e0)
