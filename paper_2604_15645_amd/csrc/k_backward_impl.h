@@ -471,34 +471,56 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward_split(const BwdArgs A)
       }
       barrier_lds();  // ZT complete; STG free
       Raw aop[NIBW][CPB / 2];
-#pragma unroll
-      for (int q = 0; q < NIBW; ++q)
+      if constexpr (EMB && NIB == 16) {
+        // 128 frequencies: the lane's two input blocks (wave, wave + 8) are the cosine and the
+        // sine column of one frequency, whose jets come from one evaluation
+        const int j = 16 * wave + l16;
 #pragma unroll
         for (int cc = 0; cc < CPB / 2; ++cc) {
-          float f[8];
+          float fc[8], fs[8];
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
-            f4 a;
-            if constexpr (EMB) {
-              // Fourier-feature jets: column i < m is cos(x B_i), column i >= m sin(x B_{i-m})
-              const int m = net.n_freq;
-              const int i = 16 * (wave + 8 * q) + l16;
-              f4 cj, sj;
-              rff_jets(net, BF, A.work.pts[(int64_t)s * PB + 4 * (2 * cc + h) + g], i < m ? i : i - m, cj, sj);
-              a = i < m ? cj : sj;
-            } else {
-              const f4 z = zp[q][2 * cc + h];
-              float s0v, s1v, s2v, s3v;
-              act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
-              a = jet_act<kLap>(z, s0v, s1v, s2v, lw1, lw2);
+            f4 cj, sj;
+            rff_jets(net, BF, A.work.pts[(int64_t)s * PB + 4 * (2 * cc + h) + g], j, cj, sj);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              fc[4 * h + e] = cj[e];
+              fs[4 * h + e] = sj[e];
             }
-            f[4 * h] = a.x;
-            f[4 * h + 1] = a.y;
-            f[4 * h + 2] = a.z;
-            f[4 * h + 3] = a.w;
           }
-          aop[q][cc] = Pr::make(f);
+          aop[0][cc] = Pr::make(fc);
+          aop[1][cc] = Pr::make(fs);
         }
+      } else {
+#pragma unroll
+        for (int q = 0; q < NIBW; ++q)
+#pragma unroll
+          for (int cc = 0; cc < CPB / 2; ++cc) {
+            float f[8];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              f4 a;
+              if constexpr (EMB) {
+                // Fourier-feature jets: column i < m is cos(x B_i), column i >= m sin(x B_{i-m})
+                const int m = net.n_freq;
+                const int i = 16 * (wave + 8 * q) + l16;
+                f4 cj, sj;
+                rff_jets(net, BF, A.work.pts[(int64_t)s * PB + 4 * (2 * cc + h) + g], i < m ? i : i - m, cj, sj);
+                a = i < m ? cj : sj;
+              } else {
+                const f4 z = zp[q][2 * cc + h];
+                float s0v, s1v, s2v, s3v;
+                act_eval<ACT>(z.x, net.w0, s0v, s1v, s2v, s3v);
+                a = jet_act<kLap>(z, s0v, s1v, s2v, lw1, lw2);
+              }
+              f[4 * h] = a.x;
+              f[4 * h + 1] = a.y;
+              f[4 * h + 2] = a.z;
+              f[4 * h + 3] = a.w;
+            }
+            aop[q][cc] = Pr::make(f);
+          }
+      }
       if (!EMB && k + 1 < count) load_zp(s + G);  // the next sub-tile's pre-activations load under the product
       split_weight_grad_product<PREC, NOB, NIBW, CPB>(accw, aop, STG, R, k + 1 < count ? zb_src(s + G) : nullptr,
                                                 zb_bytes, lane);
