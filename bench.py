@@ -166,6 +166,26 @@ def time_steps(case, params, B, pts, anchors, prec, steps, warmup, tune=None, pe
     return ms, kernels, out
 
 
+def time_graph(case, params, B, pts, anchors, prec, steps, warmup, tune=None):
+    """Mean ms per step of the same step captured once in a HIP graph and replayed
+    (binding.StepGraph: every kernel of the step, one graph launch)."""
+    import torch
+    from paper_2604_15645_amd import binding
+    g = binding.StepGraph(case["net"], case["pde"], params, B, pts, anchors, prec=prec, tune=tune)
+    for _ in range(max(1, warmup)):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del g
+    return ms
+
+
 def tune_shape(case, params, B, pts, anchors, prec, cache):
     """The autotuner's launch shape for one network and precision, timed on this device
     (every candidate shape, median of three calls); returns (tune, record)."""
@@ -216,9 +236,11 @@ def bench_config(name, dev, steps, warmup, sample, fp32=True, cache=None):
     for prec in precs:
         tune, trec = tune_shape(case, params, B, pts, anchors, prec, cache) if cache else (None, None)
         ms, _, _ = time_steps(case, params, B, pts, anchors, prec, steps, warmup, tune=tune, per_kernel=False)
+        gms = time_graph(case, params, B, pts, anchors, prec, steps, warmup, tune=tune)
         o = binding.residual_step(net, pde, params, B, pts[:m].contiguous(), anchors, prec=prec, tune=tune)
         torch.cuda.synchronize()
         rec[prec] = {"ms_per_step": ms, "points_per_s": n / (ms / 1e3),
+                     "graph_ms_per_step": gms, "graph_points_per_s": n / (gms / 1e3),
                      "mfma_frac": N_PROD[prec] * step_flops / (ms / 1e3) / PEAK[PEAK_OF[prec]],
                      "parity": dict(parity(o, ref), tol=TOL[prec], sample_points=m)}
         if trec:

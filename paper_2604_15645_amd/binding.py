@@ -321,6 +321,39 @@ def residual_step(net_spec, pde_spec, params, B, points, anchors=(), prec="bf16x
     return {"loss": loss, "grad": g if grad else None, "residual": res if residual else None}
 
 
+class StepGraph:
+    """One residual_step captured in a HIP graph (torch.cuda.CUDAGraph) and replayed.
+
+    The capture records the library's kernel launches with their buffers fixed: the
+    parameters, Fourier matrix, points and anchors given here, a private workspace, and the
+    output tensors in `out`.  Every replay re-reads those inputs (update them in place, e.g.
+    an optimiser step on `params`) and overwrites the outputs, at the cost of one graph
+    launch instead of one launch per kernel, which is what small steps are bound by.  The
+    library issues only kernels on the stream for a step without the finiteness check
+    (no memset or copy nodes).  Per-kernel timing (timing_enable) must be off while it is
+    built."""
+
+    def __init__(self, net_spec, pde_spec, params, B, points, anchors=(), prec="bf16x3", grad=True,
+                 residual=True, tune=None):
+        dev = points.device
+        self.workspace = Workspace(dev)
+        kw = dict(prec=prec, grad=grad, residual=residual, tune=tune, workspace=self.workspace)
+        self._args = (net_spec, pde_spec, params, B, points, tuple(anchors))
+        # outputs and workspace allocated, kernel attributes set, before the capture
+        self.out = residual_step(*self._args, **kw)
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        # relaxed: the launchers set kernel attributes (dynamic LDS) while being captured
+        with torch.cuda.graph(self.graph, capture_error_mode="relaxed"):
+            residual_step(*self._args, out=dict(self.out), **kw)
+        torch.cuda.synchronize(dev)
+
+    def replay(self):
+        """Launch the captured step on the current stream; returns the output dict."""
+        self.graph.replay()
+        return self.out
+
+
 NOALLOC_MAX_BYTES = 64 << 20   # PINN_NOALLOC_MAX_BYTES
 
 
