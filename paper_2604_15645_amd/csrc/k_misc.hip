@@ -20,8 +20,7 @@ __device__ __forceinline__ float eff_w(const StageArgs& a, int l, int o, int i) 
 }
 
 template <int PREC>
-__global__ void k_stage(const StageArgs a) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void stage_thread(const StageArgs& a, int64_t t) {
   if (t < 3 && a.omega) {  // omega_k = 2 pi / P_k of the periodic inputs (Sec. 2.6.3)
     const int k = (int)t;
     float w = 0.0f;
@@ -83,8 +82,7 @@ __global__ void k_stage(const StageArgs a) {
 
 // Gather residual and supervision points into one padded (x, y, t, 0) buffer.
 
-__global__ void k_points(const PointsArgs a) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void points_thread(const PointsArgs& a, int64_t p) {
   if (p < a.n_zero) a.zero[p] = 0u;
   if (p >= a.n_pad) return;
   int s = 0;
@@ -99,6 +97,19 @@ __global__ void k_points(const PointsArgs a) {
     if (a.d_in > 2) v.z = x[2];
   }
   a.dst[p] = v;
+}
+
+__global__ void k_points(const PointsArgs a) { points_thread(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x); }
+
+// Points and weight staging in one launch (independent work): the first nbp blocks gather
+// the points, the rest stage the weights.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_prepare(const PointsArgs pa, const StageArgs sa, int nbp) {
+  const int b = blockIdx.x;
+  if (b < nbp)
+    points_thread(pa, (int64_t)b * 256 + threadIdx.x);
+  else
+    stage_thread<PREC>(sa, (int64_t)(b - nbp) * 256 + threadIdx.x);
 }
 
 __global__ __launch_bounds__(kThreads, 1) void k_grad0(const Grad0Args A) {
@@ -280,17 +291,18 @@ __global__ void k_reduce_loss_batched(const BatchLossArgs A) {
 
 __global__ void k_zero_int(int* p) { *p = 0; }
 
-// Loss terms: thread s sums slots s, s + 256, ... (in that order), then a fixed tree over
-// the 256 threads per term.
-__global__ __launch_bounds__(256) void k_reduce_loss(const LossArgs A) {
+// Loss terms: thread s < 256 sums slots s, s + 256, ... (in that order), then a fixed tree
+// over those 256 threads per term (any further threads of the block only pass the barriers).
+__device__ __forceinline__ void reduce_loss_block(const LossArgs& A) {
   __shared__ double red[kMaxTerms][256];
   const int tid = threadIdx.x;
   const int nt = A.n_res + A.n_anchor;
-  for (int k = 0; k < nt; ++k) {
-    double t = 0.0;
-    for (int sl = tid; sl < A.n_slots; sl += 256) t += A.slots[(size_t)sl * kMaxTerms + k];
-    red[k][tid] = t;
-  }
+  if (tid < 256)
+    for (int k = 0; k < nt; ++k) {
+      double t = 0.0;
+      for (int sl = tid; sl < A.n_slots; sl += 256) t += A.slots[(size_t)sl * kMaxTerms + k];
+      red[k][tid] = t;
+    }
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if (tid < st)
@@ -307,6 +319,19 @@ __global__ __launch_bounds__(256) void k_reduce_loss(const LossArgs A) {
     }
     A.loss[0] = total + (A.accumulate ? A.loss[0] : 0.0);
   }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_loss(const LossArgs A) { reduce_loss_block(A); }
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_all(const ReduceAllArgs A) {
+  const int b = blockIdx.x;
+  if (b >= A.row0[A.n_layers]) {
+    reduce_loss_block(A.loss);
+    return;
+  }
+  int l = 0;
+  while (b >= A.row0[l + 1]) ++l;
+  reduce_row(A.layer[l], b - A.row0[l]);
 }
 
 // NaN / Inf scan of the parameters (opt-in check).
@@ -330,18 +355,6 @@ int launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t s) {
 int launch_points(const PointsArgs& a, hipStream_t s) {
   const int64_t n = a.n_pad > a.n_zero ? a.n_pad : a.n_zero;
   hipLaunchKernelGGL(k_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
-  return launch_status(hipGetLastError());
-}
-
-int launch_stage(int prec, const StageArgs& a, hipStream_t s) {
-  const int64_t n = a.cum[a.n_layers];
-  const dim3 grid((unsigned)((n + 255) / 256));
-  if (prec == kFP32)
-    hipLaunchKernelGGL(k_stage<kFP32>, grid, dim3(256), 0, s, a);
-  else if (prec == kFP16X3)
-    hipLaunchKernelGGL(k_stage<kFP16X3>, grid, dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_stage<kBF16X3>, grid, dim3(256), 0, s, a);
   return launch_status(hipGetLastError());
 }
 
@@ -461,6 +474,25 @@ int launch_reduce_layer(const ReduceArgs& a, hipStream_t s) {
 
 int launch_reduce_loss(const LossArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(256), 0, s, a);
+  return launch_status(hipGetLastError());
+}
+
+int launch_reduce_all(const ReduceAllArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_all, dim3((unsigned)(a.row0[a.n_layers] + 1)), dim3(kRedThreads), 0, s, a);
+  return launch_status(hipGetLastError());
+}
+
+int launch_prepare(int prec, const PointsArgs& pa, const StageArgs& sa, hipStream_t s) {
+  const int64_t np = pa.n_pad > pa.n_zero ? pa.n_pad : pa.n_zero;
+  const int nbp = (int)((np + 255) / 256);
+  const int nbs = (int)((sa.cum[sa.n_layers] + 255) / 256);
+  const dim3 grid((unsigned)(nbp + (nbs > 0 ? nbs : 1)));
+  if (prec == kFP32)
+    hipLaunchKernelGGL(k_prepare<kFP32>, grid, dim3(256), 0, s, pa, sa, nbp);
+  else if (prec == kFP16X3)
+    hipLaunchKernelGGL(k_prepare<kFP16X3>, grid, dim3(256), 0, s, pa, sa, nbp);
+  else
+    hipLaunchKernelGGL(k_prepare<kBF16X3>, grid, dim3(256), 0, s, pa, sa, nbp);
   return launch_status(hipGetLastError());
 }
 

@@ -709,26 +709,21 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     if (h) return PINN_E_NONFINITE;
   }
 
-  // points
+  // points and weights (one launch)
   {
-    PointsArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.d_in = D.d_in;
-    a.n_seg = p.n_seg;
+    PointsArgs pa;
+    std::memset(&pa, 0, sizeof(pa));
+    pa.d_in = D.d_in;
+    pa.n_seg = p.n_seg;
     for (int s = 0; s < p.n_seg; ++s) {
-      a.start[s] = p.seg_start[s];
-      a.n[s] = p.seg_n[s];
-      a.src[s] = s == 0 ? points : anchors[s - 1].points;
+      pa.start[s] = p.seg_start[s];
+      pa.n[s] = p.seg_n[s];
+      pa.src[s] = s == 0 ? points : anchors[s - 1].points;
     }
-    a.n_pad = p.n_pad;
-    a.dst = reinterpret_cast<float4*>(ws + p.o_pts);
-    a.zero = reinterpret_cast<unsigned int*>(ws + p.o_amax);
-    a.n_zero = kMaxHidden;
-    rc = timed(allow_timing, "k_points", stream, [&] { return launch_points(a, stream); });
-    if (rc) return rc;
-  }
-  // weights
-  {
+    pa.n_pad = p.n_pad;
+    pa.dst = reinterpret_cast<float4*>(ws + p.o_pts);
+    pa.zero = reinterpret_cast<unsigned int*>(ws + p.o_amax);
+    pa.n_zero = kMaxHidden;
     StageArgs a;
     std::memset(&a, 0, sizeof(a));
     a.n_layers = D.n_layers;
@@ -757,7 +752,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       cum += nbo * kci * 64 + nbi * kco * 64 + (int64_t)D.n_out[l] * D.n_in[l] + D.n_out[l];
     }
     a.cum[D.n_layers] = cum;
-    rc = timed(allow_timing, "k_stage", stream, [&] { return launch_stage(p.prec, a, stream); });
+    rc = timed(allow_timing, "k_prepare", stream, [&] { return launch_prepare(p.prec, pa, a, stream); });
     if (rc) return rc;
   }
 
@@ -805,6 +800,9 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
     if (rc) return rc;
   }
   int cur = 0;
+  // every layer's slot reduction and the loss terms: one launch after the backward
+  ReduceAllArgs ra;
+  std::memset(&ra, 0, sizeof(ra));
   if (p.with_grad) {
     for (int j = D.L - 1; j >= 1; --j) {
       BwdArgs a;
@@ -858,8 +856,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       if (rc) return rc;
     }
     for (int l = 0; l < D.n_layers; ++l) {
-      ReduceArgs a;
-      std::memset(&a, 0, sizeof(a));
+      ReduceArgs& a = ra.layer[l];
       a.accumulate = accumulate;
       a.n_out = D.n_out[l];
       a.n_in = D.n_in[l];
@@ -879,10 +876,27 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
         a.n_slots = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : (p.fuse0 ? p.grid_b / 2 : p.grid_g0))
                            : (p.split ? p.grid_b / 2 : p.grid_b);
       }
-      rc = timed(allow_timing, "k_reduce_layer", stream, [&] { return launch_reduce_layer(a, stream); });
-      if (rc) return rc;
+      ra.row0[l + 1] = ra.row0[l] + D.n_out[l];
     }
-    if (D.n_tp > 0) {  // trained periods of the periodic embedding (after layer 0's sums)
+    ra.n_layers = D.n_layers;
+  }
+  {
+    LossArgs& a = ra.loss;
+    a.slots = wk.loss_slots;
+    a.n_slots = p.grid_f;
+    a.n_res = p.n_res;
+    a.n_anchor = n_anchor;
+    for (int k = 0; k < kMaxOut; ++k) a.w_res[k] = N > 0 ? pde->lambda_res[k] / N : 0.0;
+    for (int k = 0; k < n_anchor; ++k)
+      a.w_anchor[k] = anchors[k].n > 0 ? anchors[k].lambda / (double)anchors[k].n : 0.0;
+    a.loss = loss;
+    a.wscale = wscale;
+    a.accumulate = accumulate;
+    rc = timed(allow_timing, "k_reduce", stream, [&] { return launch_reduce_all(ra, stream); });
+    if (rc) return rc;
+  }
+  if (p.with_grad) {
+    if (D.n_tp > 0) {  // trained periods of the periodic embedding (from layer 0's slots)
       PeriodReduceArgs a;
       std::memset(&a, 0, sizeof(a));
       a.slots = wk.layer_slots[0];
@@ -901,22 +915,6 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
       rc = timed(allow_timing, "k_reduce_period", stream, [&] { return launch_reduce_period(a, stream); });
       if (rc) return rc;
     }
-  }
-  {
-    LossArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.slots = wk.loss_slots;
-    a.n_slots = p.grid_f;
-    a.n_res = p.n_res;
-    a.n_anchor = n_anchor;
-    for (int k = 0; k < kMaxOut; ++k) a.w_res[k] = N > 0 ? pde->lambda_res[k] / N : 0.0;
-    for (int k = 0; k < n_anchor; ++k)
-      a.w_anchor[k] = anchors[k].n > 0 ? anchors[k].lambda / (double)anchors[k].n : 0.0;
-    a.loss = loss;
-    a.wscale = wscale;
-    a.accumulate = accumulate;
-    rc = timed(allow_timing, "k_reduce_loss", stream, [&] { return launch_reduce_loss(a, stream); });
-    if (rc) return rc;
   }
   return hip_rc(hipGetLastError());
 }
@@ -1169,8 +1167,6 @@ int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* p
     pa.src[0] = points[i];
     pa.n_pad = b.n_pad[i];
     pa.dst = reinterpret_cast<float4*>(ws + b.o_pts) + b.pts_off[i];
-    rc = timed(allow_timing, "k_points", stream, [&] { return launch_points(pa, stream); });
-    if (rc) return rc;
     StageArgs sa;
     std::memset(&sa, 0, sizeof(sa));
     sa.n_layers = D.n_layers;
@@ -1194,7 +1190,7 @@ int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* p
       cum += nbo * kci * 64 + nbi * kco * 64 + (int64_t)D.n_out[l] * D.n_in[l] + D.n_out[l];
     }
     sa.cum[D.n_layers] = cum;
-    rc = timed(allow_timing, "k_stage", stream, [&] { return launch_stage(b.prec, sa, stream); });
+    rc = timed(allow_timing, "k_prepare", stream, [&] { return launch_prepare(b.prec, pa, sa, stream); });
     if (rc) return rc;
   }
   int* counter = reinterpret_cast<int*>(ws + b.o_counter);

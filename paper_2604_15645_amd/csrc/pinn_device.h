@@ -22,11 +22,12 @@
 // lane-local.
 //
 // Kernels (one translation unit each group, so that they compile in parallel):
-//   k_misc.hip      k_stage (effective weights W = diag(exp s) V, Sec. 2.6.2, and operand
-//                   fragments), k_points (residual and supervision points gathered into one
-//                   padded buffer), k_grad0 (identity-embedding first layer's weight
-//                   gradient), k_reduce_* (fixed-order FP64 reductions of the per-work-group
-//                   partial sums);
+//   k_misc.hip      k_prepare (in one launch: residual and supervision points gathered into
+//                   one padded buffer, effective weights W = diag(exp s) V, Sec. 2.6.2, and
+//                   operand fragments), k_grad0 (identity-embedding first layer's weight
+//                   gradient), k_reduce_all (fixed-order FP64 reductions of every layer's
+//                   per-work-group partial sums and of the loss terms, one launch), the other
+//                   k_reduce_* kernels;
 //   k_forward.hip   per tile: embedding jets, hidden layers, output layer, residual, loss
 //                   partial sums, residual adjoint seed and the output layer's backward;
 //                   stores the pre-activation jets of the hidden layers the backward reads;

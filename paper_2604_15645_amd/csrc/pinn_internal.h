@@ -48,7 +48,7 @@ struct NetDev {
   int e;               // embedding width (d_in, 2 * n_freq, or inputs with periodic ones twice)
   int n_freq;
   int periodic_mask;   // inputs embedded as [cos, sin](omega_k x_k) (0: identity or Fourier)
-  const float* omega;  // omega_k = 2 pi / P_k of the periodic inputs (workspace, from k_stage)
+  const float* omega;  // omega_k = 2 pi / P_k of the periodic inputs (workspace, from k_prepare)
   int lap_mask;        // inputs in the Laplacian set
   int lapch;           // channel of the Laplacian (-1 if none)
   float w0;
@@ -202,6 +202,16 @@ struct LossArgs {
   int accumulate;         // add to loss instead of overwriting it
 };
 
+// Every layer's slot reduction and the loss terms in one launch: blocks row0[l] ..
+// row0[l + 1] - 1 reduce the rows of layer l, block row0[n_layers] the loss.
+struct ReduceAllArgs {
+  ReduceArgs layer[kMaxLayers];
+  int row0[kMaxLayers + 1];
+  int n_layers;
+  LossArgs loss;
+};
+
+
 // Many independent networks in one persistent launch.
 struct BatchInst {
   NetDev net;
@@ -324,7 +334,6 @@ constexpr bool fwd_double_x(int P) { return P <= 16; }
 // Launchers (k_*.hip).  Each returns a pinn_status value.
 int launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t s);
 int launch_points(const PointsArgs& a, hipStream_t s);
-int launch_stage(int prec, const StageArgs& a, hipStream_t s);
 int launch_forward(int prec, int act, int H, int P, const FwdArgs& a, int grid, size_t lds, hipStream_t s);
 int launch_backward(int prec, int act, int H, bool embed, const BwdArgs& a, int grid, size_t lds, hipStream_t s);
 int launch_grad0(const Grad0Args& a, int grid, hipStream_t s);
@@ -336,6 +345,8 @@ int launch_causal_weights(const double* bin_loss, int stride, int n_bins, double
 int launch_balance(const double* grads, int n_terms, int64_t n_params, double* lambda, double* hat, double alpha,
                    double eps, hipStream_t s);
 int launch_reduce_loss(const LossArgs& a, hipStream_t s);
+int launch_reduce_all(const ReduceAllArgs& a, hipStream_t s);
+int launch_prepare(int prec, const PointsArgs& pa, const StageArgs& sa, hipStream_t s);
 int launch_batched(int prec, int act, const BatchArgs& a, int grid, size_t lds, hipStream_t s);
 int launch_reduce_batched(const BatchReduceArgs& a, hipStream_t s);
 int launch_reduce_loss_batched(const BatchLossArgs& a, hipStream_t s);
