@@ -23,8 +23,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_backward(const BwdArgs A) {
   const int64_t count = A.n_sub > blockIdx.x ? (A.n_sub - blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
   const float asc = adj_scale<PREC>(A.work.amax[A.layer]);
   float amx = 0.0f;
+  // layer 1 over an identity embedding: the first layer's sums from the input adjoint
+  double* g0 = A.g0_slots ? A.g0_slots + (size_t)blockIdx.x * A.net.layer[0].n_out * (A.net.d_in + 1) : nullptr;
   bwd_range<PREC, ACT, NOB, NIB, PB>(A.net, A.layer, A.work.pts, blockIdx.x, gridDim.x, count, A.zb_in, A.zb_out,
-                                     A.z_prev, smem, accw, bsum, asc, amx);
+                                     A.z_prev, smem, accw, bsum, asc, amx, g0);
   if constexpr (PREC == kFP16X3)
     if (A.z_prev) amax_publish(amx, &A.work.amax[A.layer - 1]);
   const LayerDev& ly = A.net.layer[A.layer];

@@ -205,7 +205,8 @@ struct Plan {
   int pb0;
   bool wide, wide0;       // wide bf16x3 backward for the hidden layers / the embedding layer
   bool split;             // split-role bf16x3 backward for the hidden layers
-  bool fuse0;             // identity first layer: its gradient summed by layer 1's split backward
+  bool fuse0;             // identity first layer: its gradient summed by layer 1's backward
+                          // (split-role or plain kernel; one slot per work-group or pair)
   int64_t n_tiles, n_sub, n_sub0;
   int grid_f, grid_b, grid_b0, grid_g0;
   size_t lds_f, lds_b, lds_b0;
@@ -217,6 +218,11 @@ struct Plan {
   int64_t zs_stride;
   int64_t bytes;
 };
+
+// Slots of the first layer's sums when layer 1's backward forms them: one per work-group
+// pair of the split-role kernel, one per work-group of the plain kernel.
+int fused0_slots(const Plan& p) { return p.split ? p.grid_b / 2 : p.grid_b; }
+
 
 int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const pinn_anchor* anchors,
               int n_anchor, int prec, int with_grad, const pinn_tune* tune, Plan* P) {
@@ -298,7 +304,7 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
   }
   p.grid_b0 = (int)std::min<int64_t>(p.n_sub0, cap);
   p.grid_g0 = (int)std::min<int64_t>(std::max<int64_t>(1, p.n_pad / 4 / 64), kGridCap);
-  p.fuse0 = p.with_grad && p.split && D.L >= 2 && net->n_freq == 0 && !net->periodic_mask;
+  p.fuse0 = p.with_grad && (p.split || !p.wide) && D.L >= 2 && net->n_freq == 0 && !net->periodic_mask;
   // workspace layout
   int64_t o = 0;
   auto take = [&](int64_t bytes) { int64_t r = o; o = align_up(o + bytes, kAlign); return r; };
@@ -324,7 +330,7 @@ int make_plan(const pinn_net* net, const pinn_pde* pde, int64_t n_points, const 
     p.o_zb[1] = take(p.n_pad * 4 * D.hmax * 4);
     p.o_out = take((int64_t)p.grid_f * D.d_out * (D.n_in[D.L] + 1) * 8);
     for (int l = 0; l < D.L; ++l) {
-      int grid = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : (p.fuse0 ? p.grid_b / 2 : p.grid_g0)) : p.grid_b;
+      int grid = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : (p.fuse0 ? fused0_slots(p) : p.grid_g0)) : p.grid_b;
       p.o_layer[l] = take((int64_t)grid * D.n_out[l] * (D.n_in[l] + 1 + (l == 0 ? p.ng0 : 0)) * 8);
     }
   }
@@ -873,7 +879,7 @@ int run(const pinn_net* net, const pinn_pde* pde, const float* params, const flo
         a.n_slots = p.grid_f;
       } else {
         a.slots = wk.layer_slots[l];
-        a.n_slots = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : (p.fuse0 ? p.grid_b / 2 : p.grid_g0))
+        a.n_slots = l == 0 ? (net->n_freq > 0 ? p.grid_b0 : (p.fuse0 ? fused0_slots(p) : p.grid_g0))
                            : (p.split ? p.grid_b / 2 : p.grid_b);
       }
       ra.row0[l + 1] = ra.row0[l] + D.n_out[l];
