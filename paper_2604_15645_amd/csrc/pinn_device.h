@@ -1371,10 +1371,11 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
   constexpr int CPB = S::CPB, NOBW = S::NOBW, NIBW = S::NIBW, NIBA = S::NIBA, CBA = S::CBA;
   // g0_slot (layer 1 over an identity embedding): the first layer's weight and bias sums
   // are formed here from the input adjoint, which is then not written (slot layout
-  // [n_in][d_in] then [n_in])
-  float g0s[NIBA][4];
+  // [n_in][d_in] then [n_in]).  Each lane adds its terms in FP64: a work-group's range
+  // holds thousands of points per lane and neuron.
+  double g0s[NIBA][4];
 #pragma unroll
-  for (int q = 0; q < NIBA; ++q) g0s[q][0] = g0s[q][1] = g0s[q][2] = g0s[q][3] = 0.0f;
+  for (int q = 0; q < NIBA; ++q) g0s[q][0] = g0s[q][1] = g0s[q][2] = g0s[q][3] = 0.0;
   constexpr int WO = S::WO, WA = S::WA;
   const LayerDev& ly = net.layer[layer];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -1494,10 +1495,10 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
           if (g0_slot) {
             // the identity input's jets are (x_k, e_k, 0)
             const float4 x = pts[(cb0 + cb) * 4 + g];
-            g0s[q][0] += zb.x * x.x + zb.y;
-            g0s[q][1] += zb.x * x.y + zb.z;
-            g0s[q][2] += zb.x * x.z + zb.w;
-            g0s[q][3] += zb.x;
+            g0s[q][0] += (double)(zb.x * x.x + zb.y);
+            g0s[q][1] += (double)(zb.x * x.y + zb.z);
+            g0s[q][2] += (double)(zb.x * x.z + zb.w);
+            g0s[q][3] += (double)zb.x;
           } else {
             *jet_frag(zb_out, cb0 + cb, ib, nib, lane) = to_float4(zb);
           }
@@ -1534,14 +1535,14 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
   }
   if (g0_slot) {
     // over the lanes of a neuron, then over the waves that share it (fixed order)
-    float* red = reinterpret_cast<float*>(smem);
+    double* red = reinterpret_cast<double*>(smem);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NIBA; ++q) {
       const int ib = wa + WA * q;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        float v = g0s[q][k];
+        double v = g0s[q][k];
         v += __shfl_xor(v, 16, 64);
         v += __shfl_xor(v, 32, 64);
         if (g == 0 && ib < nib) red[((size_t)wca * n_in + 16 * ib + l16) * 4 + k] = v;
@@ -1552,7 +1553,7 @@ __device__ __forceinline__ void bwd_range(const NetDev& net, int layer, const fl
     for (int i = tid; i < n_in; i += kThreads) {
       double t[4] = {0.0, 0.0, 0.0, 0.0};
       for (int w = 0; w < kWaves / WA; ++w)
-        for (int k = 0; k < 4; ++k) t[k] += (double)red[((size_t)w * n_in + i) * 4 + k];
+        for (int k = 0; k < 4; ++k) t[k] += red[((size_t)w * n_in + i) * 4 + k];
       for (int k = 0; k < d; ++k) g0_slot[(size_t)i * d + k] = t[k];
       g0_slot[(size_t)n_in * d + i] = t[3];
     }
