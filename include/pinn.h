@@ -153,7 +153,9 @@ typedef struct {
                             (uniform hidden width 128 or 256, split precisions): the
                             default (32 at width 128, 16 at 256) or half of it            */
   int32_t chunk_points;  /* batched call: points per work item, a multiple of 128
-                            (default 1024 for width 256, 2048 for 128, 4096 below)       */
+                            (default 1024 for width 256, 2048 for 128, 4096 below), or
+                            -1: the instance runs as a fused step of its own (the
+                            single-network kernels) after the persistent launch          */
 } pinn_tune;
 
 /* Number of FP32 parameters of the network (layout above).  < 0 on a bad descriptor. */
@@ -290,6 +292,11 @@ int pinn_balance_update(const double* grads, int n_terms, int64_t n_params, doub
 int pinn_batched_workspace_bytes(const pinn_net* nets, const pinn_pde* pde,
                                  const int64_t* n_points, int n_inst, int prec,
                                  const pinn_tune* tune_table, size_t* bytes);
+/* An instance whose tune entry has chunk_points == -1 takes no part in the persistent
+ * launch: after it, on the same stream, it runs the fused step of pinn_residual_bwd (its
+ * own launches, a region of the same workspace), with the same loss and gradient layout
+ * and the same 1 / n_points[i] mean.  The autotuner uses this where the single-network
+ * kernels are faster for a width class. */
 int pinn_batched_bwd(const pinn_net* nets, const pinn_pde* pde, const float* const* params,
                      const float* const* points, const int64_t* n_points, int n_inst,
                      int prec, const pinn_tune* tune_table, double* const* grads,

@@ -26,7 +26,9 @@ import statistics
 from . import binding
 
 GRIDS = (0, 128)                        # 0 = the library's default (one per compute unit)
-CHUNKS = (512, 1024, 2048, 4096, 8192)  # batched work-item sizes (multiples of 128)
+# batched work-item sizes (multiples of 128); -1: the class's instances run as fused steps
+# of their own after the persistent launch
+CHUNKS = (512, 1024, 2048, 4096, 8192, -1)
 DEFAULT_CHUNK = {32: 4096, 64: 4096, 128: 2048, 256: 1024}   # the library's defaults
 
 

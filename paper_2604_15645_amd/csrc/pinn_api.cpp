@@ -933,6 +933,8 @@ struct BatchPlan {
   std::vector<Dims> D;
   std::vector<int64_t> chunk, pts_off, n_pad, item0, n_items_of, n_eff, slot_base;
   std::vector<int> kmax;
+  std::vector<char> sep;   // instance runs as a fused step of its own (chunk_points == -1)
+  int64_t o_sep, sep_bytes;
   std::vector<BatchItem> items;
   std::vector<int64_t> order;
   int64_t n_pad_all, scratch_per_wg, n_slot_doubles;
@@ -958,6 +960,8 @@ int make_batch_plan(const pinn_net* nets, const pinn_pde* pde, const int64_t* n_
   b.D.resize(n_inst);
   b.chunk.resize(n_inst);
   b.kmax.resize(n_inst);
+  b.sep.assign(n_inst, 0);
+  b.sep_bytes = 0;
   for (int i = 0; i < n_inst; ++i) {
     int rc = check_net(&nets[i], &b.D[i]);
     if (rc) return rc;
@@ -970,8 +974,16 @@ int make_batch_plan(const pinn_net* nets, const pinn_pde* pde, const int64_t* n_
       return PINN_E_UNSUPPORTED;
     if (n_points[i] <= 0) return PINN_E_INVALID;
     int c = default_chunk(b.D[i].H);
-    if (tune && tune[i].chunk_points > 0) {
-      if (tune[i].chunk_points % kSegAlign) return PINN_E_INVALID;
+    if (tune && tune[i].chunk_points == -1) {
+      b.sep[i] = 1;
+      pinn_pde pd = *pde;
+      pd.norm_N = 0.0;  // the mean over the instance's own points
+      int64_t sb = 0;
+      rc = plan_bytes(&nets[i], &pd, n_points[i], nullptr, 0, prec, 1, nullptr, &sb);
+      if (rc) return rc;
+      b.sep_bytes = std::max(b.sep_bytes, sb);
+    } else if (tune && tune[i].chunk_points != 0) {
+      if (tune[i].chunk_points < 0 || tune[i].chunk_points % kSegAlign) return PINN_E_INVALID;
       c = tune[i].chunk_points;
     }
     if (tune && tune[i].tile_points > 0 && tune[i].tile_points != default_fwd_p(b.D[i].H)) return PINN_E_UNSUPPORTED;
@@ -1004,6 +1016,8 @@ int make_batch_plan(const pinn_net* nets, const pinn_pde* pde, const int64_t* n_
     b.n_eff[i] = ne;
     b.item0[i] = (int64_t)b.items.size();
     b.slot_base[i] = slots;
+    b.n_items_of[i] = 0;
+    if (b.sep[i]) continue;
     for (int64_t p0 = 0; p0 < b.n_pad[i]; p0 += b.chunk[i]) {
       BatchItem it;
       it.inst = i;
@@ -1058,6 +1072,7 @@ int make_batch_plan(const pinn_net* nets, const pinn_pde* pde, const int64_t* n_
   b.o_loss = take((int64_t)b.n_items * kMaxTerms * 8);
   b.o_grad = take(b.n_slot_doubles * 8);
   b.o_scratch = take(b.scratch_per_wg * 4 * b.grid);
+  b.o_sep = take(b.sep_bytes);
   b.bytes = o;
   return PINN_OK;
 }
@@ -1163,6 +1178,7 @@ int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* p
   if (hipStreamSynchronize(stream) != hipSuccess) return PINN_E_HIP;
 
   for (int i = 0; i < n_inst; ++i) {
+    if (b.sep[i]) continue;
     const Dims& D = b.D[i];
     PointsArgs pa;
     std::memset(&pa, 0, sizeof(pa));
@@ -1200,8 +1216,6 @@ int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* p
     if (rc) return rc;
   }
   int* counter = reinterpret_cast<int*>(ws + b.o_counter);
-  rc = timed(allow_timing, "k_zero_int", stream, [&] { return launch_zero_int(counter, stream); });
-  if (rc) return rc;
   BatchArgs ba;
   std::memset(&ba, 0, sizeof(ba));
   ba.inst = reinterpret_cast<const BatchInst*>(dev(hinst));
@@ -1218,8 +1232,12 @@ int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* p
   ba.loss_slots = reinterpret_cast<double*>(ws + b.o_loss);
   ba.grad_slots = reinterpret_cast<double*>(ws + b.o_grad);
   for (int k = 0; k < kMaxOut; ++k) ba.lambda_res[k] = (float)pde->lambda_res[k];
-  rc = timed(allow_timing, "k_batched", stream, [&] { return launch_batched(b.prec, b.act | (pde->lap_mask ? kLapFlag : 0), ba, b.grid, b.lds, stream); });
-  if (rc) return rc;
+  if (b.n_items > 0) {
+    rc = timed(allow_timing, "k_zero_int", stream, [&] { return launch_zero_int(counter, stream); });
+    if (rc) return rc;
+    rc = timed(allow_timing, "k_batched", stream, [&] { return launch_batched(b.prec, b.act | (pde->lap_mask ? kLapFlag : 0), ba, b.grid, b.lds, stream); });
+    if (rc) return rc;
+  }
   BatchReduceArgs ra;
   ra.rows = reinterpret_cast<const BatchRow*>(dev(hrows));
   ra.n_entries = (int)n_entries;
@@ -1237,6 +1255,17 @@ int run_batched(const pinn_net* nets, const pinn_pde* pde, const float* const* p
   la.losses = losses;
   rc = timed(allow_timing, "k_reduce_loss_batched", stream, [&] { return launch_reduce_loss_batched(la, stream); });
   if (rc) return rc;
+  // instances on their own launches: after the batched reductions, which wrote zeros for
+  // them, their fused steps write their loss and gradient
+  for (int i = 0; i < n_inst; ++i) {
+    if (!b.sep[i]) continue;
+    pinn_pde pd = *pde;
+    pd.norm_N = 0.0;
+    rc = run(&nets[i], &pd, params[i], nullptr, points[i], n_points[i], nullptr, 0, prec, 0, nullptr, nullptr,
+             losses + (size_t)i * (1 + b.n_res), grads[i], ws + b.o_sep, (size_t)b.sep_bytes, stream_, true,
+             allow_timing);
+    if (rc) return rc;
+  }
   return hip_rc(hipGetLastError());
 }
 

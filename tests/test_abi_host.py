@@ -229,3 +229,22 @@ def test_binding_rejects_mis_sized_buffers():
     binding._check_shapes(c["net"], p, None, x, a)
     with pytest.raises(ValueError):
         binding._check_shapes(c["net"], p, None, x, [dict(a[0], targets=a[0]["targets"][:-1])])
+
+
+def test_batched_tune_table_validation(lib):
+    """chunk_points: a multiple of 128, 0 (the default) or -1 (the instance on launches of
+    its own, whose single-network workspace is added to the call's)."""
+    cfg = synth.CONFIGS["burgers"]
+    nets = [dict(cfg["net"], widths=[64] * 3), dict(cfg["net"], widths=[256] * 3)]
+    n = [5000, 7000]
+    base = binding.batched_workspace_bytes(nets, cfg["pde"], n, "bf16x3")
+    sep = binding.batched_workspace_bytes(nets, cfg["pde"], n, "bf16x3",
+                                          [dict(chunk_points=0), dict(chunk_points=-1)])
+    single = ws(nets[1], cfg["pde"], 7000, prec="bf16x3")
+    assert sep >= single
+    assert binding.batched_workspace_bytes(nets, cfg["pde"], n, "bf16x3",
+                                           [dict(chunk_points=-1), dict(chunk_points=-1)]) >= single
+    assert base > 0
+    for bad in (-2, 100):
+        assert code_of(lambda: binding.batched_workspace_bytes(nets, cfg["pde"], n, "bf16x3",
+                                                               [dict(chunk_points=bad), {}])) == -1

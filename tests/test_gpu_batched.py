@@ -158,3 +158,31 @@ def test_batched_first_layer_gradient(oracle, dev, prec):
         e0 = relerr(got[:n0], ref["grad"][:n0])
         print(prec, i, c["net"]["widths"], "loss %.2e grad %.2e first layer %.2e" % (el, eg, e0))
         assert el <= SWEEP_TOL[prec] and eg <= SWEEP_TOL[prec] and e0 <= SWEEP_TOL[prec], (i, el, eg, e0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_batched_instances_on_own_launches(dev, prec):
+    """chunk_points = -1: those instances run the single-network fused step after the
+    persistent launch (bit for bit the separate call); the others are unaffected; with every
+    instance on its own launches there is no persistent launch at all."""
+    import torch
+    from paper_2604_15645_amd import binding
+    insts = small_sweep(8, scale=0.03)
+    params, pts = to_dev(insts, dev)
+    nets = [c["net"] for c in insts]
+    pde = insts[0]["pde"]
+    base = binding.batched_step(nets, pde, params, pts, prec=prec)
+    base_l, base_g = base["losses"].clone(), [g.clone() for g in base["grads"]]
+    for sep in ([i % 2 == 1 for i in range(8)], [True] * 8):
+        table = [dict(chunk_points=-1 if s else 0) for s in sep]
+        out = binding.batched_step(nets, pde, params, pts, prec=prec, tune_table=table)
+        losses, grads = out["losses"].clone(), [g.clone() for g in out["grads"]]
+        torch.cuda.synchronize()
+        for i, c in enumerate(insts):
+            if sep[i]:
+                one = binding.residual_step(c["net"], pde, params[i], None, pts[i], (), prec=prec, residual=False)
+                torch.cuda.synchronize()
+                assert torch.equal(losses[i], one["loss"]), i
+                assert torch.equal(grads[i], one["grad"]), i
+            else:
+                assert torch.equal(losses[i], base_l[i]) and torch.equal(grads[i], base_g[i]), i
