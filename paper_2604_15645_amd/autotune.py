@@ -7,7 +7,9 @@ The tunable launch parameters are those of `pinn_tune` in include/pinn.h:
   hidden-layer backward (`bwd_points`: the default or half of it) and the work-group count
   (`grid`); every combination the library builds for the network is timed;
 * many networks in one persistent launch (`pinn_batched_bwd`): the points per work item
-  (`chunk_points`) for each hidden-width class, and the work-group count.
+  (`chunk_points`) for each hidden-width class, or -1 for a class whose networks run
+  faster as fused steps of their own after the persistent launch, and the work-group
+  count.
 
 Each candidate is timed on the device with HIP events around real calls of the library
 (median of `reps` calls after one warm-up call), and the fastest is kept.  The batched
