@@ -172,7 +172,8 @@ def tune_single(net_spec, pde_spec, params, B, points, anchors=(), prec="bf16x3"
 def tune_batched(net_specs, pde_spec, params, points, prec="bf16x3", reps=2, cache=None, force=False,
                  chunks=CHUNKS, grids=GRIDS):
     """Per-instance tune table for one batched launch, by coordinate descent over the
-    width classes present, then over the work-group count.  Returns (table, ms, log)."""
+    width classes present (two rounds), then over the work-group count.  Returns (table, ms,
+    log)."""
     dev = points[0].device
     cache = cache if cache is not None else TuneCache()
     sig = batch_signature(net_specs, [p.shape[0] for p in points], prec)
@@ -195,16 +196,19 @@ def tune_batched(net_specs, pde_spec, params, points, prec="bf16x3", reps=2, cac
     run(best_chunks, best_grid)          # untimed: first-use costs
     best_ms = run(best_chunks, best_grid)
     log.append({"chunks": dict(best_chunks), "grid": best_grid, "ms": best_ms})
-    for h in classes:
-        for c in chunks:
-            if c == best_chunks[h]:
-                continue
-            trial = dict(best_chunks)
-            trial[h] = c
-            ms = run(trial, best_grid)
-            log.append({"chunks": dict(trial), "grid": best_grid, "ms": ms})
-            if ms < best_ms:
-                best_ms, best_chunks = ms, trial
+    # two rounds over the classes: a class's best choice depends on what the others run
+    # (which networks share the persistent launch)
+    for _ in range(2):
+        for h in classes:
+            for c in chunks:
+                if c == best_chunks[h]:
+                    continue
+                trial = dict(best_chunks)
+                trial[h] = c
+                ms = run(trial, best_grid)
+                log.append({"chunks": dict(trial), "grid": best_grid, "ms": ms})
+                if ms < best_ms:
+                    best_ms, best_chunks = ms, trial
     for grid in grids:
         if grid == best_grid:
             continue
