@@ -180,6 +180,19 @@ def test_uneven_widths_no_bias_sine(oracle, dev, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("widths,n_freq", [([64], 0), ([256], 0), ([32] * 8, 0), ([64] * 8, 16)])
+def test_depth_extremes(oracle, dev, prec, widths, n_freq):
+    """One hidden layer (the identity first layer's gradient from its own pass, no layer 1
+    to form it) and the deepest network the library takes (eight hidden layers), with the
+    identity and the Fourier embedding."""
+    from paper_2604_15645_amd import synth
+    net = dict(d_in=2, d_out=1, widths=widths, act="tanh", w0=1.0, n_freq=n_freq, rwf=False, has_bias=True)
+    pde = dict(pde="burgers", lap_mask=1, coef=[0.01, 0, 0, 0], lambda_res=[1.0, 1, 1], norm_N=0.0)
+    case = synth.make_custom(net, pde, [(-1, 1), (0, 1)], 450, seed=91 + len(widths), sigma=1.0)
+    check(run_gpu(case, dev, prec), run_oracle(oracle, case), prec, "depth-%d-%d" % (len(widths), widths[0]))
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_rff_rwf_burgers_with_anchor_weights(oracle, dev, prec):
     from paper_2604_15645_amd import synth
     net = dict(d_in=2, d_out=1, widths=[128, 128], act="tanh", w0=1.0, n_freq=32, rwf=True,
