@@ -160,7 +160,7 @@ def test_batched_first_layer_gradient(oracle, dev, prec):
         assert el <= SWEEP_TOL[prec] and eg <= SWEEP_TOL[prec] and e0 <= SWEEP_TOL[prec], (i, el, eg, e0)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
 def test_batched_instances_on_own_launches(dev, prec):
     """chunk_points = -1: those instances run the single-network fused step after the
     persistent launch (bit for bit the separate call); the others are unaffected; with every
